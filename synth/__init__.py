@@ -1,0 +1,318 @@
+"""Seeded synthetic scenarios for the hex-raster Saint-Venant stepper.
+
+This module only draws inputs: terrain, porosity and drag fields, rain forcing,
+initial states and boundary descriptions.  It holds none of the scheme's
+arithmetic, so the CPU oracle and the GPU library can both consume its output
+without sharing code.  Random numbers come from NumPy's PCG64 with the seed
+``14933 + 1000 * config + scenario``.
+
+The paper's own workloads (real DEMs and flume measurements) are not available;
+the recipes below stand in for them (fractal relief with an outlet, Gaussian
+vegetation patches, constant or triangular rain).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+INTERIOR, WALL, OUTFLOW, PERIODIC = 0, 1, 2, 3
+S, E, N, W = 0, 1, 2, 3
+
+G_ACCEL = 9.81          # m/s^2 (value used by the paper's experiments)
+ALPHA_P = 73.39         # 1/m, plant drag coefficient calibrated in the paper's flume study
+ALPHA_S = 0.00709       # Darcy-Weisbach soil coefficient calibrated there too
+MMH = 1.0e-3 / 3600.0   # 1 mm/h in m/s
+
+
+def seed_of(config: int, scenario: int = 0) -> int:
+    return 14933 + 1000 * config + scenario
+
+
+def rng_of(config: int, scenario: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed_of(config, scenario)))
+
+
+@dataclass
+class Scenario:
+    """Everything one run needs; arrays are FP64, index i = r*nq + q."""
+    name: str
+    nq: int
+    nr: int
+    a: float
+    z: np.ndarray
+    theta: np.ndarray
+    alpha_p: np.ndarray
+    alpha_s: float = ALPHA_S
+    side: tuple = (OUTFLOW, WALL, WALL, WALL)
+    segs: tuple = ()
+    active: np.ndarray | None = None
+    mask_code: int = WALL
+    rain_kind: int = 0
+    i_a: float = 0.0
+    t_a: float = 0.0
+    T_d: float = float("inf")
+    h0: np.ndarray | None = None
+    v10: np.ndarray | None = None
+    v20: np.ndarray | None = None
+    t_end: float = 600.0
+    g: float = G_ACCEL
+    cfl: float = 0.5
+    dt_max: float = 1.0
+    h_dry: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        n = self.nq * self.nr
+        if self.h0 is None:
+            self.h0 = np.zeros(n)
+        if self.v10 is None:
+            self.v10 = np.zeros(n)
+        if self.v20 is None:
+            self.v20 = np.zeros(n)
+
+    @property
+    def n(self) -> int:
+        return self.nq * self.nr
+
+    @property
+    def rain(self):
+        return (self.rain_kind, self.i_a, self.t_a, self.T_d)
+
+    def with_(self, **kw) -> "Scenario":
+        return replace(self, **kw)
+
+
+# ------------------------------------------------------------ raster layout
+
+def centres(nq: int, nr: int, a: float):
+    """Hex centre coordinates of the axial parallelogram (pointy-top, edge a)."""
+    q = np.tile(np.arange(nq, dtype=np.float64), nr)
+    r = np.repeat(np.arange(nr, dtype=np.float64), nq)
+    x = a * math.sqrt(3.0) * (q + 0.5 * r)
+    y = 1.5 * a * r
+    return x, y
+
+
+# ---------------------------------------------------------------- terrain
+
+def fractal_field(nq, nr, a, rng, beta=2.0):
+    """Gaussian random surface with power spectrum ~ |k|^-beta, sampled at hex centres.
+
+    Built by an inverse real FFT on a rectangle covering the parallelogram, with
+    random phases, then bilinear interpolation at the centres.  Returned in [0, 1].
+    """
+    dx, dy = a * math.sqrt(3.0), 1.5 * a
+    nx = nq + (nr + 1) // 2 + 2
+    ny = nr + 2
+    kx = np.fft.rfftfreq(nx, d=dx)
+    ky = np.fft.fftfreq(ny, d=dy)
+    K = np.sqrt(kx[None, :] ** 2 + ky[:, None] ** 2)
+    K[0, 0] = 1.0
+    amp = K ** (-beta / 2.0)
+    amp[0, 0] = 0.0
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=amp.shape)
+    spec = (amp * np.exp(1j * phase)).astype(np.complex128)
+    f = np.fft.irfft2(spec, s=(ny, nx))
+    x, y = centres(nq, nr, a)
+    fx, fy = x / dx, y / dy
+    i0 = np.clip(np.floor(fx).astype(np.int64), 0, nx - 2)
+    j0 = np.clip(np.floor(fy).astype(np.int64), 0, ny - 2)
+    tx, ty = fx - i0, fy - j0
+    v = ((1 - tx) * (1 - ty) * f[j0, i0] + tx * (1 - ty) * f[j0, i0 + 1]
+         + (1 - tx) * ty * f[j0 + 1, i0] + tx * ty * f[j0 + 1, i0 + 1])
+    v = (v - v.min()) / max(v.max() - v.min(), 1e-300)
+    return v
+
+
+def carve_outlet(z, nq, nr, a, width=16, radius_cells=256, grade=0.01):
+    """Lower the terrain around an outlet in the middle of the S side.
+
+    z <- min(z, z_out + grade * d) within radius_cells*a of the outlet centre, with
+    z_out = min(z) - 1 m.  Returns (z, segs) with segs the OUTFLOW segment of the S side.
+    """
+    x, y = centres(nq, nr, a)
+    q0 = nq // 2 - width // 2
+    xo = a * math.sqrt(3.0) * (nq // 2)
+    d = np.hypot(x - xo, y)
+    z_out = z.min() - 1.0
+    near = d <= radius_cells * a
+    z = z.copy()
+    z[near] = np.minimum(z[near], z_out + grade * d[near])
+    segs = ((S, q0, q0 + width, OUTFLOW),)
+    return z, segs
+
+
+# ------------------------------------------------------------- vegetation
+
+def vegetation_density(nq, nr, a, rng, n_patches, peak_lo=0.0, peak_hi=0.6, dmax=0.6,
+                       sig_lo=4.0, sig_hi=32.0):
+    """Sum of Gaussian patches of plant density, capped at dmax.
+
+    Centres uniform over the raster, widths U[sig_lo*a, sig_hi*a], peaks U[peak_lo, peak_hi].
+    Each patch is evaluated only within 4 widths of its centre.
+    """
+    n = nq * nr
+    d = np.zeros(n)
+    x, y = centres(nq, nr, a)
+    sq3 = math.sqrt(3.0)
+    cq = rng.uniform(0, nq, size=n_patches)
+    cr = rng.uniform(0, nr, size=n_patches)
+    sig = rng.uniform(sig_lo * a, sig_hi * a, size=n_patches)
+    peak = rng.uniform(peak_lo, peak_hi, size=n_patches)
+    d2 = d.reshape(nr, nq)
+    for p in range(n_patches):
+        cx = a * sq3 * (cq[p] + 0.5 * cr[p])
+        cy = 1.5 * a * cr[p]
+        R = 4.0 * sig[p]
+        r_lo = max(0, int(math.floor((cy - R) / (1.5 * a))))
+        r_hi = min(nr, int(math.ceil((cy + R) / (1.5 * a))) + 1)
+        if r_lo >= r_hi:
+            continue
+        q_lo = max(0, int(math.floor((cx - R) / (a * sq3) - 0.5 * (r_hi - 1))))
+        q_hi = min(nq, int(math.ceil((cx + R) / (a * sq3) - 0.5 * r_lo)) + 1)
+        if q_lo >= q_hi:
+            continue
+        qq = np.arange(q_lo, q_hi, dtype=np.float64)
+        rr = np.arange(r_lo, r_hi, dtype=np.float64)
+        X = a * sq3 * (qq[None, :] + 0.5 * rr[:, None])
+        Y = 1.5 * a * rr[:, None] + 0.0 * qq[None, :]
+        g = peak[p] * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * sig[p] ** 2))
+        d2[r_lo:r_hi, q_lo:q_hi] += g
+    return np.minimum(d, dmax)
+
+
+# ----------------------------------------------------------------- configs
+
+def c1_planar(nq=64, nr=64, a=1.0, slope=0.05, theta=0.8, rain_mmh=50.0, t_end=600.0):
+    """Plain method, FP64: uniform planar slope, porosity 0.8, constant drag, dry start."""
+    n = nq * nr
+    _, y = centres(nq, nr, a)
+    return Scenario(
+        name=f"planar{nq}x{nr}", nq=nq, nr=nr, a=a, z=slope * y, theta=np.full(n, theta),
+        alpha_p=np.full(n, ALPHA_P), side=(OUTFLOW, WALL, WALL, WALL), rain_kind=0,
+        i_a=rain_mmh * MMH, T_d=float("inf"), t_end=t_end,
+        meta={"slope": slope, "rain_mmh": rain_mmh})
+
+
+def catchment(nq, nr, a, config, relief=40.0, rain_mmh=100.0, t_end=3600.0, rain_T=None,
+              outlet_width=16, scenario=0):
+    """Single fractal catchment with a carved outlet and Gaussian vegetation patches."""
+    rng = rng_of(config, scenario)
+    z = relief * fractal_field(nq, nr, a, rng)
+    z, segs = carve_outlet(z, nq, nr, a, width=outlet_width,
+                           radius_cells=min(256, max(nq, nr) // 4))
+    n = nq * nr
+    d = vegetation_density(nq, nr, a, rng, max(1, n // 2048))
+    return Scenario(
+        name=f"catchment{nq}x{nr}", nq=nq, nr=nr, a=a, z=z, theta=1.0 - d,
+        alpha_p=np.full(n, ALPHA_P), side=(WALL, WALL, WALL, WALL), segs=segs, rain_kind=0,
+        i_a=rain_mmh * MMH, T_d=float("inf") if rain_T is None else rain_T, t_end=t_end,
+        meta={"relief": relief, "rain_mmh": rain_mmh, "seed": seed_of(config, scenario)})
+
+
+def c2_catchment(nq=1024, nr=1024, a=2.0, t_end=3600.0):
+    """Single catchment, FP64 vs FP32: fractal relief 0-40 m, outlet, 100 mm/h for 3600 s."""
+    return catchment(nq, nr, a, config=2, rain_mmh=100.0, t_end=t_end)
+
+
+def c4_large(nq=4096, nr=4096, a=2.0, t_end=3600.0):
+    """Large single domain, FP32: as C2 with a 150 mm/h storm for 1800 s then recession."""
+    return catchment(nq, nr, a, config=4, rain_mmh=150.0, t_end=t_end, rain_T=1800.0)
+
+
+def ensemble_member(s, nmin=128, nmax=512, a=1.0, t_end=1800.0, config=3, size=None):
+    """One scenario of the batched ensemble: planar slope, patches, constant or triangular rain."""
+    rng = rng_of(config, s)
+    ns = int(rng.integers(nmin, nmax + 1)) if size is None else int(size)
+    slope = float(rng.uniform(0.01, 0.20))
+    peak = float(rng.uniform(0.0, 0.6))
+    i_mmh = float(rng.uniform(10.0, 150.0))
+    tri = bool(rng.integers(0, 2))
+    n = ns * ns
+    _, y = centres(ns, ns, a)
+    d = vegetation_density(ns, ns, a, rng, max(1, n // 2048), peak_lo=0.0, peak_hi=peak)
+    if tri:
+        kind, t_a, T_d = 1, 0.25 * t_end, t_end
+    else:
+        kind, t_a, T_d = 0, 0.0, float("inf")
+    return Scenario(
+        name=f"ens{config}_{s}_{ns}", nq=ns, nr=ns, a=a, z=slope * y, theta=1.0 - d,
+        alpha_p=np.full(n, ALPHA_P), side=(OUTFLOW, WALL, WALL, WALL), rain_kind=kind,
+        i_a=i_mmh * MMH, t_a=t_a, T_d=T_d, t_end=t_end,
+        meta={"slope": slope, "peak": peak, "rain_mmh": i_mmh, "triangular": tri,
+              "seed": seed_of(config, s)})
+
+
+def c3_ensemble(n_scen=256, nmin=128, nmax=512, t_end=1800.0, config=3):
+    return [ensemble_member(s, nmin, nmax, t_end=t_end, config=config) for s in range(n_scen)]
+
+
+# ------------------------------------------------------- invariant set-ups
+
+def hexagon_mask(nq, nr, R):
+    """Active cells within hex distance R of the centre cell (nq//2, nr//2)."""
+    q = np.tile(np.arange(nq), nr) - nq // 2
+    r = np.repeat(np.arange(nr), nq) - nr // 2
+    return (np.maximum(np.maximum(np.abs(q), np.abs(r)), np.abs(q + r)) <= R).astype(np.uint8)
+
+
+def cone(R=12, a=1.0, H=2.0, crater=False, rain_mmh=200.0, t_end=60.0, rim=WALL, theta=0.9):
+    """Six-fold symmetric cone (or crater) on a hexagonal active region of radius R."""
+    nq = nr = 2 * R + 3
+    act = hexagon_mask(nq, nr, R)
+    x, y = centres(nq, nr, a)
+    xc, yc = a * math.sqrt(3.0) * (nq // 2 + 0.5 * (nr // 2)), 1.5 * a * (nr // 2)
+    rho = np.hypot(x - xc, y - yc)
+    rho_max = R * a * math.sqrt(3.0)
+    zf = H * (1.0 - rho / rho_max)
+    if crater:
+        zf = H * rho / rho_max
+    n = nq * nr
+    return Scenario(
+        name=f"cone{R}{'c' if crater else ''}", nq=nq, nr=nr, a=a, z=zf, theta=np.full(n, theta),
+        alpha_p=np.full(n, ALPHA_P), side=(WALL, WALL, WALL, WALL), active=act, mask_code=rim,
+        rain_kind=0, i_a=rain_mmh * MMH, t_end=t_end, meta={"R": R})
+
+
+def kinematic_strip(nq=8, nr=64, a=1.0, slope=0.05, theta=0.8, rain_mmh=50.0, t_end=3600.0):
+    """Planar slope periodic in q, wall at the top row, free outflow at r = 0."""
+    n = nq * nr
+    _, y = centres(nq, nr, a)
+    return Scenario(
+        name=f"strip{nq}x{nr}", nq=nq, nr=nr, a=a, z=slope * y, theta=np.full(n, theta),
+        alpha_p=np.full(n, ALPHA_P), side=(OUTFLOW, PERIODIC, WALL, PERIODIC), rain_kind=0,
+        i_a=rain_mmh * MMH, t_end=t_end, meta={"slope": slope})
+
+
+def lake_at_rest(nq=24, nr=20, a=1.0, level=1.0, emerged=False, seed=7):
+    """Still water over rough dyadic terrain: w = g*(z+h) is constant on wet cells.
+
+    Terrain values are multiples of 2^-10 below the level so z + h == level exactly.
+    With emerged=True some cells rise above the level and stay dry.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = nq * nr
+    z = np.round(rng.uniform(0.0, 0.75, size=n) * 1024.0) / 1024.0
+    if emerged:
+        bumps = rng.random(n) < 0.15
+        z[bumps] = level + np.round(rng.uniform(0.01, 0.3, size=bumps.sum()) * 1024.0) / 1024.0
+    h = np.maximum(level - z, 0.0)
+    th = np.round(rng.uniform(0.4, 1.0, size=n) * 256.0) / 256.0
+    return Scenario(
+        name="lake", nq=nq, nr=nr, a=a, z=z, theta=th, alpha_p=np.full(n, ALPHA_P),
+        side=(WALL, WALL, WALL, WALL), rain_kind=0, i_a=0.0, h0=h, t_end=50.0)
+
+
+def random_state(sc: Scenario, seed: int, depth=0.05, speed=0.3, dry_frac=0.2):
+    """A rough wet/dry state on sc's raster (for one-step checks)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = sc.n
+    h = rng.uniform(0.0, depth, size=n)
+    h[rng.random(n) < dry_frac] = 0.0
+    v1 = rng.uniform(-speed, speed, size=n)
+    v2 = rng.uniform(-speed, speed, size=n)
+    v1[h == 0] = 0.0
+    v2[h == 0] = 0.0
+    return h, v1, v2
