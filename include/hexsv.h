@@ -1,0 +1,213 @@
+/*
+ * hexsv.h — C-ABI of the MI355X (gfx950) time stepper for the porous
+ * Saint-Venant model on a regular hexagonal raster.
+ *
+ * Method: Ion, Marinescu, Cruceanu, "ASTERIX: Module for modelling the water
+ * flow on vegetated hillslopes" (arXiv 2406.14933).  Model: Sec. 2.1,
+ * eq. swe_vegm_rm.02 with the Darcy-Weisbach soil friction (eq_tsa_darcy), the
+ * plant drag (eq_tpa) and their sum K(h, theta) (eq_K_h_theta).  Scheme:
+ * Sec. 2.2, eqs. fvm_2D_eq.04-.06 (interface values), fvm_2D_eq_frac.01
+ * (operators L, J, S) and fvm_2D_eq_frac.07 (full step), solved as in
+ * Appendix A (fractional steps .05/.06, CFL time step .12/.13, closed-form
+ * friction solve miu-formula).  Rain: constant or the triangular hyetograph
+ * of Appendix C.
+ *
+ * Conventions
+ *  - Units SI (m, s, m/s).  g defaults to 9.81 m/s^2.
+ *  - Raster: nq x nr axial parallelogram of pointy-top hexagons of edge a
+ *    (the paper's "cell radius"), cell (q, r) at index i = r*nq + q, centre
+ *    (a*sqrt(3)*(q + r/2), 1.5*a*r).  Direction k in 0..5 points at k*60
+ *    degrees: (dq,dr) = (+1,0),(0,+1),(-1,+1),(-1,0),(0,-1),(+1,-1).
+ *  - Sides: S is r = -1, E is q = nq, N is r = nr, W is q = -1.  An edge that
+ *    leaves the raster (after periodic wraps) takes the code of the side its
+ *    outside neighbour lies on (S/N when r is out of range, else E/W), or of
+ *    a segment of that side containing the outside neighbour's position
+ *    along the side (q for S/N, r for E/W).  Edges into inactive cells take
+ *    mask_bc.  WALL edges carry no flux or pressure term; OUTFLOW edges see a
+ *    ghost with the cell's h, v, theta and the terrain extrapolated linearly
+ *    through the opposite neighbour.
+ *  - Every d_* pointer is caller-owned device memory (e.g. a torch tensor's
+ *    data_ptr()), read or written only during the call (stream-ordered on
+ *    `stream`); the library copies inputs into its own buffers and never frees
+ *    caller memory.  Handles are library-owned; *_destroy frees them.  A
+ *    handle is not thread-safe; distinct handles are independent.
+ *  - Every int-returning call returns HEXSV_OK (0) or a negative hexsv_status
+ *    and sets a thread-local message readable with hexsv_last_error().  No
+ *    call aborts or throws.
+ */
+#ifndef HEXSV_H
+#define HEXSV_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HEXSV_OK = 0,
+    HEXSV_EINVAL = -1,      /* malformed argument (null handle, bad size, ...) */
+    HEXSV_EDOMAIN = -2,     /* a field or parameter outside the model's domain */
+    HEXSV_ENOMEM = -3,      /* device or host allocation failed */
+    HEXSV_EHIP = -4,        /* a HIP runtime call failed (message has hipGetErrorString) */
+    HEXSV_ENUMERIC = -5,    /* a non-finite value appeared during a run */
+    HEXSV_ESTATE = -6,      /* call out of order (e.g. run before set_state) */
+    HEXSV_EUNSUPPORTED = -7 /* option not built */
+} hexsv_status;
+
+typedef enum { HEXSV_FP64 = 0, HEXSV_FP32 = 1 } hexsv_precision;
+
+/* edge codes and side kinds */
+enum { HEXSV_INTERIOR = 0, HEXSV_WALL = 1, HEXSV_OUTFLOW = 2, HEXSV_PERIODIC = 3 };
+/* sides */
+enum { HEXSV_S = 0, HEXSV_E = 1, HEXSV_N = 2, HEXSV_W = 3 };
+
+#define HEXSV_MAX_SEGMENTS 8
+
+/* Part [lo, hi) of a side whose boundary edges take `code` (WALL or OUTFLOW). */
+typedef struct {
+    int32_t side, lo, hi, code;
+} hexsv_segment;
+
+/* Raster and boundary description (Sec. 2.2 (a) cell decomposition; boundary
+ * kinds of Sec. 3 "Boundary conditions": free discharge and impermeable wall). */
+typedef struct {
+    int32_t nq, nr;          /* cells along q and r, each >= 1 */
+    double edge;             /* hexagon edge length a > 0 (m) */
+    int32_t side_bc[4];      /* WALL, OUTFLOW or PERIODIC per side S,E,N,W;
+                                E/W (and S/N) must agree on PERIODIC */
+    int32_t nseg;            /* number of valid entries in seg (<= 8) */
+    hexsv_segment seg[HEXSV_MAX_SEGMENTS];
+    const uint8_t *active;   /* host, nq*nr, nullable (all active): 1 = in the domain */
+    int32_t mask_bc;         /* code of edges into inactive cells: WALL or OUTFLOW */
+} hexsv_grid_desc;
+
+/* Scheme parameters (Appendix A; control parameters listed in Sec. 3). */
+typedef struct {
+    double g;                /* gravitational acceleration, > 0 */
+    double cfl;              /* Courant number in (0, 1) (Appendix A, eq. .12) */
+    double dt_max;           /* maximum time step, > 0 */
+    double h_dry;            /* >= 0; cells with h^{n+1} < h_dry get v = 0 (0: off) */
+    int32_t precision;       /* hexsv_precision */
+    int32_t steps_per_graph; /* steps captured per graph replay (0: default 100) */
+    int32_t tile;            /* tile variant index (< 0: tuned or default) */
+    int32_t reserved;
+} hexsv_params;
+
+/* Rain source of the mass equation (Sec. 2.1 (c), Appendix C).
+ * kind 0: r = i_a for 0 <= t <= T_d (T_d may be +inf), else 0.
+ * kind 1: triangular hyetograph: i_a t/t_a on [0, t_a], i_a (1 - t/T_d)/(1 - t_a/T_d)
+ *         on (t_a, T_d], 0 otherwise.  r is evaluated at t^{n+1}. */
+typedef struct {
+    int32_t kind;
+    double i_a;              /* m/s */
+    double t_a, T_d;         /* s */
+} hexsv_rain;
+
+/* Volume books (the rainfall / water out / water left table of the paper's
+ * Susita experiment), all FP64, in m^3. */
+typedef struct {
+    double t;         /* current time */
+    double initial;   /* sum sigma*theta*h at set_state */
+    double stored;    /* sum sigma*theta*h now */
+    double rain;      /* rain volume added */
+    double outflow;   /* volume that left through OUTFLOW edges */
+    double clamp;     /* volume added by clamping negative theta*h to zero */
+    double residual;  /* |stored - (initial + rain - outflow + clamp)| / (initial + rain) */
+    int64_t steps;    /* steps taken since set_state */
+    double dt_min, dt_max_seen;
+} hexsv_books;
+
+typedef struct hexsv_grid hexsv_grid;
+typedef struct hexsv_sim hexsv_sim;
+typedef struct hexsv_ensemble hexsv_ensemble;
+
+/* Library version and the thread-local message of the last failed call. */
+const char *hexsv_version(void);
+const char *hexsv_last_error(void);
+
+/* ---------------------------------------------------------------- raster */
+
+/* Validate `desc` and build a raster handle (copies `active`).
+ * EINVAL: sizes, codes or segments malformed.  ENOMEM. */
+int hexsv_grid_create(const hexsv_grid_desc *desc, hexsv_grid **out);
+void hexsv_grid_destroy(hexsv_grid *grid);
+/* Number of cells nq*nr and of active cells. */
+int hexsv_grid_counts(const hexsv_grid *grid, int64_t *cells, int64_t *active);
+
+/* Neighbour and edge-code tables computed on the device (one thread per cell):
+ * d_nbr[i*6+k] = index of the neighbour across edge k for INTERIOR edges, -1
+ * otherwise; d_code[i*6+k] = edge code; inactive cells get six WALL codes.
+ * Caller-allocated device arrays of nq*nr*6 int32 and uint8. */
+int hexsv_grid_tables(const hexsv_grid *grid, int32_t *d_nbr, uint8_t *d_code,
+                      hipStream_t stream);
+
+/* ------------------------------------------------------ single catchment */
+
+/* Create a simulation on `grid` (the grid must outlive it).  Allocates the
+ * double-buffered state and static fields in the chosen precision.
+ * EDOMAIN: cfl not in (0,1), dt_max <= 0, g <= 0, h_dry < 0. */
+int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *params, hexsv_sim **out);
+void hexsv_sim_destroy(hexsv_sim *sim);
+
+/* Static fields (Sec. 2.1 (a), (b), (f), (e)): terrain z, porosity theta and
+ * plant coefficient alpha_p per cell (device FP64 arrays of nq*nr), uniform
+ * soil coefficient alpha_s.  EDOMAIN (after a device check, synchronising
+ * `stream`): theta not in (0,1] on an active cell, alpha_p < 0, non-finite z,
+ * alpha_s < 0.  The message names the first offending cell. */
+int hexsv_sim_set_fields(hexsv_sim *sim, const double *d_z, const double *d_theta,
+                         const double *d_alpha_p, double alpha_s, hipStream_t stream);
+
+/* Rain forcing.  EDOMAIN: i_a < 0, kind 1 with t_a <= 0 or T_d <= t_a. */
+int hexsv_sim_set_rain(hexsv_sim *sim, const hexsv_rain *rain);
+
+/* Initial state (the paper's "initial water layer", Sec. 3) at time t0:
+ * h, v1, v2 per cell (device FP64 arrays of nq*nr).  Resets the books and
+ * the step count, and computes the first CFL bound.  EDOMAIN: h < 0 or a
+ * non-finite value on an active cell.  ESTATE: set_fields not called. */
+int hexsv_sim_set_state(hexsv_sim *sim, double t0, const double *d_h, const double *d_v1,
+                        const double *d_v2, hipStream_t stream);
+
+/* Advance to t_end, or until max_steps more steps were taken (max_steps <= 0:
+ * no limit).  Each step: dt = min(dt_max, CFL*phi_min/c_max, t_end - t),
+ * then eq. fvm_2D_eq_frac.07 on every active cell, then c_max and the FP64
+ * books of the new state; the last step lands on t_end exactly.  Runs as
+ * replays of a captured graph of steps_per_graph steps on `stream`, reading
+ * a 128-byte control block back after each replay.  EDOMAIN: t_end < t.
+ * ENUMERIC: a non-finite value appeared (state left at the failing step). */
+int hexsv_sim_run(hexsv_sim *sim, double t_end, int64_t max_steps, hipStream_t stream);
+
+/* Current state as FP64 device arrays (each nullable): h, v1, v2 and the
+ * discharges q_a = theta*h*v_a. */
+int hexsv_sim_get_state(const hexsv_sim *sim, double *d_h, double *d_v1, double *d_v2,
+                        double *d_q1, double *d_q2, hipStream_t stream);
+
+/* Books of the current state (synchronises `stream`). */
+int hexsv_sim_get_books(hexsv_sim *sim, hexsv_books *out, hipStream_t stream);
+/* Restore books saved with get_books after set_state of the saved state
+ * (checkpoint/resume).  The time t and step count are restored too. */
+int hexsv_sim_set_books(hexsv_sim *sim, const hexsv_books *books, hipStream_t stream);
+
+/* Device timing of run(): while enabled, run() brackets every graph replay
+ * with hipEvents on its stream and accumulates the replays' GPU time and the
+ * steps they took.  Reads the totals since the last reset; enable >= 0
+ * switches timing on (1) or off (0) and resets the totals, enable < 0 only
+ * reads.  Each step is one kernel launch, so gpu_ms/steps is the step
+ * kernel's average duration including launch gaps inside the graph. */
+int hexsv_sim_timing(hexsv_sim *sim, int32_t enable, double *gpu_ms, int64_t *steps,
+                     int64_t *replays);
+
+/* Launch/tile statistics of the step kernel: number of workgroups, tile
+ * variant in use and its shape (tq x tr cells, threads). */
+int hexsv_sim_info(const hexsv_sim *sim, int32_t *workgroups, int32_t *tile, int32_t *tq,
+                   int32_t *tr, int32_t *threads);
+
+/* Number of tile variants built, and the shape of variant v. */
+int hexsv_tile_count(void);
+int hexsv_tile_shape(int32_t v, int32_t *tq, int32_t *tr, int32_t *threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,540 @@
+// hexsv_capi.hip — the C-ABI declared in include/hexsv.h: handles, input
+// validation, graph capture of the step loop, books and error reporting.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hexsv.h"
+#include "hexsv_internal.h"
+
+using namespace hexsv;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_msg;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_msg = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(HEXSV_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+extern "C" const char *hexsv_last_error(void) { return g_msg.c_str(); }
+extern "C" const char *hexsv_version(void) { return "hexsv 0.1 gfx950"; }
+
+// ------------------------------------------------------------------ raster
+
+struct hexsv_grid {
+    KGrid kg;
+    double edge;
+    int64_t n, n_active;
+    uint8_t *d_active;  // nullptr when every cell is active
+};
+
+static bool valid_side(int c) {
+    return c == HEXSV_WALL || c == HEXSV_OUTFLOW || c == HEXSV_PERIODIC;
+}
+
+extern "C" int hexsv_grid_create(const hexsv_grid_desc *desc, hexsv_grid **out) {
+    if (!desc || !out) return fail(HEXSV_EINVAL, "grid_create: null argument");
+    *out = nullptr;
+    if (desc->nq < 1 || desc->nr < 1)
+        return fail(HEXSV_EINVAL, "grid_create: nq=%d nr=%d must be >= 1", desc->nq, desc->nr);
+    const int64_t n = (int64_t)desc->nq * desc->nr;
+    if (n > 0x7fffffffLL) return fail(HEXSV_EINVAL, "grid_create: %lld cells exceed 2^31-1", (long long)n);
+    if (!(desc->edge > 0.0) || !isfinite(desc->edge))
+        return fail(HEXSV_EINVAL, "grid_create: edge length must be finite and > 0");
+    for (int s = 0; s < 4; ++s)
+        if (!valid_side(desc->side_bc[s]))
+            return fail(HEXSV_EINVAL, "grid_create: side %d has invalid code %d", s, desc->side_bc[s]);
+    const bool perq = desc->side_bc[HEXSV_E] == HEXSV_PERIODIC;
+    const bool perr = desc->side_bc[HEXSV_S] == HEXSV_PERIODIC;
+    if (perq != (desc->side_bc[HEXSV_W] == HEXSV_PERIODIC) ||
+        perr != (desc->side_bc[HEXSV_N] == HEXSV_PERIODIC))
+        return fail(HEXSV_EINVAL, "grid_create: opposite sides must both be PERIODIC or neither");
+    if (desc->nseg < 0 || desc->nseg > HEXSV_MAX_SEGMENTS)
+        return fail(HEXSV_EINVAL, "grid_create: nseg=%d outside [0,%d]", desc->nseg, HEXSV_MAX_SEGMENTS);
+    if (desc->mask_bc != HEXSV_WALL && desc->mask_bc != HEXSV_OUTFLOW)
+        return fail(HEXSV_EINVAL, "grid_create: mask_bc must be WALL or OUTFLOW");
+    KGrid kg;
+    memset(&kg, 0, sizeof kg);
+    kg.nq = desc->nq;
+    kg.nr = desc->nr;
+    kg.perq = perq;
+    kg.perr = perr;
+    for (int s = 0; s < 4; ++s) kg.side[s] = desc->side_bc[s];
+    kg.nseg = desc->nseg;
+    kg.mask_bc = desc->mask_bc;
+    for (int s = 0; s < desc->nseg; ++s) {
+        const hexsv_segment &g = desc->seg[s];
+        if (g.side < 0 || g.side > 3 || (g.code != HEXSV_WALL && g.code != HEXSV_OUTFLOW) || g.lo > g.hi)
+            return fail(HEXSV_EINVAL, "grid_create: segment %d malformed", s);
+        if (desc->side_bc[g.side] == HEXSV_PERIODIC)
+            return fail(HEXSV_EINVAL, "grid_create: segment %d lies on a periodic side", s);
+        kg.seg_side[s] = g.side;
+        kg.seg_lo[s] = g.lo;
+        kg.seg_hi[s] = g.hi;
+        kg.seg_code[s] = g.code;
+    }
+    hexsv_grid *gr = new (std::nothrow) hexsv_grid();
+    if (!gr) return fail(HEXSV_ENOMEM, "grid_create: out of host memory");
+    gr->kg = kg;
+    gr->edge = desc->edge;
+    gr->n = n;
+    gr->n_active = n;
+    gr->d_active = nullptr;
+    if (desc->active) {
+        int64_t na = 0;
+        for (int64_t i = 0; i < n; ++i) na += desc->active[i] != 0;
+        gr->n_active = na;
+        if (na < n) {
+            std::vector<uint8_t> a01(n);
+            for (int64_t i = 0; i < n; ++i) a01[i] = desc->active[i] != 0;
+            hipError_t e = hipMalloc(&gr->d_active, n);
+            if (e != hipSuccess) {
+                delete gr;
+                return fail(HEXSV_ENOMEM, "grid_create: hipMalloc(active): %s", hipGetErrorString(e));
+            }
+            e = hipMemcpy(gr->d_active, a01.data(), n, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(gr->d_active);
+                delete gr;
+                return fail(HEXSV_EHIP, "grid_create: hipMemcpy(active): %s", hipGetErrorString(e));
+            }
+        }
+    }
+    *out = gr;
+    return HEXSV_OK;
+}
+
+extern "C" void hexsv_grid_destroy(hexsv_grid *grid) {
+    if (!grid) return;
+    if (grid->d_active) (void)hipFree(grid->d_active);
+    delete grid;
+}
+
+extern "C" int hexsv_grid_counts(const hexsv_grid *grid, int64_t *cells, int64_t *active) {
+    if (!grid) return fail(HEXSV_EINVAL, "grid_counts: null grid");
+    if (cells) *cells = grid->n;
+    if (active) *active = grid->n_active;
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_grid_tables(const hexsv_grid *grid, int32_t *d_nbr, uint8_t *d_code,
+                                 hipStream_t stream) {
+    if (!grid || !d_nbr || !d_code) return fail(HEXSV_EINVAL, "grid_tables: null argument");
+    HIP_TRY(launch_tables(grid->kg, grid->d_active, d_nbr, d_code, stream));
+    return HEXSV_OK;
+}
+
+// ------------------------------------------------------------- simulation
+
+struct hexsv_sim {
+    const hexsv_grid *grid;
+    hexsv_params p;
+    int prec;
+    size_t esz;
+    void *buf;  // [h0 v10 v20 h1 v11 v21 z th ap], n elements each
+    KConst kc;
+    KRain rn;
+    Ctl *d_ctl;
+    Ctl *h_ctl;  // pinned mirror
+    Part *d_part;
+    Part *d_gpart;
+    uint32_t *d_ctr;
+    int32_t *d_chk;
+    int32_t *h_chk;  // pinned
+    int tile, ntq, ntiles;
+    int gsteps;
+    hipStream_t cap;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    bool graph_ok, fields_set, state_set;
+    // optional device timing of graph replays (hipEvents on the run stream)
+    bool timing;
+    hipEvent_t ev0, ev1;
+    double timed_ms;
+    int64_t timed_steps, timed_replays;
+};
+
+template <typename T>
+static KDom<T> dom_of(const hexsv_sim *s) {
+    KDom<T> d;
+    T *b = (T *)s->buf;
+    const int64_t n = s->grid->n;
+    for (int p = 0; p < 2; ++p)
+        for (int f = 0; f < 3; ++f) d.st[p][f] = b + (int64_t)(3 * p + f) * n;
+    d.z = b + 6 * n;
+    d.th = b + 7 * n;
+    d.ap = b + 8 * n;
+    return d;
+}
+
+static const double S3H = 0.86602540378443864676;
+
+static void drop_graph(hexsv_sim *s) {
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+    s->graph_ok = false;
+}
+
+extern "C" int hexsv_tile_count(void) { return NUM_TILES; }
+
+extern "C" int hexsv_tile_shape(int32_t v, int32_t *tq, int32_t *tr, int32_t *threads) {
+    if (v < 0 || v >= NUM_TILES) return fail(HEXSV_EINVAL, "tile_shape: variant %d out of range", v);
+    if (tq) *tq = TILES[v].tq;
+    if (tr) *tr = TILES[v].tr;
+    if (threads) *threads = TILES[v].nt;
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *params, hexsv_sim **out) {
+    if (!grid || !params || !out) return fail(HEXSV_EINVAL, "sim_create: null argument");
+    *out = nullptr;
+    const hexsv_params &p = *params;
+    if (!(p.g > 0.0) || !isfinite(p.g)) return fail(HEXSV_EDOMAIN, "sim_create: g must be > 0");
+    if (!(p.cfl > 0.0 && p.cfl < 1.0)) return fail(HEXSV_EDOMAIN, "sim_create: cfl=%g not in (0,1)", p.cfl);
+    if (!(p.dt_max > 0.0)) return fail(HEXSV_EDOMAIN, "sim_create: dt_max must be > 0");
+    if (!(p.h_dry >= 0.0)) return fail(HEXSV_EDOMAIN, "sim_create: h_dry must be >= 0");
+    if (p.precision != HEXSV_FP64 && p.precision != HEXSV_FP32)
+        return fail(HEXSV_EINVAL, "sim_create: precision %d unknown", p.precision);
+    if (p.tile >= NUM_TILES) return fail(HEXSV_EINVAL, "sim_create: tile %d not built", p.tile);
+    hexsv_sim *s = new (std::nothrow) hexsv_sim();
+    if (!s) return fail(HEXSV_ENOMEM, "sim_create: out of host memory");
+    s->grid = grid;
+    s->p = p;
+    s->prec = p.precision;
+    s->esz = p.precision == HEXSV_FP64 ? sizeof(double) : sizeof(float);
+    s->tile = p.tile >= 0 ? p.tile : DEFAULT_TILE;
+    tile_grid(s->tile, grid->kg.nq, grid->kg.nr, &s->ntq, &s->ntiles);
+    s->gsteps = p.steps_per_graph > 0 ? p.steps_per_graph : 100;
+    const double a = grid->edge;
+    s->kc.g = p.g;
+    s->kc.a = a;
+    s->kc.sigma = 6.0 * (0.5 * a * (S3H * a));
+    s->kc.cfl_phi = p.cfl * (s->kc.sigma / (6.0 * a));
+    s->kc.h_dry = p.h_dry;
+    s->kc.alpha_s = 0.0;
+    s->kc.area_active = s->kc.sigma * (double)grid->n_active;
+    s->rn.kind = 0;
+    s->rn.i_a = 0.0;
+    s->rn.t_a = 0.0;
+    s->rn.T_d = INFINITY;
+    const size_t nparts = (size_t)(s->ntiles > PRIME_BLOCKS ? s->ntiles : PRIME_BLOCKS);
+    hipError_t e = hipMalloc(&s->buf, s->esz * 9 * (size_t)grid->n);
+    if (e == hipSuccess) e = hipMalloc(&s->d_ctl, sizeof(Ctl));
+    if (e == hipSuccess) e = hipMalloc(&s->d_part, sizeof(Part) * nparts);
+    const size_t ngroups = (size_t)(s->ntiles + GROUP - 1) / GROUP;
+    if (e == hipSuccess) e = hipMalloc(&s->d_gpart, sizeof(Part) * ngroups);
+    if (e == hipSuccess) e = hipMalloc(&s->d_ctr, sizeof(uint32_t) * (1 + ngroups));
+    if (e == hipSuccess) e = hipMemset(s->d_ctr, 0, sizeof(uint32_t) * (1 + ngroups));
+    if (e == hipSuccess) e = hipMalloc(&s->d_chk, 4 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_ctl, sizeof(Ctl), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_chk, 4 * sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        hexsv_sim_destroy(s);
+        return fail(HEXSV_ENOMEM, "sim_create: allocation failed: %s", hipGetErrorString(e));
+    }
+    memset(s->h_ctl, 0, sizeof(Ctl));
+    *out = s;
+    return HEXSV_OK;
+}
+
+extern "C" void hexsv_sim_destroy(hexsv_sim *s) {
+    if (!s) return;
+    drop_graph(s);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    if (s->buf) (void)hipFree(s->buf);
+    if (s->d_ctl) (void)hipFree(s->d_ctl);
+    if (s->d_part) (void)hipFree(s->d_part);
+    if (s->d_gpart) (void)hipFree(s->d_gpart);
+    if (s->d_ctr) (void)hipFree(s->d_ctr);
+    if (s->d_chk) (void)hipFree(s->d_chk);
+    if (s->h_ctl) (void)hipHostFree(s->h_ctl);
+    if (s->h_chk) (void)hipHostFree(s->h_chk);
+    delete s;
+}
+
+extern "C" int hexsv_sim_info(const hexsv_sim *s, int32_t *workgroups, int32_t *tile, int32_t *tq,
+                              int32_t *tr, int32_t *threads) {
+    if (!s) return fail(HEXSV_EINVAL, "sim_info: null sim");
+    if (workgroups) *workgroups = s->ntiles;
+    if (tile) *tile = s->tile;
+    return hexsv_tile_shape(s->tile, tq, tr, threads);
+}
+
+// Run a device check; returns the count of offending cells (chk[0]).
+static int run_check(hexsv_sim *s, hipStream_t stream, bool fields, const double *a, const double *b,
+                     const double *c, int32_t *count, int32_t *first, int32_t *reason) {
+    const int32_t init[4] = {0, 0x7fffffff, 0, 0};
+    memcpy(s->h_chk, init, sizeof init);
+    HIP_TRY(hipMemcpyAsync(s->d_chk, s->h_chk, sizeof init, hipMemcpyHostToDevice, stream));
+    if (fields) HIP_TRY(launch_check_fields(a, b, c, s->grid->d_active, s->grid->n, s->d_chk, stream));
+    else HIP_TRY(launch_check_state(a, b, c, s->grid->d_active, s->grid->n, s->d_chk, stream));
+    HIP_TRY(hipMemcpyAsync(s->h_chk, s->d_chk, sizeof init, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    *count = s->h_chk[0];
+    *first = s->h_chk[1];
+    *reason = s->h_chk[2];
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_set_fields(hexsv_sim *s, const double *d_z, const double *d_theta,
+                                    const double *d_alpha_p, double alpha_s, hipStream_t stream) {
+    if (!s || !d_z || !d_theta || !d_alpha_p) return fail(HEXSV_EINVAL, "set_fields: null argument");
+    if (!(alpha_s >= 0.0) || !isfinite(alpha_s)) return fail(HEXSV_EDOMAIN, "set_fields: alpha_s must be >= 0");
+    int32_t cnt, first, why;
+    int rc = run_check(s, stream, true, d_z, d_theta, d_alpha_p, &cnt, &first, &why);
+    if (rc) return rc;
+    if (cnt)
+        return fail(HEXSV_EDOMAIN,
+                    "set_fields: %d active cells invalid; first cell %d (%s%s%s)", cnt, first,
+                    (why & 1) ? "theta not in (0,1] " : "", (why & 2) ? "alpha_p < 0 " : "",
+                    (why & 4) ? "z not finite" : "");
+    const int64_t n = s->grid->n;
+    const uint8_t *act = s->grid->d_active;
+    if (s->prec == HEXSV_FP64) {
+        KDom<double> d = dom_of<double>(s);
+        HIP_TRY(launch_import<double>(d_z, (double *)d.z, act, 0, n, stream));
+        HIP_TRY(launch_import<double>(d_theta, (double *)d.th, act, 1, n, stream));
+        HIP_TRY(launch_import<double>(d_alpha_p, (double *)d.ap, act, 0, n, stream));
+    } else {
+        KDom<float> d = dom_of<float>(s);
+        HIP_TRY(launch_import<float>(d_z, (float *)d.z, act, 0, n, stream));
+        HIP_TRY(launch_import<float>(d_theta, (float *)d.th, act, 1, n, stream));
+        HIP_TRY(launch_import<float>(d_alpha_p, (float *)d.ap, act, 0, n, stream));
+    }
+    s->kc.alpha_s = alpha_s;
+    s->fields_set = true;
+    drop_graph(s);
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_set_rain(hexsv_sim *s, const hexsv_rain *rain) {
+    if (!s || !rain) return fail(HEXSV_EINVAL, "set_rain: null argument");
+    if (rain->kind != 0 && rain->kind != 1) return fail(HEXSV_EINVAL, "set_rain: kind %d unknown", rain->kind);
+    if (!(rain->i_a >= 0.0) || !isfinite(rain->i_a)) return fail(HEXSV_EDOMAIN, "set_rain: i_a must be >= 0");
+    if (rain->kind == 1 && !(rain->t_a > 0.0 && rain->T_d > rain->t_a && isfinite(rain->T_d)))
+        return fail(HEXSV_EDOMAIN, "set_rain: triangular rain needs 0 < t_a < T_d < inf");
+    if (rain->kind == 0 && !(rain->T_d >= 0.0)) return fail(HEXSV_EDOMAIN, "set_rain: T_d must be >= 0");
+    s->rn.kind = rain->kind;
+    s->rn.i_a = rain->i_a;
+    s->rn.t_a = rain->t_a;
+    s->rn.T_d = rain->T_d;
+    drop_graph(s);
+    return HEXSV_OK;
+}
+
+template <typename T>
+static hipError_t prime(hexsv_sim *s, int reset, hipStream_t stream) {
+    return launch_prime<T>(dom_of<T>(s), s->grid->n, s->kc, s->d_ctl, s->d_part, PRIME_BLOCKS, reset,
+                           stream);
+}
+
+extern "C" int hexsv_sim_set_state(hexsv_sim *s, double t0, const double *d_h, const double *d_v1,
+                                   const double *d_v2, hipStream_t stream) {
+    if (!s || !d_h || !d_v1 || !d_v2) return fail(HEXSV_EINVAL, "set_state: null argument");
+    if (!s->fields_set) return fail(HEXSV_ESTATE, "set_state: call set_fields first");
+    if (!isfinite(t0)) return fail(HEXSV_EDOMAIN, "set_state: t0 must be finite");
+    int32_t cnt, first, why;
+    int rc = run_check(s, stream, false, d_h, d_v1, d_v2, &cnt, &first, &why);
+    if (rc) return rc;
+    if (cnt)
+        return fail(HEXSV_EDOMAIN, "set_state: %d active cells invalid; first cell %d (%s%s)", cnt,
+                    first, (why & 1) ? "h < 0 or not finite " : "", (why & 2) ? "v not finite" : "");
+    const int64_t n = s->grid->n;
+    const uint8_t *act = s->grid->d_active;
+    for (int p = 0; p < 2; ++p) {
+        if (s->prec == HEXSV_FP64) {
+            KDom<double> d = dom_of<double>(s);
+            HIP_TRY(launch_import<double>(d_h, d.st[p][0], act, 1, n, stream));
+            HIP_TRY(launch_import<double>(d_v1, d.st[p][1], act, 1, n, stream));
+            HIP_TRY(launch_import<double>(d_v2, d.st[p][2], act, 1, n, stream));
+        } else {
+            KDom<float> d = dom_of<float>(s);
+            HIP_TRY(launch_import<float>(d_h, d.st[p][0], act, 1, n, stream));
+            HIP_TRY(launch_import<float>(d_v1, d.st[p][1], act, 1, n, stream));
+            HIP_TRY(launch_import<float>(d_v2, d.st[p][2], act, 1, n, stream));
+        }
+    }
+    Ctl &c = *s->h_ctl;
+    memset(&c, 0, sizeof c);
+    c.t = t0;
+    c.t_end = t0;
+    c.dt_max = s->p.dt_max;
+    c.steps = 0;
+    c.step_limit = 0;
+    c.parity = 0;
+    c.err_cell = -1;
+    HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+    HIP_TRY(s->prec == HEXSV_FP64 ? prime<double>(s, 1, stream) : prime<float>(s, 1, stream));
+    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    s->state_set = true;
+    return HEXSV_OK;
+}
+
+static int capture(hexsv_sim *s) {
+    drop_graph(s);
+    HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < s->gsteps && e == hipSuccess; ++k) {
+        if (s->prec == HEXSV_FP64)
+            e = launch_step<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
+                                    s->d_part, s->d_gpart, s->d_ctr, s->ntq, s->ntiles, s->cap);
+        else
+            e = launch_step<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
+                                   s->d_part, s->d_gpart, s->d_ctr, s->ntq, s->ntiles, s->cap);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(HEXSV_EHIP, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    s->graph = g;
+    HIP_TRY(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+    s->graph_ok = true;
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_run(hexsv_sim *s, double t_end, int64_t max_steps, hipStream_t stream) {
+    if (!s) return fail(HEXSV_EINVAL, "run: null sim");
+    if (!s->state_set) return fail(HEXSV_ESTATE, "run: call set_state first");
+    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    Ctl &c = *s->h_ctl;
+    if (!(t_end >= c.t)) return fail(HEXSV_EDOMAIN, "run: t_end=%g before t=%g", t_end, c.t);
+    c.t_end = t_end;
+    c.dt_max = s->p.dt_max;
+    c.step_limit = max_steps > 0 ? c.steps + max_steps : INT64_MAX;
+    const int64_t limit = c.step_limit;
+    HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+    if (!s->graph_ok) {
+        int rc = capture(s);
+        if (rc) return rc;
+    }
+    int64_t last_steps = -1;
+    for (;;) {
+        const int64_t before = c.steps;
+        if (s->timing) HIP_TRY(hipEventRecord(s->ev0, stream));
+        HIP_TRY(hipGraphLaunch(s->gexec, stream));
+        if (s->timing) HIP_TRY(hipEventRecord(s->ev1, stream));
+        HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (s->timing) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+            s->timed_ms += ms;
+            s->timed_steps += c.steps - before;
+            s->timed_replays += 1;
+        }
+        if (c.err)
+            return fail(HEXSV_ENUMERIC, "run: non-finite value at cell %d in step %lld (t=%g)",
+                        c.err_cell, (long long)c.steps + 1, c.t);
+        if (c.t >= t_end || c.steps >= limit || c.steps == last_steps) break;
+        last_steps = c.steps;
+    }
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_get_state(const hexsv_sim *sc, double *d_h, double *d_v1, double *d_v2,
+                                   double *d_q1, double *d_q2, hipStream_t stream) {
+    hexsv_sim *s = const_cast<hexsv_sim *>(sc);
+    if (!s) return fail(HEXSV_EINVAL, "get_state: null sim");
+    if (!s->state_set) return fail(HEXSV_ESTATE, "get_state: no state set");
+    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const int par = s->h_ctl->parity;
+    if (s->prec == HEXSV_FP64)
+        HIP_TRY(launch_export<double>(dom_of<double>(s), par, s->grid->n, d_h, d_v1, d_v2, d_q1, d_q2, stream));
+    else
+        HIP_TRY(launch_export<float>(dom_of<float>(s), par, s->grid->n, d_h, d_v1, d_v2, d_q1, d_q2, stream));
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_timing(hexsv_sim *s, int32_t enable, double *gpu_ms, int64_t *steps,
+                                int64_t *replays) {
+    if (!s) return fail(HEXSV_EINVAL, "timing: null sim");
+    if (gpu_ms) *gpu_ms = s->timed_ms;
+    if (steps) *steps = s->timed_steps;
+    if (replays) *replays = s->timed_replays;
+    if (enable >= 0) {
+        if (enable && !s->ev0) {
+            HIP_TRY(hipEventCreate(&s->ev0));
+            HIP_TRY(hipEventCreate(&s->ev1));
+        }
+        s->timing = enable != 0;
+        s->timed_ms = 0.0;
+        s->timed_steps = 0;
+        s->timed_replays = 0;
+    }
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_get_books(hexsv_sim *s, hexsv_books *out, hipStream_t stream) {
+    if (!s || !out) return fail(HEXSV_EINVAL, "get_books: null argument");
+    if (!s->state_set) return fail(HEXSV_ESTATE, "get_books: no state set");
+    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const Ctl &c = *s->h_ctl;
+    out->t = c.t;
+    out->initial = c.initial;
+    out->stored = c.stored;
+    out->rain = c.rain;
+    out->outflow = c.outflow;
+    out->clamp = c.clamp;
+    double ref = c.initial + c.rain;
+    if (ref < 1e-300) ref = 1e-300;
+    out->residual = fabs(c.stored - (c.initial + c.rain - c.outflow + c.clamp)) / ref;
+    out->steps = c.steps;
+    out->dt_min = c.dt_min;
+    out->dt_max_seen = c.dt_max_seen;
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_set_books(hexsv_sim *s, const hexsv_books *b, hipStream_t stream) {
+    if (!s || !b) return fail(HEXSV_EINVAL, "set_books: null argument");
+    if (!s->state_set) return fail(HEXSV_ESTATE, "set_books: call set_state first");
+    if (!isfinite(b->t) || b->steps < 0) return fail(HEXSV_EDOMAIN, "set_books: bad time or step count");
+    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    Ctl &c = *s->h_ctl;
+    c.t = b->t;
+    c.t_end = b->t;
+    c.initial = b->initial;
+    c.rain = b->rain;
+    c.outflow = b->outflow;
+    c.clamp = b->clamp;
+    c.steps = b->steps;
+    c.step_limit = b->steps;
+    c.dt_min = b->dt_min;
+    c.dt_max_seen = b->dt_max_seen;
+    HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+    HIP_TRY(s->prec == HEXSV_FP64 ? prime<double>(s, 0, stream) : prime<float>(s, 0, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return HEXSV_OK;
+}

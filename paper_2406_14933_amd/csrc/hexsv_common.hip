@@ -1,0 +1,145 @@
+// hexsv_common.hip — precision-independent kernels: the single-workgroup
+// finalize that closes each step (FP64 books, time, CFL bound), the priming
+// pass after set_state, input validation and the neighbour/edge-code tables.
+#include <math.h>
+
+#include "hexsv_internal.h"
+
+namespace hexsv {
+
+// Deterministic reduction of partial records: fixed strided assignment to
+// threads, xor-butterfly within waves, fixed order across waves.
+template <int NT>
+__device__ inline Part reduce_parts(const Part *part, int nparts) {
+    double c = 0.0, s = 0.0, o = 0.0, cl = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += NT) {
+        const Part p = part[i];
+        c = p.cmax > c ? p.cmax : c;
+        s += p.stored;
+        o += p.outflow;
+        cl += p.clamp;
+    }
+    return block_reduce<NT>(c, s, o, cl);
+}
+
+__global__ __launch_bounds__(1024) void k_prime_finalize(Ctl *ctl, const Part *part, int nparts,
+                                                         KConst kc, int reset_books) {
+    const Part p = reduce_parts<1024>(part, nparts);
+    if (threadIdx.x == 0) {
+        ctl->last_cmax = p.cmax;
+        ctl->tau = p.cmax > 0.0 ? kc.cfl_phi / p.cmax : INFINITY;
+        ctl->stored = p.stored;
+        if (reset_books) {
+            ctl->initial = p.stored;
+            ctl->rain = 0.0;
+            ctl->outflow = 0.0;
+            ctl->clamp = 0.0;
+            ctl->steps = 0;
+            ctl->dt_min = INFINITY;
+            ctl->dt_max_seen = 0.0;
+        }
+        ctl->err = 0;
+        ctl->err_cell = -1;
+    }
+}
+
+hipError_t launch_prime_finalize(Ctl *ctl, const Part *part, int nparts, const KConst &kc,
+                                 int reset_books, hipStream_t stream) {
+    hipLaunchKernelGGL(k_prime_finalize, dim3(1), dim3(1024), 0, stream, ctl, part, nparts, kc,
+                       reset_books);
+    return hipGetLastError();
+}
+
+// chk[0] = number of offending active cells, chk[1] = lowest offending index,
+// chk[2] = reason of that cell (bit mask).
+__device__ inline void flag_bad(int32_t *chk, int64_t i, int reason) {
+    atomicAdd(&chk[0], 1);
+    atomicMin(&chk[1], (int32_t)i);
+    atomicOr(&chk[2], reason);
+}
+
+__global__ void k_check_fields(const double *z, const double *th, const double *ap,
+                               const uint8_t *active, int64_t n, int32_t *chk) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (active && !active[i]) continue;
+        int reason = 0;
+        if (!(th[i] > 0.0 && th[i] <= 1.0)) reason |= 1;
+        if (!(ap[i] >= 0.0) || !__builtin_isfinite(ap[i])) reason |= 2;
+        if (!__builtin_isfinite(z[i])) reason |= 4;
+        if (reason) flag_bad(chk, i, reason);
+    }
+}
+
+__global__ void k_check_state(const double *h, const double *v1, const double *v2,
+                              const uint8_t *active, int64_t n, int32_t *chk) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (active && !active[i]) continue;
+        int reason = 0;
+        if (!(h[i] >= 0.0) || !__builtin_isfinite(h[i])) reason |= 1;
+        if (!__builtin_isfinite(v1[i]) || !__builtin_isfinite(v2[i])) reason |= 2;
+        if (reason) flag_bad(chk, i, reason);
+    }
+}
+
+static int grid_blocks(int64_t n) {
+    const int64_t nb = (n + 255) / 256;
+    return (int)(nb < 1 ? 1 : (nb > 65536 ? 65536 : nb));
+}
+
+hipError_t launch_check_fields(const double *z, const double *th, const double *ap,
+                               const uint8_t *active, int64_t n, int32_t *chk,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(k_check_fields, dim3(grid_blocks(n)), dim3(256), 0, stream, z, th, ap,
+                       active, n, chk);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_state(const double *h, const double *v1, const double *v2,
+                              const uint8_t *active, int64_t n, int32_t *chk,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(k_check_state, dim3(grid_blocks(n)), dim3(256), 0, stream, h, v1, v2,
+                       active, n, chk);
+    return hipGetLastError();
+}
+
+// Neighbour / edge-code tables, one thread per cell, with the same target
+// rules the step kernel applies to its staged halo.
+__global__ void k_tables(KGrid g, const uint8_t *active, int32_t *nbr, uint8_t *code) {
+    const int64_t n = (int64_t)g.nq * g.nr;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+        const bool act = active ? active[i] != 0 : true;
+        for (int k = 0; k < 6; ++k) {
+            int qn = q + dq_of(k), rn = r + dr_of(k);
+            int32_t j = -1;
+            int cd;
+            if (!act) {
+                cd = CODE_WALL;
+            } else if (wrap_pos(g, qn, rn)) {
+                const int64_t jj = (int64_t)rn * g.nq + qn;
+                if (active && !active[jj]) {
+                    cd = g.mask_bc;
+                } else {
+                    cd = CODE_INTERIOR;
+                    j = (int32_t)jj;
+                }
+            } else {
+                cd = side_code(g, qn, rn);
+            }
+            nbr[i * 6 + k] = j;
+            code[i * 6 + k] = (uint8_t)cd;
+        }
+    }
+}
+
+hipError_t launch_tables(const KGrid &g, const uint8_t *active, int32_t *nbr, uint8_t *code,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(k_tables, dim3(grid_blocks((int64_t)g.nq * g.nr)), dim3(256), 0, stream, g,
+                       active, nbr, code);
+    return hipGetLastError();
+}
+
+}  // namespace hexsv

@@ -1,0 +1,68 @@
+// hexsv_internal.h — interface between the host library and the per-precision
+// kernel translation units (FP64 built without contraction, FP32 with it).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hexsv_device.h"
+
+namespace hexsv {
+
+struct TileShape {
+    int tq, tr, nt;
+};
+
+// Tile variants the step kernels are built for (the autotuner picks one).
+constexpr TileShape TILES[] = {
+    {64, 4, 256}, {64, 8, 256}, {64, 16, 256}, {128, 4, 256},
+    {128, 8, 256}, {128, 8, 512}, {256, 4, 256}, {64, 8, 512},
+};
+constexpr int NUM_TILES = sizeof(TILES) / sizeof(TILES[0]);
+constexpr int DEFAULT_TILE = 1;
+
+// Number of tiles covering an nq x nr raster with variant v.
+inline void tile_grid(int v, int nq, int nr, int *ntq, int *ntiles) {
+    const TileShape s = TILES[v];
+    *ntq = (nq + s.tq - 1) / s.tq;
+    *ntiles = *ntq * ((nr + s.tr - 1) / s.tr);
+}
+
+// One step = one launch.  part: ntiles records, gpart: ceil(ntiles/64)
+// records, ctr: 1 + ceil(ntiles/64) zero-initialised counters (the kernel
+// leaves them zero again).
+template <typename T>
+hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
+                       const KRain &rn, Ctl *ctl, Part *part, Part *gpart, uint32_t *ctr,
+                       int ntq, int ntiles, hipStream_t stream);
+// Close a priming pass over nparts partial records: tau (and, with
+// reset_books, the initial books) of the current state.
+hipError_t launch_prime_finalize(Ctl *ctl, const Part *part, int nparts, const KConst &kc,
+                                 int reset_books, hipStream_t stream);
+constexpr int PRIME_BLOCKS = 1024;
+
+template <typename T>
+hipError_t launch_prime(const KDom<T> &d, int64_t n, const KConst &kc, Ctl *ctl, Part *part,
+                        int nblocks, int reset_books, hipStream_t stream);
+
+// FP64 caller arrays -> internal precision (theta forced to 0 outside the mask).
+template <typename T>
+hipError_t launch_import(const double *src, T *dst, const uint8_t *active, int zero_inactive,
+                         int64_t n, hipStream_t stream);
+// internal state -> FP64 caller arrays (each output nullable).
+template <typename T>
+hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double *v1,
+                         double *v2, double *q1, double *q2, hipStream_t stream);
+
+// Validation of caller inputs: counts offending active cells and records the
+// lowest offending index in chk[0] (count) / chk[1] (index) / chk[2] (reason).
+hipError_t launch_check_fields(const double *z, const double *th, const double *ap,
+                               const uint8_t *active, int64_t n, int32_t *chk,
+                               hipStream_t stream);
+hipError_t launch_check_state(const double *h, const double *v1, const double *v2,
+                              const uint8_t *active, int64_t n, int32_t *chk, hipStream_t stream);
+
+hipError_t launch_tables(const KGrid &g, const uint8_t *active, int32_t *nbr, uint8_t *code,
+                         hipStream_t stream);
+
+}  // namespace hexsv

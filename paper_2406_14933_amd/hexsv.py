@@ -1,0 +1,270 @@
+"""Thin ctypes binding of ``libhexsv.so`` (C-ABI in ``include/hexsv.h``).
+
+Argument marshalling only: every step of the time stepper runs in the HIP
+library.  PyTorch provides the device memory (tensor ``data_ptr()``) and the
+stream (``torch.cuda.current_stream().cuda_stream``).  The binding refuses to
+work without the built library: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "lib", "libhexsv.so")
+
+OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ENUMERIC, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+FP64, FP32 = 0, 1
+INTERIOR, WALL, OUTFLOW, PERIODIC = 0, 1, 2, 3
+S, E, N, W = 0, 1, 2, 3
+MAX_SEGMENTS = 8
+
+
+class HexsvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hexsv error {code}: {msg}")
+        self.code = code
+
+
+class Segment(C.Structure):
+    _fields_ = [("side", C.c_int32), ("lo", C.c_int32), ("hi", C.c_int32), ("code", C.c_int32)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nq", C.c_int32), ("nr", C.c_int32), ("edge", C.c_double),
+                ("side_bc", C.c_int32 * 4), ("nseg", C.c_int32),
+                ("seg", Segment * MAX_SEGMENTS), ("active", C.POINTER(C.c_uint8)),
+                ("mask_bc", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("g", C.c_double), ("cfl", C.c_double), ("dt_max", C.c_double),
+                ("h_dry", C.c_double), ("precision", C.c_int32), ("steps_per_graph", C.c_int32),
+                ("tile", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Rain(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("i_a", C.c_double), ("t_a", C.c_double), ("T_d", C.c_double)]
+
+
+class Books(C.Structure):
+    _fields_ = [("t", C.c_double), ("initial", C.c_double), ("stored", C.c_double),
+                ("rain", C.c_double), ("outflow", C.c_double), ("clamp", C.c_double),
+                ("residual", C.c_double), ("steps", C.c_int64), ("dt_min", C.c_double),
+                ("dt_max_seen", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# (name, restype, argtypes)
+_VP = C.c_void_p
+_SIGS = [
+    ("hexsv_version", C.c_char_p, []),
+    ("hexsv_last_error", C.c_char_p, []),
+    ("hexsv_grid_create", C.c_int, [C.POINTER(GridDesc), C.POINTER(_VP)]),
+    ("hexsv_grid_destroy", None, [_VP]),
+    ("hexsv_grid_counts", C.c_int, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hexsv_grid_tables", C.c_int, [_VP, _VP, _VP, _VP]),
+    ("hexsv_sim_create", C.c_int, [_VP, C.POINTER(Params), C.POINTER(_VP)]),
+    ("hexsv_sim_destroy", None, [_VP]),
+    ("hexsv_sim_set_fields", C.c_int, [_VP, _VP, _VP, _VP, C.c_double, _VP]),
+    ("hexsv_sim_set_rain", C.c_int, [_VP, C.POINTER(Rain)]),
+    ("hexsv_sim_set_state", C.c_int, [_VP, C.c_double, _VP, _VP, _VP, _VP]),
+    ("hexsv_sim_run", C.c_int, [_VP, C.c_double, C.c_int64, _VP]),
+    ("hexsv_sim_get_state", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("hexsv_sim_get_books", C.c_int, [_VP, C.POINTER(Books), _VP]),
+    ("hexsv_sim_set_books", C.c_int, [_VP, C.POINTER(Books), _VP]),
+    ("hexsv_sim_info", C.c_int, [_VP] + [C.POINTER(C.c_int32)] * 5),
+    ("hexsv_sim_timing", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64)]),
+    ("hexsv_tile_count", C.c_int, []),
+    ("hexsv_tile_shape", C.c_int, [C.c_int32] + [C.POINTER(C.c_int32)] * 3),
+]
+
+_lib = None
+
+
+def lib():
+    """Load libhexsv.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2406_14933_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [s[0] for s in _SIGS]
+
+
+def _check(rc):
+    if rc != OK:
+        raise HexsvError(rc, lib().hexsv_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype=torch.float64, n=None):
+    """A contiguous CUDA tensor of dtype (copies host data to the device)."""
+    if isinstance(x, np.ndarray) or not torch.is_tensor(x):
+        x = torch.from_numpy(np.ascontiguousarray(np.asarray(x), dtype=np.float64 if dtype == torch.float64 else None))
+    x = x.to(device="cuda", dtype=dtype).contiguous()
+    if n is not None and x.numel() != n:
+        raise ValueError(f"expected {n} values, got {x.numel()}")
+    return x
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def tile_shapes():
+    out = []
+    for v in range(lib().hexsv_tile_count()):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().hexsv_tile_shape(v, C.byref(a), C.byref(b), C.byref(c)))
+        out.append((a.value, b.value, c.value))
+    return out
+
+
+class Grid:
+    """Hexagonal raster handle (axial nq x nr parallelogram, edge a)."""
+
+    def __init__(self, nq, nr, edge, side=(OUTFLOW, WALL, WALL, WALL), segs=(), active=None,
+                 mask_bc=WALL):
+        d = GridDesc()
+        d.nq, d.nr, d.edge = int(nq), int(nr), float(edge)
+        for k in range(4):
+            d.side_bc[k] = int(side[k])
+        segs = list(segs)
+        if len(segs) > MAX_SEGMENTS:
+            raise ValueError("too many segments")
+        d.nseg = len(segs)
+        for k, (s_, lo, hi, code) in enumerate(segs):
+            d.seg[k] = Segment(int(s_), int(lo), int(hi), int(code))
+        self._active = None
+        if active is not None:
+            self._active = np.ascontiguousarray(np.asarray(active).reshape(-1) != 0, dtype=np.uint8)
+            d.active = self._active.ctypes.data_as(C.POINTER(C.c_uint8))
+        d.mask_bc = int(mask_bc)
+        h = C.c_void_p()
+        _check(lib().hexsv_grid_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.nq, self.nr, self.edge = int(nq), int(nr), float(edge)
+        n, na = C.c_int64(), C.c_int64()
+        _check(lib().hexsv_grid_counts(h, C.byref(n), C.byref(na)))
+        self.cells, self.active_cells = n.value, na.value
+
+    @classmethod
+    def from_scenario(cls, sc):
+        return cls(sc.nq, sc.nr, sc.a, sc.side, sc.segs, sc.active, sc.mask_code)
+
+    def tables(self):
+        """(nbr int32 (N,6), code uint8 (N,6)) computed by the device table kernel."""
+        nbr = torch.empty((self.cells, 6), dtype=torch.int32, device="cuda")
+        code = torch.empty((self.cells, 6), dtype=torch.uint8, device="cuda")
+        _check(lib().hexsv_grid_tables(self._h, _ptr(nbr), _ptr(code), _stream()))
+        return nbr, code
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.hexsv_grid_destroy(h)
+            self._h = None
+
+
+class Sim:
+    """Single-catchment time stepper (FP64 or FP32 state, FP64 books and dt)."""
+
+    def __init__(self, grid: Grid, precision="fp32", g=9.81, cfl=0.5, dt_max=1.0, h_dry=0.0,
+                 steps_per_graph=100, tile=-1):
+        self.grid = grid
+        prec = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[precision]
+        p = Params(float(g), float(cfl), float(dt_max), float(h_dry), prec, int(steps_per_graph),
+                   int(tile), 0)
+        h = C.c_void_p()
+        _check(lib().hexsv_sim_create(grid._h, C.byref(p), C.byref(h)))
+        self._h = h
+        self.precision = "fp64" if prec == FP64 else "fp32"
+
+    @classmethod
+    def from_scenario(cls, sc, precision="fp32", grid=None, **kw):
+        grid = grid or Grid.from_scenario(sc)
+        s = cls(grid, precision, g=sc.g, cfl=sc.cfl, dt_max=sc.dt_max, h_dry=sc.h_dry, **kw)
+        s.set_fields(sc.z, sc.theta, sc.alpha_p, sc.alpha_s)
+        s.set_rain(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d)
+        s.set_state(sc.h0, sc.v10, sc.v20, 0.0)
+        return s
+
+    def set_fields(self, z, theta, alpha_p, alpha_s):
+        n = self.grid.cells
+        z, th, ap = (_dev(x, n=n) for x in (z, theta, alpha_p))
+        _check(lib().hexsv_sim_set_fields(self._h, _ptr(z), _ptr(th), _ptr(ap), float(alpha_s),
+                                          _stream()))
+
+    def set_rain(self, kind=0, i_a=0.0, t_a=0.0, T_d=float("inf")):
+        r = Rain(int(kind), float(i_a), float(t_a), float(T_d))
+        _check(lib().hexsv_sim_set_rain(self._h, C.byref(r)))
+
+    def set_state(self, h, v1, v2, t0=0.0):
+        n = self.grid.cells
+        h, v1, v2 = (_dev(x, n=n) for x in (h, v1, v2))
+        _check(lib().hexsv_sim_set_state(self._h, float(t0), _ptr(h), _ptr(v1), _ptr(v2),
+                                         _stream()))
+
+    def run(self, t_end, max_steps=0):
+        _check(lib().hexsv_sim_run(self._h, float(t_end), int(max_steps), _stream()))
+        return self
+
+    def state(self):
+        n = self.grid.cells
+        out = {k: torch.empty(n, dtype=torch.float64, device="cuda")
+               for k in ("h", "v1", "v2", "q1", "q2")}
+        _check(lib().hexsv_sim_get_state(self._h, *(_ptr(out[k]) for k in
+                                                     ("h", "v1", "v2", "q1", "q2")), _stream()))
+        return out
+
+    def state_numpy(self):
+        st = self.state()
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in st.items()}
+
+    def books(self):
+        b = Books()
+        _check(lib().hexsv_sim_get_books(self._h, C.byref(b), _stream()))
+        return b.as_dict()
+
+    def set_books(self, d):
+        b = Books(**{k: d[k] for k, _ in Books._fields_})
+        _check(lib().hexsv_sim_set_books(self._h, C.byref(b), _stream()))
+
+    def timing(self, enable=None):
+        """Totals of the device-timed replays since the last reset; enable=True/False resets."""
+        ms, st, rp = C.c_double(), C.c_int64(), C.c_int64()
+        en = -1 if enable is None else int(bool(enable))
+        _check(lib().hexsv_sim_timing(self._h, en, C.byref(ms), C.byref(st), C.byref(rp)))
+        return {"gpu_ms": ms.value, "steps": st.value, "replays": rp.value}
+
+    def info(self):
+        vals = [C.c_int32() for _ in range(5)]
+        _check(lib().hexsv_sim_info(self._h, *(C.byref(v) for v in vals)))
+        return dict(zip(("workgroups", "tile", "tq", "tr", "threads"), (v.value for v in vals)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.hexsv_sim_destroy(h)
+            self._h = None

@@ -1,0 +1,270 @@
+"""Parity of the HIP stepper with the FP64 CPU oracle (needs an MI355X).
+
+Tolerances: FP64 path <= 1e-12 relative L1 on h, v and q = theta*h*v; FP32 path
+<= 1e-4 relative L1 on h and <= 1e-3 on q; neighbour/edge-code tables bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests._util import ref_grid, ref_params, ref_rain, ref_run, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": {"h": 1e-12, "v": 1e-12, "q": 1e-12},
+       "fp32": {"h": 1e-4, "v": 1e-3, "q": 1e-3}}
+
+
+@pytest.fixture(scope="module")
+def hx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_14933_amd import hexsv
+    hexsv.lib()  # raises if the library is missing: no fallback
+    return hexsv
+
+
+def gpu_run(hx, sc, precision, t_end=None, tile=-1, max_steps=0, steps_per_graph=100):
+    sim = hx.Sim.from_scenario(sc, precision, tile=tile, steps_per_graph=steps_per_graph)
+    sim.run(sc.t_end if t_end is None else t_end, max_steps)
+    out = sim.state_numpy()
+    out["books"] = sim.books()
+    out["sim"] = sim
+    return out
+
+
+def assert_parity(got, ref, precision, label=""):
+    tol = TOL[precision]
+    e = {
+        "h": rel_l1(got["h"], ref["h"]),
+        "v": max(rel_l1(got["v1"], ref["v1"]), rel_l1(got["v2"], ref["v2"])),
+        "q": max(rel_l1(got["q1"], ref["q1"]), rel_l1(got["q2"], ref["q2"])),
+    }
+    print(f"[parity {label} {precision}] rel L1 h={e['h']:.3e} v={e['v']:.3e} q={e['q']:.3e}",
+          flush=True)
+    assert e["h"] <= tol["h"], e
+    assert e["q"] <= tol["q"], e
+    if precision == "fp64":
+        assert e["v"] <= tol["v"], e
+    return e
+
+
+def assert_books(got, ref, rel):
+    gb, rb = got["books"], ref["books"]
+    assert gb["t"] == rb["t"]
+    scale = max(rb["initial"] + rb["rain"], 1e-300)
+    for k in ("stored", "rain", "outflow", "clamp"):
+        assert abs(gb[k] - rb[k]) <= rel * scale, (k, gb[k], rb[k])
+    assert gb["residual"] <= max(1e-12, rel)
+
+
+# ------------------------------------------------------------- a1 tables
+
+GRIDS = [
+    dict(nq=37, nr=23, side=(synth.OUTFLOW, synth.WALL, synth.WALL, synth.OUTFLOW)),
+    dict(nq=20, nr=9, side=(synth.WALL, synth.PERIODIC, synth.OUTFLOW, synth.PERIODIC)),
+    dict(nq=11, nr=14, side=(synth.PERIODIC, synth.OUTFLOW, synth.PERIODIC, synth.WALL)),
+    dict(nq=64, nr=40, side=(synth.WALL,) * 4, segs=((synth.S, 24, 40, synth.OUTFLOW),
+                                                     (synth.E, 3, 7, synth.OUTFLOW))),
+]
+
+
+@pytest.mark.parametrize("gi", range(len(GRIDS)))
+def test_tables_bit_exact(hx, gi):
+    g = GRIDS[gi]
+    nbr_ref, code_ref = oracle.tables(g["nq"], g["nr"], g["side"], g.get("segs", ()))
+    grid = hx.Grid(g["nq"], g["nr"], 1.0, g["side"], g.get("segs", ()))
+    nbr, code = grid.tables()
+    np.testing.assert_array_equal(nbr.cpu().numpy(), nbr_ref)
+    np.testing.assert_array_equal(code.cpu().numpy(), code_ref)
+
+
+@pytest.mark.parametrize("mask_bc", [synth.WALL, synth.OUTFLOW])
+def test_tables_bit_exact_masked(hx, mask_bc):
+    act = synth.hexagon_mask(31, 31, 12)
+    nbr_ref, code_ref = oracle.tables(31, 31, (synth.WALL,) * 4, (), act, mask_bc)
+    grid = hx.Grid(31, 31, 1.0, (synth.WALL,) * 4, (), act, mask_bc)
+    nbr, code = grid.tables()
+    np.testing.assert_array_equal(nbr.cpu().numpy(), nbr_ref)
+    np.testing.assert_array_equal(code.cpu().numpy(), code_ref)
+    assert grid.active_cells == int(act.sum())
+
+
+# -------------------------------------------------- full trajectories
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_planar_slope_full_run(hx, precision):
+    """64 x 64 planar 5% slope, theta 0.8, 50 mm/h for 600 s from dry."""
+    sc = synth.c1_planar()
+    ref = ref_run(sc)
+    got = gpu_run(hx, sc, precision)
+    assert_parity(got, ref, precision, "planar64")
+    assert_books(got, ref, 1e-11 if precision == "fp64" else 1e-5)
+    if precision == "fp64":
+        assert got["books"]["steps"] == ref["books"]["steps"]
+    assert (got["h"] >= 0).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_catchment_ragged_run(hx, precision):
+    """Fractal catchment, vegetation patches, outlet segment; size not a tile multiple."""
+    sc = synth.catchment(150, 131, 2.0, config=2, t_end=300.0)
+    ref = ref_run(sc)
+    got = gpu_run(hx, sc, precision)
+    assert_parity(got, ref, precision, "catchment150x131")
+    assert_books(got, ref, 1e-11 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("tile", range(8))
+def test_every_tile_variant_fp64(hx, tile):
+    sc = synth.catchment(133, 70, 1.0, config=2, t_end=40.0)
+    ref = ref_run(sc)
+    got = gpu_run(hx, sc, "fp64", tile=tile)
+    assert_parity(got, ref, "fp64", f"tile{tile}")
+
+
+def test_masked_cone_and_symmetry(hx):
+    sc = synth.cone(R=20, rim=synth.OUTFLOW, t_end=60.0)
+    ref = ref_run(sc)
+    got = gpu_run(hx, sc, "fp64")
+    assert_parity(got, ref, "fp64", "cone")
+    act = sc.active.astype(bool)
+    assert (got["h"][~act] == 0).all()
+
+
+def test_periodic_strip(hx):
+    sc = synth.kinematic_strip(nq=6, nr=64, t_end=600.0)
+    ref = ref_run(sc)
+    got = gpu_run(hx, sc, "fp64")
+    assert_parity(got, ref, "fp64", "strip")
+    H = got["h"].reshape(sc.nr, sc.nq)
+    assert (H == H[:, :1]).all()
+
+
+def test_triangular_rain(hx):
+    sc = synth.ensemble_member(5, nmin=70, nmax=70, t_end=400.0).with_(
+        rain_kind=1, t_a=100.0, T_d=400.0)
+    ref = ref_run(sc)
+    got = gpu_run(hx, sc, "fp64")
+    assert_parity(got, ref, "fp64", "triangular")
+    assert_books(got, ref, 1e-11)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lake_at_rest(hx, precision):
+    for emerged in (False, True):
+        sc = synth.lake_at_rest(emerged=emerged)
+        got = gpu_run(hx, sc, precision)
+        assert got["books"]["steps"] > 10
+        if precision == "fp64":
+            np.testing.assert_array_equal(got["h"], sc.h0)
+            assert (got["v1"] == 0).all() and (got["v2"] == 0).all()
+        else:
+            assert np.abs(got["h"] - sc.h0).max() <= 1e-6
+            assert np.abs(got["v1"]).max() <= 1e-5 and np.abs(got["v2"]).max() <= 1e-5
+
+
+# ------------------------------------------------ run control and books
+
+def test_graph_length_does_not_change_results(hx):
+    sc = synth.c1_planar(nq=40, nr=30, t_end=120.0)
+    a = gpu_run(hx, sc, "fp64", steps_per_graph=100)
+    b = gpu_run(hx, sc, "fp64", steps_per_graph=7)
+    np.testing.assert_array_equal(a["h"], b["h"])
+    assert a["books"]["steps"] == b["books"]["steps"]
+
+
+def test_max_steps_and_resume(hx):
+    sc = synth.c1_planar(nq=40, nr=30, t_end=120.0)
+    full = gpu_run(hx, sc, "fp64")
+    sim = hx.Sim.from_scenario(sc, "fp64", steps_per_graph=16)
+    sim.run(sc.t_end, max_steps=37)
+    assert sim.books()["steps"] == 37
+    mid = sim.state_numpy()
+    bk = sim.books()
+    # checkpoint -> fresh simulation -> resume
+    sim2 = hx.Sim.from_scenario(sc, "fp64")
+    sim2.set_state(mid["h"], mid["v1"], mid["v2"], bk["t"])
+    sim2.set_books(bk)
+    sim2.run(sc.t_end)
+    fin = sim2.state_numpy()
+    np.testing.assert_array_equal(fin["h"], full["h"])
+    np.testing.assert_array_equal(fin["v1"], full["v1"])
+    assert sim2.books()["steps"] == full["books"]["steps"]
+    assert sim2.books()["stored"] == pytest.approx(full["books"]["stored"], rel=1e-13)
+
+
+def test_runs_are_deterministic(hx):
+    sc = synth.catchment(96, 80, 2.0, config=2, t_end=60.0)
+    a = gpu_run(hx, sc, "fp32")
+    b = gpu_run(hx, sc, "fp32")
+    np.testing.assert_array_equal(a["h"], b["h"])
+    assert a["books"]["stored"] == b["books"]["stored"]
+
+
+def test_invalid_inputs_are_rejected(hx):
+    sc = synth.c1_planar(nq=16, nr=16)
+    grid = hx.Grid.from_scenario(sc)
+    sim = hx.Sim(grid, "fp32")
+    th = sc.theta.copy()
+    th[5] = 0.0
+    with pytest.raises(hx.HexsvError) as ei:
+        sim.set_fields(sc.z, th, sc.alpha_p, sc.alpha_s)
+    assert ei.value.code == hx.EDOMAIN and "first cell 5" in str(ei.value)
+    with pytest.raises(hx.HexsvError) as ei:
+        sim.set_state(sc.h0, sc.v10, sc.v20)
+    assert ei.value.code == hx.ESTATE
+    sim.set_fields(sc.z, sc.theta, sc.alpha_p, sc.alpha_s)
+    h = sc.h0.copy()
+    h[7] = np.nan
+    with pytest.raises(hx.HexsvError) as ei:
+        sim.set_state(h, sc.v10, sc.v20)
+    assert ei.value.code == hx.EDOMAIN
+    sim.set_state(sc.h0, sc.v10, sc.v20, 10.0)
+    with pytest.raises(hx.HexsvError) as ei:
+        sim.run(5.0)
+    assert ei.value.code == hx.EDOMAIN
+    with pytest.raises(hx.HexsvError):
+        hx.Sim(grid, "fp32", cfl=1.0)
+
+
+# ------------------------------------------------ full-size sampled parity
+
+@pytest.mark.parametrize("precision,which", [("fp64", "c2"), ("fp32", "c2"), ("fp32", "c4")])
+def test_full_size_one_step_sampled(hx, precision, which):
+    """At the benchmark's sizes: after n steps, one more GPU step matches the oracle's step
+    of the same state on sampled cells (every boundary kind plus random interior cells)."""
+    sc = synth.c2_catchment() if which == "c2" else synth.c4_large()
+    nsteps = 300 if which == "c2" else 100
+    sim = hx.Sim.from_scenario(sc, precision)
+    sim.run(sc.t_end, max_steps=nsteps)
+    s0 = sim.state_numpy()
+    b0 = sim.books()
+    sim.run(sc.t_end, max_steps=1)
+    s1 = sim.state_numpy()
+    b1 = sim.books()
+    dt = b1["t"] - b0["t"]
+    assert dt > 0
+    rng = np.random.Generator(np.random.PCG64(11))
+    n = sc.n
+    cells = np.concatenate([
+        rng.integers(0, n, 4000),
+        np.arange(0, sc.nq),                        # S row (outlet segment + walls)
+        np.arange(n - sc.nq, n),                    # N row
+        np.arange(0, n, sc.nq), np.arange(sc.nq - 1, n, sc.nq),  # W and E columns
+        np.nonzero(s0["h"] > np.quantile(s0["h"], 0.999))[0][:2000],  # deepest cells
+    ]).astype(np.int32)
+    cells = np.unique(cells)
+    G = ref_grid(sc)
+    hn, v1n, v2n, _ = oracle.step_cells(G, sc.z, sc.theta, sc.alpha_p, ref_params(sc),
+                                        ref_rain(sc), dt, b1["t"], s0["h"], s0["v1"], s0["v2"],
+                                        cells)
+    th = sc.theta[cells]
+    ref = {"h": hn, "v1": v1n, "v2": v2n, "q1": th * hn * v1n, "q2": th * hn * v2n}
+    got = {k: s1[k][cells] for k in ("h", "v1", "v2")}
+    got["q1"] = th * got["h"] * got["v1"]
+    got["q2"] = th * got["h"] * got["v2"]
+    assert_parity(got, ref, precision, f"{which}-sampled")
+    assert b1["residual"] <= (1e-12 if precision == "fp64" else 1e-5)
