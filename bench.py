@@ -39,6 +39,7 @@ def workload(name):
 
 
 def time_gpu(sc, precision, steps, warmup, tile, spg):
+    """Time `steps` solver steps (graph replays) after `warmup`, then the step kernel alone."""
     import torch
     from paper_2406_14933_amd import hexsv
     sim = hexsv.Sim.from_scenario(sc, precision, tile=tile, steps_per_graph=spg)
@@ -55,20 +56,24 @@ def time_gpu(sc, precision, steps, warmup, tile, spg):
     b1 = sim.books()
     sim.timing(False)
     assert b1["steps"] - b0["steps"] == steps, (b0["steps"], b1["steps"])
+    # the dominant kernel in isolation: back-to-back launches bracketed by hipEvents
+    kern_ms = sim.time_kernel(max(20, min(200, steps // 10)))
     cells = sim.grid.active_cells
-    kern_ms = tm["gpu_ms"] / max(tm["steps"], 1)
-    info = sim.info()
+    bpc = BYTES_PER_CELL[precision]
+    achieved = bpc * cells / (kern_ms * 1e-3) / 1e9
     return {
         "wall_s": wall,
         "value": cells * steps / wall,
         "ms_per_step": 1e3 * wall / steps,
-        "kernel_ms": kern_ms,
-        "gpu_ms": tm["gpu_ms"],
-        "timed_steps": tm["steps"],
+        "gpu_us_per_step": 1e3 * tm["gpu_ms"] / max(tm["steps"], 1),
+        "kernel_us": kern_ms * 1e3,
         "cells": cells,
-        "info": info,
+        "info": sim.info(),
         "residual": b1["residual"],
-        "sim_time_s": b1["t"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_step",
+                     "kernel_us": kern_ms * 1e3, "bytes_per_cell": bpc,
+                     "bytes_per_launch": bpc * cells},
     }
 
 
@@ -106,8 +111,12 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--steps-per-graph", type=int, default=100)
+    ap.add_argument("--large-steps", type=int, default=400,
+                    help="steps of the 4096x4096 catchment timed beside the main workload (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -117,19 +126,21 @@ def main():
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "launches": 5}))
+        return
     sc, wname = workload(args.workload)
     print(f"[bench] workload {wname}: {sc.n} cells, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     main_run = time_gpu(sc, args.precision, args.steps, args.warmup, args.tile,
                         args.steps_per_graph)
-    print(f"[bench] {args.precision}: {main_run['value']:.3e} cell-updates/s, "
-          f"kernel {main_run['kernel_ms'] * 1e3:.1f} us/step", file=sys.stderr, flush=True)
-    other = None
-    if not args.no_fp64 and args.precision == "fp32":
-        other = time_gpu(sc, "fp64", args.steps, args.warmup, args.tile, args.steps_per_graph)
-        print(f"[bench] fp64: {other['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
-    bpc = BYTES_PER_CELL[args.precision]
-    achieved = bpc * main_run["cells"] / (main_run["kernel_ms"] * 1e-3) / 1e9
+    print(f"[bench] {args.precision}: {main_run['value']:.3e} cell-updates/s, step kernel "
+          f"{main_run['kernel_us']:.1f} us", file=sys.stderr, flush=True)
     line = {
         "metric": METRIC,
         "value": main_run["value"],
@@ -146,18 +157,25 @@ def main():
         "config": {"workload": wname, "cells": main_run["cells"], "edge_m": sc.a,
                    "precision": args.precision, "tile": main_run["info"],
                    "steps_per_graph": args.steps_per_graph},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step", "kernel_us": main_run["kernel_ms"] * 1e3,
-                     "bytes_per_cell": bpc},
+        "roofline": main_run["roofline"],
+        "gpu_us_per_step": main_run["gpu_us_per_step"],
         "books_residual": main_run["residual"],
     }
-    if other is not None:
+    if not args.no_fp64 and args.precision == "fp32":
+        other = time_gpu(sc, "fp64", args.steps, args.warmup, args.tile, args.steps_per_graph)
+        print(f"[bench] fp64: {other['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
         line["fp64"] = {"value": other["value"], "ms_per_step": other["ms_per_step"],
-                        "kernel_us": other["kernel_ms"] * 1e3,
-                        "hbm_GBs": BYTES_PER_CELL["fp64"] * other["cells"]
-                        / (other["kernel_ms"] * 1e-3) / 1e9,
-                        "books_residual": other["residual"]}
+                        "roofline": other["roofline"], "books_residual": other["residual"]}
+    if args.large_steps > 0 and args.workload != "c4":
+        big, bname = workload("c4")
+        print(f"[bench] large: {bname}", file=sys.stderr, flush=True)
+        lr = time_gpu(big, args.precision, args.large_steps, 50, args.tile, args.steps_per_graph)
+        print(f"[bench] large {args.precision}: {lr['value']:.3e} cell-updates/s, step kernel "
+              f"{lr['kernel_us']:.1f} us", file=sys.stderr, flush=True)
+        line["large"] = {"workload": bname, "value": lr["value"], "steps": args.large_steps,
+                         "ms_per_step": lr["ms_per_step"], "roofline": lr["roofline"],
+                         "books_residual": lr["residual"]}
+        del big
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(line), flush=True)

@@ -92,7 +92,7 @@ typedef struct {
     int32_t precision;       /* hexsv_precision */
     int32_t steps_per_graph; /* steps captured per graph replay (0: default 100) */
     int32_t tile;            /* tile variant index (< 0: tuned or default) */
-    int32_t reserved;
+    int32_t flags;           /* must be 0 */
 } hexsv_params;
 
 /* Rain source of the mass equation (Sec. 2.1 (c), Appendix C).
@@ -197,6 +197,12 @@ int hexsv_sim_set_books(hexsv_sim *sim, const hexsv_books *books, hipStream_t st
  * kernel's average duration including launch gaps inside the graph. */
 int hexsv_sim_timing(hexsv_sim *sim, int32_t enable, double *gpu_ms, int64_t *steps,
                      int64_t *replays);
+
+/* Average duration of the step kernel alone: nlaunch back-to-back launches of
+ * the tile kernel (without the finalize kernel) between two hipEvents on
+ * `stream`.  Every launch recomputes the next step from the current state,
+ * so the state, time and books are unchanged afterwards. */
+int hexsv_sim_time_kernel(hexsv_sim *sim, int32_t nlaunch, double *avg_ms, hipStream_t stream);
 
 /* Launch/tile statistics of the step kernel: number of workgroups, tile
  * variant in use and its shape (tq x tr cells, threads). */

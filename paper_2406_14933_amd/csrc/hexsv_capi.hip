@@ -105,6 +105,7 @@ extern "C" int hexsv_grid_create(const hexsv_grid_desc *desc, hexsv_grid **out) 
         for (int64_t i = 0; i < n; ++i) na += desc->active[i] != 0;
         gr->n_active = na;
         if (na < n) {
+            gr->kg.has_mask = 1;
             std::vector<uint8_t> a01(n);
             for (int64_t i = 0; i < n; ++i) a01[i] = desc->active[i] != 0;
             hipError_t e = hipMalloc(&gr->d_active, n);
@@ -157,8 +158,6 @@ struct hexsv_sim {
     Ctl *d_ctl;
     Ctl *h_ctl;  // pinned mirror
     Part *d_part;
-    Part *d_gpart;
-    uint32_t *d_ctr;
     int32_t *d_chk;
     int32_t *h_chk;  // pinned
     int tile, ntq, ntiles;
@@ -227,6 +226,10 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->tile = p.tile >= 0 ? p.tile : DEFAULT_TILE;
     tile_grid(s->tile, grid->kg.nq, grid->kg.nr, &s->ntq, &s->ntiles);
     s->gsteps = p.steps_per_graph > 0 ? p.steps_per_graph : 100;
+    if (p.flags != 0) {
+        delete s;
+        return fail(HEXSV_EINVAL, "sim_create: flags must be 0");
+    }
     const double a = grid->edge;
     s->kc.g = p.g;
     s->kc.a = a;
@@ -243,10 +246,6 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     hipError_t e = hipMalloc(&s->buf, s->esz * 9 * (size_t)grid->n);
     if (e == hipSuccess) e = hipMalloc(&s->d_ctl, sizeof(Ctl));
     if (e == hipSuccess) e = hipMalloc(&s->d_part, sizeof(Part) * nparts);
-    const size_t ngroups = (size_t)(s->ntiles + GROUP - 1) / GROUP;
-    if (e == hipSuccess) e = hipMalloc(&s->d_gpart, sizeof(Part) * ngroups);
-    if (e == hipSuccess) e = hipMalloc(&s->d_ctr, sizeof(uint32_t) * (1 + ngroups));
-    if (e == hipSuccess) e = hipMemset(s->d_ctr, 0, sizeof(uint32_t) * (1 + ngroups));
     if (e == hipSuccess) e = hipMalloc(&s->d_chk, 4 * sizeof(int32_t));
     if (e == hipSuccess) e = hipHostMalloc(&s->h_ctl, sizeof(Ctl), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&s->h_chk, 4 * sizeof(int32_t), hipHostMallocDefault);
@@ -269,8 +268,6 @@ extern "C" void hexsv_sim_destroy(hexsv_sim *s) {
     if (s->buf) (void)hipFree(s->buf);
     if (s->d_ctl) (void)hipFree(s->d_ctl);
     if (s->d_part) (void)hipFree(s->d_part);
-    if (s->d_gpart) (void)hipFree(s->d_gpart);
-    if (s->d_ctr) (void)hipFree(s->d_ctr);
     if (s->d_chk) (void)hipFree(s->d_chk);
     if (s->h_ctl) (void)hipHostFree(s->h_ctl);
     if (s->h_chk) (void)hipHostFree(s->h_chk);
@@ -403,10 +400,10 @@ static int capture(hexsv_sim *s) {
     for (int k = 0; k < s->gsteps && e == hipSuccess; ++k) {
         if (s->prec == HEXSV_FP64)
             e = launch_step<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
-                                    s->d_part, s->d_gpart, s->d_ctr, s->ntq, s->ntiles, s->cap);
+                                    s->d_part, s->ntq, s->ntiles, s->cap);
         else
             e = launch_step<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
-                                   s->d_part, s->d_gpart, s->d_ctr, s->ntq, s->ntiles, s->cap);
+                                   s->d_part, s->ntq, s->ntiles, s->cap);
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->cap, &g);
@@ -492,6 +489,48 @@ extern "C" int hexsv_sim_timing(hexsv_sim *s, int32_t enable, double *gpu_ms, in
         s->timed_steps = 0;
         s->timed_replays = 0;
     }
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_time_kernel(hexsv_sim *s, int32_t nlaunch, double *avg_ms,
+                                     hipStream_t stream) {
+    if (!s || !avg_ms || nlaunch < 1) return fail(HEXSV_EINVAL, "time_kernel: bad argument");
+    if (!s->state_set) return fail(HEXSV_ESTATE, "time_kernel: no state set");
+    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    Ctl &c = *s->h_ctl;
+    // make the current step live without advancing it: every launch recomputes the
+    // same step from the same buffer, so the state is untouched afterwards
+    const double t_end = c.t_end, dtm = c.dt_max;
+    const int64_t lim = c.step_limit;
+    c.t_end = INFINITY;
+    c.step_limit = c.steps + 1;
+    HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+    if (!s->ev0) {
+        HIP_TRY(hipEventCreate(&s->ev0));
+        HIP_TRY(hipEventCreate(&s->ev1));
+    }
+    hipError_t e = hipSuccess;
+    HIP_TRY(hipEventRecord(s->ev0, stream));
+    for (int k = 0; k < nlaunch && e == hipSuccess; ++k) {
+        if (s->prec == HEXSV_FP64)
+            e = launch_step_only<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn,
+                                         s->d_ctl, s->d_part, s->ntq, s->ntiles, stream);
+        else
+            e = launch_step_only<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn,
+                                        s->d_ctl, s->d_part, s->ntq, s->ntiles, stream);
+    }
+    HIP_TRY(e);
+    HIP_TRY(hipEventRecord(s->ev1, stream));
+    HIP_TRY(hipEventSynchronize(s->ev1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    *avg_ms = ms / nlaunch;
+    c.t_end = t_end;
+    c.dt_max = dtm;
+    c.step_limit = lim;
+    HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
     return HEXSV_OK;
 }
 

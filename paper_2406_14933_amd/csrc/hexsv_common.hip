@@ -22,6 +22,22 @@ __device__ inline Part reduce_parts(const Part *part, int nparts) {
     return block_reduce<NT>(c, s, o, cl);
 }
 
+// Closes one step from the per-tile records (used when the step kernel does
+// not close the step itself).
+__global__ __launch_bounds__(1024) void k_finalize(Ctl *ctl, const Part *part, int nparts,
+                                                   KConst kc, KRain rn) {
+    const StepTime st = step_time(ctl);
+    if (!st.live) return;
+    const Part p = reduce_parts<1024>(part, nparts);
+    if (threadIdx.x == 0) close_step(ctl, p, st, kc, rain_rate(rn, st.t_next));
+}
+
+hipError_t launch_finalize(Ctl *ctl, const Part *part, int nparts, const KConst &kc,
+                           const KRain &rn, hipStream_t stream) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, stream, ctl, part, nparts, kc, rn);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(1024) void k_prime_finalize(Ctl *ctl, const Part *part, int nparts,
                                                          KConst kc, int reset_books) {
     const Part p = reduce_parts<1024>(part, nparts);

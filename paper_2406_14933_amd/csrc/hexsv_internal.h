@@ -16,10 +16,10 @@ struct TileShape {
 // Tile variants the step kernels are built for (the autotuner picks one).
 constexpr TileShape TILES[] = {
     {64, 4, 256}, {64, 8, 256}, {64, 16, 256}, {128, 4, 256},
-    {128, 8, 256}, {128, 8, 512}, {256, 4, 256}, {64, 8, 512},
+    {128, 8, 256}, {128, 8, 512}, {64, 32, 256}, {64, 8, 512},
 };
 constexpr int NUM_TILES = sizeof(TILES) / sizeof(TILES[0]);
-constexpr int DEFAULT_TILE = 1;
+constexpr int DEFAULT_TILE = 2;
 
 // Number of tiles covering an nq x nr raster with variant v.
 inline void tile_grid(int v, int nq, int nr, int *ntq, int *ntiles) {
@@ -28,13 +28,22 @@ inline void tile_grid(int v, int nq, int nr, int *ntq, int *ntiles) {
     *ntiles = *ntq * ((nr + s.tr - 1) / s.tr);
 }
 
-// One step = one launch.  part: ntiles records, gpart: ceil(ntiles/64)
-// records, ctr: 1 + ceil(ntiles/64) zero-initialised counters (the kernel
-// leaves them zero again).
+// One step: the tile kernel (one workgroup per tile, ntiles records in
+// part) followed by the single-workgroup finalize kernel.
 template <typename T>
 hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                       const KRain &rn, Ctl *ctl, Part *part, Part *gpart, uint32_t *ctr,
-                       int ntq, int ntiles, hipStream_t stream);
+                       const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
+                       hipStream_t stream);
+
+// The tile kernel alone (no finalize): used to time the kernel in isolation.
+template <typename T>
+hipError_t launch_step_only(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
+                            const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
+                            hipStream_t stream);
+
+// Close a step from the per-tile records (single workgroup).
+hipError_t launch_finalize(Ctl *ctl, const Part *part, int ntiles, const KConst &kc,
+                           const KRain &rn, hipStream_t stream);
 // Close a priming pass over nparts partial records: tau (and, with
 // reset_books, the initial books) of the current state.
 hipError_t launch_prime_finalize(Ctl *ctl, const Part *part, int nparts, const KConst &kc,

@@ -5,6 +5,7 @@
 #include <math.h>
 
 #include "hexsv_internal.h"
+#include "hexsv_tile.h"
 
 namespace hexsv {
 
@@ -12,41 +13,43 @@ namespace hexsv {
 // recomputes the step's dt from the control block; a step past t_end or
 // past the step limit does nothing, so a captured graph of many steps can
 // overrun the end of a run safely.
-// The workgroups that finish last also close the step (finish_tile), so a
-// step is exactly one kernel launch.
+// One explicit step of one tile (tile_step); the per-tile record is folded
+// into the control block by the single-workgroup finalize kernel launched
+// right after, so every workgroup of the next step sees the new dt.
 template <typename T, int TQ, int TR, int NT>
 __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRain rn, Ctl *ctl,
-                                             Part *part, Part *gpart, uint32_t *ctr, int ntq,
-                                             int ntiles) {
+                                             Part *part, int ntq, int ntiles) {
     const StepTime st = step_time(ctl);
     if (!st.live) return;
     const int tile = xcd_tile(blockIdx.x, ntiles);
     const int tr = tile / ntq, tq = tile - tr * ntq;
     __shared__ TileLDS<T, TQ, TR> L;
     const double r_next = rain_rate(rn, st.t_next);
-    const Part p = tile_step<T, TQ, TR, NT>(L, d, g, kc, ctl->parity, tq, tr, st.dt, r_next,
-                                            &ctl->err, &ctl->err_cell);
-    finish_tile<NT>(p, tile, ntiles, part, gpart, ctr, ctl, st, kc, r_next);
+    const Part p = tile_step<T, TQ, TR, NT, true>(L, d, g, kc, ctl->parity, tq, tr, st.dt, r_next,
+                                                  &ctl->err, &ctl->err_cell);
+    if (threadIdx.x == 0) part[tile] = p;
 }
 
 template <typename T, int TQ, int TR, int NT>
 static hipError_t launch_step_v(const KDom<T> &d, const KGrid &g, const KConst &kc,
-                                const KRain &rn, Ctl *ctl, Part *part, Part *gpart,
-                                uint32_t *ctr, int ntq, int ntiles, hipStream_t stream) {
+                                const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
+                                bool finalize, hipStream_t stream) {
     hipLaunchKernelGGL((k_step<T, TQ, TR, NT>), dim3(ntiles), dim3(NT), 0, stream, d, g, kc, rn,
-                       ctl, part, gpart, ctr, ntq, ntiles);
-    return hipGetLastError();
+                       ctl, part, ntq, ntiles);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !finalize) return e;
+    return launch_finalize(ctl, part, ntiles, kc, rn, stream);
 }
 
 template <typename T>
-hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                       const KRain &rn, Ctl *ctl, Part *part, Part *gpart, uint32_t *ctr,
-                       int ntq, int ntiles, hipStream_t stream) {
+static hipError_t launch_step_any(int variant, const KDom<T> &d, const KGrid &g,
+                                  const KConst &kc, const KRain &rn, Ctl *ctl, Part *part,
+                                  int ntq, int ntiles, bool finalize, hipStream_t stream) {
     switch (variant) {
-#define HEXSV_CASE(V)                                                                         \
-    case V:                                                                                   \
-        return launch_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(d, g, kc, rn, ctl, part, \
-                                                                       gpart, ctr, ntq, ntiles, \
+#define HEXSV_CASE(V)                                                                          \
+    case V:                                                                                    \
+        return launch_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(d, g, kc, rn, ctl, part,  \
+                                                                       ntq, ntiles, finalize, \
                                                                        stream);
         HEXSV_CASE(0)
         HEXSV_CASE(1)
@@ -60,6 +63,20 @@ hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KCon
         default:
             return hipErrorInvalidValue;
     }
+}
+
+template <typename T>
+hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
+                       const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
+                       hipStream_t stream) {
+    return launch_step_any<T>(variant, d, g, kc, rn, ctl, part, ntq, ntiles, true, stream);
+}
+
+template <typename T>
+hipError_t launch_step_only(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
+                            const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
+                            hipStream_t stream) {
+    return launch_step_any<T>(variant, d, g, kc, rn, ctl, part, ntq, ntiles, false, stream);
 }
 
 // Initial c_max and stored volume of the current buffer.
@@ -137,8 +154,10 @@ hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double
 
 #define HEXSV_INSTANTIATE(T)                                                                  \
     template hipError_t launch_step<T>(int, const KDom<T> &, const KGrid &, const KConst &,   \
-                                       const KRain &, Ctl *, Part *, Part *, uint32_t *, int, \
-                                       int, hipStream_t);                                     \
+                                       const KRain &, Ctl *, Part *, int, int, hipStream_t);  \
+    template hipError_t launch_step_only<T>(int, const KDom<T> &, const KGrid &, const KConst &, \
+                                            const KRain &, Ctl *, Part *, int, int,           \
+                                            hipStream_t);                                     \
     template hipError_t launch_prime<T>(const KDom<T> &, int64_t, const KConst &, Ctl *, Part *, \
                                         int, int, hipStream_t);                               \
     template hipError_t launch_import<T>(const double *, T *, const uint8_t *, int, int64_t,  \

@@ -43,7 +43,7 @@ class GridDesc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("cfl", C.c_double), ("dt_max", C.c_double),
                 ("h_dry", C.c_double), ("precision", C.c_int32), ("steps_per_graph", C.c_int32),
-                ("tile", C.c_int32), ("reserved", C.c_int32)]
+                ("tile", C.c_int32), ("flags", C.c_int32)]
 
 
 class Rain(C.Structure):
@@ -81,6 +81,7 @@ _SIGS = [
     ("hexsv_sim_info", C.c_int, [_VP] + [C.POINTER(C.c_int32)] * 5),
     ("hexsv_sim_timing", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64)]),
+    ("hexsv_sim_time_kernel", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_double), _VP]),
     ("hexsv_tile_count", C.c_int, []),
     ("hexsv_tile_shape", C.c_int, [C.c_int32] + [C.POINTER(C.c_int32)] * 3),
 ]
@@ -190,11 +191,11 @@ class Sim:
     """Single-catchment time stepper (FP64 or FP32 state, FP64 books and dt)."""
 
     def __init__(self, grid: Grid, precision="fp32", g=9.81, cfl=0.5, dt_max=1.0, h_dry=0.0,
-                 steps_per_graph=100, tile=-1):
+                 steps_per_graph=100, tile=-1, flags=0):
         self.grid = grid
         prec = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[precision]
         p = Params(float(g), float(cfl), float(dt_max), float(h_dry), prec, int(steps_per_graph),
-                   int(tile), 0)
+                   int(tile), int(flags))
         h = C.c_void_p()
         _check(lib().hexsv_sim_create(grid._h, C.byref(p), C.byref(h)))
         self._h = h
@@ -257,6 +258,12 @@ class Sim:
         en = -1 if enable is None else int(bool(enable))
         _check(lib().hexsv_sim_timing(self._h, en, C.byref(ms), C.byref(st), C.byref(rp)))
         return {"gpu_ms": ms.value, "steps": st.value, "replays": rp.value}
+
+    def time_kernel(self, nlaunch=50):
+        """Average duration (ms) of the step kernel alone, from hipEvents on the current stream."""
+        ms = C.c_double()
+        _check(lib().hexsv_sim_time_kernel(self._h, int(nlaunch), C.byref(ms), _stream()))
+        return ms.value
 
     def info(self):
         vals = [C.c_int32() for _ in range(5)]
