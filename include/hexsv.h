@@ -92,7 +92,8 @@ typedef struct {
     int32_t precision;       /* hexsv_precision */
     int32_t steps_per_graph; /* steps captured per graph replay (0: default 100) */
     int32_t tile;            /* tile variant index (< 0: tuned or default) */
-    int32_t flags;           /* must be 0 */
+    int32_t wg_per_cu;       /* > 0: grid-stride step launch with at most this many
+                                workgroups per CU; <= 0: one workgroup per tile */
 } hexsv_params;
 
 /* Rain source of the mass equation (Sec. 2.1 (c), Appendix C).
@@ -208,6 +209,47 @@ int hexsv_sim_time_kernel(hexsv_sim *sim, int32_t nlaunch, double *avg_ms, hipSt
  * variant in use and its shape (tq x tr cells, threads). */
 int hexsv_sim_info(const hexsv_sim *sim, int32_t *workgroups, int32_t *tile, int32_t *tq,
                    int32_t *tr, int32_t *threads);
+
+/* ---------------------------------------------------- batched ensemble */
+
+/* An ensemble of n independent catchments on rasters of any sizes, advanced
+ * together by one persistent kernel (each scenario with its own CFL time
+ * step, rain and books; same g, cfl, dt_max, h_dry and precision).  One
+ * workgroup sweeps one scenario at a time; workgroups take scenarios largest
+ * first.  params->steps_per_graph is the number of steps each scenario
+ * advances per launch (0: 50); params->tile selects the ensemble tile
+ * variant (< 0: default).  The grids must outlive the ensemble. */
+int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids, const hexsv_params *params,
+                          hexsv_ensemble **out);
+void hexsv_ensemble_destroy(hexsv_ensemble *ens);
+
+/* Fields, rain and initial state of scenario s (device FP64 arrays sized for
+ * its raster), with the same validation as the single-catchment calls;
+ * resets the scenario's books.  Synchronises `stream`. */
+int hexsv_ensemble_set_scenario(hexsv_ensemble *ens, int32_t s, const double *d_z,
+                                const double *d_theta, const double *d_alpha_p, double alpha_s,
+                                const hexsv_rain *rain, double t0, const double *d_h,
+                                const double *d_v1, const double *d_v2, hipStream_t stream);
+
+/* Advance every scenario s to t_end[s] (host array of n), or by at most
+ * max_steps steps (<= 0: no limit).  Replays a captured graph of one
+ * persistent launch until every scenario is done.  EDOMAIN: t_end[s] before
+ * the scenario's time.  ENUMERIC: a non-finite value appeared. */
+int hexsv_ensemble_run(hexsv_ensemble *ens, const double *t_end, int64_t max_steps,
+                       hipStream_t stream);
+
+/* State (FP64 device arrays sized for scenario s, each nullable) and books. */
+int hexsv_ensemble_get_state(const hexsv_ensemble *ens, int32_t s, double *d_h, double *d_v1,
+                             double *d_v2, double *d_q1, double *d_q2, hipStream_t stream);
+int hexsv_ensemble_get_books(hexsv_ensemble *ens, int32_t s, hexsv_books *out, hipStream_t stream);
+
+/* Device timing of ensemble runs (as hexsv_sim_timing): GPU time of the
+ * launches, cell-updates they performed (sum over scenarios of active cells
+ * times steps taken) and number of launches. */
+int hexsv_ensemble_timing(hexsv_ensemble *ens, int32_t enable, double *gpu_ms,
+                          int64_t *cell_updates, int64_t *launches);
+int hexsv_ensemble_info(const hexsv_ensemble *ens, int32_t *workgroups, int32_t *tile,
+                        int64_t *cells, int32_t *steps_per_launch);
 
 /* Number of tile variants built, and the shape of variant v. */
 int hexsv_tile_count(void);

@@ -31,6 +31,7 @@ UNITS = [
     ("hexsv_f32.hip", ["-ffp-contract=fast"]),
     ("hexsv_common.hip", ["-ffp-contract=off"]),
     ("hexsv_capi.hip", ["-ffp-contract=off"]),
+    ("hexsv_ens.hip", ["-ffp-contract=off"]),
 ]
 
 

@@ -12,14 +12,15 @@
 
 #include "hexsv.h"
 #include "hexsv_internal.h"
+#include "hexsv_host.h"
 
 using namespace hexsv;
 
 // ------------------------------------------------------------------ errors
 
-static thread_local std::string g_msg;
+thread_local std::string g_msg;
 
-static int fail(int code, const char *fmt, ...) {
+int hexsv_fail(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -29,24 +30,10 @@ static int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                       \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail(HEXSV_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
-    } while (0)
-
 extern "C" const char *hexsv_last_error(void) { return g_msg.c_str(); }
 extern "C" const char *hexsv_version(void) { return "hexsv 0.1 gfx950"; }
 
 // ------------------------------------------------------------------ raster
-
-struct hexsv_grid {
-    KGrid kg;
-    double edge;
-    int64_t n, n_active;
-    uint8_t *d_active;  // nullptr when every cell is active
-};
 
 static bool valid_side(int c) {
     return c == HEXSV_WALL || c == HEXSV_OUTFLOW || c == HEXSV_PERIODIC;
@@ -160,7 +147,7 @@ struct hexsv_sim {
     Part *d_part;
     int32_t *d_chk;
     int32_t *h_chk;  // pinned
-    int tile, ntq, ntiles;
+    int tile, ntq, ntiles, nwg;
     int gsteps;
     hipStream_t cap;
     hipGraph_t graph;
@@ -185,8 +172,6 @@ static KDom<T> dom_of(const hexsv_sim *s) {
     d.ap = b + 8 * n;
     return d;
 }
-
-static const double S3H = 0.86602540378443864676;
 
 static void drop_graph(hexsv_sim *s) {
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
@@ -226,15 +211,10 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->tile = p.tile >= 0 ? p.tile : DEFAULT_TILE;
     tile_grid(s->tile, grid->kg.nq, grid->kg.nr, &s->ntq, &s->ntiles);
     s->gsteps = p.steps_per_graph > 0 ? p.steps_per_graph : 100;
-    if (p.flags != 0) {
-        delete s;
-        return fail(HEXSV_EINVAL, "sim_create: flags must be 0");
-    }
     const double a = grid->edge;
     s->kc.g = p.g;
     s->kc.a = a;
-    s->kc.sigma = 6.0 * (0.5 * a * (S3H * a));
-    s->kc.cfl_phi = p.cfl * (s->kc.sigma / (6.0 * a));
+    hexsv_geometry(a, p.cfl, &s->kc.sigma, &s->kc.cfl_phi);
     s->kc.h_dry = p.h_dry;
     s->kc.alpha_s = 0.0;
     s->kc.area_active = s->kc.sigma * (double)grid->n_active;
@@ -242,7 +222,9 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->rn.i_a = 0.0;
     s->rn.t_a = 0.0;
     s->rn.T_d = INFINITY;
-    const size_t nparts = (size_t)(s->ntiles > PRIME_BLOCKS ? s->ntiles : PRIME_BLOCKS);
+    s->nwg = p.precision == HEXSV_FP64 ? step_workgroups<double>(s->tile, s->ntiles, p.wg_per_cu)
+                                       : step_workgroups<float>(s->tile, s->ntiles, p.wg_per_cu);
+    const size_t nparts = (size_t)(s->nwg > PRIME_BLOCKS ? s->nwg : PRIME_BLOCKS);
     hipError_t e = hipMalloc(&s->buf, s->esz * 9 * (size_t)grid->n);
     if (e == hipSuccess) e = hipMalloc(&s->d_ctl, sizeof(Ctl));
     if (e == hipSuccess) e = hipMalloc(&s->d_part, sizeof(Part) * nparts);
@@ -277,7 +259,7 @@ extern "C" void hexsv_sim_destroy(hexsv_sim *s) {
 extern "C" int hexsv_sim_info(const hexsv_sim *s, int32_t *workgroups, int32_t *tile, int32_t *tq,
                               int32_t *tr, int32_t *threads) {
     if (!s) return fail(HEXSV_EINVAL, "sim_info: null sim");
-    if (workgroups) *workgroups = s->ntiles;
+    if (workgroups) *workgroups = s->nwg;
     if (tile) *tile = s->tile;
     return hexsv_tile_shape(s->tile, tq, tr, threads);
 }
@@ -400,10 +382,10 @@ static int capture(hexsv_sim *s) {
     for (int k = 0; k < s->gsteps && e == hipSuccess; ++k) {
         if (s->prec == HEXSV_FP64)
             e = launch_step<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
-                                    s->d_part, s->ntq, s->ntiles, s->cap);
+                                    s->d_part, s->ntq, s->ntiles, s->nwg, s->cap);
         else
             e = launch_step<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
-                                   s->d_part, s->ntq, s->ntiles, s->cap);
+                                   s->d_part, s->ntq, s->ntiles, s->nwg, s->cap);
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->cap, &g);
@@ -515,10 +497,12 @@ extern "C" int hexsv_sim_time_kernel(hexsv_sim *s, int32_t nlaunch, double *avg_
     for (int k = 0; k < nlaunch && e == hipSuccess; ++k) {
         if (s->prec == HEXSV_FP64)
             e = launch_step_only<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn,
-                                         s->d_ctl, s->d_part, s->ntq, s->ntiles, stream);
+                                         s->d_ctl, s->d_part, s->ntq, s->ntiles, s->nwg,
+                                         stream);
         else
             e = launch_step_only<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn,
-                                        s->d_ctl, s->d_part, s->ntq, s->ntiles, stream);
+                                        s->d_ctl, s->d_part, s->ntq, s->ntiles, s->nwg,
+                                        stream);
     }
     HIP_TRY(e);
     HIP_TRY(hipEventRecord(s->ev1, stream));

@@ -9,15 +9,27 @@ namespace hexsv {
 
 // Deterministic reduction of partial records: fixed strided assignment to
 // threads, xor-butterfly within waves, fixed order across waves.
+// Deterministic reduction of partial records: fixed strided assignment to
+// threads (eight independent loads in flight per thread), xor-butterfly within
+// waves, fixed order across waves.
 template <int NT>
 __device__ inline Part reduce_parts(const Part *part, int nparts) {
     double c = 0.0, s = 0.0, o = 0.0, cl = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += NT) {
-        const Part p = part[i];
-        c = p.cmax > c ? p.cmax : c;
-        s += p.stored;
-        o += p.outflow;
-        cl += p.clamp;
+    constexpr int U = 8;
+    for (int base = 0; base < nparts; base += NT * U) {
+        Part p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * NT + threadIdx.x;
+            p[u] = i < nparts ? part[i] : Part{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c = p[u].cmax > c ? p[u].cmax : c;
+            s += p[u].stored;
+            o += p[u].outflow;
+            cl += p[u].clamp;
+        }
     }
     return block_reduce<NT>(c, s, o, cl);
 }
@@ -149,6 +161,15 @@ __global__ void k_tables(KGrid g, const uint8_t *active, int32_t *nbr, uint8_t *
             code[i * 6 + k] = (uint8_t)cd;
         }
     }
+}
+
+__global__ void k_queue_reset(uint32_t *queue) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0u;
+}
+
+hipError_t launch_queue_reset(uint32_t *queue, hipStream_t stream) {
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, queue);
+    return hipGetLastError();
 }
 
 hipError_t launch_tables(const KGrid &g, const uint8_t *active, int32_t *nbr, uint8_t *code,

@@ -205,13 +205,20 @@ __device__ inline void close_step(Ctl *ctl, const Part &p, const StepTime &st, c
     ctl->parity ^= 1;
 }
 
-// Logical tile of hardware workgroup b: workgroups are dispatched round-robin
-// over the 8 XCDs, so give each XCD a contiguous band of tiles (its L2 then
-// holds the halo rows shared by vertically adjacent tiles).
-__device__ inline int xcd_tile(int b, int ntiles) {
+// Tile schedule of a grid-stride launch of G workgroups over ntiles tiles.
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8), so each XCD gets a contiguous band of tiles and its workgroups
+// sweep the band together: concurrently processed tiles are neighbours and
+// their shared halo rows stay in that XCD's L2.  Returns -1 past the end.
+__device__ inline int xcd_tile(int b, int G, int ntiles, int k) {
+    const int x = b & 7;
+    const int gx = (G >> 3) + (x < (G & 7) ? 1 : 0);  // workgroups on XCD x
+    const int j = b >> 3;                               // rank among them
     const int per = ntiles >> 3, rem = ntiles & 7;
-    const int x = b & 7, j = b >> 3;
-    return x * per + (x < rem ? x : rem) + j;
+    const int cnt = per + (x < rem ? 1 : 0);            // tiles of XCD x
+    const int start = x * per + (x < rem ? x : rem);
+    const int t = j + k * gx;
+    return t < cnt ? start + t : -1;
 }
 
 }  // namespace hexsv

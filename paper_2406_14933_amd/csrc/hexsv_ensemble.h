@@ -1,0 +1,159 @@
+// hexsv_ensemble.h — persistent kernel that advances a batch of independent
+// catchments (uneven raster sizes, each with its own time step, rain and
+// books) in one launch.
+//
+// One workgroup owns one scenario at a time and sweeps all of its tiles for
+// every step, so all synchronisation of a step (tiles done before the next
+// step reads them, reduction of c_max and of the FP64 books, the new dt) is
+// inside one workgroup: a barrier with workgroup-scope fences.  Workgroups
+// take scenarios from a queue ordered largest first and advance each by up to
+// `ksteps` steps per launch.  Within a workgroup the loads of the next tile
+// are issued before the arithmetic of the current tile (two register sets),
+// so every CU keeps HBM requests in flight while it computes.
+//
+// Cross-workgroup coordination is avoided on purpose: on gfx950 each of the
+// 8 XCDs has its own L2, and an agent-scope release per tile (needed for a
+// step barrier shared by several workgroups) writes back the whole L2.
+#pragma once
+
+#include "hexsv_internal.h"
+#include "hexsv_tile.h"
+
+namespace hexsv {
+
+// One scenario of the batch: where its cells live in the concatenated
+// arrays and its raster, constants and rain.
+struct EnsScen {
+    int64_t off;
+    KGrid g;
+    KConst kc;
+    KRain rn;
+    int32_t ntq, ntiles;
+};
+
+template <typename T>
+__device__ inline KDom<T> dom_at(const KDom<T> &base, int64_t off) {
+    KDom<T> d;
+    for (int p = 0; p < 2; ++p)
+        for (int f = 0; f < 3; ++f) d.st[p][f] = base.st[p][f] + off;
+    d.z = base.z + off;
+    d.th = base.th + off;
+    d.ap = base.ap + off;
+    return d;
+}
+
+template <typename T, int TQ, int TR, int NT>
+__global__ __launch_bounds__(NT) void k_ensemble(KDom<T> base, const EnsScen *__restrict__ scen,
+                                                 Ctl *__restrict__ ctl,
+                                                 const int32_t *__restrict__ order, int nscen,
+                                                 uint32_t *queue, int ksteps) {
+    __shared__ TileLDS<T, TQ, TR> L;
+    __shared__ Ctl sc;
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int qi = s_next;
+        if (qi >= nscen) break;
+        const int s = order[qi];
+        const KGrid g = scen[s].g;
+        const KConst kc = scen[s].kc;
+        const KRain rn = scen[s].rn;
+        const int ntq = scen[s].ntq, ntiles = scen[s].ntiles;
+        const KDom<T> d = dom_at(base, scen[s].off);
+        if (threadIdx.x == 0) sc = ctl[s];
+        __syncthreads();
+        for (int step = 0; step < ksteps; ++step) {
+            const StepTime st = step_time(&sc);
+            if (!st.live) break;
+            const double r_next = rain_rate(rn, st.t_next);
+            const int par = sc.parity;
+            Acc acc{0.0, 0.0, 0.0, 0.0};
+            TileRegs<T, TQ, TR, NT> R0, R1;
+            tile_load<T, TQ, TR, NT>(R0, d, g, par, 0, 0);
+            for (int t = 0; t < ntiles; t += 2) {
+                {
+                    const int tr = t / ntq, tq = t - tr * ntq;
+                    const bool bad = tile_stage<T, TQ, TR, NT>(L, R0, g, kc, tq, tr);
+                    const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
+                    const bool general = __syncthreads_or((!inner) || bad) != 0;
+                    if (t + 1 < ntiles) {
+                        const int tr1 = (t + 1) / ntq, tq1 = (t + 1) - tr1 * ntq;
+                        tile_load<T, TQ, TR, NT>(R1, d, g, par, tq1, tr1);
+                    }
+                    tile_compute<T, TQ, TR, NT, false>(L, R0, general, d, g, kc, par, tq, tr,
+                                                       st.dt, r_next, acc, &ctl[s].err,
+                                                       &ctl[s].err_cell);
+                    __syncthreads();
+                }
+                if (t + 1 >= ntiles) break;
+                {
+                    const int tr = (t + 1) / ntq, tq = (t + 1) - tr * ntq;
+                    const bool bad = tile_stage<T, TQ, TR, NT>(L, R1, g, kc, tq, tr);
+                    const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
+                    const bool general = __syncthreads_or((!inner) || bad) != 0;
+                    if (t + 2 < ntiles) {
+                        const int tr2 = (t + 2) / ntq, tq2 = (t + 2) - tr2 * ntq;
+                        tile_load<T, TQ, TR, NT>(R0, d, g, par, tq2, tr2);
+                    }
+                    tile_compute<T, TQ, TR, NT, false>(L, R1, general, d, g, kc, par, tq, tr,
+                                                       st.dt, r_next, acc, &ctl[s].err,
+                                                       &ctl[s].err_cell);
+                    __syncthreads();
+                }
+            }
+            const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
+            if (threadIdx.x == 0) {
+                close_step(&sc, p, st, kc, r_next);
+                sc.err = ctl[s].err;
+            }
+            // the new state must be visible to every thread of the workgroup
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        if (threadIdx.x == 0) {
+            const int32_t err = ctl[s].err, cell = ctl[s].err_cell;
+            ctl[s] = sc;
+            ctl[s].err = err;
+            ctl[s].err_cell = cell;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int TQ, int TR, int NT>
+static hipError_t launch_ensemble_v(const KDom<T> &base, const EnsScen *scen, Ctl *ctl,
+                                    const int32_t *order, int nscen, uint32_t *queue, int ksteps,
+                                    int nwg, hipStream_t stream) {
+    hipError_t e = launch_queue_reset(queue, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ensemble<T, TQ, TR, NT>), dim3(nwg), dim3(NT), 0, stream, base, scen, ctl,
+                       order, nscen, queue, ksteps);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ensemble(int variant, const KDom<T> &base, const EnsScen *scen, Ctl *ctl,
+                           const int32_t *order, int nscen, uint32_t *queue, int ksteps, int nwg,
+                           hipStream_t stream) {
+    switch (variant) {
+#define HEXSV_CASE(V)                                                                        \
+    case V:                                                                                  \
+        return launch_ensemble_v<T, ENS_TILES[V].tq, ENS_TILES[V].tr, ENS_TILES[V].nt>(      \
+            base, scen, ctl, order, nscen, queue, ksteps, nwg, stream);
+        HEXSV_CASE(0)
+        HEXSV_CASE(1)
+        HEXSV_CASE(2)
+#undef HEXSV_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+#define HEXSV_INSTANTIATE_ENSEMBLE(T)                                                         \
+    template hipError_t launch_ensemble<T>(int, const KDom<T> &, const EnsScen *, Ctl *,      \
+                                           const int32_t *, int, uint32_t *, int, int,        \
+                                           hipStream_t);
+
+}  // namespace hexsv

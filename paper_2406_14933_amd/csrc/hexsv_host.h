@@ -1,0 +1,33 @@
+// hexsv_host.h — host-side helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hexsv.h"
+#include "hexsv_device.h"
+
+// Record a thread-local message (read by hexsv_last_error) and return code.
+int hexsv_fail(int code, const char *fmt, ...);
+#define fail hexsv_fail
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(HEXSV_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+// The raster handle (shared by the single-domain and ensemble APIs).
+struct hexsv_grid {
+    hexsv::KGrid kg;
+    double edge;
+    int64_t n, n_active;
+    uint8_t *d_active;  // nullptr when every cell is active
+};
+
+// Geometry constants of a raster of edge a (regular hexagon area, CFL bound).
+inline void hexsv_geometry(double a, double cfl, double *sigma, double *cfl_phi) {
+    const double S3H = 0.86602540378443864676;
+    *sigma = 6.0 * (0.5 * a * (S3H * a));
+    *cfl_phi = cfl * (*sigma / (6.0 * a));
+}

@@ -19,6 +19,21 @@ constexpr TileShape TILES[] = {
     {128, 8, 256}, {128, 8, 512}, {64, 32, 256}, {64, 8, 512},
 };
 constexpr int NUM_TILES = sizeof(TILES) / sizeof(TILES[0]);
+
+// Tile variants of the persistent ensemble kernel (one 1024-thread workgroup
+// sweeps a whole scenario).
+constexpr TileShape ENS_TILES[] = {{64, 16, 1024}, {64, 32, 1024}, {128, 16, 1024}};
+constexpr int NUM_ENS_TILES = sizeof(ENS_TILES) / sizeof(ENS_TILES[0]);
+
+struct EnsScen;
+// Reset the ensemble's scenario queue (a one-thread kernel, safe inside graphs).
+hipError_t launch_queue_reset(uint32_t *queue, hipStream_t stream);
+// One launch of the persistent ensemble kernel: nwg workgroups take the
+// scenarios in `order` from the queue and advance each by up to ksteps steps.
+template <typename T>
+hipError_t launch_ensemble(int variant, const KDom<T> &base, const EnsScen *scen, Ctl *ctl,
+                           const int32_t *order, int nscen, uint32_t *queue, int ksteps, int nwg,
+                           hipStream_t stream);
 constexpr int DEFAULT_TILE = 2;
 
 // Number of tiles covering an nq x nr raster with variant v.
@@ -28,17 +43,21 @@ inline void tile_grid(int v, int nq, int nr, int *ntq, int *ntiles) {
     *ntiles = *ntq * ((nr + s.tr - 1) / s.tr);
 }
 
-// One step: the tile kernel (one workgroup per tile, ntiles records in
+// One step: the grid-stride tile kernel (nwg workgroups, nwg records in
 // part) followed by the single-workgroup finalize kernel.
 template <typename T>
 hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                       const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
+                       const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles, int nwg,
                        hipStream_t stream);
+// Workgroups of the grid-stride step launch: one per tile, or at most per_cu
+// per CU when per_cu > 0.
+template <typename T>
+int step_workgroups(int variant, int ntiles, int per_cu);
 
 // The tile kernel alone (no finalize): used to time the kernel in isolation.
 template <typename T>
 hipError_t launch_step_only(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                            const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
+                            const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles, int nwg,
                             hipStream_t stream);
 
 // Close a step from the per-tile records (single workgroup).

@@ -13,52 +13,70 @@ namespace hexsv {
 // recomputes the step's dt from the control block; a step past t_end or
 // past the step limit does nothing, so a captured graph of many steps can
 // overrun the end of a run safely.
-// One explicit step of one tile (tile_step); the per-tile record is folded
-// into the control block by the single-workgroup finalize kernel launched
-// right after, so every workgroup of the next step sees the new dt.
+// One explicit step over the raster: a grid-stride launch in which every
+// workgroup advances its tiles (tile_step) and writes one partial record; the
+// single-workgroup finalize kernel launched right after folds the records
+// into the control block, so every workgroup of the next step sees the new dt.
 template <typename T, int TQ, int TR, int NT>
 __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRain rn, Ctl *ctl,
                                              Part *part, int ntq, int ntiles) {
     const StepTime st = step_time(ctl);
     if (!st.live) return;
-    const int tile = xcd_tile(blockIdx.x, ntiles);
-    const int tr = tile / ntq, tq = tile - tr * ntq;
     __shared__ TileLDS<T, TQ, TR> L;
     const double r_next = rain_rate(rn, st.t_next);
-    const Part p = tile_step<T, TQ, TR, NT, true>(L, d, g, kc, ctl->parity, tq, tr, st.dt, r_next,
-                                                  &ctl->err, &ctl->err_cell);
-    if (threadIdx.x == 0) part[tile] = p;
+    const int par = ctl->parity;
+    Acc acc{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0;; ++k) {
+        const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, k);
+        if (tile < 0) break;
+        if (k > 0) __syncthreads();
+        const int tr = tile / ntq, tq = tile - tr * ntq;
+        tile_step<T, TQ, TR, NT, true>(L, d, g, kc, par, tq, tr, st.dt, r_next, acc, &ctl->err,
+                                       &ctl->err_cell);
+    }
+    const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
+    if (threadIdx.x == 0) part[blockIdx.x] = p;
 }
 
 template <typename T, int TQ, int TR, int NT>
 static hipError_t launch_step_v(const KDom<T> &d, const KGrid &g, const KConst &kc,
                                 const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
-                                bool finalize, hipStream_t stream) {
-    hipLaunchKernelGGL((k_step<T, TQ, TR, NT>), dim3(ntiles), dim3(NT), 0, stream, d, g, kc, rn,
-                       ctl, part, ntq, ntiles);
+                                int nwg, bool finalize, hipStream_t stream) {
+    hipLaunchKernelGGL((k_step<T, TQ, TR, NT>), dim3(nwg), dim3(NT), 0, stream, d, g, kc, rn, ctl,
+                       part, ntq, ntiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !finalize) return e;
-    return launch_finalize(ctl, part, ntiles, kc, rn, stream);
+    return launch_finalize(ctl, part, nwg, kc, rn, stream);
 }
+
+// Workgroups of one grid-stride step launch: at most `per_cu` workgroups per
+// CU (per_cu <= 0: one tile per workgroup, which measured fastest on large
+// rasters because finished workgroups are replaced at once).
+template <typename T, int TQ, int TR, int NT>
+static int step_workgroups_v(int ntiles, int per_cu) {
+    if (per_cu <= 0) return ntiles;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ntiles;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return ntiles;
+    const int cap = ncu * per_cu;
+    return ntiles < cap ? ntiles : cap;
+}
+
+#define HEXSV_TILE_SWITCH(X) \
+    X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 template <typename T>
 static hipError_t launch_step_any(int variant, const KDom<T> &d, const KGrid &g,
                                   const KConst &kc, const KRain &rn, Ctl *ctl, Part *part,
-                                  int ntq, int ntiles, bool finalize, hipStream_t stream) {
+                                  int ntq, int ntiles, int nwg, bool finalize,
+                                  hipStream_t stream) {
     switch (variant) {
 #define HEXSV_CASE(V)                                                                          \
     case V:                                                                                    \
-        return launch_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(d, g, kc, rn, ctl, part,  \
-                                                                       ntq, ntiles, finalize, \
-                                                                       stream);
-        HEXSV_CASE(0)
-        HEXSV_CASE(1)
-        HEXSV_CASE(2)
-        HEXSV_CASE(3)
-        HEXSV_CASE(4)
-        HEXSV_CASE(5)
-        HEXSV_CASE(6)
-        HEXSV_CASE(7)
+        return launch_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(                        \
+            d, g, kc, rn, ctl, part, ntq, ntiles, nwg, finalize, stream);
+        HEXSV_TILE_SWITCH(HEXSV_CASE)
 #undef HEXSV_CASE
         default:
             return hipErrorInvalidValue;
@@ -66,17 +84,30 @@ static hipError_t launch_step_any(int variant, const KDom<T> &d, const KGrid &g,
 }
 
 template <typename T>
+int step_workgroups(int variant, int ntiles, int per_cu) {
+    switch (variant) {
+#define HEXSV_CASE(V) \
+    case V:           \
+        return step_workgroups_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(ntiles, per_cu);
+        HEXSV_TILE_SWITCH(HEXSV_CASE)
+#undef HEXSV_CASE
+        default:
+            return ntiles;
+    }
+}
+
+template <typename T>
 hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                       const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
+                       const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles, int nwg,
                        hipStream_t stream) {
-    return launch_step_any<T>(variant, d, g, kc, rn, ctl, part, ntq, ntiles, true, stream);
+    return launch_step_any<T>(variant, d, g, kc, rn, ctl, part, ntq, ntiles, nwg, true, stream);
 }
 
 template <typename T>
 hipError_t launch_step_only(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                            const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
+                            const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles, int nwg,
                             hipStream_t stream) {
-    return launch_step_any<T>(variant, d, g, kc, rn, ctl, part, ntq, ntiles, false, stream);
+    return launch_step_any<T>(variant, d, g, kc, rn, ctl, part, ntq, ntiles, nwg, false, stream);
 }
 
 // Initial c_max and stored volume of the current buffer.
@@ -154,10 +185,12 @@ hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double
 
 #define HEXSV_INSTANTIATE(T)                                                                  \
     template hipError_t launch_step<T>(int, const KDom<T> &, const KGrid &, const KConst &,   \
-                                       const KRain &, Ctl *, Part *, int, int, hipStream_t);  \
+                                       const KRain &, Ctl *, Part *, int, int, int,           \
+                                       hipStream_t);                                          \
     template hipError_t launch_step_only<T>(int, const KDom<T> &, const KGrid &, const KConst &, \
-                                            const KRain &, Ctl *, Part *, int, int,           \
+                                            const KRain &, Ctl *, Part *, int, int, int,      \
                                             hipStream_t);                                     \
+    template int step_workgroups<T>(int, int, int);                                           \
     template hipError_t launch_prime<T>(const KDom<T> &, int64_t, const KConst &, Ctl *, Part *, \
                                         int, int, hipStream_t);                               \
     template hipError_t launch_import<T>(const double *, T *, const uint8_t *, int, int64_t,  \

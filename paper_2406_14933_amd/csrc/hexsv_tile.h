@@ -1,16 +1,21 @@
 // hexsv_tile.h — one explicit step of one TQ x TR tile of the raster.
 //
-// Staging: every thread loads the (h, v1, v2, z, theta, alpha_p) of the cells
-// it owns (coalesced rows of the tile) and one-cell halo slots along the tile
-// rim, and writes a 4-word record per staged position to LDS:
-//   {mass, w = g (z + h), v1/2, v2/2}
-// with mass = theta*h (FP64) or l*theta*h (FP32).  Interface velocities of
-// eq. fvm_2D_eq.04 are then a single add (v_i/2 + v_j/2 equals
-// (v_i + v_j)/2 exactly), and each neighbour is one 16-byte LDS read.
-//
-// Tiles whose halo lies inside the raster and holds no inactive cell take
-// the interior path (no edge codes); the others read an edge code per staged
-// position (INTERIOR, WALL, OUTFLOW).
+// A tile step has three phases, kept apart so that a persistent kernel can
+// overlap the loads of the next tile with the arithmetic of the current one:
+//   load:    every thread loads (h, v1, v2, z, theta, alpha_p) of the cells it
+//            owns (coalesced rows of the tile) and the halo slots of the tile
+//            rim it is responsible for, into registers;
+//   stage:   registers -> one 4-word LDS record per staged position,
+//              {mass, w = g (z + h), v1/2, v2/2},
+//            with mass = theta*h (FP64) or l*theta*h (FP32), plus an edge
+//            code per position when the tile touches the raster boundary or
+//            an inactive cell.  Interface velocities of eq. fvm_2D_eq.04 are
+//            then one add (v_i/2 + v_j/2 equals (v_i + v_j)/2 exactly) and a
+//            neighbour is one 16-byte LDS read;
+//   compute: per owned cell, the six edge terms of eq. fvm_2D_eq_frac.01 with
+//            the interface rules of eqs. fvm_2D_eq.05-.06, the mass update
+//            with rain at t^{n+1} and clamping (eqs. .05-1/.06-1), and the
+//            closed-form friction solve (Appendix A, miu-formula).
 //
 // FP64 evaluates the equations operation for operation as the CPU reference
 // (contraction off); FP32 regroups them (J + S in one accumulator, l folded
@@ -53,10 +58,20 @@ __device__ inline void ring_slot(int t, int &lq, int &lr) {
     else { lq = TQ + 1; lr = 1 + (t - 2 * W - TR); }
 }
 
-template <typename T>
-struct CellRegs {
-    T h, th, ap, z, m, w, vh1, vh2;
-    bool ok;
+// Where a staged position lies: a cell of the tile, a raster cell reached
+// through the halo (or a periodic wrap), or outside the raster.
+enum : uint8_t { POS_OWN = 0, POS_NEIGHBOUR = 1, POS_OUTSIDE = 2 };
+
+template <typename T, int TQ, int TR, int NT>
+struct TileRegs {
+    static constexpr int CPT = (TQ * TR) / NT;
+    static constexpr int NRING = 2 * (TQ + 2) + 2 * TR;
+    static constexpr int RPT = (NRING + NT - 1) / NT;
+    static_assert(CPT * NT == TQ * TR, "tile must be a multiple of the workgroup");
+    T h[CPT], th[CPT], ap[CPT], z[CPT], v1[CPT], v2[CPT];
+    uint8_t pos[CPT];
+    T rh[RPT], rth[RPT], rz[RPT], rv1[RPT], rv2[RPT];
+    uint8_t rpos[RPT];
 };
 
 template <typename T>
@@ -75,91 +90,141 @@ __device__ inline void put(T *p, T v) {
     else *p = v;
 }
 
-// Advance tile (tq, tr) by one step: reads state buffer `par`, writes par^1.
-// Returns the tile's partial record in thread 0.
-template <typename T, int TQ, int TR, int NT, bool NT_STORE>
-__device__ inline Part tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const KGrid &g,
-                                 const KConst &kc, int par, int tq, int tr, double dt,
-                                 double r_next, int32_t *err_flag, int32_t *err_cell) {
-    constexpr int W = TQ + 2;
-    constexpr int CPT = (TQ * TR) / NT;
-    static_assert(CPT * NT == TQ * TR, "tile must be a multiple of the workgroup");
-    constexpr int NRING = 2 * (TQ + 2) + 2 * TR;
+// Per-thread accumulators of the step's reductions (c_max and FP64 books).
+struct Acc {
+    double c, s, o, cl;
+};
+
+__device__ inline bool tile_inner(const KGrid &g, int q0, int r0, int TQ, int TR) {
+    return q0 >= 1 && q0 + TQ + 1 <= g.nq && r0 >= 1 && r0 + TR + 1 <= g.nr;
+}
+
+// ------------------------------------------------------------------ load
+
+template <typename T, int TQ, int TR, int NT>
+__device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, const KGrid &g,
+                                 int par, int tq, int tr) {
+    using Regs = TileRegs<T, TQ, TR, NT>;
     const int q0 = tq * TQ, r0 = tr * TR;
     const T *__restrict__ hin = d.st[par][0];
     const T *__restrict__ v1in = d.st[par][1];
     const T *__restrict__ v2in = d.st[par][2];
+    const bool inner = tile_inner(g, q0, r0, TQ, TR);
+#pragma unroll
+    for (int k = 0; k < Regs::CPT; ++k) {
+        const int cc = threadIdx.x + k * NT;
+        const int lr = cc / TQ, lq = cc - lr * TQ;
+        int q = q0 + lq, r = r0 + lr;
+        uint8_t pos = POS_OWN;
+        if (!(inner || (q < g.nq && r < g.nr)))
+            pos = wrap_pos(g, q, r) ? POS_NEIGHBOUR : POS_OUTSIDE;
+        R.pos[k] = pos;
+        if (pos != POS_OUTSIDE) {
+            const int64_t i = (int64_t)r * g.nq + q;
+            R.h[k] = hin[i];
+            R.th[k] = d.th[i];
+            R.ap[k] = d.ap[i];
+            R.z[k] = d.z[i];
+            R.v1[k] = v1in[i];
+            R.v2[k] = v2in[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < Regs::RPT; ++k) {
+        const int t = threadIdx.x + k * NT;
+        R.rpos[k] = POS_OUTSIDE;
+        if (t < Regs::NRING) {
+            int lq, lr;
+            ring_slot<TQ, TR>(t, lq, lr);
+            int q = q0 + lq - 1, r = r0 + lr - 1;
+            if (inner || wrap_pos(g, q, r)) {
+                R.rpos[k] = POS_NEIGHBOUR;
+                const int64_t i = (int64_t)r * g.nq + q;
+                R.rh[k] = hin[i];
+                R.rth[k] = d.th[i];
+                R.rz[k] = d.z[i];
+                R.rv1[k] = v1in[i];
+                R.rv2[k] = v2in[i];
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------- stage
+
+// Write the LDS records; returns true if a staged raster cell is inactive.
+template <typename T, int TQ, int TR, int NT>
+__device__ inline bool tile_stage(TileLDS<T, TQ, TR> &L, const TileRegs<T, TQ, TR, NT> &R,
+                                  const KGrid &g, const KConst &kc, int tq, int tr) {
+    using Regs = TileRegs<T, TQ, TR, NT>;
+    constexpr int W = TQ + 2;
+    constexpr bool F32 = sizeof(T) == 4;
+    const int q0 = tq * TQ, r0 = tr * TR;
+    const bool inner = tile_inner(g, q0, r0, TQ, TR);
+    const bool need_codes = !inner || g.has_mask;
+    const T G = (T)kc.g;
+    const T mscale = F32 ? (T)kc.a : T(1);
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < Regs::CPT; ++k) {
+        const int cc = threadIdx.x + k * NT;
+        const int lr = cc / TQ, lq = cc - lr * TQ;
+        const int s = (lr + 1) * W + (lq + 1);
+        if (R.pos[k] != POS_OUTSIDE) {
+            const T m = R.th[k] * R.h[k];
+            L.rec[s] = make_rec<T>(mscale * m, G * (R.z[k] + R.h[k]), R.v1[k] * T(0.5),
+                                   R.v2[k] * T(0.5));
+            const bool act = R.th[k] > T(0);
+            bad |= !act;
+            if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
+        } else {
+            int q = q0 + lq, r = r0 + lr;
+            wrap_pos(g, q, r);
+            L.rec[s] = make_rec<T>(T(0), T(0), T(0), T(0));
+            L.code[s] = (uint8_t)side_code(g, q, r);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < Regs::RPT; ++k) {
+        const int t = threadIdx.x + k * NT;
+        if (t >= Regs::NRING) continue;
+        int lq, lr;
+        ring_slot<TQ, TR>(t, lq, lr);
+        const int s = lr * W + lq;
+        if (R.rpos[k] != POS_OUTSIDE) {
+            const T m = R.rth[k] * R.rh[k];
+            L.rec[s] = make_rec<T>(mscale * m, G * (R.rz[k] + R.rh[k]), R.rv1[k] * T(0.5),
+                                   R.rv2[k] * T(0.5));
+            const bool act = R.rth[k] > T(0);
+            bad |= !act;
+            if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
+        } else {
+            int q = q0 + lq - 1, r = r0 + lr - 1;
+            wrap_pos(g, q, r);
+            L.rec[s] = make_rec<T>(T(0), T(0), T(0), T(0));
+            L.code[s] = (uint8_t)side_code(g, q, r);
+        }
+    }
+    return bad;
+}
+
+// --------------------------------------------------------------- compute
+
+template <typename T, int TQ, int TR, int NT, bool NT_STORE>
+__device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<T, TQ, TR, NT> &R,
+                                    bool general, const KDom<T> &d, const KGrid &g,
+                                    const KConst &kc, int par, int tq, int tr, double dt,
+                                    double r_next, Acc &acc, int32_t *err_flag,
+                                    int32_t *err_cell) {
+    using Regs = TileRegs<T, TQ, TR, NT>;
+    constexpr int W = TQ + 2;
+    constexpr bool F32 = sizeof(T) == 4;
+    const int q0 = tq * TQ, r0 = tr * TR;
     T *__restrict__ hout = d.st[par ^ 1][0];
     T *__restrict__ v1out = d.st[par ^ 1][1];
     T *__restrict__ v2out = d.st[par ^ 1][2];
     const T G = (T)kc.g;
-    constexpr bool F32 = sizeof(T) == 4;
-    // FP32 stages l*theta*h; FP64 stages theta*h
     const T mscale = F32 ? (T)kc.a : T(1);
-
-    const bool inner = q0 >= 1 && q0 + TQ + 1 <= g.nq && r0 >= 1 && r0 + TR + 1 <= g.nr;
-    const bool need_codes = !inner || g.has_mask;
-    bool bad = false;
-
-    // ---- stage owned cells (positions past the raster edge of a ragged tile
-    //      are staged like halo slots: wrapped neighbour or boundary code)
-    CellRegs<T> c[CPT];
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-        const int cc = threadIdx.x + k * NT;
-        const int lr = cc / TQ, lq = cc - lr * TQ;
-        int q = q0 + lq, r = r0 + lr;
-        const int s = (lr + 1) * W + (lq + 1);
-        c[k].ok = false;
-        if (q < g.nq && r < g.nr) {
-            const int64_t i = (int64_t)r * g.nq + q;
-            c[k].h = hin[i];
-            c[k].th = d.th[i];
-            c[k].ap = d.ap[i];
-            c[k].z = d.z[i];
-            const T v1 = v1in[i], v2 = v2in[i];
-            c[k].m = c[k].th * c[k].h;
-            c[k].w = G * (c[k].z + c[k].h);
-            c[k].vh1 = v1 * T(0.5);
-            c[k].vh2 = v2 * T(0.5);
-            L.rec[s] = make_rec<T>(mscale * c[k].m, c[k].w, c[k].vh1, c[k].vh2);
-            const bool act = c[k].th > T(0);
-            c[k].ok = act;
-            bad |= !act;
-            if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
-        } else if (wrap_pos(g, q, r)) {
-            const int64_t i = (int64_t)r * g.nq + q;
-            const T h = hin[i], th = d.th[i], z = d.z[i];
-            L.rec[s] = make_rec<T>(mscale * (th * h), G * (z + h), v1in[i] * T(0.5),
-                                   v2in[i] * T(0.5));
-            L.code[s] = th > T(0) ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
-        } else {
-            L.rec[s] = make_rec<T>(T(0), T(0), T(0), T(0));
-            L.code[s] = (uint8_t)side_code(g, q, r);
-        }
-    }
-    // ---- stage the halo ring
-    for (int t = threadIdx.x; t < NRING; t += NT) {
-        int lq, lr;
-        ring_slot<TQ, TR>(t, lq, lr);
-        int q = q0 + lq - 1, r = r0 + lr - 1;
-        const int s = lr * W + lq;
-        const bool in = inner ? true : wrap_pos(g, q, r);
-        if (in) {
-            const int64_t i = (int64_t)r * g.nq + q;
-            const T h = hin[i], th = d.th[i], z = d.z[i];
-            L.rec[s] = make_rec<T>(mscale * (th * h), G * (z + h), v1in[i] * T(0.5),
-                                   v2in[i] * T(0.5));
-            const bool act = th > T(0);
-            bad |= !act;
-            if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
-        } else {
-            L.rec[s] = make_rec<T>(T(0), T(0), T(0), T(0));
-            L.code[s] = (uint8_t)side_code(g, q, r);
-        }
-    }
-    const bool general = __syncthreads_or((!inner) || bad) != 0;
-
     const T l = (T)kc.a;
     const T half_l = (T)(0.5 * kc.a);
     const T dtT = (T)dt;
@@ -174,18 +239,21 @@ __device__ inline Part tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const 
     const T NYh[6] = {T(0), T(0.5) * S3H, T(0.5) * S3H, T(0), -T(0.5) * S3H, -T(0.5) * S3H};
     constexpr int OFF[6] = {1, W, W - 1, -1, -W, -W + 1};
 
-    double c_loc = 0.0, s_loc = 0.0, o_loc = 0.0, cl_loc = 0.0;
-
-    auto cell = [&](const CellRegs<T> &cr, int lq, int lr, auto gen_tag) {
+    auto cell = [&](int k, auto gen_tag) {
         constexpr bool GEN = decltype(gen_tag)::value;
+        const int cc = threadIdx.x + k * NT;
+        const int lr = cc / TQ, lq = cc - lr * TQ;
         const int s = (lr + 1) * W + (lq + 1);
         const int q = q0 + lq, r = r0 + lr;
-        const T mi = cr.m, wi = cr.w, vh1i = cr.vh1, vh2i = cr.vh2;
+        const T hi = R.h[k], thi = R.th[k], zi = R.z[k];
+        const T mi = thi * hi;
+        const T wi = G * (zi + hi);
+        const T vh1i = R.v1[k] * T(0.5), vh2i = R.v2[k] * T(0.5);
         const T Mi = mscale * mi;
         T Ls = T(0), A1 = T(0), A2 = T(0), S1 = T(0), S2 = T(0), Fout = T(0);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const int sn = s + OFF[k];
+        for (int e = 0; e < 6; ++e) {
+            const int sn = s + OFF[e];
             T mj, wj, vh1j, vh2j;
             int cd = CODE_INTERIOR;
             if constexpr (GEN) {
@@ -201,14 +269,14 @@ __device__ inline Part tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const 
             } else {
                 // free outflow ghost: the cell's h, v, theta; terrain extrapolated linearly
                 // through the opposite neighbour (read from memory: rim cells only)
-                T zg = cr.z;
-                if (L.code[s - OFF[k]] == CODE_INTERIOR) {
-                    int qo = q - dq_of(k), ro = r - dr_of(k);
+                T zg = zi;
+                if (L.code[s - OFF[e]] == CODE_INTERIOR) {
+                    int qo = q - dq_of(e), ro = r - dr_of(e);
                     wrap_pos(g, qo, ro);
-                    zg = T(2) * cr.z - d.z[(int64_t)ro * g.nq + qo];
+                    zg = T(2) * zi - d.z[(int64_t)ro * g.nq + qo];
                 }
                 mj = Mi;
-                wj = G * (zg + cr.h);
+                wj = G * (zg + hi);
                 vh1j = vh1i;
                 vh2j = vh2i;
             }
@@ -216,7 +284,7 @@ __device__ inline Part tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const 
             const T vb2 = vh2i + vh2j;
             if constexpr (F32) {
                 // mj holds l*theta_j*h_j
-                const T vn = (k == 0) ? vb1 : ((k == 3) ? -vb1 : vb1 * NX[k] + vb2 * NY[k]);
+                const T vn = (e == 0) ? vb1 : ((e == 3) ? -vb1 : vb1 * NX[e] + vb2 * NY[e]);
                 const bool up = vn > T(0);
                 const T F = (up ? Mi : mj) * vn;
                 Ls -= F;
@@ -225,11 +293,11 @@ __device__ inline Part tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const 
                 const T dw = wj - wi;
                 const bool take_i = up || (vn == T(0) && dw < T(0));
                 const T Q = dw * (take_i ? Mi : mj);
-                A1 -= Q * NXh[k];
-                if (k != 0 && k != 3) A2 -= Q * NYh[k];
+                A1 -= Q * NXh[e];
+                if (e != 0 && e != 3) A2 -= Q * NYh[e];
                 if (GEN && cd == CODE_OUTFLOW) Fout += F;
             } else {
-                const T vn = vb1 * NX[k] + vb2 * NY[k];
+                const T vn = vb1 * NX[e] + vb2 * NY[e];
                 const T mup = vn > T(0) ? mi : (vn < T(0) ? mj : T(0));
                 const T mhat = vn != T(0) ? mup : (wi > wj ? mi : mj);
                 const T F = l * mup * vn;
@@ -237,19 +305,18 @@ __device__ inline Part tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const 
                 A1 -= F * vb1;
                 A2 -= F * vb2;
                 const T P = half_l * (wj - wi) * mhat;
-                S1 -= P * NX[k];
-                S2 -= P * NY[k];
+                S1 -= P * NX[e];
+                S2 -= P * NY[e];
                 if (GEN && cd == CODE_OUTFLOW) Fout += F;
             }
         }
-        const T thi = cr.th, hi = cr.h;
-        const T v1i = vh1i * T(2), v2i = vh2i * T(2);
+        const T v1i = R.v1[k], v2i = R.v2[k];
         T m1, h1, g1, g2;
         if constexpr (F32) {
             const T dm = dts * Ls + dtT * rT;
             m1 = mi + dm;
             if (m1 < T(0)) {
-                cl_loc += kc.sigma * (-(double)m1);
+                acc.cl += kc.sigma * (-(double)m1);
                 m1 = T(0);
                 h1 = T(0);
             } else {
@@ -262,14 +329,14 @@ __device__ inline Part tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const 
             const T ms = mi + dts * Ls;
             m1 = ms + dtT * rT;
             if (m1 < T(0)) {
-                cl_loc += kc.sigma * (-(double)m1);
+                acc.cl += kc.sigma * (-(double)m1);
                 m1 = T(0);
             }
             h1 = p_div(m1, thi);
             g1 = mi * v1i + dts * (A1 + S1);
             g2 = mi * v2i + dts * (A2 + S2);
         }
-        const T K = cr.ap * h1 * (T(1) - thi) + thi * alpha_s;
+        const T K = R.ap[k] * h1 * (T(1) - thi) + thi * alpha_s;
         const T beta = dtT * K;
         const T Gm = p_sqrt(g1 * g1 + g2 * g2);
         const T D = m1 + p_sqrt(m1 * m1 + T(4) * beta * Gm);
@@ -280,10 +347,10 @@ __device__ inline Part tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const 
         put<T, NT_STORE>(hout + i, h1);
         put<T, NT_STORE>(v1out + i, v1n);
         put<T, NT_STORE>(v2out + i, v2n);
-        const T cc = p_sqrt(v1n * v1n + v2n * v2n) + p_sqrt(G * h1);
-        c_loc = (double)cc > c_loc ? (double)cc : c_loc;
-        s_loc += kc.sigma * ((double)thi * (double)h1);
-        if (GEN) o_loc += dt * (double)Fout;
+        const T cc2 = p_sqrt(v1n * v1n + v2n * v2n) + p_sqrt(G * h1);
+        acc.c = (double)cc2 > acc.c ? (double)cc2 : acc.c;
+        acc.s += kc.sigma * ((double)thi * (double)h1);
+        if (GEN) acc.o += dt * (double)Fout;
         if (!__builtin_isfinite(h1) || !__builtin_isfinite(v1n) || !__builtin_isfinite(v2n)) {
             if (atomicOr(err_flag, 1) == 0) *err_cell = (int32_t)i;
         }
@@ -291,20 +358,27 @@ __device__ inline Part tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const 
 
     if (general) {
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            const int cc = threadIdx.x + k * NT;
-            const int lr = cc / TQ, lq = cc - lr * TQ;
-            if (c[k].ok) cell(c[k], lq, lr, std::true_type{});
-        }
+        for (int k = 0; k < Regs::CPT; ++k)
+            if (R.pos[k] == POS_OWN && R.th[k] > T(0)) cell(k, std::true_type{});
     } else {
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            const int cc = threadIdx.x + k * NT;
-            const int lr = cc / TQ, lq = cc - lr * TQ;
-            cell(c[k], lq, lr, std::false_type{});
-        }
+        for (int k = 0; k < Regs::CPT; ++k) cell(k, std::false_type{});
     }
-    return block_reduce<NT>(c_loc, s_loc, o_loc, cl_loc);
+}
+
+// All three phases for one tile (the caller separates consecutive tiles on
+// the same LDS with a barrier).
+template <typename T, int TQ, int TR, int NT, bool NT_STORE>
+__device__ inline void tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const KGrid &g,
+                                 const KConst &kc, int par, int tq, int tr, double dt,
+                                 double r_next, Acc &acc, int32_t *err_flag, int32_t *err_cell) {
+    TileRegs<T, TQ, TR, NT> R;
+    tile_load<T, TQ, TR, NT>(R, d, g, par, tq, tr);
+    const bool bad = tile_stage<T, TQ, TR, NT>(L, R, g, kc, tq, tr);
+    const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
+    const bool general = __syncthreads_or((!inner) || bad) != 0;
+    tile_compute<T, TQ, TR, NT, NT_STORE>(L, R, general, d, g, kc, par, tq, tr, dt, r_next, acc,
+                                          err_flag, err_cell);
 }
 
 }  // namespace hexsv

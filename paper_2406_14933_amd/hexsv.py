@@ -43,7 +43,7 @@ class GridDesc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("cfl", C.c_double), ("dt_max", C.c_double),
                 ("h_dry", C.c_double), ("precision", C.c_int32), ("steps_per_graph", C.c_int32),
-                ("tile", C.c_int32), ("flags", C.c_int32)]
+                ("tile", C.c_int32), ("wg_per_cu", C.c_int32)]
 
 
 class Rain(C.Structure):
@@ -82,6 +82,18 @@ _SIGS = [
     ("hexsv_sim_timing", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64)]),
     ("hexsv_sim_time_kernel", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_double), _VP]),
+    ("hexsv_ensemble_create", C.c_int, [C.c_int32, C.POINTER(_VP), C.POINTER(Params),
+                                        C.POINTER(_VP)]),
+    ("hexsv_ensemble_destroy", None, [_VP]),
+    ("hexsv_ensemble_set_scenario", C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_double,
+                                              C.POINTER(Rain), C.c_double, _VP, _VP, _VP, _VP]),
+    ("hexsv_ensemble_run", C.c_int, [_VP, C.POINTER(C.c_double), C.c_int64, _VP]),
+    ("hexsv_ensemble_get_state", C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("hexsv_ensemble_get_books", C.c_int, [_VP, C.c_int32, C.POINTER(Books), _VP]),
+    ("hexsv_ensemble_timing", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hexsv_ensemble_info", C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     ("hexsv_tile_count", C.c_int, []),
     ("hexsv_tile_shape", C.c_int, [C.c_int32] + [C.POINTER(C.c_int32)] * 3),
 ]
@@ -191,11 +203,11 @@ class Sim:
     """Single-catchment time stepper (FP64 or FP32 state, FP64 books and dt)."""
 
     def __init__(self, grid: Grid, precision="fp32", g=9.81, cfl=0.5, dt_max=1.0, h_dry=0.0,
-                 steps_per_graph=100, tile=-1, flags=0):
+                 steps_per_graph=100, tile=-1, wg_per_cu=0):
         self.grid = grid
         prec = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[precision]
         p = Params(float(g), float(cfl), float(dt_max), float(h_dry), prec, int(steps_per_graph),
-                   int(tile), int(flags))
+                   int(tile), int(wg_per_cu))
         h = C.c_void_p()
         _check(lib().hexsv_sim_create(grid._h, C.byref(p), C.byref(h)))
         self._h = h
@@ -274,4 +286,84 @@ class Sim:
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.hexsv_sim_destroy(h)
+            self._h = None
+
+
+class Ensemble:
+    """Batch of independent catchments (uneven rasters) advanced by one persistent kernel."""
+
+    def __init__(self, grids, precision="fp32", g=9.81, cfl=0.5, dt_max=1.0, h_dry=0.0,
+                 steps_per_launch=50, tile=-1):
+        self.grids = list(grids)
+        prec = {"fp64": FP64, "fp32": FP32}[precision]
+        p = Params(float(g), float(cfl), float(dt_max), float(h_dry), prec, int(steps_per_launch),
+                   int(tile), 0)
+        arr = (C.c_void_p * len(self.grids))(*[gr._h for gr in self.grids])
+        h = C.c_void_p()
+        _check(lib().hexsv_ensemble_create(len(self.grids), arr, C.byref(p), C.byref(h)))
+        self._h = h
+        self.precision = precision
+
+    @classmethod
+    def from_scenarios(cls, scs, precision="fp32", **kw):
+        s0 = scs[0]
+        ens = cls([Grid.from_scenario(sc) for sc in scs], precision, g=s0.g, cfl=s0.cfl,
+                  dt_max=s0.dt_max, h_dry=s0.h_dry, **kw)
+        for i, sc in enumerate(scs):
+            ens.set_scenario(i, sc)
+        return ens
+
+    def set_scenario(self, s, sc, t0=0.0):
+        n = self.grids[s].cells
+        z, th, ap, h, v1, v2 = (_dev(x, n=n) for x in (sc.z, sc.theta, sc.alpha_p, sc.h0, sc.v10,
+                                                       sc.v20))
+        r = Rain(int(sc.rain_kind), float(sc.i_a), float(sc.t_a), float(sc.T_d))
+        _check(lib().hexsv_ensemble_set_scenario(self._h, int(s), _ptr(z), _ptr(th), _ptr(ap),
+                                                 float(sc.alpha_s), C.byref(r), float(t0),
+                                                 _ptr(h), _ptr(v1), _ptr(v2), _stream()))
+
+    def run(self, t_end, max_steps=0):
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t_end, np.float64),
+                                                 (len(self.grids),)))
+        _check(lib().hexsv_ensemble_run(self._h, t.ctypes.data_as(C.POINTER(C.c_double)),
+                                        int(max_steps), _stream()))
+        return self
+
+    def state(self, s):
+        n = self.grids[s].cells
+        out = {k: torch.empty(n, dtype=torch.float64, device="cuda")
+               for k in ("h", "v1", "v2", "q1", "q2")}
+        _check(lib().hexsv_ensemble_get_state(self._h, int(s), *(_ptr(out[k]) for k in
+                                                                 ("h", "v1", "v2", "q1", "q2")),
+                                              _stream()))
+        return out
+
+    def state_numpy(self, s):
+        st = self.state(s)
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in st.items()}
+
+    def books(self, s):
+        b = Books()
+        _check(lib().hexsv_ensemble_get_books(self._h, int(s), C.byref(b), _stream()))
+        return b.as_dict()
+
+    def timing(self, enable=None):
+        ms, cu, ln = C.c_double(), C.c_int64(), C.c_int64()
+        en = -1 if enable is None else int(bool(enable))
+        _check(lib().hexsv_ensemble_timing(self._h, en, C.byref(ms), C.byref(cu), C.byref(ln)))
+        return {"gpu_ms": ms.value, "cell_updates": cu.value, "launches": ln.value}
+
+    def info(self):
+        wg, tile, spl = C.c_int32(), C.c_int32(), C.c_int32()
+        cells = C.c_int64()
+        _check(lib().hexsv_ensemble_info(self._h, C.byref(wg), C.byref(tile), C.byref(cells),
+                                         C.byref(spl)))
+        return {"workgroups": wg.value, "tile": tile.value, "cells": cells.value,
+                "steps_per_launch": spl.value}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.hexsv_ensemble_destroy(h)
             self._h = None

@@ -1,0 +1,84 @@
+"""Batched ensemble (one persistent kernel over uneven rasters) against the oracle and
+against the single-catchment GPU path (needs an MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests._util import ref_run, rel_l1
+from tests.test_gpu_parity import TOL, assert_parity, hx  # noqa: F401  (fixture)
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_scenarios():
+    return [
+        synth.ensemble_member(0, nmin=40, nmax=40, t_end=90.0),
+        synth.ensemble_member(1, nmin=70, nmax=70, t_end=120.0),
+        synth.catchment(90, 77, 2.0, config=2, t_end=60.0),
+        synth.cone(R=14, rim=synth.OUTFLOW, t_end=45.0),
+        synth.kinematic_strip(nq=6, nr=48, t_end=150.0),
+        synth.ensemble_member(2, nmin=130, nmax=130, t_end=70.0).with_(nr=130),
+        synth.c1_planar(nq=64, nr=64, t_end=100.0),
+    ]
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_ensemble_fp64_matches_oracle_and_single(hx, tile):
+    scs = mixed_scenarios()
+    ens = hx.Ensemble.from_scenarios(scs, "fp64", steps_per_launch=23, tile=tile)
+    ens.run([sc.t_end for sc in scs])
+    for s, sc in enumerate(scs):
+        got = ens.state_numpy(s)
+        got["books"] = ens.books(s)
+        ref = ref_run(sc)
+        assert got["books"]["t"] == sc.t_end
+        assert got["books"]["steps"] == ref["books"]["steps"], s
+        assert_parity(got, ref, "fp64", f"ens{s}")
+        single = hx.Sim.from_scenario(sc, "fp64")
+        single.run(sc.t_end)
+        st = single.state_numpy()
+        # the same per-cell arithmetic and the same time steps: bit-identical states
+        np.testing.assert_array_equal(got["h"], st["h"])
+        np.testing.assert_array_equal(got["v1"], st["v1"])
+        np.testing.assert_array_equal(got["v2"], st["v2"])
+        assert got["books"]["stored"] == pytest.approx(single.books()["stored"], rel=1e-13)
+        assert got["books"]["residual"] <= 1e-12
+
+
+def test_ensemble_fp32_members(hx):
+    scs = [synth.ensemble_member(s, nmin=60, nmax=140, t_end=600.0) for s in range(6)]
+    ens = hx.Ensemble.from_scenarios(scs, "fp32")
+    ens.run([sc.t_end for sc in scs])
+    for s, sc in enumerate(scs):
+        got = ens.state_numpy(s)
+        ref = ref_run(sc)
+        assert_parity(got, ref, "fp32", f"ens32-{s}")
+        # FP32 state: each step rounds every cell's depth, so the FP64 books drift by
+        # about sqrt(steps) * 2^-24 relative to the stored volume
+        assert ens.books(s)["residual"] <= 1e-4
+
+
+def test_ensemble_step_limit_and_resume(hx):
+    scs = mixed_scenarios()[:3]
+    ens = hx.Ensemble.from_scenarios(scs, "fp64", steps_per_launch=10)
+    ens.run([sc.t_end for sc in scs], max_steps=17)
+    for s in range(3):
+        assert ens.books(s)["steps"] == 17
+    ens.run([sc.t_end for sc in scs])
+    for s, sc in enumerate(scs):
+        ref = ref_run(sc)
+        got = ens.state_numpy(s)
+        assert ens.books(s)["t"] == sc.t_end
+        assert_parity(got, ref, "fp64", f"resume{s}")
+
+
+def test_ensemble_timing_counts_cell_updates(hx):
+    scs = mixed_scenarios()[:4]
+    ens = hx.Ensemble.from_scenarios(scs, "fp32")
+    ens.timing(True)
+    ens.run([1e9] * 4, max_steps=40)
+    tm = ens.timing()
+    assert tm["cell_updates"] == sum(40 * int(np.count_nonzero(
+        sc.active if sc.active is not None else np.ones(sc.n))) for sc in scs)
+    assert tm["gpu_ms"] > 0 and tm["launches"] >= 1
