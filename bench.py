@@ -77,6 +77,38 @@ def time_gpu(sc, precision, steps, warmup, tile, spg):
     }
 
 
+def time_ensemble(precision, launches, ksteps, n_scen, tune):
+    """Batched ensemble of uneven catchments advanced by the persistent kernel."""
+    import torch
+
+    import synth
+    from paper_2406_14933_amd import hexsv
+    scs = synth.c3_ensemble(n_scen=n_scen)
+    ens = hexsv.Ensemble.from_scenarios(scs, precision, steps_per_launch=ksteps)
+    del scs
+    if tune:
+        ens.autotune(ksteps=max(2, ksteps // 10))
+    ens.run([1e30] * n_scen, max_steps=ksteps)  # warm-up launch
+    torch.cuda.synchronize()
+    ens.timing(True)
+    t0 = time.perf_counter()
+    ens.run([1e30] * n_scen, max_steps=launches * ksteps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = ens.timing()
+    ens.timing(False)
+    info = ens.info()
+    bpc = BYTES_PER_CELL[precision]
+    achieved = bpc * tm["cell_updates"] / (tm["gpu_ms"] * 1e-3) / 1e9
+    return {"value": tm["cell_updates"] / wall, "cells": info["cells"], "scenarios": n_scen,
+            "steps_per_scenario": launches * ksteps, "wall_s": wall,
+            "gpu_value": tm["cell_updates"] / (tm["gpu_ms"] * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_ensemble", "bytes_per_cell": bpc},
+            "info": info}
+
+
 def cpu_baseline(sc, budget_s=12.0):
     """The FP64 oracle as it stands, on the host cores, over a bounded number of steps."""
     import numpy as np
@@ -113,6 +145,10 @@ def main():
     ap.add_argument("--steps-per-graph", type=int, default=100)
     ap.add_argument("--large-steps", type=int, default=400,
                     help="steps of the 4096x4096 catchment timed beside the main workload (0: skip)")
+    ap.add_argument("--ensemble-launches", type=int, default=4,
+                    help="timed launches of the 256-scenario batched ensemble (0: skip)")
+    ap.add_argument("--ensemble-ksteps", type=int, default=25)
+    ap.add_argument("--ensemble-scenarios", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -176,6 +212,16 @@ def main():
                          "ms_per_step": lr["ms_per_step"], "roofline": lr["roofline"],
                          "books_residual": lr["residual"]}
         del big
+    if args.ensemble_launches > 0:
+        print("[bench] batched ensemble", file=sys.stderr, flush=True)
+        er = time_ensemble(args.precision, args.ensemble_launches, args.ensemble_ksteps,
+                           args.ensemble_scenarios, tune=True)
+        print(f"[bench] batched {args.precision}: {er['value']:.3e} cell-updates/s",
+              file=sys.stderr, flush=True)
+        line["batched"] = {"workload": f"ensemble-{er['scenarios']}-catchments-128..512sq",
+                           "value": er["value"], "cells": er["cells"],
+                           "steps_per_scenario": er["steps_per_scenario"],
+                           "roofline": er["roofline"], "config": er["info"]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(line), flush=True)

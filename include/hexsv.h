@@ -92,9 +92,15 @@ typedef struct {
     int32_t precision;       /* hexsv_precision */
     int32_t steps_per_graph; /* steps captured per graph replay (0: default 100) */
     int32_t tile;            /* tile variant index (< 0: tuned or default) */
-    int32_t wg_per_cu;       /* > 0: grid-stride step launch with at most this many
-                                workgroups per CU; <= 0: one workgroup per tile */
+    int32_t wg_per_cu;       /* must be 0 (one workgroup per tile) */
+    int32_t ensemble_mode;   /* ensembles only: HEXSV_ENS_* */
+    int32_t reserved;
 } hexsv_params;
+
+/* Ensemble execution modes: the persistent kernel (one workgroup sweeps one
+ * scenario, all scenarios in one launch), or batched steps (each launch moves
+ * every live scenario one step, one workgroup per tile of any scenario). */
+enum { HEXSV_ENS_AUTO = 0, HEXSV_ENS_PERSISTENT = 1, HEXSV_ENS_BATCHED = 2 };
 
 /* Rain source of the mass equation (Sec. 2.1 (c), Appendix C).
  * kind 0: r = i_a for 0 <= t <= T_d (T_d may be +inf), else 0.
@@ -205,6 +211,15 @@ int hexsv_sim_timing(hexsv_sim *sim, int32_t enable, double *gpu_ms, int64_t *st
  * so the state, time and books are unchanged afterwards. */
 int hexsv_sim_time_kernel(hexsv_sim *sim, int32_t nlaunch, double *avg_ms, hipStream_t stream);
 
+/* Autotuner: time every tile variant of the step kernel on this simulation's
+ * raster and current state (nlaunch launches each, as hexsv_sim_time_kernel,
+ * leaving state and books unchanged), switch the simulation to the fastest
+ * and, if cache_path is non-null, record the result there (JSON keyed by
+ * architecture, kernel, precision and size bucket).  hexsv_sim_create
+ * consults the file named by $HEXSV_TUNE_CACHE when params->tile < 0. */
+int hexsv_sim_autotune(hexsv_sim *sim, int32_t nlaunch, const char *cache_path,
+                       int32_t *best_tile, double *best_ms, hipStream_t stream);
+
 /* Launch/tile statistics of the step kernel: number of workgroups, tile
  * variant in use and its shape (tq x tr cells, threads). */
 int hexsv_sim_info(const hexsv_sim *sim, int32_t *workgroups, int32_t *tile, int32_t *tq,
@@ -213,12 +228,15 @@ int hexsv_sim_info(const hexsv_sim *sim, int32_t *workgroups, int32_t *tile, int
 /* ---------------------------------------------------- batched ensemble */
 
 /* An ensemble of n independent catchments on rasters of any sizes, advanced
- * together by one persistent kernel (each scenario with its own CFL time
- * step, rain and books; same g, cfl, dt_max, h_dry and precision).  One
- * workgroup sweeps one scenario at a time; workgroups take scenarios largest
- * first.  params->steps_per_graph is the number of steps each scenario
- * advances per launch (0: 50); params->tile selects the ensemble tile
- * variant (< 0: default).  The grids must outlive the ensemble. */
+ * together (each scenario with its own CFL time step, rain and books; same
+ * g, cfl, dt_max, h_dry and precision).  params->ensemble_mode picks the
+ * persistent kernel (one workgroup sweeps one scenario at a time, scenarios
+ * taken largest first, params->steps_per_graph steps per scenario per launch,
+ * 0: 50) or batched steps (a graph of steps_per_graph steps, each a tile
+ * kernel over the tiles of every live scenario plus a per-scenario close);
+ * AUTO means batched unless the tuning cache says otherwise.  params->tile
+ * selects the tile variant of the chosen mode (< 0: tuned or default).  The
+ * grids must outlive the ensemble. */
 int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids, const hexsv_params *params,
                           hexsv_ensemble **out);
 void hexsv_ensemble_destroy(hexsv_ensemble *ens);
@@ -248,8 +266,13 @@ int hexsv_ensemble_get_books(hexsv_ensemble *ens, int32_t s, hexsv_books *out, h
  * times steps taken) and number of launches. */
 int hexsv_ensemble_timing(hexsv_ensemble *ens, int32_t enable, double *gpu_ms,
                           int64_t *cell_updates, int64_t *launches);
+/* Autotuner of the ensemble: ksteps steps of every tile variant of both modes
+ * from the current state (state and books are restored afterwards); switch
+ * to the fastest mode and variant; record it in cache_path when non-null. */
+int hexsv_ensemble_autotune(hexsv_ensemble *ens, int32_t ksteps, const char *cache_path,
+                            int32_t *best_tile, double *best_ms, hipStream_t stream);
 int hexsv_ensemble_info(const hexsv_ensemble *ens, int32_t *workgroups, int32_t *tile,
-                        int64_t *cells, int32_t *steps_per_launch);
+                        int64_t *cells, int32_t *steps_per_launch, int32_t *mode);
 
 /* Number of tile variants built, and the shape of variant v. */
 int hexsv_tile_count(void);

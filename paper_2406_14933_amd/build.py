@@ -32,6 +32,7 @@ UNITS = [
     ("hexsv_common.hip", ["-ffp-contract=off"]),
     ("hexsv_capi.hip", ["-ffp-contract=off"]),
     ("hexsv_ens.hip", ["-ffp-contract=off"]),
+    ("hexsv_tune.cpp", ["-x", "hip"]),
 ]
 
 

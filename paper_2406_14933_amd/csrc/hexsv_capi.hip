@@ -202,13 +202,14 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     if (p.precision != HEXSV_FP64 && p.precision != HEXSV_FP32)
         return fail(HEXSV_EINVAL, "sim_create: precision %d unknown", p.precision);
     if (p.tile >= NUM_TILES) return fail(HEXSV_EINVAL, "sim_create: tile %d not built", p.tile);
+    if (p.wg_per_cu != 0) return fail(HEXSV_EUNSUPPORTED, "sim_create: wg_per_cu must be 0");
     hexsv_sim *s = new (std::nothrow) hexsv_sim();
     if (!s) return fail(HEXSV_ENOMEM, "sim_create: out of host memory");
     s->grid = grid;
     s->p = p;
     s->prec = p.precision;
     s->esz = p.precision == HEXSV_FP64 ? sizeof(double) : sizeof(float);
-    s->tile = p.tile >= 0 ? p.tile : DEFAULT_TILE;
+    s->tile = p.tile >= 0 ? p.tile : tuned_tile("step", p.precision, grid->n, DEFAULT_TILE);
     tile_grid(s->tile, grid->kg.nq, grid->kg.nr, &s->ntq, &s->ntiles);
     s->gsteps = p.steps_per_graph > 0 ? p.steps_per_graph : 100;
     const double a = grid->edge;
@@ -222,9 +223,14 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->rn.i_a = 0.0;
     s->rn.t_a = 0.0;
     s->rn.T_d = INFINITY;
-    s->nwg = p.precision == HEXSV_FP64 ? step_workgroups<double>(s->tile, s->ntiles, p.wg_per_cu)
-                                       : step_workgroups<float>(s->tile, s->ntiles, p.wg_per_cu);
-    const size_t nparts = (size_t)(s->nwg > PRIME_BLOCKS ? s->nwg : PRIME_BLOCKS);
+    s->nwg = s->ntiles;
+    // room for the partial records of every tile variant (the autotuner switches)
+    size_t nparts = PRIME_BLOCKS;
+    for (int v = 0; v < NUM_TILES; ++v) {
+        int nq_t, nt_t;
+        tile_grid(v, grid->kg.nq, grid->kg.nr, &nq_t, &nt_t);
+        if ((size_t)nt_t > nparts) nparts = (size_t)nt_t;
+    }
     hipError_t e = hipMalloc(&s->buf, s->esz * 9 * (size_t)grid->n);
     if (e == hipSuccess) e = hipMalloc(&s->d_ctl, sizeof(Ctl));
     if (e == hipSuccess) e = hipMalloc(&s->d_part, sizeof(Part) * nparts);
@@ -515,6 +521,44 @@ extern "C" int hexsv_sim_time_kernel(hexsv_sim *s, int32_t nlaunch, double *avg_
     c.step_limit = lim;
     HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    return HEXSV_OK;
+}
+
+static int set_tile(hexsv_sim *s, int v) {
+    s->tile = v;
+    tile_grid(v, s->grid->kg.nq, s->grid->kg.nr, &s->ntq, &s->ntiles);
+    s->nwg = s->ntiles;
+    drop_graph(s);
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_autotune(hexsv_sim *s, int32_t nlaunch, const char *cache_path,
+                                  int32_t *best_tile, double *best_ms, hipStream_t stream) {
+    if (!s || nlaunch < 1) return fail(HEXSV_EINVAL, "autotune: bad argument");
+    if (!s->state_set) return fail(HEXSV_ESTATE, "autotune: set the state first (it is left unchanged)");
+    int best = -1;
+    double bms = INFINITY;
+    std::vector<double> times(NUM_TILES, INFINITY);
+    for (int v = 0; v < NUM_TILES; ++v) {
+        set_tile(s, v);
+        double ms = 0.0;
+        int rc = hexsv_sim_time_kernel(s, 2, &ms, stream);  // warm-up
+        if (rc == HEXSV_OK) rc = hexsv_sim_time_kernel(s, nlaunch, &ms, stream);
+        if (rc != HEXSV_OK) return rc;
+        times[v] = ms;
+        if (ms < bms) {
+            bms = ms;
+            best = v;
+        }
+    }
+    set_tile(s, best);
+    if (best_tile) *best_tile = best;
+    if (best_ms) *best_ms = bms;
+    if (cache_path && *cache_path) {
+        int rc = tune_cache_store(cache_path, "step", s->prec, s->grid->n, best, bms, times.data(),
+                                  NUM_TILES);
+        if (rc) return rc;
+    }
     return HEXSV_OK;
 }
 

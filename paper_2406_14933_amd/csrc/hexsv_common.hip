@@ -3,6 +3,7 @@
 // pass after set_state, input validation and the neighbour/edge-code tables.
 #include <math.h>
 
+#include "hexsv_ensemble.h"
 #include "hexsv_internal.h"
 
 namespace hexsv {
@@ -161,6 +162,23 @@ __global__ void k_tables(KGrid g, const uint8_t *active, int32_t *nbr, uint8_t *
             code[i * 6 + k] = (uint8_t)cd;
         }
     }
+}
+
+// Per-scenario close of a batched step: workgroup s folds the records of
+// scenario s's tiles (same order as the single-catchment finalize).
+__global__ __launch_bounds__(1024) void k_ens_finalize(const EnsScen *scen, Ctl *ctl,
+                                                       const Part *part) {
+    const int s = blockIdx.x;
+    const StepTime st = step_time(&ctl[s]);
+    if (!st.live) return;
+    const Part p = reduce_parts<1024>(part + scen[s].bbase, scen[s].bntiles);
+    if (threadIdx.x == 0) close_step(&ctl[s], p, st, scen[s].kc, rain_rate(scen[s].rn, st.t_next));
+}
+
+hipError_t launch_ens_finalize(const EnsScen *scen, Ctl *ctl, const Part *part, int nscen,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(k_ens_finalize, dim3(nscen), dim3(1024), 0, stream, scen, ctl, part);
+    return hipGetLastError();
 }
 
 __global__ void k_queue_reset(uint32_t *queue) {

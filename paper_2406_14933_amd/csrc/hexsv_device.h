@@ -68,6 +68,7 @@ template <typename T>
 struct KDom {
     T *st[2][3];      // state buffers [parity][h, v1, v2]
     const T *z, *th, *ap;
+    __device__ __host__ T *buf(int p, int f) const { return st[p][f]; }
 };
 
 // ------------------------------------------------------------- helpers

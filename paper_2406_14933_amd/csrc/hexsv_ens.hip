@@ -20,6 +20,10 @@ struct hexsv_ensemble {
     int prec;
     size_t esz;
     int tile, ksteps, nwg;
+    int mode;                   // HEXSV_ENS_PERSISTENT or HEXSV_ENS_BATCHED
+    int btile, btotal;          // batched mode: tile variant and total tiles
+    int32_t *d_tile_scen;       // batched mode: scenario of every global tile
+    Part *d_bpart;              // batched mode: one record per global tile
     double dt_max;
     std::vector<const hexsv_grid *> grids;
     std::vector<EnsScen> scen;  // host copy
@@ -74,6 +78,40 @@ static void ens_drop_graph(hexsv_ensemble *e) {
     e->graph = nullptr;
 }
 
+static void ens_set_tile(hexsv_ensemble *e, int v) {
+    e->tile = v;
+    const TileShape ts = ENS_TILES[v];
+    for (int s = 0; s < e->n; ++s) {
+        EnsScen &sc = e->scen[s];
+        sc.ntq = (sc.g.nq + ts.tq - 1) / ts.tq;
+        sc.ntiles = sc.ntq * ((sc.g.nr + ts.tr - 1) / ts.tr);
+    }
+    ens_drop_graph(e);
+}
+
+// Batched-mode tiling: tile shape TILES[v] per scenario, global tile order
+// scenario by scenario; rebuilds the tile -> scenario table on the device.
+static int ens_set_btile(hexsv_ensemble *e, int v) {
+    e->btile = v;
+    int base = 0;
+    std::vector<int32_t> map;
+    for (int s = 0; s < e->n; ++s) {
+        EnsScen &sc = e->scen[s];
+        int ntq, nt;
+        tile_grid(v, sc.g.nq, sc.g.nr, &ntq, &nt);
+        sc.bntq = ntq;
+        sc.bntiles = nt;
+        sc.bbase = base;
+        base += nt;
+        map.insert(map.end(), (size_t)nt, s);
+    }
+    e->btotal = base;
+    ens_drop_graph(e);
+    if (e->d_tile_scen) HIP_TRY(hipMemcpy(e->d_tile_scen, map.data(), sizeof(int32_t) * map.size(),
+                                          hipMemcpyHostToDevice));
+    return HEXSV_OK;
+}
+
 extern "C" void hexsv_ensemble_destroy(hexsv_ensemble *e) {
     if (!e) return;
     ens_drop_graph(e);
@@ -87,6 +125,8 @@ extern "C" void hexsv_ensemble_destroy(hexsv_ensemble *e) {
     if (e->d_chk) (void)hipFree(e->d_chk);
     if (e->d_order) (void)hipFree(e->d_order);
     if (e->d_queue) (void)hipFree(e->d_queue);
+    if (e->d_tile_scen) (void)hipFree(e->d_tile_scen);
+    if (e->d_bpart) (void)hipFree(e->d_bpart);
     if (e->h_ctl) (void)hipHostFree(e->h_ctl);
     if (e->h_chk) (void)hipHostFree(e->h_chk);
     delete e;
@@ -101,7 +141,8 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         return fail(HEXSV_EDOMAIN, "ensemble_create: g, cfl, dt_max or h_dry out of range");
     if (p.precision != HEXSV_FP64 && p.precision != HEXSV_FP32)
         return fail(HEXSV_EINVAL, "ensemble_create: precision %d unknown", p.precision);
-    if (p.tile >= NUM_ENS_TILES) return fail(HEXSV_EINVAL, "ensemble_create: tile %d not built", p.tile);
+    if (p.ensemble_mode < HEXSV_ENS_AUTO || p.ensemble_mode > HEXSV_ENS_BATCHED)
+        return fail(HEXSV_EINVAL, "ensemble_create: mode %d unknown", p.ensemble_mode);
     for (int s = 0; s < n; ++s)
         if (!grids[s]) return fail(HEXSV_EINVAL, "ensemble_create: grid %d is null", s);
     hexsv_ensemble *e = new (std::nothrow) hexsv_ensemble();
@@ -109,7 +150,7 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
     e->n = n;
     e->prec = p.precision;
     e->esz = p.precision == HEXSV_FP64 ? sizeof(double) : sizeof(float);
-    e->tile = p.tile >= 0 ? p.tile : 0;
+    e->tile = 0;
     e->ksteps = p.steps_per_graph > 0 ? p.steps_per_graph : 50;
     e->dt_max = p.dt_max;
     e->grids.assign(grids, grids + n);
@@ -117,7 +158,6 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
     e->active.resize(n);
     e->ready.assign(n, 0);
     int64_t off = 0;
-    const TileShape ts = ENS_TILES[e->tile];
     for (int s = 0; s < n; ++s) {
         EnsScen &sc = e->scen[s];
         memset(&sc, 0, sizeof sc);
@@ -131,13 +171,29 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         sc.kc.area_active = sc.kc.sigma * (double)grids[s]->n_active;
         sc.rn.kind = 0;
         sc.rn.T_d = INFINITY;
-        sc.ntq = (sc.g.nq + ts.tq - 1) / ts.tq;
-        sc.ntiles = sc.ntq * ((sc.g.nr + ts.tr - 1) / ts.tr);
         e->active[s] = grids[s]->n_active;
         off += grids[s]->n;
         off = (off + 63) / 64 * 64;  // keep every scenario 256-byte aligned
     }
     e->total = off;
+    // mode and tile: explicit, else from the tuning cache (encoded as
+    // 100 * mode + tile), else batched steps with the default step tile
+    {
+        int64_t cells = 0;
+        for (int s = 0; s < n; ++s) cells += grids[s]->n_active;
+        const int tuned = tuned_tile("ensemble", p.precision, cells, 100 * HEXSV_ENS_BATCHED + DEFAULT_TILE);
+        e->mode = p.ensemble_mode == HEXSV_ENS_AUTO ? tuned / 100 : p.ensemble_mode;
+        if (e->mode != HEXSV_ENS_PERSISTENT && e->mode != HEXSV_ENS_BATCHED) e->mode = HEXSV_ENS_BATCHED;
+        int v = p.tile >= 0 ? p.tile : (p.ensemble_mode == HEXSV_ENS_AUTO ? tuned % 100 : 0);
+        if (p.tile < 0 && p.ensemble_mode == HEXSV_ENS_BATCHED) v = DEFAULT_TILE;
+        const int lim = e->mode == HEXSV_ENS_PERSISTENT ? NUM_ENS_TILES : NUM_TILES;
+        if (v < 0 || v >= lim) {
+            delete e;
+            return fail(HEXSV_EINVAL, "ensemble_create: tile %d not built for this mode", v);
+        }
+        ens_set_tile(e, e->mode == HEXSV_ENS_PERSISTENT ? v : 0);
+        ens_set_btile(e, e->mode == HEXSV_ENS_BATCHED ? v : DEFAULT_TILE);
+    }
     // largest scenarios first: they bound the length of every launch
     std::vector<int32_t> order(n);
     std::iota(order.begin(), order.end(), 0);
@@ -154,12 +210,26 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
     if (err == hipSuccess) err = hipMalloc(&e->d_chk, 4 * sizeof(int32_t));
     if (err == hipSuccess) err = hipMalloc(&e->d_order, sizeof(int32_t) * n);
     if (err == hipSuccess) err = hipMalloc(&e->d_queue, sizeof(uint32_t));
+    // records for the batched tile variant with the most tiles
+    int maxtiles = 0;
+    for (int v = 0; v < NUM_TILES; ++v) {
+        int tot = 0;
+        for (int s = 0; s < n; ++s) {
+            int ntq, nt;
+            tile_grid(v, grids[s]->kg.nq, grids[s]->kg.nr, &ntq, &nt);
+            tot += nt;
+        }
+        maxtiles = std::max(maxtiles, tot);
+    }
+    if (err == hipSuccess) err = hipMalloc(&e->d_bpart, sizeof(Part) * (size_t)maxtiles);
+    if (err == hipSuccess) err = hipMalloc(&e->d_tile_scen, sizeof(int32_t) * (size_t)maxtiles);
     if (err == hipSuccess) err = hipHostMalloc(&e->h_ctl, sizeof(Ctl) * n, hipHostMallocDefault);
     if (err == hipSuccess) err = hipHostMalloc(&e->h_chk, 4 * sizeof(int32_t), hipHostMallocDefault);
     if (err == hipSuccess) err = hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking);
     if (err == hipSuccess) err = hipMemcpy(e->d_scen, e->scen.data(), sizeof(EnsScen) * n, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(e->d_order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemset(e->buf, 0, e->esz * 9 * (size_t)e->total);
+    if (err == hipSuccess && ens_set_btile(e, e->btile) != HEXSV_OK) err = hipErrorUnknown;
     if (err != hipSuccess) {
         hexsv_ensemble_destroy(e);
         return fail(HEXSV_ENOMEM, "ensemble_create: allocation failed: %s", hipGetErrorString(err));
@@ -245,15 +315,29 @@ extern "C" int hexsv_ensemble_set_scenario(hexsv_ensemble *e, int32_t s, const d
     return HEXSV_OK;
 }
 
+// One persistent launch of ksteps steps, or ksteps batched steps.
+static hipError_t ens_launch(hexsv_ensemble *e, int mode, int v, int ksteps, hipStream_t st) {
+    if (mode == HEXSV_ENS_PERSISTENT)
+        return e->prec == HEXSV_FP64
+                   ? launch_ensemble<double>(v, ens_base<double>(e), e->d_scen, e->d_ctl, e->d_order,
+                                             e->n, e->d_queue, ksteps, e->nwg, st)
+                   : launch_ensemble<float>(v, ens_base<float>(e), e->d_scen, e->d_ctl, e->d_order,
+                                            e->n, e->d_queue, ksteps, e->nwg, st);
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < ksteps && err == hipSuccess; ++k)
+        err = e->prec == HEXSV_FP64
+                  ? launch_ens_step<double>(v, ens_base<double>(e), e->d_scen, e->d_tile_scen,
+                                            e->d_ctl, e->d_bpart, e->btotal, e->n, st)
+                  : launch_ens_step<float>(v, ens_base<float>(e), e->d_scen, e->d_tile_scen,
+                                           e->d_ctl, e->d_bpart, e->btotal, e->n, st);
+    return err;
+}
+
 static int ens_capture(hexsv_ensemble *e) {
     ens_drop_graph(e);
     HIP_TRY(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t err =
-        e->prec == HEXSV_FP64
-            ? launch_ensemble<double>(e->tile, ens_base<double>(e), e->d_scen, e->d_ctl, e->d_order,
-                                      e->n, e->d_queue, e->ksteps, e->nwg, e->cap)
-            : launch_ensemble<float>(e->tile, ens_base<float>(e), e->d_scen, e->d_ctl, e->d_order,
-                                     e->n, e->d_queue, e->ksteps, e->nwg, e->cap);
+    hipError_t err = ens_launch(e, e->mode, e->mode == HEXSV_ENS_PERSISTENT ? e->tile : e->btile,
+                                e->ksteps, e->cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(e->cap, &g);
     if (err != hipSuccess || e2 != hipSuccess) {
@@ -372,11 +456,83 @@ extern "C" int hexsv_ensemble_timing(hexsv_ensemble *e, int32_t enable, double *
     return HEXSV_OK;
 }
 
+extern "C" int hexsv_ensemble_autotune(hexsv_ensemble *e, int32_t ksteps, const char *cache_path,
+                                       int32_t *best_tile, double *best_ms, hipStream_t stream) {
+    if (!e || ksteps < 1) return fail(HEXSV_EINVAL, "ensemble_autotune: bad argument");
+    for (int s = 0; s < e->n; ++s)
+        if (!e->ready[s]) return fail(HEXSV_ESTATE, "ensemble_autotune: scenario %d has no state", s);
+    // save state and control blocks; every variant runs from the same start
+    const size_t sbytes = e->esz * 6 * (size_t)e->total;
+    void *save = nullptr;
+    HIP_TRY(hipMalloc(&save, sbytes));
+    std::vector<Ctl> c0(e->n);
+    int rc = HEXSV_OK;
+    hipError_t he = hipMemcpyAsync(save, e->buf, sbytes, hipMemcpyDeviceToDevice, stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(c0.data(), e->d_ctl, sizeof(Ctl) * e->n, hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(stream);
+    const int nvar = NUM_ENS_TILES + NUM_TILES;  // persistent variants, then batched ones
+    std::vector<double> times(nvar, INFINITY);
+    int best = -1;
+    double bms = INFINITY;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (he == hipSuccess) he = hipEventCreate(&a);
+    if (he == hipSuccess) he = hipEventCreate(&b);
+    for (int c = 0; c < nvar && he == hipSuccess; ++c) {
+        const int mode = c < NUM_ENS_TILES ? HEXSV_ENS_PERSISTENT : HEXSV_ENS_BATCHED;
+        const int v = c < NUM_ENS_TILES ? c : c - NUM_ENS_TILES;
+        if (mode == HEXSV_ENS_PERSISTENT) ens_set_tile(e, v);
+        else if (ens_set_btile(e, v) != HEXSV_OK) he = hipErrorUnknown;
+        std::vector<Ctl> cc = c0;
+        for (auto &x : cc) {
+            x.t_end = INFINITY;
+            x.step_limit = x.steps + ksteps;
+        }
+        if (he == hipSuccess) he = hipMemcpyAsync(e->d_scen, e->scen.data(), sizeof(EnsScen) * e->n, hipMemcpyHostToDevice, stream);
+        if (he == hipSuccess) he = hipMemcpyAsync(e->d_ctl, cc.data(), sizeof(Ctl) * e->n, hipMemcpyHostToDevice, stream);
+        if (he == hipSuccess) he = hipEventRecord(a, stream);
+        if (he == hipSuccess) he = ens_launch(e, mode, v, ksteps, stream);
+        if (he == hipSuccess) he = hipEventRecord(b, stream);
+        if (he == hipSuccess) he = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, a, b);
+        if (he == hipSuccess) {
+            times[c] = ms;
+            if (ms < bms) { bms = ms; best = c; }
+        }
+        if (he == hipSuccess) he = hipMemcpyAsync(e->buf, save, sbytes, hipMemcpyDeviceToDevice, stream);
+    }
+    if (he == hipSuccess) he = hipMemcpyAsync(e->d_ctl, c0.data(), sizeof(Ctl) * e->n, hipMemcpyHostToDevice, stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(stream);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipFree(save);
+    if (he != hipSuccess) return fail(HEXSV_EHIP, "ensemble_autotune: %s", hipGetErrorString(he));
+    if (best < NUM_ENS_TILES) {
+        e->mode = HEXSV_ENS_PERSISTENT;
+        ens_set_tile(e, best);
+    } else {
+        e->mode = HEXSV_ENS_BATCHED;
+        if (ens_set_btile(e, best - NUM_ENS_TILES) != HEXSV_OK) return HEXSV_EHIP;
+    }
+    HIP_TRY(hipMemcpy(e->d_scen, e->scen.data(), sizeof(EnsScen) * e->n, hipMemcpyHostToDevice));
+    ens_drop_graph(e);
+    const int code = e->mode == HEXSV_ENS_PERSISTENT ? 100 * HEXSV_ENS_PERSISTENT + e->tile
+                                                      : 100 * HEXSV_ENS_BATCHED + e->btile;
+    if (best_tile) *best_tile = code;
+    if (best_ms) *best_ms = bms;
+    int64_t cells = 0;
+    for (int s = 0; s < e->n; ++s) cells += e->active[s];
+    if (cache_path && *cache_path)
+        rc = tune_cache_store(cache_path, "ensemble", e->prec, cells, code, bms, times.data(), nvar);
+    return rc;
+}
+
 extern "C" int hexsv_ensemble_info(const hexsv_ensemble *e, int32_t *workgroups, int32_t *tile,
-                                   int64_t *cells, int32_t *steps_per_launch) {
+                                   int64_t *cells, int32_t *steps_per_launch, int32_t *mode) {
     if (!e) return fail(HEXSV_EINVAL, "ensemble_info: null ensemble");
-    if (workgroups) *workgroups = e->nwg;
-    if (tile) *tile = e->tile;
+    if (workgroups) *workgroups = e->mode == HEXSV_ENS_PERSISTENT ? e->nwg : e->btotal;
+    if (tile) *tile = e->mode == HEXSV_ENS_PERSISTENT ? e->tile : e->btile;
+    if (mode) *mode = e->mode;
     if (cells) {
         int64_t c = 0;
         for (int s = 0; s < e->n; ++s) c += e->active[s];

@@ -28,14 +28,20 @@ struct EnsScen {
     KGrid g;
     KConst kc;
     KRain rn;
-    int32_t ntq, ntiles;
+    int32_t ntq, ntiles;          // persistent mode tiling
+    int32_t bntq, bntiles, bbase;  // batched-step mode tiling and first global tile
 };
 
+// The domain of the scenario at `off`, with its buffers ordered so that
+// parity 0 is the current state (a run-time parity index into a local copy of
+// the struct would place it in scratch memory).
 template <typename T>
-__device__ inline KDom<T> dom_at(const KDom<T> &base, int64_t off) {
+__device__ inline KDom<T> dom_at(const KDom<T> &base, int64_t off, int par) {
     KDom<T> d;
-    for (int p = 0; p < 2; ++p)
-        for (int f = 0; f < 3; ++f) d.st[p][f] = base.st[p][f] + off;
+    for (int f = 0; f < 3; ++f) {
+        d.st[0][f] = (par ? base.st[1][f] : base.st[0][f]) + off;
+        d.st[1][f] = (par ? base.st[0][f] : base.st[1][f]) + off;
+    }
     d.z = base.z + off;
     d.th = base.th + off;
     d.ap = base.ap + off;
@@ -56,18 +62,21 @@ __global__ __launch_bounds__(NT) void k_ensemble(KDom<T> base, const EnsScen *__
         const int qi = s_next;
         if (qi >= nscen) break;
         const int s = order[qi];
-        const KGrid g = scen[s].g;
-        const KConst kc = scen[s].kc;
-        const KRain rn = scen[s].rn;
+        // by reference: the segment tables are indexed dynamically, and a local
+        // copy of them would live in scratch memory
+        const KGrid &g = scen[s].g;
+        const KConst &kc = scen[s].kc;
+        const KRain &rn = scen[s].rn;
         const int ntq = scen[s].ntq, ntiles = scen[s].ntiles;
-        const KDom<T> d = dom_at(base, scen[s].off);
+        const int64_t off = scen[s].off;
         if (threadIdx.x == 0) sc = ctl[s];
         __syncthreads();
         for (int step = 0; step < ksteps; ++step) {
             const StepTime st = step_time(&sc);
             if (!st.live) break;
             const double r_next = rain_rate(rn, st.t_next);
-            const int par = sc.parity;
+            const KDom<T> d = dom_at(base, off, sc.parity);
+            const int par = 0;
             Acc acc{0.0, 0.0, 0.0, 0.0};
             TileRegs<T, TQ, TR, NT> R0, R1;
             tile_load<T, TQ, TR, NT>(R0, d, g, par, 0, 0);
@@ -122,6 +131,62 @@ __global__ __launch_bounds__(NT) void k_ensemble(KDom<T> base, const EnsScen *__
     }
 }
 
+// Batched-step mode: one launch advances every live scenario by one step.
+// The tiles of all scenarios form one index space (one workgroup per tile,
+// XCD-banded); each workgroup finds its scenario, reads that scenario's dt and
+// writes one partial record; k_ens_finalize (one workgroup per scenario) then
+// closes each scenario's step.  Kernel boundaries order the steps.
+template <typename T, int TQ, int TR, int NT>
+__global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__restrict__ scen,
+                                                 const int32_t *__restrict__ tile_scen,
+                                                 Ctl *__restrict__ ctl, Part *__restrict__ part,
+                                                 int ntiles_total) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x, ntiles_total, 0);
+    if (t < 0) return;
+    const int s = tile_scen[t];
+    const StepTime st = step_time(&ctl[s]);
+    if (!st.live) return;
+    const KGrid &g = scen[s].g;  // by reference (see k_ensemble)
+    const KConst &kc = scen[s].kc;
+    const int lt = t - scen[s].bbase, ntq = scen[s].bntq;
+    const int tr = lt / ntq, tq = lt - tr * ntq;
+    const KDom<T> d = dom_at(base, scen[s].off, ctl[s].parity);
+    const double r_next = rain_rate(scen[s].rn, st.t_next);
+    __shared__ TileLDS<T, TQ, TR> L;
+    Acc acc{0.0, 0.0, 0.0, 0.0};
+    tile_step<T, TQ, TR, NT, true>(L, d, g, kc, 0, tq, tr, st.dt, r_next, acc, &ctl[s].err,
+                                   &ctl[s].err_cell);
+    const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
+    if (threadIdx.x == 0) part[t] = p;
+}
+
+template <typename T, int TQ, int TR, int NT>
+static hipError_t launch_ens_step_v(const KDom<T> &base, const EnsScen *scen,
+                                    const int32_t *tile_scen, Ctl *ctl, Part *part,
+                                    int ntiles_total, int nscen, hipStream_t stream) {
+    hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT>), dim3(ntiles_total), dim3(NT), 0, stream, base,
+                       scen, tile_scen, ctl, part, ntiles_total);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_ens_finalize(scen, ctl, part, nscen, stream);
+}
+
+template <typename T>
+hipError_t launch_ens_step(int variant, const KDom<T> &base, const EnsScen *scen,
+                           const int32_t *tile_scen, Ctl *ctl, Part *part, int ntiles_total,
+                           int nscen, hipStream_t stream) {
+    switch (variant) {
+#define HEXSV_CASE(V)                                                                          \
+    case V:                                                                                    \
+        return launch_ens_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(                    \
+            base, scen, tile_scen, ctl, part, ntiles_total, nscen, stream);
+        HEXSV_TILE_SWITCH(HEXSV_CASE)
+#undef HEXSV_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, int TQ, int TR, int NT>
 static hipError_t launch_ensemble_v(const KDom<T> &base, const EnsScen *scen, Ctl *ctl,
                                     const int32_t *order, int nscen, uint32_t *queue, int ksteps,
@@ -154,6 +219,9 @@ hipError_t launch_ensemble(int variant, const KDom<T> &base, const EnsScen *scen
 #define HEXSV_INSTANTIATE_ENSEMBLE(T)                                                         \
     template hipError_t launch_ensemble<T>(int, const KDom<T> &, const EnsScen *, Ctl *,      \
                                            const int32_t *, int, uint32_t *, int, int,        \
+                                           hipStream_t);                                      \
+    template hipError_t launch_ens_step<T>(int, const KDom<T> &, const EnsScen *,             \
+                                           const int32_t *, Ctl *, Part *, int, int,          \
                                            hipStream_t);
 
 }  // namespace hexsv

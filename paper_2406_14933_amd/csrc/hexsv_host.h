@@ -31,3 +31,13 @@ inline void hexsv_geometry(double a, double cfl, double *sigma, double *cfl_phi)
     *sigma = 6.0 * (0.5 * a * (S3H * a));
     *cfl_phi = cfl * (*sigma / (6.0 * a));
 }
+
+// ---------------------------------------------------------- tuning cache
+// A small JSON object keyed by "gfx950/<kernel>/<precision>/<size bucket>"
+// (size bucket = round(log2(cells))) whose values are {"tile": v, "us": t,
+// "all_us": [...]}.  The cache path comes from the caller or from the
+// HEXSV_TUNE_CACHE environment variable.
+int tune_cache_store(const char *path, const char *kernel, int prec, int64_t cells, int tile,
+                     double ms, const double *all_ms, int nvar);
+// Tile recorded for this key in $HEXSV_TUNE_CACHE, else `fallback`.
+int tuned_tile(const char *kernel, int prec, int64_t cells, int fallback);

@@ -19,6 +19,7 @@ constexpr TileShape TILES[] = {
     {128, 8, 256}, {128, 8, 512}, {64, 32, 256}, {64, 8, 512},
 };
 constexpr int NUM_TILES = sizeof(TILES) / sizeof(TILES[0]);
+#define HEXSV_TILE_SWITCH(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 // Tile variants of the persistent ensemble kernel (one 1024-thread workgroup
 // sweeps a whole scenario).
@@ -26,6 +27,14 @@ constexpr TileShape ENS_TILES[] = {{64, 16, 1024}, {64, 32, 1024}, {128, 16, 102
 constexpr int NUM_ENS_TILES = sizeof(ENS_TILES) / sizeof(ENS_TILES[0]);
 
 struct EnsScen;
+// Batched-step mode of the ensemble: the tile kernel over the tiles of all
+// scenarios (one workgroup each) followed by the per-scenario finalize.
+template <typename T>
+hipError_t launch_ens_step(int variant, const KDom<T> &base, const EnsScen *scen,
+                           const int32_t *tile_scen, Ctl *ctl, Part *part, int ntiles_total,
+                           int nscen, hipStream_t stream);
+hipError_t launch_ens_finalize(const EnsScen *scen, Ctl *ctl, const Part *part, int nscen,
+                               hipStream_t stream);
 // Reset the ensemble's scenario queue (a one-thread kernel, safe inside graphs).
 hipError_t launch_queue_reset(uint32_t *queue, hipStream_t stream);
 // One launch of the persistent ensemble kernel: nwg workgroups take the
@@ -43,16 +52,13 @@ inline void tile_grid(int v, int nq, int nr, int *ntq, int *ntiles) {
     *ntiles = *ntq * ((nr + s.tr - 1) / s.tr);
 }
 
-// One step: the grid-stride tile kernel (nwg workgroups, nwg records in
-// part) followed by the single-workgroup finalize kernel.
+// One step: the tile kernel (nwg == ntiles workgroups, one record per tile
+// in part) followed by the single-workgroup finalize kernel.
 template <typename T>
 hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
                        const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles, int nwg,
                        hipStream_t stream);
-// Workgroups of the grid-stride step launch: one per tile, or at most per_cu
-// per CU when per_cu > 0.
-template <typename T>
-int step_workgroups(int variant, int ntiles, int per_cu);
+
 
 // The tile kernel alone (no finalize): used to time the kernel in isolation.
 template <typename T>

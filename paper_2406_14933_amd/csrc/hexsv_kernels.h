@@ -13,10 +13,10 @@ namespace hexsv {
 // recomputes the step's dt from the control block; a step past t_end or
 // past the step limit does nothing, so a captured graph of many steps can
 // overrun the end of a run safely.
-// One explicit step over the raster: a grid-stride launch in which every
-// workgroup advances its tiles (tile_step) and writes one partial record; the
-// single-workgroup finalize kernel launched right after folds the records
-// into the control block, so every workgroup of the next step sees the new dt.
+// One explicit step over the raster, one workgroup per tile (tiles mapped to
+// XCD bands, see xcd_tile); every workgroup writes its tile's partial record
+// and the single-workgroup finalize kernel launched right after folds the
+// records into the control block, so the next step sees the new dt.
 template <typename T, int TQ, int TR, int NT>
 __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRain rn, Ctl *ctl,
                                              Part *part, int ntq, int ntiles) {
@@ -24,18 +24,13 @@ __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRai
     if (!st.live) return;
     __shared__ TileLDS<T, TQ, TR> L;
     const double r_next = rain_rate(rn, st.t_next);
-    const int par = ctl->parity;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
+    const int tr = tile / ntq, tq = tile - tr * ntq;
     Acc acc{0.0, 0.0, 0.0, 0.0};
-    for (int k = 0;; ++k) {
-        const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, k);
-        if (tile < 0) break;
-        if (k > 0) __syncthreads();
-        const int tr = tile / ntq, tq = tile - tr * ntq;
-        tile_step<T, TQ, TR, NT, true>(L, d, g, kc, par, tq, tr, st.dt, r_next, acc, &ctl->err,
-                                       &ctl->err_cell);
-    }
+    tile_step<T, TQ, TR, NT, true>(L, d, g, kc, ctl->parity, tq, tr, st.dt, r_next, acc,
+                                   &ctl->err, &ctl->err_cell);
     const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
-    if (threadIdx.x == 0) part[blockIdx.x] = p;
+    if (threadIdx.x == 0) part[tile] = p;
 }
 
 template <typename T, int TQ, int TR, int NT>
@@ -48,23 +43,6 @@ static hipError_t launch_step_v(const KDom<T> &d, const KGrid &g, const KConst &
     if (e != hipSuccess || !finalize) return e;
     return launch_finalize(ctl, part, nwg, kc, rn, stream);
 }
-
-// Workgroups of one grid-stride step launch: at most `per_cu` workgroups per
-// CU (per_cu <= 0: one tile per workgroup, which measured fastest on large
-// rasters because finished workgroups are replaced at once).
-template <typename T, int TQ, int TR, int NT>
-static int step_workgroups_v(int ntiles, int per_cu) {
-    if (per_cu <= 0) return ntiles;
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return ntiles;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return ntiles;
-    const int cap = ncu * per_cu;
-    return ntiles < cap ? ntiles : cap;
-}
-
-#define HEXSV_TILE_SWITCH(X) \
-    X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 template <typename T>
 static hipError_t launch_step_any(int variant, const KDom<T> &d, const KGrid &g,
@@ -80,19 +58,6 @@ static hipError_t launch_step_any(int variant, const KDom<T> &d, const KGrid &g,
 #undef HEXSV_CASE
         default:
             return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
-int step_workgroups(int variant, int ntiles, int per_cu) {
-    switch (variant) {
-#define HEXSV_CASE(V) \
-    case V:           \
-        return step_workgroups_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(ntiles, per_cu);
-        HEXSV_TILE_SWITCH(HEXSV_CASE)
-#undef HEXSV_CASE
-        default:
-            return ntiles;
     }
 }
 
@@ -115,7 +80,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_prime(KDom<T> d, int64_t n, KConst kc, Ctl *ctl,
                                                Part *part) {
     const int par = ctl->parity;
-    const T *h = d.st[par][0], *v1 = d.st[par][1], *v2 = d.st[par][2];
+    const T *h = d.buf(par, 0), *v1 = d.buf(par, 1), *v2 = d.buf(par, 2);
     double c = 0.0, s = 0.0;
     const T G = (T)kc.g;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -162,9 +127,9 @@ __global__ void k_export(KDom<T> d, int par, int64_t n, double *h, double *v1, d
                          double *q1, double *q2) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double hh = (double)d.st[par][0][i];
-        const double a = (double)d.st[par][1][i];
-        const double b = (double)d.st[par][2][i];
+        const double hh = (double)d.buf(par, 0)[i];
+        const double a = (double)d.buf(par, 1)[i];
+        const double b = (double)d.buf(par, 2)[i];
         const double th = (double)d.th[i];
         if (h) h[i] = hh;
         if (v1) v1[i] = a;
@@ -190,7 +155,6 @@ hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double
     template hipError_t launch_step_only<T>(int, const KDom<T> &, const KGrid &, const KConst &, \
                                             const KRain &, Ctl *, Part *, int, int, int,      \
                                             hipStream_t);                                     \
-    template int step_workgroups<T>(int, int, int);                                           \
     template hipError_t launch_prime<T>(const KDom<T> &, int64_t, const KConst &, Ctl *, Part *, \
                                         int, int, hipStream_t);                               \
     template hipError_t launch_import<T>(const double *, T *, const uint8_t *, int, int64_t,  \

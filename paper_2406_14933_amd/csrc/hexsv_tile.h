@@ -106,9 +106,9 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
                                  int par, int tq, int tr) {
     using Regs = TileRegs<T, TQ, TR, NT>;
     const int q0 = tq * TQ, r0 = tr * TR;
-    const T *__restrict__ hin = d.st[par][0];
-    const T *__restrict__ v1in = d.st[par][1];
-    const T *__restrict__ v2in = d.st[par][2];
+    const T *__restrict__ hin = d.buf(par, 0);
+    const T *__restrict__ v1in = d.buf(par, 1);
+    const T *__restrict__ v2in = d.buf(par, 2);
     const bool inner = tile_inner(g, q0, r0, TQ, TR);
 #pragma unroll
     for (int k = 0; k < Regs::CPT; ++k) {
@@ -220,9 +220,9 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
     constexpr int W = TQ + 2;
     constexpr bool F32 = sizeof(T) == 4;
     const int q0 = tq * TQ, r0 = tr * TR;
-    T *__restrict__ hout = d.st[par ^ 1][0];
-    T *__restrict__ v1out = d.st[par ^ 1][1];
-    T *__restrict__ v2out = d.st[par ^ 1][2];
+    T *__restrict__ hout = d.buf(par ^ 1, 0);
+    T *__restrict__ v1out = d.buf(par ^ 1, 1);
+    T *__restrict__ v2out = d.buf(par ^ 1, 2);
     const T G = (T)kc.g;
     const T mscale = F32 ? (T)kc.a : T(1);
     const T l = (T)kc.a;

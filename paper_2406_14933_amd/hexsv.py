@@ -43,7 +43,8 @@ class GridDesc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("cfl", C.c_double), ("dt_max", C.c_double),
                 ("h_dry", C.c_double), ("precision", C.c_int32), ("steps_per_graph", C.c_int32),
-                ("tile", C.c_int32), ("wg_per_cu", C.c_int32)]
+                ("tile", C.c_int32), ("wg_per_cu", C.c_int32),
+                ("ensemble_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Rain(C.Structure):
@@ -92,8 +93,13 @@ _SIGS = [
     ("hexsv_ensemble_get_books", C.c_int, [_VP, C.c_int32, C.POINTER(Books), _VP]),
     ("hexsv_ensemble_timing", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_double),
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hexsv_ensemble_autotune", C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_double), _VP]),
     ("hexsv_ensemble_info", C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                      C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]),
+    ("hexsv_sim_autotune", C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double), _VP]),
     ("hexsv_tile_count", C.c_int, []),
     ("hexsv_tile_shape", C.c_int, [C.c_int32] + [C.POINTER(C.c_int32)] * 3),
 ]
@@ -207,7 +213,7 @@ class Sim:
         self.grid = grid
         prec = {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[precision]
         p = Params(float(g), float(cfl), float(dt_max), float(h_dry), prec, int(steps_per_graph),
-                   int(tile), int(wg_per_cu))
+                   int(tile), int(wg_per_cu), 0, 0)
         h = C.c_void_p()
         _check(lib().hexsv_sim_create(grid._h, C.byref(p), C.byref(h)))
         self._h = h
@@ -277,6 +283,14 @@ class Sim:
         _check(lib().hexsv_sim_time_kernel(self._h, int(nlaunch), C.byref(ms), _stream()))
         return ms.value
 
+    def autotune(self, nlaunch=30, cache_path=None):
+        """Pick the fastest tile variant for this raster (state and books are unchanged)."""
+        best, ms = C.c_int32(), C.c_double()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().hexsv_sim_autotune(self._h, int(nlaunch), path, C.byref(best), C.byref(ms),
+                                        _stream()))
+        return best.value, ms.value
+
     def info(self):
         vals = [C.c_int32() for _ in range(5)]
         _check(lib().hexsv_sim_info(self._h, *(C.byref(v) for v in vals)))
@@ -292,12 +306,14 @@ class Sim:
 class Ensemble:
     """Batch of independent catchments (uneven rasters) advanced by one persistent kernel."""
 
+    MODES = {"auto": 0, "persistent": 1, "batched": 2}
+
     def __init__(self, grids, precision="fp32", g=9.81, cfl=0.5, dt_max=1.0, h_dry=0.0,
-                 steps_per_launch=50, tile=-1):
+                 steps_per_launch=50, tile=-1, mode="auto"):
         self.grids = list(grids)
         prec = {"fp64": FP64, "fp32": FP32}[precision]
         p = Params(float(g), float(cfl), float(dt_max), float(h_dry), prec, int(steps_per_launch),
-                   int(tile), 0)
+                   int(tile), 0, self.MODES[mode], 0)
         arr = (C.c_void_p * len(self.grids))(*[gr._h for gr in self.grids])
         h = C.c_void_p()
         _check(lib().hexsv_ensemble_create(len(self.grids), arr, C.byref(p), C.byref(h)))
@@ -354,13 +370,22 @@ class Ensemble:
         _check(lib().hexsv_ensemble_timing(self._h, en, C.byref(ms), C.byref(cu), C.byref(ln)))
         return {"gpu_ms": ms.value, "cell_updates": cu.value, "launches": ln.value}
 
+    def autotune(self, ksteps=5, cache_path=None):
+        """Pick the fastest ensemble tile variant (state and books are restored)."""
+        best, ms = C.c_int32(), C.c_double()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().hexsv_ensemble_autotune(self._h, int(ksteps), path, C.byref(best),
+                                             C.byref(ms), _stream()))
+        return best.value, ms.value
+
     def info(self):
-        wg, tile, spl = C.c_int32(), C.c_int32(), C.c_int32()
+        wg, tile, spl, mode = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         cells = C.c_int64()
         _check(lib().hexsv_ensemble_info(self._h, C.byref(wg), C.byref(tile), C.byref(cells),
-                                         C.byref(spl)))
+                                         C.byref(spl), C.byref(mode)))
         return {"workgroups": wg.value, "tile": tile.value, "cells": cells.value,
-                "steps_per_launch": spl.value}
+                "steps_per_launch": spl.value,
+                "mode": {1: "persistent", 2: "batched"}.get(mode.value, "?")}
 
     def __del__(self):
         h = getattr(self, "_h", None)

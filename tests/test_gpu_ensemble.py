@@ -23,10 +23,12 @@ def mixed_scenarios():
     ]
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2])
-def test_ensemble_fp64_matches_oracle_and_single(hx, tile):
+@pytest.mark.parametrize("mode,tile", [("persistent", 0), ("persistent", 1), ("persistent", 2),
+                                       ("batched", 2), ("batched", 0), ("batched", 5)])
+def test_ensemble_fp64_matches_oracle_and_single(hx, mode, tile):
     scs = mixed_scenarios()
-    ens = hx.Ensemble.from_scenarios(scs, "fp64", steps_per_launch=23, tile=tile)
+    ens = hx.Ensemble.from_scenarios(scs, "fp64", steps_per_launch=23, tile=tile, mode=mode)
+    assert ens.info()["mode"] == mode
     ens.run([sc.t_end for sc in scs])
     for s, sc in enumerate(scs):
         got = ens.state_numpy(s)
@@ -42,13 +44,17 @@ def test_ensemble_fp64_matches_oracle_and_single(hx, tile):
         np.testing.assert_array_equal(got["h"], st["h"])
         np.testing.assert_array_equal(got["v1"], st["v1"])
         np.testing.assert_array_equal(got["v2"], st["v2"])
+        if mode == "batched" and tile == 2:
+            # same tiles and the same reduction tree as the single-catchment path
+            assert got["books"]["stored"] == single.books()["stored"]
         assert got["books"]["stored"] == pytest.approx(single.books()["stored"], rel=1e-13)
         assert got["books"]["residual"] <= 1e-12
 
 
-def test_ensemble_fp32_members(hx):
+@pytest.mark.parametrize("mode", ["persistent", "batched"])
+def test_ensemble_fp32_members(hx, mode):
     scs = [synth.ensemble_member(s, nmin=60, nmax=140, t_end=600.0) for s in range(6)]
-    ens = hx.Ensemble.from_scenarios(scs, "fp32")
+    ens = hx.Ensemble.from_scenarios(scs, "fp32", mode=mode)
     ens.run([sc.t_end for sc in scs])
     for s, sc in enumerate(scs):
         got = ens.state_numpy(s)
@@ -59,9 +65,10 @@ def test_ensemble_fp32_members(hx):
         assert ens.books(s)["residual"] <= 1e-4
 
 
-def test_ensemble_step_limit_and_resume(hx):
+@pytest.mark.parametrize("mode", ["persistent", "batched"])
+def test_ensemble_step_limit_and_resume(hx, mode):
     scs = mixed_scenarios()[:3]
-    ens = hx.Ensemble.from_scenarios(scs, "fp64", steps_per_launch=10)
+    ens = hx.Ensemble.from_scenarios(scs, "fp64", steps_per_launch=10, mode=mode)
     ens.run([sc.t_end for sc in scs], max_steps=17)
     for s in range(3):
         assert ens.books(s)["steps"] == 17
@@ -82,3 +89,41 @@ def test_ensemble_timing_counts_cell_updates(hx):
     assert tm["cell_updates"] == sum(40 * int(np.count_nonzero(
         sc.active if sc.active is not None else np.ones(sc.n))) for sc in scs)
     assert tm["gpu_ms"] > 0 and tm["launches"] >= 1
+
+
+def test_ensemble_autotune_restores_state(hx, tmp_path):
+    scs = mixed_scenarios()
+    ref = hx.Ensemble.from_scenarios(scs, "fp64", tile=0)
+    ref.run([sc.t_end for sc in scs])
+    ens = hx.Ensemble.from_scenarios(scs, "fp64")
+    cache = str(tmp_path / "tune.json")
+    best, ms = ens.autotune(ksteps=4, cache_path=cache)
+    assert best // 100 in (1, 2) and ms > 0
+    info = ens.info()
+    assert info["tile"] == best % 100
+    assert info["mode"] == {1: "persistent", 2: "batched"}[best // 100]
+    ens.run([sc.t_end for sc in scs])
+    for s in range(len(scs)):
+        np.testing.assert_array_equal(ens.state_numpy(s)["h"], ref.state_numpy(s)["h"])
+        assert ens.books(s)["steps"] == ref.books(s)["steps"]
+    assert "gfx950/ensemble/fp64" in open(cache).read()
+
+
+def test_sim_autotune_and_cache(hx, tmp_path, monkeypatch):
+    sc = synth.catchment(200, 150, 2.0, config=2, t_end=30.0)
+    sim = hx.Sim.from_scenario(sc, "fp64")
+    sim.run(10.0)
+    before = sim.state_numpy()
+    cache = str(tmp_path / "tune.json")
+    best, ms = sim.autotune(nlaunch=5, cache_path=cache)
+    assert 0 <= best < len(hx.tile_shapes()) and ms > 0
+    after = sim.state_numpy()
+    np.testing.assert_array_equal(before["h"], after["h"])
+    assert sim.info()["tile"] == best
+    sim.run(sc.t_end)
+    monkeypatch.setenv("HEXSV_TUNE_CACHE", cache)
+    sim2 = hx.Sim.from_scenario(sc, "fp64")
+    assert sim2.info()["tile"] == best
+    sim2.run(10.0)
+    sim2.run(sc.t_end)
+    np.testing.assert_array_equal(sim2.state_numpy()["h"], sim.state_numpy()["h"])
