@@ -1,0 +1,172 @@
+"""Pins of the surrogate oracle (hex convolution, network gradients, bf16, Adam)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import surrogate as so
+
+SQ3 = math.sqrt(3.0)
+
+
+def _brute_conv(nq, nr, x, W, b):
+    """Hex convolution from hex-centre geometry: neighbour in direction k is the centre at
+    distance sqrt(3)*a and angle 60k degrees; missing neighbours contribute nothing."""
+    xs, ys = synth.centres(nq, nr, 1.0)
+    n = nq * nr
+    cout = W.shape[0]
+    y = np.zeros((cout, n))
+    for i in range(n):
+        taps = [i] + [-1] * 6
+        for j in range(n):
+            dx, dy = xs[j] - xs[i], ys[j] - ys[i]
+            if abs(math.hypot(dx, dy) - SQ3) < 1e-9:
+                k = int(round(math.degrees(math.atan2(dy, dx)) % 360 / 60.0)) % 6
+                taps[1 + k] = j
+        for o in range(cout):
+            acc = b[o]
+            for t, j in enumerate(taps):
+                if j >= 0:
+                    acc += float(W[o, :, t] @ x[:, j])
+            y[o, i] = acc
+    return y
+
+
+def test_hexconv_matches_geometry():
+    rng = np.random.default_rng(0)
+    nq, nr, cin, cout = 5, 4, 3, 2
+    G = oracle.grid(nq, nr, 1.0)
+    x = rng.normal(size=(cin, nq * nr))
+    W = rng.normal(size=(cout, cin, 7))
+    b = rng.normal(size=cout)
+    np.testing.assert_allclose(oracle.hexconv_fwd(G, x, W, b), _brute_conv(nq, nr, x, W, b),
+                               rtol=1e-13, atol=1e-13)
+
+
+def test_hexconv_single_tap_is_a_matmul():
+    rng = np.random.default_rng(1)
+    G = oracle.grid(6, 5, 1.0)
+    x = rng.normal(size=(4, 30))
+    W = np.zeros((3, 4, 7))
+    W[:, :, 0] = rng.normal(size=(3, 4))
+    b = rng.normal(size=3)
+    np.testing.assert_allclose(oracle.hexconv_fwd(G, x, W, b), W[:, :, 0] @ x + b[:, None],
+                               rtol=1e-13, atol=1e-13)
+
+
+def test_hexconv_backward_is_the_adjoint():
+    rng = np.random.default_rng(2)
+    G = oracle.grid(7, 6, 1.0)
+    n = 42
+    x = rng.normal(size=(5, n))
+    W = rng.normal(size=(4, 5, 7))
+    dy = rng.normal(size=(4, n))
+    zero = np.zeros(4)
+    y = oracle.hexconv_fwd(G, x, W, zero)
+    dx, dW, db = oracle.hexconv_bwd(G, x, W, dy)
+    # <dy, A x> == <A^T dy, x>
+    assert (dy * y).sum() == pytest.approx((dx * x).sum(), rel=1e-12)
+    # y is linear in W: the directional derivative is exact
+    D = rng.normal(size=W.shape)
+    y2 = oracle.hexconv_fwd(G, x, W + 0.5 * D, zero)
+    assert ((dy * (y2 - y)).sum()) == pytest.approx(0.5 * (dW * D).sum(), rel=1e-11)
+    np.testing.assert_allclose(db, dy.sum(axis=1), rtol=1e-13)
+
+
+def test_network_gradient_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    G = oracle.grid(6, 5, 1.0)
+    layers, ch = 3, 4
+    p = so.init_params(7, layers, ch, out_scale=1.0).astype(np.float64)
+    p += rng.normal(scale=0.05, size=p.shape)
+    xs = [rng.normal(size=(30, so.FEATURES)) for _ in range(2)]
+    ts = [rng.normal(size=(30, so.OUTPUTS)) for _ in range(2)]
+
+    def smooth_loss(q):
+        # squared error keeps the check smooth: same backward path with dy = 2 diff / count
+        tot = 0.0
+        for x0, t in zip(xs, ts):
+            out, _, _ = so.forward(G, q, x0, layers, ch, bf16=False)
+            tot += ((out - t) ** 2).sum()
+        return tot / (2 * 30 * so.OUTPUTS)
+
+    def smooth_grad(q):
+        g = np.zeros_like(q)
+        count = 2 * 30 * so.OUTPUTS
+        for x0, t in zip(xs, ts):
+            out, acts, params = so.forward(G, q, x0, layers, ch, bf16=False)
+            dy = 2 * (out - t) / count
+            gl = []
+            for li in range(len(params) - 1, -1, -1):
+                dx, dW, db = so._conv_bwd(G, acts[li], params[li][0], dy)
+                gl.append((dW, db))
+                if li > 0:
+                    dy = dx * (acts[li] > 0)
+            g += so.flatten(gl[::-1])
+        return g
+
+    g = smooth_grad(p)
+    idx = rng.choice(len(p), 40, replace=False)
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = 1e-6
+        fd = (smooth_loss(p + e) - smooth_loss(p - e)) / 2e-6
+        assert fd == pytest.approx(g[i], rel=1e-5, abs=1e-9)
+
+
+def test_l1_loss_gradient_sign_structure():
+    """The L1 gradient is the squared-error path with dy = sign(diff)/count."""
+    rng = np.random.default_rng(4)
+    G = oracle.grid(5, 4, 1.0)
+    p = so.init_params(1, 2, 3, out_scale=1.0).astype(np.float64)
+    x = rng.normal(size=(20, so.FEATURES))
+    t = rng.normal(size=(20, so.OUTPUTS))
+    loss, g = so.loss_and_grad(G, p, [x], [t], 2, 3, bf16=False)
+    out, _, _ = so.forward(G, p, x, 2, 3, bf16=False)
+    assert loss == pytest.approx(np.abs(out - t).mean(), rel=1e-14)
+    # directional derivative of a piecewise-linear loss away from kinks
+    d = rng.normal(size=p.shape)
+    eps = 1e-7
+    l2, _ = so.loss_and_grad(G, p + eps * d, [x], [t], 2, 3, bf16=False)
+    assert (l2 - loss) / eps == pytest.approx(g @ d, rel=1e-4)
+
+
+def test_bf16_rounding_matches_torch():
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -2.7182818, 3.1e-5, 65504.0, 1e-40,
+                     0.0, -0.0, 1.7e38], np.float32)
+    ours = so.bf16_round(vals)
+    ref = torch.tensor(vals).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(ours, ref)
+    assert ours[1] == 1.0 and ours[2] == 1 + 2 ** -6  # ties to even
+    rng = np.random.default_rng(5)
+    r = rng.normal(size=10000).astype(np.float32) * 10.0 ** rng.integers(-8, 8, 10000)
+    np.testing.assert_array_equal(so.bf16_round(r),
+                                  torch.tensor(r).to(torch.bfloat16).to(torch.float64).numpy())
+
+
+def test_adam_matches_torch():
+    rng = np.random.default_rng(6)
+    p0 = rng.normal(size=50)
+    t = torch.tensor(p0.copy(), requires_grad=True)
+    opt = torch.optim.Adam([t], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    for step in range(1, 6):
+        g = rng.normal(size=50)
+        t.grad = torch.tensor(g.copy())
+        opt.step()
+        p, m, v = so.adam_update(p, m, v, g, step, 1e-2)
+    np.testing.assert_allclose(p, t.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_param_layout():
+    shapes = so.layer_shapes(4, 32)
+    assert shapes == [(6, 32), (32, 32), (32, 32), (32, 3)]
+    n = so.num_params(4, 32)
+    assert n == 6 * 32 * 7 + 32 + 2 * (32 * 32 * 7 + 32) + 32 * 3 * 7 + 3
+    p = so.init_params(0)
+    assert p.shape == (n,) and p.dtype == np.float32
+    back = so.flatten(so.unflatten(p))
+    np.testing.assert_array_equal(back, p.astype(np.float64))
