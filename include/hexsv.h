@@ -129,6 +129,7 @@ typedef struct {
 typedef struct hexsv_grid hexsv_grid;
 typedef struct hexsv_sim hexsv_sim;
 typedef struct hexsv_ensemble hexsv_ensemble;
+typedef struct hexsv_surrogate hexsv_surrogate;
 
 /* Library version and the thread-local message of the last failed call. */
 const char *hexsv_version(void);
@@ -273,6 +274,44 @@ int hexsv_ensemble_autotune(hexsv_ensemble *ens, int32_t ksteps, const char *cac
                             int32_t *best_tile, double *best_ms, hipStream_t stream);
 int hexsv_ensemble_info(const hexsv_ensemble *ens, int32_t *workgroups, int32_t *tile,
                         int64_t *cells, int32_t *steps_per_launch, int32_t *mode);
+
+/* ------------------------------------------------------ learned surrogate */
+
+/* A hex-convolution residual network that predicts the change of the state
+ * over a window of k solver steps (not part of the paper's method; the
+ * solver stays its fallback and judge).  Layers: hex_conv(6 -> C), ReLU,
+ * (layers - 2) x [hex_conv(C -> C), ReLU], hex_conv(C -> 3), where
+ * hex_conv(x)[i][o] = b[o] + sum_{t<7, c} W[o][c][t] x[nbr_t(i)][c], tap 0
+ * the cell, tap 1+k its neighbour in direction k, zero outside the raster.
+ * Operands are bfloat16 with FP32 accumulation (MFMA); parameters are an FP32
+ * master vector laid out per layer as W[o][c][t] then b[o].  Inputs are 6
+ * FP32 features per cell, outputs 4 FP32 per cell (3 used), for a batch of
+ * samples on one nq x nr raster (cell (b, r, q) at b*nq*nr + r*nq + q).
+ * Only C = 32 is built (EUNSUPPORTED otherwise); 2 <= layers <= 16. */
+int hexsv_surrogate_create(int32_t layers, int32_t channels, hexsv_surrogate **out);
+void hexsv_surrogate_destroy(hexsv_surrogate *sur);
+int64_t hexsv_surrogate_num_params(const hexsv_surrogate *sur);
+/* Copy parameters in (device FP32, n == num_params; resets Adam) or out. */
+int hexsv_surrogate_set_params(hexsv_surrogate *sur, const float *d_params, int64_t n,
+                               hipStream_t stream);
+int hexsv_surrogate_get_params(const hexsv_surrogate *sur, float *d_params, int64_t n,
+                               hipStream_t stream);
+/* Normalisation scales used when the surrogate advances a simulation:
+ * {H, Q, Z, dH, dQ} (depth, discharge, terrain, output depth and discharge). */
+int hexsv_surrogate_set_scales(hexsv_surrogate *sur, const float *scales, int32_t n);
+int hexsv_surrogate_get_scales(const hexsv_surrogate *sur, float *scales, int32_t n);
+/* Batched forward: d_features (batch*nq*nr x 6) -> d_out (batch*nq*nr x 4). */
+int hexsv_surrogate_forward(hexsv_surrogate *sur, int32_t batch, int32_t nq, int32_t nr,
+                            const float *d_features, float *d_out, hipStream_t stream);
+/* Mean L1 loss against d_target (batch*nq*nr x 3) and its parameter gradient
+ * (d_grad nullable, num_params floats); synchronises `stream`. */
+int hexsv_surrogate_gradient(hexsv_surrogate *sur, int32_t batch, int32_t nq, int32_t nr,
+                             const float *d_features, const float *d_target, float *d_grad,
+                             double *loss, hipStream_t stream);
+/* gradient + one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at rate lr. */
+int hexsv_surrogate_train_step(hexsv_surrogate *sur, int32_t batch, int32_t nq, int32_t nr,
+                               const float *d_features, const float *d_target, float lr,
+                               double *loss, hipStream_t stream);
 
 /* Number of tile variants built, and the shape of variant v. */
 int hexsv_tile_count(void);

@@ -33,6 +33,8 @@ UNITS = [
     ("hexsv_capi.hip", ["-ffp-contract=off"]),
     ("hexsv_ens.hip", ["-ffp-contract=off"]),
     ("hexsv_tune.cpp", ["-x", "hip"]),
+    ("hexsv_nn.hip", ["-ffp-contract=fast"]),
+    ("hexsv_sur.hip", ["-ffp-contract=off"]),
 ]
 
 

@@ -1,0 +1,37 @@
+// hexsv_nn.h — launchers of the surrogate's kernels (hexsv_nn.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hexsv {
+namespace nn {
+
+enum { EPI_RELU = 0, EPI_LIN = 1, EPI_MASK = 2 };
+constexpr int OUT_STRIDE = 4;  // floats per cell of the network output (3 used)
+
+// Workgroups (tiles of 64 x 4 cells) of one conv launch over a batch.
+int conv_tiles(int nq, int nr, int batch);
+
+// Hex convolution of channels-last bf16 x (cinp channels) with the MFMA
+// weight layout wm[t][coutp][cinp]; epilogue per EPI_* (see hexsv_nn.hip).
+// Built for (cinp, coutp, epi) in {(8,32,RELU), (32,32,RELU), (32,16,LIN),
+// (16,32,MASK), (32,32,MASK)}.
+hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf16 *wm,
+                       const float *bias, void *out, const __bf16 *mask, int nq, int nr,
+                       int batch, int cout_real, hipStream_t st);
+// Per-tile weight-gradient partials (7*coutp*cinp + coutp floats per tile).
+hipError_t launch_wgrad(int cinp, int coutp, const __bf16 *x, const __bf16 *dy, float *part,
+                        int nq, int nr, int batch, hipStream_t st);
+hipError_t launch_wgrad_reduce(const float *part, int ntiles, int cinp, int coutp, int cin,
+                               int cout, float *grad, hipStream_t st);
+hipError_t launch_prepare_weights(const float *p, int cin, int cout, int cinp, int coutp,
+                                  __bf16 *wm, __bf16 *wt, float *bias, hipStream_t st);
+hipError_t launch_adam(float *p, float *m, float *v, const float *g, int64_t n, float lr,
+                       int step, hipStream_t st);
+hipError_t launch_l1_loss(const float *pred, const float *target, int64_t ncell, double inv_count,
+                          __bf16 *dy, double *part, int nparts, hipStream_t st);
+hipError_t launch_pack_features(const float *f, int64_t ncell, __bf16 *x, hipStream_t st);
+
+}  // namespace nn
+}  // namespace hexsv

@@ -1,0 +1,452 @@
+// hexsv_nn.hip — kernels of the learned hex-convolution surrogate: BF16 MFMA
+// forward / data-gradient / weight-gradient hex convolutions with FP32
+// accumulation, the L1 loss, Adam, and the weight-layout preparation.
+//
+// Hex convolution on an nq x nr raster (per sample of a batch):
+//   y[i][o] = b[o] + sum_{t<7, c} W[o][c][t] * x[nbr_t(i)][c]
+// tap 0 is the cell, tap 1+k its neighbour in direction k, zero outside the
+// raster.  Activations are channels-last bfloat16 (x[cell][c], C = 8 or 32).
+//
+// MFMA mapping (v_mfma_f32_16x16x32_bf16): the output block is 16 output
+// channels x 16 cells, A = weights (16 channels x 32 K), B = gathered
+// activations (32 K x 16 cells), K = the 32 input channels of one tap (or
+// four taps of 8 channels for the 8-channel input layer).  A lane holds the
+// 8 consecutive K values of its row/column, i.e. 16 contiguous bytes of a
+// weight row or of one neighbour's channel vector in LDS.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hexsv_nn.h"
+
+namespace hexsv {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TQ = 64, TR = 4, NT = 256;  // 256 cells per workgroup, one row per wave
+constexpr int SW = TQ + 2, SH = TR + 2, NSLOT = SW * SH;
+constexpr int OFFS[7] = {0, 1, SW, SW - 1, -1, -SW, -SW + 1};  // tap -> LDS slot offset
+constexpr int OPP[7] = {0, 4, 5, 6, 1, 2, 3};                   // tap of the opposite direction
+
+__device__ inline int tile_of(int tile, int ntq, int ntr, int &b, int &q0, int &r0) {
+    const int per = ntq * ntr;
+    b = tile / per;
+    const int lt = tile - b * per;
+    const int tr = lt / ntq;
+    q0 = (lt - tr * ntq) * TQ;
+    r0 = tr * TR;
+    return lt;
+}
+
+// Stage the (TQ+2) x (TR+2) halo of channels-last bf16 activations of one
+// sample into LDS as 16-byte chunks; positions outside the raster are zero.
+template <int C>
+__device__ inline void stage_act(uint4 *lds, const __bf16 *__restrict__ x, int nq, int nr,
+                                 int64_t sample_off, int q0, int r0) {
+    constexpr int CH = C / 8;  // 16-byte chunks per cell
+    for (int e = threadIdx.x; e < NSLOT * CH; e += NT) {
+        const int s = e / CH, ch = e - s * CH;
+        const int lr = s / SW, lq = s - lr * SW;
+        const int q = q0 + lq - 1, r = r0 + lr - 1;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (q >= 0 && q < nq && r >= 0 && r < nr) {
+            const int64_t i = sample_off + (int64_t)r * nq + q;
+            v = reinterpret_cast<const uint4 *>(x + i * C)[ch];
+        }
+        lds[e] = v;
+    }
+}
+
+// ---------------------------------------------------------------- conv
+
+// out[i][co] for the tile; EPI selects the epilogue:
+//   EPI_RELU:  bf16 out = max(acc + b, 0)           (hidden layers, forward)
+//   EPI_LIN:   f32 out[i][co < cout_real] = acc + b  (last layer, forward)
+//   EPI_MASK:  bf16 out = acc * (mask[i][co] > 0)    (data gradient through ReLU)
+template <int CIN, int COUT, int EPI>
+__global__ __launch_bounds__(NT) void k_hexconv(const __bf16 *__restrict__ x,
+                                                const __bf16 *__restrict__ wm,
+                                                const float *__restrict__ bias, void *out,
+                                                const __bf16 *__restrict__ mask, int nq, int nr,
+                                                int ntiles_total, int cout_real) {
+    constexpr int CH = CIN / 8;
+    constexpr int MB = COUT / 16;                 // output-channel blocks
+    constexpr int TPK = 32 / CIN;                 // taps per K step of 32
+    constexpr int KSTEPS = (7 + TPK - 1) / TPK;
+    __shared__ uint4 lds[NSLOT * CH];
+    const int ntq = (nq + TQ - 1) / TQ, ntr = (nr + TR - 1) / TR;
+    const int tile = blockIdx.x;
+    if (tile >= ntiles_total) return;
+    int b, q0, r0;
+    tile_of(tile, ntq, ntr, b, q0, r0);
+    const int64_t soff = (int64_t)b * nq * nr;
+    stage_act<CIN>(lds, x, nq, nr, soff, q0, r0);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;  // wave w: tile row w
+    const int g = lane >> 4, l16 = lane & 15;
+    f32x4 acc[MB][4];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        // tap and channel offset of this lane's 8 K values
+        const int tap = ks * TPK + g / CH;
+        const int c0 = (g % CH) * 8;
+        bf16x8 a[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            if (tap < 7) {
+                a[m] = *reinterpret_cast<const bf16x8 *>(wm + ((int64_t)(tap * COUT + m * 16 + l16)) * CIN + c0);
+            } else {
+                a[m] = bf16x8{};
+            }
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int lq = n * 16 + l16;             // cell column in the tile
+            const int s = (w + 1) * SW + (lq + 1);   // its staged slot
+            bf16x8 bv = bf16x8{};
+            if (tap < 7) {
+                const uint4 raw = lds[(s + OFFS[tap]) * CH + c0 / 8];
+                bv = *reinterpret_cast<const bf16x8 *>(&raw);
+            }
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bv, acc[m][n], 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds channels co = m*16 + 4g + j of cell n*16 + l16
+    const int r = r0 + w;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const int q = q0 + n * 16 + l16;
+        if (q >= nq || r >= nr) continue;
+        const int64_t i = soff + (int64_t)r * nq + q;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            const int co = m * 16 + 4 * g;
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = acc[m][n][j];
+            if constexpr (EPI == EPI_RELU || EPI == EPI_LIN) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] += bias[co + j];
+            }
+            if constexpr (EPI == EPI_LIN) {
+                float *o = reinterpret_cast<float *>(out) + i * OUT_STRIDE;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (co + j < cout_real) o[co + j] = v[j];
+            } else {
+                if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = v[j] > 0.f ? v[j] : 0.f;
+                }
+                if constexpr (EPI == EPI_MASK) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (!((float)mask[i * COUT + co + j] > 0.f)) v[j] = 0.f;
+                }
+                __bf16 *o = reinterpret_cast<__bf16 *>(out) + i * COUT + co;
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                bf16x4 pk;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) pk[j] = (__bf16)v[j];
+                *reinterpret_cast<bf16x4 *>(o) = pk;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ weight grad
+
+// Per-tile partial dW[t][co][ci] = sum_cells dy[cell][co] x[nbr_t(cell)][ci] and
+// db[co] = sum_cells dy[cell][co], in FP32; wave w handles taps w and w+4.
+// A = dy^T (16 channels x 32 cells), B = x_t (32 cells x 16 channels).
+template <int CIN, int COUT>
+__global__ __launch_bounds__(NT) void k_hexconv_wgrad(const __bf16 *__restrict__ x,
+                                                      const __bf16 *__restrict__ dy,
+                                                      float *__restrict__ part, int nq, int nr,
+                                                      int ntiles_total) {
+    constexpr int CH = CIN / 8;
+    constexpr int MB = COUT / 16;
+    constexpr int NB = CIN == 32 ? 2 : 1;
+    constexpr int PSZ = 7 * COUT * CIN + COUT;
+    __shared__ uint4 lds[NSLOT * CH];
+    __shared__ __bf16 sdy[TQ * TR * COUT];
+    const int ntq = (nq + TQ - 1) / TQ, ntr = (nr + TR - 1) / TR;
+    const int tile = blockIdx.x;
+    float *P = part + (int64_t)tile * PSZ;
+    int b, q0, r0;
+    tile_of(tile, ntq, ntr, b, q0, r0);
+    const int64_t soff = (int64_t)b * nq * nr;
+    stage_act<CIN>(lds, x, nq, nr, soff, q0, r0);
+    // dy of the tile's cells (zero outside the raster), channels-last
+    for (int e = threadIdx.x; e < TQ * TR * COUT / 8; e += NT) {
+        const int c = e / (COUT / 8), ch = e - c * (COUT / 8);
+        const int lr = c / TQ, lq = c - lr * TQ;
+        const int q = q0 + lq, r = r0 + lr;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (q < nq && r < nr) v = reinterpret_cast<const uint4 *>(dy + (soff + (int64_t)r * nq + q) * COUT)[ch];
+        reinterpret_cast<uint4 *>(sdy)[e] = v;
+    }
+    __syncthreads();
+    const uint16_t *sx16 = reinterpret_cast<const uint16_t *>(lds);
+    const uint16_t *sdy16 = reinterpret_cast<const uint16_t *>(sdy);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, l16 = lane & 15;
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const int tap = w + 4 * tt;
+        if (tap >= 7) break;
+        f32x4 acc[MB][NB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // K = 256 cells in 8 steps of 32; a group of 8 consecutive cells stays in one row
+#pragma unroll 2
+        for (int ks = 0; ks < (TQ * TR) / 32; ++ks) {
+            const int c0 = ks * 32 + 8 * g;  // first of this lane's 8 cells
+            const int lr = c0 / TQ, lq0 = c0 - lr * TQ;
+            bf16x8 a[MB], bv[NB];
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                const int co = m * 16 + l16;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const uint16_t u = sdy16[(c0 + j) * COUT + co];
+                    a[m][j] = __builtin_bit_cast(__bf16, u);
+                }
+            }
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int ci = n * 16 + l16;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int s = (lr + 1) * SW + (lq0 + j + 1) + OFFS[tap];
+                    const uint16_t u = ci < CIN ? sx16[s * CIN + ci] : (uint16_t)0;
+                    bv[n][j] = __builtin_bit_cast(__bf16, u);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bv[n], acc[m][n], 0, 0, 0);
+        }
+        // lane holds dW rows co = m*16 + 4g + j, column ci = n*16 + l16
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int ci = n * 16 + l16;
+                if (ci >= CIN) continue;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int co = m * 16 + 4 * g + j;
+                    P[(tap * COUT + co) * CIN + ci] = acc[m][n][j];
+                }
+            }
+    }
+    // bias gradient: thread co sums its channel over the tile in cell order
+    if (threadIdx.x < COUT) {
+        float s = 0.f;
+        for (int c = 0; c < TQ * TR; ++c) s += (float)sdy[c * COUT + threadIdx.x];
+        P[7 * COUT * CIN + threadIdx.x] = s;
+    }
+}
+
+// Sum the per-tile partials in tile order (deterministic) and scatter them
+// into the flat parameter-gradient layout W[o][c][t] (o < cout, c < cin), b[o].
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int ntiles, int cinp, int coutp,
+                               int cin, int cout, float *__restrict__ grad) {
+    const int psz = 7 * coutp * cinp + coutp;
+    const int nw = cout * cin * 7;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nw + cout; e += gridDim.x * blockDim.x) {
+        int src;
+        if (e < nw) {
+            const int o = e / (cin * 7), rem = e - o * cin * 7, c = rem / 7, t = rem - c * 7;
+            src = (t * coutp + o) * cinp + c;
+        } else {
+            src = 7 * coutp * cinp + (e - nw);
+        }
+        float s = 0.f;
+        for (int k = 0; k < ntiles; ++k) s += part[(int64_t)k * psz + src];
+        grad[e] = s;
+    }
+}
+
+// ------------------------------------------------------------ parameters
+
+// From the flat FP32 parameters of one layer (W[o][c][t], b[o]) build the
+// bf16 MFMA weights: forward wm[t][co][ci] = W[co][ci][t]; data gradient
+// wt[t][ci][co] = W[co][ci][opp(t)] (the transposed, mirrored stencil).
+// Padded channels are zero.
+__global__ void k_prepare_weights(const float *__restrict__ p, int cin, int cout, int cinp,
+                                  int coutp, __bf16 *__restrict__ wm, __bf16 *__restrict__ wt,
+                                  float *__restrict__ bias) {
+    const int n = 7 * coutp * cinp;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int t = e / (coutp * cinp), rem = e - t * coutp * cinp;
+        const int co = rem / cinp, ci = rem - co * cinp;
+        const float v = (co < cout && ci < cin) ? p[(co * cin + ci) * 7 + t] : 0.f;
+        wm[e] = (__bf16)v;
+        // wt is [t][ci][co] with cinp/coutp swapped roles
+        const float vt = (co < cout && ci < cin) ? p[(co * cin + ci) * 7 + OPP[t]] : 0.f;
+        wt[(t * cinp + ci) * coutp + co] = (__bf16)vt;
+    }
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < coutp; e += gridDim.x * blockDim.x)
+        bias[e] = e < cout ? p[cout * cin * 7 + e] : 0.f;
+}
+
+__global__ void k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// ------------------------------------------------------------ loss, pack
+
+// L1 loss of pred (OUT_STRIDE floats per cell, 3 used) against target (3 per
+// cell): per-workgroup FP64 partial sums and dy = sign(diff)/count as bf16
+// in the 16-channel layout of the last layer.
+__global__ __launch_bounds__(256) void k_l1_loss(const float *__restrict__ pred,
+                                                 const float *__restrict__ target, int64_t ncell,
+                                                 double inv_count, __bf16 *__restrict__ dy,
+                                                 double *__restrict__ part) {
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 d0 = bf16x4{}, d1 = bf16x4{}, d2 = bf16x4{}, d3 = bf16x4{};
+        for (int c = 0; c < 3; ++c) {
+            const float df = pred[i * OUT_STRIDE + c] - target[i * 3 + c];
+            s += fabs((double)df);
+            const float gs = df > 0.f ? (float)inv_count : (df < 0.f ? -(float)inv_count : 0.f);
+            d0[c] = (__bf16)gs;
+        }
+        bf16x4 *o = reinterpret_cast<bf16x4 *>(dy + i * 16);
+        o[0] = d0;
+        o[1] = d1;
+        o[2] = d2;
+        o[3] = d3;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// FP32 features (6 per cell) -> bf16 activations (8 channels, 2 zero).
+__global__ void k_pack_features(const float *__restrict__ f, int64_t ncell,
+                                __bf16 *__restrict__ x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        bf16x8 v = bf16x8{};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = (__bf16)f[i * 6 + c];
+        *reinterpret_cast<bf16x8 *>(x + i * 8) = v;
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+static int blocks_for(int64_t n, int per = 256) {
+    const int64_t b = (n + per - 1) / per;
+    return (int)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+int conv_tiles(int nq, int nr, int batch) {
+    return ((nq + TQ - 1) / TQ) * ((nr + TR - 1) / TR) * batch;
+}
+
+hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf16 *wm,
+                       const float *bias, void *out, const __bf16 *mask, int nq, int nr,
+                       int batch, int cout_real, hipStream_t st) {
+    const int nt = conv_tiles(nq, nr, batch);
+#define HEXSV_CONV(CI, CO, E)                                                                   \
+    if (cinp == CI && coutp == CO && epi == E) {                                                \
+        hipLaunchKernelGGL((k_hexconv<CI, CO, E>), dim3(nt), dim3(NT), 0, st, x, wm, bias, out, \
+                           mask, nq, nr, nt, cout_real);                                        \
+        return hipGetLastError();                                                               \
+    }
+    HEXSV_CONV(8, 32, EPI_RELU)
+    HEXSV_CONV(32, 32, EPI_RELU)
+    HEXSV_CONV(32, 16, EPI_LIN)
+    HEXSV_CONV(16, 32, EPI_MASK)
+    HEXSV_CONV(32, 32, EPI_MASK)
+#undef HEXSV_CONV
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_wgrad(int cinp, int coutp, const __bf16 *x, const __bf16 *dy, float *part,
+                        int nq, int nr, int batch, hipStream_t st) {
+    const int nt = conv_tiles(nq, nr, batch);
+#define HEXSV_WG(CI, CO)                                                                       \
+    if (cinp == CI && coutp == CO) {                                                           \
+        hipLaunchKernelGGL((k_hexconv_wgrad<CI, CO>), dim3(nt), dim3(NT), 0, st, x, dy, part, nq, \
+                           nr, nt);                                                            \
+        return hipGetLastError();                                                              \
+    }
+    HEXSV_WG(8, 32)
+    HEXSV_WG(32, 32)
+    HEXSV_WG(32, 16)
+#undef HEXSV_WG
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_wgrad_reduce(const float *part, int ntiles, int cinp, int coutp, int cin,
+                               int cout, float *grad, hipStream_t st) {
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(7 * cin * cout + cout)), dim3(256), 0, st,
+                       part, ntiles, cinp, coutp, cin, cout, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_weights(const float *p, int cin, int cout, int cinp, int coutp,
+                                  __bf16 *wm, __bf16 *wt, float *bias, hipStream_t st) {
+    hipLaunchKernelGGL(k_prepare_weights, dim3(blocks_for(7 * cinp * coutp)), dim3(256), 0, st, p,
+                       cin, cout, cinp, coutp, wm, wt, bias);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, float *m, float *v, const float *g, int64_t n, float lr,
+                       int step, hipStream_t st) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, st, p, m, v, g, n, lr, b1, b2,
+                       1e-8f, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_l1_loss(const float *pred, const float *target, int64_t ncell, double inv_count,
+                          __bf16 *dy, double *part, int nparts, hipStream_t st) {
+    hipLaunchKernelGGL(k_l1_loss, dim3(nparts), dim3(256), 0, st, pred, target, ncell, inv_count,
+                       dy, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_features(const float *f, int64_t ncell, __bf16 *x, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_features, dim3(blocks_for(ncell)), dim3(256), 0, st, f, ncell, x);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace hexsv

@@ -100,6 +100,18 @@ _SIGS = [
                                       C.POINTER(C.c_int32)]),
     ("hexsv_sim_autotune", C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), _VP]),
+    ("hexsv_surrogate_create", C.c_int, [C.c_int32, C.c_int32, C.POINTER(_VP)]),
+    ("hexsv_surrogate_destroy", None, [_VP]),
+    ("hexsv_surrogate_num_params", C.c_int64, [_VP]),
+    ("hexsv_surrogate_set_params", C.c_int, [_VP, _VP, C.c_int64, _VP]),
+    ("hexsv_surrogate_get_params", C.c_int, [_VP, _VP, C.c_int64, _VP]),
+    ("hexsv_surrogate_set_scales", C.c_int, [_VP, C.POINTER(C.c_float), C.c_int32]),
+    ("hexsv_surrogate_get_scales", C.c_int, [_VP, C.POINTER(C.c_float), C.c_int32]),
+    ("hexsv_surrogate_forward", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP, _VP]),
+    ("hexsv_surrogate_gradient", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP, _VP,
+                                           C.POINTER(C.c_double), _VP]),
+    ("hexsv_surrogate_train_step", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
+                                             C.c_float, C.POINTER(C.c_double), _VP]),
     ("hexsv_tile_count", C.c_int, []),
     ("hexsv_tile_shape", C.c_int, [C.c_int32] + [C.POINTER(C.c_int32)] * 3),
 ]
@@ -391,4 +403,71 @@ class Ensemble:
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.hexsv_ensemble_destroy(h)
+            self._h = None
+
+
+class Surrogate:
+    """Hex-convolution residual network (BF16 MFMA kernels, FP32 master weights)."""
+
+    def __init__(self, layers=4, channels=32):
+        h = C.c_void_p()
+        _check(lib().hexsv_surrogate_create(int(layers), int(channels), C.byref(h)))
+        self._h = h
+        self.layers, self.channels = layers, channels
+        self.num_params = int(lib().hexsv_surrogate_num_params(h))
+
+    def set_params(self, p):
+        t = _dev(p, dtype=torch.float32, n=self.num_params)
+        _check(lib().hexsv_surrogate_set_params(self._h, _ptr(t), self.num_params, _stream()))
+
+    def params(self):
+        t = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
+        _check(lib().hexsv_surrogate_get_params(self._h, _ptr(t), self.num_params, _stream()))
+        return t
+
+    def set_scales(self, scales):
+        a = (C.c_float * len(scales))(*[float(x) for x in scales])
+        _check(lib().hexsv_surrogate_set_scales(self._h, a, len(scales)))
+
+    def scales(self, n=5):
+        a = (C.c_float * n)()
+        _check(lib().hexsv_surrogate_get_scales(self._h, a, n))
+        return list(a)
+
+    @staticmethod
+    def _shape(x, nq, nr, ch):
+        n = x.numel() // ch
+        if x.numel() != n * ch or n % (nq * nr):
+            raise ValueError("array does not hold whole samples")
+        return n // (nq * nr)
+
+    def forward(self, features, nq, nr):
+        f = _dev(features, dtype=torch.float32)
+        batch = self._shape(f, nq, nr, 6)
+        out = torch.empty((batch * nq * nr, 4), dtype=torch.float32, device="cuda")
+        _check(lib().hexsv_surrogate_forward(self._h, batch, int(nq), int(nr), _ptr(f), _ptr(out),
+                                             _stream()))
+        return out
+
+    def gradient(self, features, target, nq, nr):
+        f = _dev(features, dtype=torch.float32)
+        t = _dev(target, dtype=torch.float32)
+        batch = self._shape(f, nq, nr, 6)
+        g = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
+        loss = C.c_double()
+        _check(lib().hexsv_surrogate_gradient(self._h, batch, int(nq), int(nr), _ptr(f), _ptr(t),
+                                              _ptr(g), C.byref(loss), _stream()))
+        return loss.value, g
+
+    def train_step(self, features, target, nq, nr, lr):
+        batch = self._shape(features, nq, nr, 6)
+        loss = C.c_double()
+        _check(lib().hexsv_surrogate_train_step(self._h, batch, int(nq), int(nr), _ptr(features),
+                                                _ptr(target), float(lr), C.byref(loss), _stream()))
+        return loss.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.hexsv_surrogate_destroy(h)
             self._h = None

@@ -1,0 +1,96 @@
+"""BF16 MFMA hex-convolution surrogate kernels against the FP64 oracle (needs an MI355X).
+
+The oracle rounds features, weights and hidden activations to bfloat16 exactly where the
+GPU does and accumulates in FP64; remaining differences come from FP32 accumulation order
+(and the rare bfloat16 rounding it flips), so values agree to about 1e-2 relative L2.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import surrogate as so
+from tests.test_gpu_parity import hx  # noqa: F401  (fixture)
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
+
+
+def setup(seed, nq, nr, batch, layers=4):
+    rng = np.random.default_rng(seed)
+    p = so.init_params(seed, layers, 32, out_scale=1.0)
+    p = (p + rng.normal(scale=0.02, size=p.shape)).astype(np.float32)
+    feats = rng.normal(size=(batch, nq * nr, 6)).astype(np.float32)
+    tgt = rng.normal(size=(batch, nq * nr, 3)).astype(np.float32)
+    G = oracle.grid(nq, nr, 1.0)
+    return p, feats, tgt, G
+
+
+@pytest.mark.parametrize("nq,nr,batch,layers", [(70, 9, 2, 4), (64, 4, 1, 4), (33, 17, 3, 3),
+                                                (130, 6, 1, 5)])
+def test_forward_matches_oracle(hx, nq, nr, batch, layers):
+    p, feats, _, G = setup(1, nq, nr, batch, layers)
+    sur = hx.Surrogate(layers, 32)
+    sur.set_params(p)
+    out = sur.forward(feats.reshape(-1, 6), nq, nr).cpu().numpy().reshape(batch, nq * nr, 4)
+    for b in range(batch):
+        ref, _, _ = so.forward(G, p, feats[b].astype(np.float64), layers, 32, bf16=True)
+        e = rel_l2(out[b, :, :3], ref)
+        print(f"[surrogate fwd {nq}x{nr} b{b}] rel L2 {e:.2e}")
+        assert e <= 1e-2
+
+
+@pytest.mark.parametrize("nq,nr,batch", [(70, 9, 2), (40, 12, 1)])
+def test_gradient_matches_oracle(hx, nq, nr, batch):
+    layers = 4
+    p, feats, tgt, G = setup(2, nq, nr, batch, layers)
+    sur = hx.Surrogate(layers, 32)
+    sur.set_params(p)
+    loss, g = sur.gradient(feats.reshape(-1, 6), tgt.reshape(-1, 3), nq, nr)
+    g = g.cpu().numpy()
+    rl, rg = so.loss_and_grad(G, p, [f.astype(np.float64) for f in feats],
+                              [t.astype(np.float64) for t in tgt], layers, 32, bf16=True)
+    assert loss == pytest.approx(rl, rel=2e-3)
+    k = 0
+    for li, (ci, co) in enumerate(so.layer_shapes(layers, 32)):
+        nw = co * ci * 7
+        ew = rel_l2(g[k:k + nw], rg[k:k + nw])
+        eb = rel_l2(g[k + nw:k + nw + co], rg[k + nw:k + nw + co])
+        print(f"[surrogate grad layer {li}] W rel L2 {ew:.2e}  b rel L2 {eb:.2e}")
+        assert ew <= 2e-2 and eb <= 2e-2
+        k += nw + co
+
+
+def test_adam_step_matches_oracle(hx):
+    nq, nr = 40, 12
+    p, feats, tgt, G = setup(3, nq, nr, 1)
+    sur = hx.Surrogate(4, 32)
+    sur.set_params(p)
+    _, g = sur.gradient(feats.reshape(-1, 6), tgt.reshape(-1, 3), nq, nr)
+    f = torch.from_numpy(feats.reshape(-1, 6)).cuda()
+    t = torch.from_numpy(tgt.reshape(-1, 3)).cuda()
+    sur.train_step(f, t, nq, nr, 1e-3)
+    p1 = sur.params().cpu().numpy()
+    ref, _, _ = so.adam_update(p.astype(np.float64), 0.0, 0.0, g.cpu().numpy().astype(np.float64),
+                               1, 1e-3)
+    np.testing.assert_allclose(p1, ref, rtol=1e-5, atol=1e-7)
+
+
+def test_training_reduces_loss(hx):
+    nq, nr, batch = 64, 32, 4
+    rng = np.random.default_rng(4)
+    p = so.init_params(5, 4, 32)
+    sur = hx.Surrogate(4, 32)
+    sur.set_params(p)
+    feats = rng.normal(size=(batch * nq * nr, 6)).astype(np.float32)
+    # a smooth target the network can represent: local linear combinations of features
+    tgt = np.stack([0.5 * feats[:, 0] - 0.3 * feats[:, 5], 0.2 * feats[:, 1],
+                    -0.4 * feats[:, 2] + 0.1 * feats[:, 3]], axis=1).astype(np.float32)
+    f = torch.from_numpy(feats).cuda()
+    t = torch.from_numpy(tgt).cuda()
+    losses = [sur.train_step(f, t, nq, nr, 3e-3) for _ in range(300)]
+    print(f"[surrogate train] loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.3 * losses[0]
