@@ -12,6 +12,7 @@ Prints ONE JSON line:  python bench.py [--steps K] [--warmup W] [--workload c2|c
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,34 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per cell-update: read h, v1, v2, z, theta, alpha_p; write h, v1, v2
 BYTES_PER_CELL = {"fp32": 9 * 4, "fp64": 9 * 8}
 
+# Measured HBM bytes of one step-kernel launch: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB
+# per dispatch, in runs of their own) scaled by what the same counters read for a plain 1 GiB
+# device copy (x2.000 and x1.000); the summary with its commands is
+# profiles/k_step_catchment-4096x4096_fp32.md.  A figure holds only for the kernel source it
+# was taken on (digest below); otherwise the line reports null.
+TRAFFIC = {
+    ("catchment-4096x4096-edge2m-storm150mmh", "fp32", 2): {
+        "bytes": 606614109, "digest": "21c9adbd738eeb33"},
+}
+
+
+def step_kernel_digest():
+    """Digest of the source of the step kernel (device helpers, tile phases, k_step)."""
+    d = os.path.join(ROOT, "paper_2406_14933_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("hexsv_device.h", "hexsv_tile.h"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(d, "hexsv_kernels.h"), "rb") as fh:
+        txt = fh.read()
+    h.update(txt[:txt.index(b"void k_prime(")])
+    return h.hexdigest()[:16]
+
+
+def traffic_of(wname, precision, tile):
+    t = TRAFFIC.get((wname, precision, tile))
+    return t["bytes"] if t and t["digest"] == step_kernel_digest() else None
+
 
 def workload(name):
     import synth
@@ -38,7 +67,7 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_gpu(sc, precision, steps, warmup, tile, spg):
+def time_gpu(sc, wname, precision, steps, warmup, tile, spg):
     """Time `steps` solver steps (graph replays) after `warmup`, then the step kernel alone."""
     import torch
     from paper_2406_14933_amd import hexsv
@@ -71,7 +100,8 @@ def time_gpu(sc, precision, steps, warmup, tile, spg):
         "info": sim.info(),
         "residual": b1["residual"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_step",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_of(wname, precision, sim.info()["tile"]), "kernel": "k_step",
                      "kernel_us": kern_ms * 1e3, "bytes_per_cell": bpc,
                      "bytes_per_launch": bpc * cells},
     }
@@ -173,7 +203,7 @@ def main():
     sc, wname = workload(args.workload)
     print(f"[bench] workload {wname}: {sc.n} cells, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
-    main_run = time_gpu(sc, args.precision, args.steps, args.warmup, args.tile,
+    main_run = time_gpu(sc, wname, args.precision, args.steps, args.warmup, args.tile,
                         args.steps_per_graph)
     print(f"[bench] {args.precision}: {main_run['value']:.3e} cell-updates/s, step kernel "
           f"{main_run['kernel_us']:.1f} us", file=sys.stderr, flush=True)
@@ -198,14 +228,14 @@ def main():
         "books_residual": main_run["residual"],
     }
     if not args.no_fp64 and args.precision == "fp32":
-        other = time_gpu(sc, "fp64", args.steps, args.warmup, args.tile, args.steps_per_graph)
+        other = time_gpu(sc, wname, "fp64", args.steps, args.warmup, args.tile, args.steps_per_graph)
         print(f"[bench] fp64: {other['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
         line["fp64"] = {"value": other["value"], "ms_per_step": other["ms_per_step"],
                         "roofline": other["roofline"], "books_residual": other["residual"]}
     if args.large_steps > 0 and args.workload != "c4":
         big, bname = workload("c4")
         print(f"[bench] large: {bname}", file=sys.stderr, flush=True)
-        lr = time_gpu(big, args.precision, args.large_steps, 50, args.tile, args.steps_per_graph)
+        lr = time_gpu(big, bname, args.precision, args.large_steps, 50, args.tile, args.steps_per_graph)
         print(f"[bench] large {args.precision}: {lr['value']:.3e} cell-updates/s, step kernel "
               f"{lr['kernel_us']:.1f} us", file=sys.stderr, flush=True)
         line["large"] = {"workload": bname, "value": lr["value"], "steps": args.large_steps,

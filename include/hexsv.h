@@ -313,6 +313,28 @@ int hexsv_surrogate_train_step(hexsv_surrogate *sur, int32_t batch, int32_t nq, 
                                const float *d_features, const float *d_target, float lr,
                                double *loss, hipStream_t stream);
 
+/* Surrogate input features from FP64 device arrays of n cells (scales from
+ * set_scales): h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, rain_depth/H;
+ * d_features is n x 6 FP32. */
+int hexsv_surrogate_features(const hexsv_surrogate *sur, int64_t n, const double *d_h,
+                             const double *d_v1, const double *d_v2, const double *d_z,
+                             const double *d_theta, double rain_depth, float *d_features,
+                             hipStream_t stream);
+
+/* Advance a simulation to t_end in windows of `window` seconds predicted by
+ * the surrogate (trained on windows of k solver steps).  Each window: the
+ * network's change is applied, then the mass-balance residual
+ *   rho = |S_pred - S_0 - (R_win - O_win)| / (S_0 + R_win)
+ * is evaluated in FP64 (S stored volume, R_win the rain volume of the window
+ * by the right-endpoint rule on k sub-steps, O_win the trapezoid of the
+ * outflow rates at both ends); if rho > residual_tol (or the prediction is not
+ * finite) the window is discarded and the plain solver advances it instead.
+ * A final window shorter than `window` is always solved.  Returns the counts
+ * of accepted and fallback windows.  Synchronises once per window. */
+int hexsv_sim_run_surrogate(hexsv_sim *sim, hexsv_surrogate *sur, double t_end, double window,
+                            int32_t k, double residual_tol, int64_t *n_accepted,
+                            int64_t *n_fallback, hipStream_t stream);
+
 /* Number of tile variants built, and the shape of variant v. */
 int hexsv_tile_count(void);
 int hexsv_tile_shape(int32_t v, int32_t *tq, int32_t *tr, int32_t *threads);

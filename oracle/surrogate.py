@@ -137,3 +137,63 @@ def adam_update(p, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1 - beta1 ** step)
     vh = v / (1 - beta2 ** step)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ------------------------------------------------------ surrogate windows
+#
+# A window advances the solver state by a fixed time span with one network
+# call instead of the explicit steps; it is accepted only if the predicted
+# state keeps the water balance the scheme conserves (stored volume = initial
+# + rain - outflow - clamped; Sec. 4.2, Table BasinSusita reports the same
+# balance).  Below are the plain definitions of the pieces.
+
+def features(h, v1, v2, z, theta, rain_depth, H, Q, Z):
+    """Network input (N, 6) of a state: h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, depth/H.
+
+    All channels but theta are zero on inactive cells (theta = 0)."""
+    h, v1, v2, z, th = (np.asarray(a, np.float64) for a in (h, v1, v2, z, theta))
+    act = th > 0.0
+    f = np.zeros((h.size, FEATURES))
+    f[:, 0] = np.where(act, h / H, 0.0)
+    f[:, 1] = np.where(act, th * h * v1 / Q, 0.0)
+    f[:, 2] = np.where(act, th * h * v2 / Q, 0.0)
+    f[:, 3] = np.where(act, z / Z, 0.0)
+    f[:, 4] = th
+    f[:, 5] = np.where(act, rain_depth / H, 0.0)
+    return f
+
+
+def apply_window(h, v1, v2, theta, out, dH, dQ, m_min=1e-6):
+    """State after a predicted window: h' = max(h + dH out0, 0), q' = theta h v + dQ (out1, out2),
+    v' = q' / (theta h') where theta h' > m_min, else 0; inactive cells unchanged."""
+    h, v1, v2, th = (np.asarray(a, np.float64) for a in (h, v1, v2, theta))
+    out = np.asarray(out, np.float64)
+    act = th > 0.0
+    hn = np.maximum(h + dH * out[:, 0], 0.0)
+    q1 = th * h * v1 + dQ * out[:, 1]
+    q2 = th * h * v2 + dQ * out[:, 2]
+    mn = th * hn
+    wet = mn > m_min
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v1n = np.where(wet, q1 / np.where(wet, mn, 1.0), 0.0)
+        v2n = np.where(wet, q2 / np.where(wet, mn, 1.0), 0.0)
+    return (np.where(act, hn, h), np.where(act, v1n, v1), np.where(act, v2n, v2))
+
+
+def outflow_rate(G, g, z, theta, h, v1, v2):
+    """Volume flux (m^3/s) leaving through the OUTFLOW edges: the F_out of every cell, summed."""
+    cells = np.nonzero((G.code == oracle.OUTFLOW).any(axis=1) & G.active)[0]
+    return float(sum(oracle.cell_sums(G, g, z, theta, h, v1, v2, int(i))[5] for i in cells))
+
+
+def window_rain_depth(kind, i_a, t_a, T_d, t0, window, k):
+    """Rain depth of a window of k equal sub-steps, each taking r at its end (eq. .05-1)."""
+    dt = window / k
+    return float(sum(dt * oracle.rain_rate(kind, i_a, t_a, T_d, t0 + j * dt) for j in range(1, k + 1)))
+
+
+def gate_residual(S0, S1, R, O0, O1, window):
+    """Relative water-balance residual of a predicted window:
+    |S1 - S0 - (R - O)| / max(S0 + R, tiny), with O the trapezoid-rule outflow volume."""
+    Ow = 0.5 * (O0 + O1) * window
+    return abs(S1 - S0 - (R - Ow)) / max(S0 + R, 1e-300)

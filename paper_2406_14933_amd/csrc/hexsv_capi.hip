@@ -153,6 +153,9 @@ struct hexsv_sim {
     hipGraph_t graph;
     hipGraphExec_t gexec;
     bool graph_ok, fields_set, state_set;
+    // surrogate windows: features, network output, outflow-rate partials
+    float *d_feat, *d_sout;
+    double *d_opart, *h_opart;
     // optional device timing of graph replays (hipEvents on the run stream)
     bool timing;
     hipEvent_t ev0, ev1;
@@ -259,6 +262,10 @@ extern "C" void hexsv_sim_destroy(hexsv_sim *s) {
     if (s->d_chk) (void)hipFree(s->d_chk);
     if (s->h_ctl) (void)hipHostFree(s->h_ctl);
     if (s->h_chk) (void)hipHostFree(s->h_chk);
+    if (s->d_feat) (void)hipFree(s->d_feat);
+    if (s->d_sout) (void)hipFree(s->d_sout);
+    if (s->d_opart) (void)hipFree(s->d_opart);
+    if (s->h_opart) (void)hipHostFree(s->h_opart);
     delete s;
 }
 
@@ -604,4 +611,130 @@ extern "C" int hexsv_sim_set_books(hexsv_sim *s, const hexsv_books *b, hipStream
     HIP_TRY(s->prec == HEXSV_FP64 ? prime<double>(s, 0, stream) : prime<float>(s, 0, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     return HEXSV_OK;
+}
+
+// ------------------------------------------------------------ surrogate
+
+static const int OUTFLOW_PARTS = 256;
+
+extern "C" int hexsv_surrogate_features(const hexsv_surrogate *sur, int64_t n, const double *d_h,
+                                        const double *d_v1, const double *d_v2, const double *d_z,
+                                        const double *d_theta, double rain_depth, float *d_features,
+                                        hipStream_t stream) {
+    if (!sur || n < 1 || !d_h || !d_v1 || !d_v2 || !d_z || !d_theta || !d_features)
+        return fail(HEXSV_EINVAL, "surrogate_features: bad argument");
+    float sc[5];
+    int rc = hexsv_surrogate_get_scales(sur, sc, 5);
+    if (rc) return rc;
+    HIP_TRY(launch_features<double>(n, d_h, d_v1, d_v2, d_z, d_theta, rain_depth, sc[0], sc[1], sc[2],
+                                    d_features, stream));
+    return HEXSV_OK;
+}
+
+template <typename T>
+static int outflow_rate(hexsv_sim *s, int par, hipStream_t st, double *rate) {
+    HIP_TRY(launch_outflow_rate<T>(dom_of<T>(s), par, s->grid->kg, s->grid->edge, s->d_opart,
+                                   OUTFLOW_PARTS, st));
+    HIP_TRY(hipMemcpyAsync(s->h_opart, s->d_opart, sizeof(double) * OUTFLOW_PARTS,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double a = 0.0;
+    for (int k = 0; k < OUTFLOW_PARTS; ++k) a += s->h_opart[k];
+    *rate = a;
+    return HEXSV_OK;
+}
+
+static double host_rain_rate(const KRain &rn, double t) {
+    if (rn.kind == 0) return (t >= 0.0 && t <= rn.T_d) ? rn.i_a : 0.0;
+    const double gamma = rn.t_a / rn.T_d;
+    if (t >= 0.0 && t <= rn.t_a) return rn.i_a * (t / rn.t_a);
+    if (t > rn.t_a && t <= rn.T_d) return rn.i_a * ((1.0 - t / rn.T_d) / (1.0 - gamma));
+    return 0.0;
+}
+
+template <typename T>
+static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, double window,
+                             int32_t k, double tol, int64_t *n_acc, int64_t *n_fb,
+                             hipStream_t st) {
+    const int64_t n = s->grid->n;
+    if (!s->d_feat) {
+        HIP_TRY(hipMalloc(&s->d_feat, sizeof(float) * 6 * n));
+        HIP_TRY(hipMalloc(&s->d_sout, sizeof(float) * 4 * n));
+        HIP_TRY(hipMalloc(&s->d_opart, sizeof(double) * OUTFLOW_PARTS));
+        HIP_TRY(hipHostMalloc(&s->h_opart, sizeof(double) * OUTFLOW_PARTS, hipHostMallocDefault));
+    }
+    float sc[5];
+    int rc = hexsv_surrogate_get_scales(sur, sc, 5);
+    if (rc) return rc;
+    const KDom<T> d = dom_of<T>(s);
+    Ctl &c = *s->h_ctl;
+    for (;;) {
+        HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (c.err) return fail(HEXSV_ENUMERIC, "run_surrogate: non-finite value at cell %d", c.err_cell);
+        const double t0 = c.t;
+        if (t0 >= t_end) break;
+        if (t_end - t0 < window) {  // last partial window: the plain solver
+            rc = hexsv_sim_run(s, t_end, 0, st);
+            if (rc) return rc;
+            *n_fb += 1;
+            break;
+        }
+        const int par = c.parity;
+        const double S0 = c.stored;
+        // rain depth of the window by the right-endpoint rule on k sub-steps (as the solver)
+        double depth = 0.0;
+        for (int j = 1; j <= k; ++j) depth += (window / k) * host_rain_rate(s->rn, t0 + j * (window / k));
+        double O0 = 0.0, O1 = 0.0;
+        rc = outflow_rate<T>(s, par, st, &O0);
+        if (rc) return rc;
+        HIP_TRY(launch_features<T>(n, d.buf(par, 0), d.buf(par, 1), d.buf(par, 2), d.z, d.th, depth,
+                                   sc[0], sc[1], sc[2], s->d_feat, st));
+        rc = hexsv_surrogate_forward(sur, 1, s->grid->kg.nq, s->grid->kg.nr, s->d_feat, s->d_sout, st);
+        if (rc) return rc;
+        HIP_TRY(launch_apply_surrogate<T>(d, par, n, s->d_sout, sc[3], sc[4], 1e-6, st));
+        rc = outflow_rate<T>(s, par ^ 1, st, &O1);
+        if (rc) return rc;
+        // stored volume and CFL bound of the predicted state (books kept)
+        const Ctl saved = c;
+        c.parity = par ^ 1;
+        HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+        HIP_TRY(prime<T>(s, 0, st));
+        HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const double R = s->kc.area_active * depth;
+        const double Ow = 0.5 * (O0 + O1) * window;
+        double ref = S0 + R;
+        if (ref < 1e-300) ref = 1e-300;
+        const double rho = fabs(c.stored - S0 - (R - Ow)) / ref;
+        if (isfinite(c.stored) && rho <= tol) {
+            c.t = t0 + window;
+            c.rain += R;
+            c.outflow += Ow;
+            HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+            *n_acc += 1;
+        } else {
+            c = saved;  // the state at t0 is intact in buffer `par`
+            HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+            rc = hexsv_sim_run(s, t0 + window, 0, st);
+            if (rc) return rc;
+            *n_fb += 1;
+        }
+    }
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_run_surrogate(hexsv_sim *s, hexsv_surrogate *sur, double t_end,
+                                       double window, int32_t k, double residual_tol,
+                                       int64_t *n_accepted, int64_t *n_fallback, hipStream_t st) {
+    if (!s || !sur || !(window > 0.0) || k < 1 || !(residual_tol >= 0.0))
+        return fail(HEXSV_EINVAL, "run_surrogate: bad argument");
+    if (!s->state_set) return fail(HEXSV_ESTATE, "run_surrogate: call set_state first");
+    int64_t a = 0, f = 0;
+    const int rc = s->prec == HEXSV_FP64
+                       ? surrogate_windows<double>(s, sur, t_end, window, k, residual_tol, &a, &f, st)
+                       : surrogate_windows<float>(s, sur, t_end, window, k, residual_tol, &a, &f, st);
+    if (n_accepted) *n_accepted = a;
+    if (n_fallback) *n_fallback = f;
+    return rc;
 }

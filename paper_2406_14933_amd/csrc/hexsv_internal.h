@@ -96,6 +96,18 @@ hipError_t launch_check_fields(const double *z, const double *th, const double *
 hipError_t launch_check_state(const double *h, const double *v1, const double *v2,
                               const uint8_t *active, int64_t n, int32_t *chk, hipStream_t stream);
 
+// Surrogate glue (see hexsv_kernels.h).
+template <typename S>
+hipError_t launch_features(int64_t n, const S *h, const S *v1, const S *v2, const S *z,
+                           const S *th, double rain_depth, float H, float Q, float Z, float *f,
+                           hipStream_t stream);
+template <typename T>
+hipError_t launch_apply_surrogate(const KDom<T> &d, int par, int64_t n, const float *out,
+                                  float dH, float dQ, double m_min, hipStream_t stream);
+template <typename T>
+hipError_t launch_outflow_rate(const KDom<T> &d, int par, const KGrid &g, double l, double *part,
+                               int nparts, hipStream_t stream);
+
 hipError_t launch_tables(const KGrid &g, const uint8_t *active, int32_t *nbr, uint8_t *code,
                          hipStream_t stream);
 

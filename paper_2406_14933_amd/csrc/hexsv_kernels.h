@@ -148,6 +148,112 @@ hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ surrogate glue
+
+// Surrogate input features of every cell (scales {H, Q, Z}):
+// h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, rain_depth/H (0 outside the domain).
+template <typename S>
+__global__ void k_features(int64_t n, const S *h, const S *v1, const S *v2, const S *z,
+                           const S *th, double rain_depth, float H, float Q, float Z,
+                           float *__restrict__ f) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float t = (float)th[i];
+        const float hh = (float)h[i];
+        const bool act = t > 0.f;
+        f[i * 6 + 0] = act ? hh / H : 0.f;
+        f[i * 6 + 1] = act ? t * hh * (float)v1[i] / Q : 0.f;
+        f[i * 6 + 2] = act ? t * hh * (float)v2[i] / Q : 0.f;
+        f[i * 6 + 3] = act ? (float)z[i] / Z : 0.f;
+        f[i * 6 + 4] = t;
+        f[i * 6 + 5] = act ? (float)(rain_depth / H) : 0.f;
+    }
+}
+
+template <typename S>
+hipError_t launch_features(int64_t n, const S *h, const S *v1, const S *v2, const S *z,
+                           const S *th, double rain_depth, float H, float Q, float Z, float *f,
+                           hipStream_t stream) {
+    const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    hipLaunchKernelGGL((k_features<S>), dim3(nb > 0 ? nb : 1), dim3(256), 0, stream, n, h, v1, v2, z,
+                       th, rain_depth, H, Q, Z, f);
+    return hipGetLastError();
+}
+
+// Apply a predicted window change to state buffer `par` into buffer par^1:
+// h' = max(h + dH*out0, 0), q' = theta h v + dQ*(out1, out2), v' = q' / (theta h')
+// (0 where theta h' <= m_min).  Inactive cells are copied.
+template <typename T>
+__global__ void k_apply_surrogate(KDom<T> d, int par, int64_t n, const float *__restrict__ out,
+                                  float dH, float dQ, double m_min) {
+    const T *h = d.buf(par, 0), *v1 = d.buf(par, 1), *v2 = d.buf(par, 2);
+    T *ho = d.buf(par ^ 1, 0), *v1o = d.buf(par ^ 1, 1), *v2o = d.buf(par ^ 1, 2);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T th = d.th[i];
+        if (!(th > T(0))) {
+            ho[i] = h[i];
+            v1o[i] = v1[i];
+            v2o[i] = v2[i];
+            continue;
+        }
+        const T m = th * h[i];
+        T hn = h[i] + (T)dH * (T)out[i * 4 + 0];
+        hn = hn > T(0) ? hn : T(0);
+        const T q1 = m * v1[i] + (T)dQ * (T)out[i * 4 + 1];
+        const T q2 = m * v2[i] + (T)dQ * (T)out[i * 4 + 2];
+        const T mn = th * hn;
+        ho[i] = hn;
+        v1o[i] = mn > (T)m_min ? q1 / mn : T(0);
+        v2o[i] = mn > (T)m_min ? q2 / mn : T(0);
+    }
+}
+
+template <typename T>
+hipError_t launch_apply_surrogate(const KDom<T> &d, int par, int64_t n, const float *out,
+                                  float dH, float dQ, double m_min, hipStream_t stream) {
+    const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    hipLaunchKernelGGL((k_apply_surrogate<T>), dim3(nb > 0 ? nb : 1), dim3(256), 0, stream, d, par,
+                       n, out, dH, dQ, m_min);
+    return hipGetLastError();
+}
+
+// Instantaneous volume flux through the OUTFLOW edges of state buffer `par`:
+// with the free-outflow ghost (the cell's own h, v, theta) an edge carries
+// l * theta h * (v . n_k) whatever its sign.  One FP64 partial per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_outflow_rate(KDom<T> d, int par, KGrid g, double l,
+                                                      double *__restrict__ part) {
+    const T *h = d.buf(par, 0), *v1 = d.buf(par, 1), *v2 = d.buf(par, 2);
+    const double S3 = 0.86602540378443864676;
+    const double NX[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+    const double NY[6] = {0.0, S3, S3, 0.0, -S3, -S3};
+    double acc = 0.0;
+    const int64_t n = (int64_t)g.nq * g.nr;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (!(d.th[i] > T(0))) continue;
+        const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+        for (int k = 0; k < 6; ++k) {
+            int qn = q + dq_of(k), rn = r + dr_of(k);
+            int cd;
+            if (wrap_pos(g, qn, rn)) cd = d.th[(int64_t)rn * g.nq + qn] > T(0) ? CODE_INTERIOR : g.mask_bc;
+            else cd = side_code(g, qn, rn);
+            if (cd != CODE_OUTFLOW) continue;
+            const double m = (double)d.th[i] * (double)h[i];
+            acc += l * m * ((double)v1[i] * NX[k] + (double)v2[i] * NY[k]);
+        }
+    }
+    const Part p = block_reduce<256>(0.0, acc, 0.0, 0.0);
+    if (threadIdx.x == 0) part[blockIdx.x] = p.stored;
+}
+
+template <typename T>
+hipError_t launch_outflow_rate(const KDom<T> &d, int par, const KGrid &g, double l, double *part,
+                               int nparts, hipStream_t stream) {
+    hipLaunchKernelGGL((k_outflow_rate<T>), dim3(nparts), dim3(256), 0, stream, d, par, g, l, part);
+    return hipGetLastError();
+}
+
 #define HEXSV_INSTANTIATE(T)                                                                  \
     template hipError_t launch_step<T>(int, const KDom<T> &, const KGrid &, const KConst &,   \
                                        const KRain &, Ctl *, Part *, int, int, int,           \
@@ -157,6 +263,13 @@ hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double
                                             hipStream_t);                                     \
     template hipError_t launch_prime<T>(const KDom<T> &, int64_t, const KConst &, Ctl *, Part *, \
                                         int, int, hipStream_t);                               \
+    template hipError_t launch_features<T>(int64_t, const T *, const T *, const T *, const T *, \
+                                           const T *, double, float, float, float, float *,   \
+                                           hipStream_t);                                      \
+    template hipError_t launch_apply_surrogate<T>(const KDom<T> &, int, int64_t, const float *, \
+                                                  float, float, double, hipStream_t);         \
+    template hipError_t launch_outflow_rate<T>(const KDom<T> &, int, const KGrid &, double,   \
+                                               double *, int, hipStream_t);                   \
     template hipError_t launch_import<T>(const double *, T *, const uint8_t *, int, int64_t,  \
                                          hipStream_t);                                        \
     template hipError_t launch_export<T>(const KDom<T> &, int, int64_t, double *, double *,   \

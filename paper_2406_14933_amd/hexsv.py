@@ -112,6 +112,11 @@ _SIGS = [
                                            C.POINTER(C.c_double), _VP]),
     ("hexsv_surrogate_train_step", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
                                              C.c_float, C.POINTER(C.c_double), _VP]),
+    ("hexsv_surrogate_features", C.c_int, [_VP, C.c_int64, _VP, _VP, _VP, _VP, _VP, C.c_double,
+                                           _VP, _VP]),
+    ("hexsv_sim_run_surrogate", C.c_int, [_VP, _VP, C.c_double, C.c_double, C.c_int32,
+                                          C.c_double, C.POINTER(C.c_int64),
+                                          C.POINTER(C.c_int64), _VP]),
     ("hexsv_tile_count", C.c_int, []),
     ("hexsv_tile_shape", C.c_int, [C.c_int32] + [C.POINTER(C.c_int32)] * 3),
 ]
@@ -303,6 +308,14 @@ class Sim:
                                         _stream()))
         return best.value, ms.value
 
+    def run_surrogate(self, sur, t_end, window, k, residual_tol=1e-3):
+        """Advance with surrogate windows and solver fallback; returns (accepted, fallback)."""
+        a, f = C.c_int64(), C.c_int64()
+        _check(lib().hexsv_sim_run_surrogate(self._h, sur._h, float(t_end), float(window), int(k),
+                                             float(residual_tol), C.byref(a), C.byref(f),
+                                             _stream()))
+        return a.value, f.value
+
     def info(self):
         vals = [C.c_int32() for _ in range(5)]
         _check(lib().hexsv_sim_info(self._h, *(C.byref(v) for v in vals)))
@@ -433,6 +446,15 @@ class Surrogate:
         a = (C.c_float * n)()
         _check(lib().hexsv_surrogate_get_scales(self._h, a, n))
         return list(a)
+
+    def features(self, h, v1, v2, z, theta, rain_depth):
+        """(n, 6) FP32 features from FP64 state arrays (device or host)."""
+        arrs = [_dev(x) for x in (h, v1, v2, z, theta)]
+        n = arrs[0].numel()
+        f = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+        _check(lib().hexsv_surrogate_features(self._h, n, *(_ptr(a) for a in arrs),
+                                              float(rain_depth), _ptr(f), _stream()))
+        return f
 
     @staticmethod
     def _shape(x, nq, nr, ch):

@@ -1,0 +1,118 @@
+"""Surrogate windows inside the solver (features, prediction, water-balance gate, fallback)
+against the oracle's window definitions (needs an MI355X).
+
+* one accepted window equals the oracle chain features -> network (bf16 emulation) -> apply,
+  and its books (t, rain, outflow, stored) follow the window definitions;
+* with a zero tolerance every window falls back, and the result is bit for bit the plain
+  solver advanced window by window.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import surrogate as so
+from tests.test_gpu_parity import hx  # noqa: F401  (fixture)
+
+pytestmark = pytest.mark.gpu
+
+SCALES = (0.05, 0.01, 10.0, 0.01, 0.002)  # H, Q, Z, dH, dQ
+WINDOW, K = 1.6, 16
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
+
+
+def wet_planar(nq=70, nr=40, seed=11):
+    sc = synth.c1_planar(nq=nq, nr=nr, rain_mmh=100.0)
+    h, v1, v2 = synth.random_state(sc, seed, depth=0.05, speed=0.2, dry_frac=0.1)
+    return sc.with_(h0=h, v10=v1, v20=v2)
+
+
+def make_surrogate(hx, seed=4):
+    sur = hx.Surrogate(4, 32)
+    p = so.init_params(seed, 4, 32, out_scale=0.1).astype(np.float32)
+    sur.set_params(p)
+    sur.set_scales(SCALES)
+    return sur, p
+
+
+def test_features_kernel(hx):
+    sc = wet_planar()
+    sur, _ = make_surrogate(hx)
+    f = sur.features(sc.h0, sc.v10, sc.v20, sc.z, sc.theta, 3e-4).cpu().numpy()
+    ref = so.features(sc.h0, sc.v10, sc.v20, sc.z, sc.theta, 3e-4, *SCALES[:3])
+    np.testing.assert_allclose(f, ref, rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_accepted_window_matches_oracle_chain(hx, prec):
+    sc = wet_planar()
+    sim = hx.Sim.from_scenario(sc, prec)
+    b0 = sim.books()
+    sur, p = make_surrogate(hx)
+    print(f"[surrogate window {prec} {sc.nq}x{sc.nr}]", flush=True)
+    acc, fb = sim.run_surrogate(sur, WINDOW, WINDOW, K, residual_tol=math.inf)
+    assert (acc, fb) == (1, 0)
+    st = sim.state_numpy()
+    b = sim.books()
+
+    G = oracle.grid(sc.nq, sc.nr, sc.a, sc.side)
+    depth = so.window_rain_depth(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d, 0.0, WINDOW, K)
+    f = so.features(sc.h0, sc.v10, sc.v20, sc.z, sc.theta, depth, *SCALES[:3])
+    out, _, _ = so.forward(G, p, f, 4, 32, bf16=True)
+    hn, v1n, v2n = so.apply_window(sc.h0, sc.v10, sc.v20, sc.theta, out, SCALES[3], SCALES[4])
+    th = sc.theta
+    e_h = rel_l2(st["h"] - sc.h0, hn - sc.h0)
+    e_q1 = rel_l2(st["q1"] - th * sc.h0 * sc.v10, th * hn * v1n - th * sc.h0 * sc.v10)
+    e_q2 = rel_l2(st["q2"] - th * sc.h0 * sc.v20, th * hn * v2n - th * sc.h0 * sc.v20)
+    print(f"  change rel L2: h {e_h:.2e} q1 {e_q1:.2e} q2 {e_q2:.2e}")
+    assert e_h <= 1e-3 and e_q1 <= 1e-3 and e_q2 <= 1e-3
+    assert np.all(st["h"] >= 0.0)
+
+    sigma, _, _ = oracle.geometry(sc.a)
+    assert b["t"] == WINDOW
+    assert b["rain"] - b0["rain"] == pytest.approx(sigma * sc.n * depth, rel=1e-12)
+    # outflow volume by the trapezoid rule on the rates of the start and predicted states
+    o0 = so.outflow_rate(G, sc.g, sc.z, th, sc.h0, sc.v10, sc.v20)
+    o1 = so.outflow_rate(G, sc.g, sc.z, th, st["h"], st["v1"], st["v2"])
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert b["outflow"] - b0["outflow"] == pytest.approx(0.5 * (o0 + o1) * WINDOW, rel=tol)
+    assert b["stored"] == pytest.approx(sigma * float(np.sum(th * st["h"])), rel=tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_tolerance_falls_back_to_the_solver(hx, prec):
+    sc = wet_planar(nq=66, nr=33, seed=12)
+    t_end = 5 * WINDOW + 0.7
+    sim = hx.Sim.from_scenario(sc, prec)
+    sur, _ = make_surrogate(hx, seed=5)
+    print(f"[surrogate fallback {prec}]", flush=True)
+    acc, fb = sim.run_surrogate(sur, t_end, WINDOW, K, residual_tol=0.0)
+    assert (acc, fb) == (0, 6)
+    ref = hx.Sim.from_scenario(sc, prec)
+    t = 0.0
+    for _ in range(5):  # the window ends as the surrogate loop forms them
+        t = t + WINDOW
+        ref.run(t)
+    ref.run(t_end)
+    a, r = sim.state_numpy(), ref.state_numpy()
+    for k in ("h", "v1", "v2"):
+        np.testing.assert_array_equal(a[k], r[k])
+    ba, br = sim.books(), ref.books()
+    for k in ("t", "initial", "stored", "rain", "outflow", "clamp", "steps"):
+        assert ba[k] == br[k], k
+
+
+def test_surrogate_window_rejects_bad_arguments(hx):
+    sc = wet_planar(nq=20, nr=12)
+    sim = hx.Sim.from_scenario(sc, "fp32")
+    sur, _ = make_surrogate(hx)
+    for window, k, tol in ((0.0, 16, 1e-3), (1.0, 0, 1e-3), (1.0, 16, -1.0)):
+        with pytest.raises(hx.HexsvError):
+            sim.run_surrogate(sur, 10.0, window, k, tol)
+    torch.cuda.synchronize()

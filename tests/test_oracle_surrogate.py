@@ -170,3 +170,89 @@ def test_param_layout():
     assert p.shape == (n,) and p.dtype == np.float32
     back = so.flatten(so.unflatten(p))
     np.testing.assert_array_equal(back, p.astype(np.float64))
+
+
+# ------------------------------------------------------ surrogate windows
+
+def test_outflow_rate_closed_form():
+    """Uniform sheet flowing straight south over an OUTFLOW south side: every cell of row r=0
+    has two outflow edges (directions 4 and 5) with v.n = V sqrt(3)/2, so the rate is
+    2 nq a theta h V sqrt(3)/2; the other sides are walls."""
+    nq, nr, a, th, h, V = 12, 10, 1.5, 0.8, 0.02, 0.3
+    G = oracle.grid(nq, nr, a, side=(oracle.OUTFLOW, oracle.WALL, oracle.WALL, oracle.WALL))
+    n = nq * nr
+    z = np.zeros(n)
+    rate = so.outflow_rate(G, 9.81, z, np.full(n, th), np.full(n, h), np.zeros(n),
+                           np.full(n, -V))
+    assert rate == pytest.approx(2 * nq * a * th * h * V * SQ3 / 2, rel=1e-14)
+    # flow along the outlet carries nothing out; a dry raster neither
+    assert so.outflow_rate(G, 9.81, z, np.full(n, th), np.full(n, h), np.full(n, V),
+                           np.zeros(n)) == pytest.approx(0.0, abs=1e-15)
+    assert so.outflow_rate(G, 9.81, z, np.full(n, th), np.zeros(n), np.zeros(n),
+                           np.full(n, -V)) == 0.0
+
+
+def test_outflow_rate_matches_the_books_of_one_step():
+    """The outflow booked by one tiny solver step is dt times the rate of the state."""
+    sc = synth.c1_planar(nq=16, nr=12)
+    h, v1, v2 = synth.random_state(sc, 5)
+    G = oracle.grid(sc.nq, sc.nr, sc.a, sc.side)
+    rate = so.outflow_rate(G, sc.g, sc.z, sc.theta, h, v1, v2)
+    dt = 2.0 ** -20
+    p = oracle.params(sc.g, sc.cfl, dt, sc.h_dry, sc.alpha_s)
+    _, _, _, b, _ = oracle.run(G, sc.z, sc.theta, sc.alpha_p, p, oracle.rain(), h, v1, v2, dt)
+    assert b.steps == 1 and rate > 0
+    assert b.outflow == pytest.approx(dt * rate, rel=1e-12)
+
+
+def test_apply_window_zero_change_keeps_the_state():
+    rng = np.random.default_rng(3)
+    n = 200
+    th = rng.uniform(0.3, 1.0, n)
+    th[:10] = 0.0  # inactive
+    h = rng.uniform(0.0, 0.1, n)
+    h[10:40] = 0.0  # dry
+    v1, v2 = rng.normal(size=n), rng.normal(size=n)
+    v1[10:40] = v2[10:40] = 0.0
+    hn, v1n, v2n = so.apply_window(h, v1, v2, th, np.zeros((n, 3)), 0.1, 0.01)
+    np.testing.assert_array_equal(hn, h)
+    wet = th * h > 1e-6
+    np.testing.assert_allclose(v1n[wet], v1[wet], rtol=1e-14)
+    np.testing.assert_allclose(v2n[wet], v2[wet], rtol=1e-14)
+    assert np.all(v1n[(th > 0) & ~wet] == 0.0)
+    # a negative predicted depth is clamped to dry, with zero velocity
+    out = np.zeros((n, 3))
+    out[:, 0] = -10.0
+    hn, v1n, _ = so.apply_window(h, v1, v2, th, out, 0.1, 0.01)
+    assert np.all(hn[th > 0] == 0.0) and np.all(v1n[th > 0] == 0.0)
+    np.testing.assert_array_equal(hn[:10], h[:10])
+
+
+def test_features_definition():
+    h = np.array([0.1, 0.0, 0.2])
+    v1 = np.array([1.0, 0.0, -2.0])
+    v2 = np.array([0.5, 0.0, 0.0])
+    z = np.array([3.0, 4.0, 5.0])
+    th = np.array([0.5, 1.0, 0.0])
+    f = so.features(h, v1, v2, z, th, 0.004, 0.1, 0.01, 10.0)
+    np.testing.assert_allclose(f[0], [1.0, 5.0, 2.5, 0.3, 0.5, 0.04])
+    np.testing.assert_allclose(f[1], [0.0, 0.0, 0.0, 0.4, 1.0, 0.04])
+    np.testing.assert_array_equal(f[2], np.zeros(6))  # inactive
+
+
+def test_window_rain_depth():
+    i = 100.0 / 3.6e6
+    assert so.window_rain_depth(0, i, 0.0, float("inf"), 10.0, 1.6, 16) == pytest.approx(1.6 * i)
+    # rain stops at T_d: sub-steps ending after it add nothing
+    assert so.window_rain_depth(0, i, 0.0, 11.0, 10.0, 1.6, 16) == pytest.approx(1.0 * i)
+    # triangular hyetograph: the right-endpoint sum tends to the integral (area i T_d / 2)
+    T = 1800.0
+    tot = sum(so.window_rain_depth(1, i, 0.25 * T, T, w * 1.6, 1.6, 16) for w in range(1125))
+    assert tot == pytest.approx(0.5 * i * T, rel=1e-3)
+
+
+def test_gate_residual_is_zero_on_an_exact_balance():
+    S0, R, O0, O1, w = 100.0, 2.0, 0.5, 0.7, 1.6
+    S1 = S0 + R - 0.5 * (O0 + O1) * w
+    assert so.gate_residual(S0, S1, R, O0, O1, w) == pytest.approx(0.0, abs=1e-15)
+    assert so.gate_residual(S0, S1 + 1.02, R, O0, O1, w) == pytest.approx(0.01)
