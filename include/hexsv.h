@@ -279,13 +279,13 @@ int hexsv_ensemble_info(const hexsv_ensemble *ens, int32_t *workgroups, int32_t 
 
 /* A hex-convolution residual network that predicts the change of the state
  * over a window of k solver steps (not part of the paper's method; the
- * solver stays its fallback and judge).  Layers: hex_conv(6 -> C), ReLU,
+ * solver stays its fallback and judge).  Layers: hex_conv(11 -> C), ReLU,
  * (layers - 2) x [hex_conv(C -> C), ReLU], hex_conv(C -> 3), where
  * hex_conv(x)[i][o] = b[o] + sum_{t<7, c} W[o][c][t] x[nbr_t(i)][c], tap 0
  * the cell, tap 1+k its neighbour in direction k, zero outside the raster.
  * Operands are bfloat16 with FP32 accumulation (MFMA); parameters are an FP32
- * master vector laid out per layer as W[o][c][t] then b[o].  Inputs are 6
- * FP32 features per cell, outputs 4 FP32 per cell (3 used), for a batch of
+ * master vector laid out per layer as W[o][c][t] then b[o].  Inputs are 11
+ * FP32 features per cell (see hexsv_sim_surrogate_features), outputs 4 FP32 per cell (3 used), for a batch of
  * samples on one nq x nr raster (cell (b, r, q) at b*nq*nr + r*nq + q).
  * Only C = 32 is built (EUNSUPPORTED otherwise); 2 <= layers <= 16. */
 int hexsv_surrogate_create(int32_t layers, int32_t channels, hexsv_surrogate **out);
@@ -297,10 +297,11 @@ int hexsv_surrogate_set_params(hexsv_surrogate *sur, const float *d_params, int6
 int hexsv_surrogate_get_params(const hexsv_surrogate *sur, float *d_params, int64_t n,
                                hipStream_t stream);
 /* Normalisation scales used when the surrogate advances a simulation:
- * {H, Q, Z, dH, dQ} (depth, discharge, terrain, output depth and discharge). */
+ * {H, Q, Z, dH, dQ, S}: input depth, discharge, elevation, output depth and
+ * discharge, input slope (1 <= n <= 8; unset scales are 1). */
 int hexsv_surrogate_set_scales(hexsv_surrogate *sur, const float *scales, int32_t n);
 int hexsv_surrogate_get_scales(const hexsv_surrogate *sur, float *scales, int32_t n);
-/* Batched forward: d_features (batch*nq*nr x 6) -> d_out (batch*nq*nr x 4). */
+/* Batched forward: d_features (batch*nq*nr x 11) -> d_out (batch*nq*nr x 4). */
 int hexsv_surrogate_forward(hexsv_surrogate *sur, int32_t batch, int32_t nq, int32_t nr,
                             const float *d_features, float *d_out, hipStream_t stream);
 /* Mean L1 loss against d_target (batch*nq*nr x 3) and its parameter gradient
@@ -313,26 +314,42 @@ int hexsv_surrogate_train_step(hexsv_surrogate *sur, int32_t batch, int32_t nq, 
                                const float *d_features, const float *d_target, float lr,
                                double *loss, hipStream_t stream);
 
-/* Surrogate input features from FP64 device arrays of n cells (scales from
- * set_scales): h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, rain_depth/H;
- * d_features is n x 6 FP32. */
-int hexsv_surrogate_features(const hexsv_surrogate *sur, int64_t n, const double *d_h,
-                             const double *d_v1, const double *d_v2, const double *d_z,
-                             const double *d_theta, double rain_depth, float *d_features,
-                             hipStream_t stream);
+/* Network inputs of a window starting at the simulation's current state,
+ * n x 11 FP32 into d_features (scales from set_scales):
+ *   h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, rain_depth/H, (dz/dx)/S,
+ *   (dz/dy)/S, x_h/dH, x_q1/dQ, x_q2/dQ,
+ * all but theta zero on inactive cells.  rain_depth is the window's rain (k
+ * equal sub-steps, each at the rate of its end).  The slope of a cell is the
+ * least-squares fit of the elevation differences along the three axes of its
+ * hexagon (central differences of the two active neighbours on an axis,
+ * one-sided with one), exact for a plane.  x is the change of one probe step
+ * of the scheme (rain included; dt = min(dt_max, CFL bound of the state))
+ * scaled by window/dt.  The state and books are not changed.  These are the
+ * inputs run_surrogate feeds the network; training pairs use them too. */
+int hexsv_sim_surrogate_features(hexsv_sim *sim, hexsv_surrogate *sur, double window, int32_t k,
+                                 float *d_features, hipStream_t stream);
 
 /* Advance a simulation to t_end in windows of `window` seconds predicted by
- * the surrogate (trained on windows of k solver steps).  Each window: the
- * network's change is applied, then the mass-balance residual
- *   rho = |S_pred - S_0 - (R_win - O_win)| / (S_0 + R_win)
- * is evaluated in FP64 (S stored volume, R_win the rain volume of the window
- * by the right-endpoint rule on k sub-steps, O_win the trapezoid of the
- * outflow rates at both ends); if rho > residual_tol (or the prediction is not
- * finite) the window is discarded and the plain solver advances it instead.
- * A final window shorter than `window` is always solved.  Returns the counts
- * of accepted and fallback windows.  Synchronises once per window. */
+ * the surrogate (trained on windows of that span).  A window runs entirely on
+ * the device: the probe step and features of the state (see
+ * hexsv_sim_surrogate_features), the network, the predicted state
+ *   h' = max(h + x_h + dH out0, 0),  theta h' v' = theta h v + x_q + dQ (out1, out2)
+ * (v' = 0 where theta h' <= 1e-6), and the FP64 water-balance residual
+ *   rho = |S' - S - (R - O)| / max(S + R, 1e-300)
+ * (S, S' stored volume sum sigma theta h at both ends, R = rain volume of the
+ * window as k equal sub-steps each taking the rate at its end, O the outflow
+ * volume by the trapezoid rule on the outflow rates of both states).  A
+ * finite window with rho <= residual_tol is kept (time, rain and outflow books
+ * and the CFL bound advance; steps does not); with project != 0 its depths are
+ * then scaled by (S + R - O) / S' so that the kept state closes the balance
+ * exactly (small residuals would otherwise add up over many windows).  A
+ * refused window is discarded and the plain solver advances that span.  A last span shorter than `window` is
+ * always solved.  Windows are chained several to a graph launch; the host
+ * synchronises once per chain.  Counts of kept and solved windows are
+ * returned.  The surrogate must not be used by another simulation while this
+ * runs (its workspace is shared). */
 int hexsv_sim_run_surrogate(hexsv_sim *sim, hexsv_surrogate *sur, double t_end, double window,
-                            int32_t k, double residual_tol, int64_t *n_accepted,
+                            int32_t k, double residual_tol, int32_t project, int64_t *n_accepted,
                             int64_t *n_fallback, hipStream_t stream);
 
 /* Number of tile variants built, and the shape of variant v. */

@@ -5,7 +5,9 @@ network that maps the solver state at time t to the state change after k
 explicit steps, used with the paper's solver as fallback and judge.  This
 module defines its arithmetic plainly so the GPU kernels can be checked:
 
-  features  x0 (N x 6):  h/H, q1/Q, q2/Q, z/Z, theta, (rain depth of the window)/H
+  features  x0 (N x 11): h/H, q1/Q, q2/Q, z/Z, theta, (rain depth of the window)/H,
+                         the terrain slope (dz/dx, dz/dy)/S, and the change of one probe step
+                         of the scheme scaled to the window, (x_h/dH, x_q1/dQ, x_q2/dQ)
   layer l:  y = b + sum_{c, t} W[o, c, t] * x[c, nbr_t(i)]   (hex_conv; tap 0 = the cell,
             tap 1+k = its neighbour in direction k, zero outside the raster)
             ReLU after layers 1..L-1; the last layer gives 3 channels
@@ -19,11 +21,13 @@ layer by layer as W[o][c][t] (o < cout, c < cin, t < 7) followed by b[o].
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 import oracle
 
-FEATURES = 6
+FEATURES = 11
 OUTPUTS = 3
 TAPS = 7
 
@@ -89,7 +93,7 @@ def _conv_bwd(G, x, W, dy):
 
 
 def forward(G, p, x0, layers=4, channels=32, bf16=True):
-    """Per-sample forward: x0 (N, 6) -> (output (N, 3), saved activations)."""
+    """Per-sample forward: x0 (N, 11) -> (output (N, 3), saved activations)."""
     rnd = bf16_round if bf16 else (lambda a: np.asarray(a, np.float64))
     params = unflatten(p, layers, channels)
     if bf16:
@@ -147,12 +151,64 @@ def adam_update(p, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 # + rain - outflow - clamped; Sec. 4.2, Table BasinSusita reports the same
 # balance).  Below are the plain definitions of the pieces.
 
-def features(h, v1, v2, z, theta, rain_depth, H, Q, Z):
-    """Network input (N, 6) of a state: h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, depth/H.
+def terrain_slope(G, z):
+    """(dz/dx, dz/dy) per cell from its neighbours along the three axes of the hexagon.
 
-    All channels but theta are zero on inactive cells (theta = 0)."""
+    Along axis k < 3 (directions k and k+3; neighbour centres at distance sqrt(3) a along
+    the edge normals +-n_k) the slope estimate is d_k = D_k / (2 sqrt(3) a), with
+    D_k = z_k - z_{k+3}, or twice the one-sided difference when one of the two edges is not
+    INTERIOR; axes with neither neighbour are skipped.  The gradient is the least-squares
+    (minimum-norm) fit of n_k . grad z = d_k over the axes present, exact for a plane when
+    two or three axes are present."""
+    z = np.asarray(z, np.float64)
+    s = np.zeros((G.n, 2))
+    for i in range(G.n):
+        M = np.zeros((2, 2))
+        b = np.zeros(2)
+        for k in range(3):
+            j, m = G.nbr[i, k], G.nbr[i, k + 3]
+            if j >= 0 and m >= 0:
+                d = z[j] - z[m]
+            elif j >= 0:
+                d = 2.0 * (z[j] - z[i])
+            elif m >= 0:
+                d = 2.0 * (z[i] - z[m])
+            else:
+                continue
+            n = np.array(oracle.normal(k))
+            M += np.outer(n, n)
+            b += n * d / (2.0 * math.sqrt(3.0) * G.a)
+        s[i] = np.linalg.pinv(M) @ b
+    return s
+
+
+def extrapolation(G, z, theta, alpha_p, p, r, t0, window, h, v1, v2):
+    """Change of one probe step of the scheme scaled to the window: (x_h, x_q1, x_q2).
+
+    The probe step is the solver's next step from the state at t0 (dt = min(dt_max, CFL
+    bound), rain at t0 + dt; eq. fvm_2D_eq_frac.07 with Appendix A); x = (window/dt) times its
+    change of h and of q = theta h v."""
+    th = np.where(G.active, np.asarray(theta, np.float64), 0.0)
+    h, v1, v2 = (np.asarray(a, np.float64) for a in (h, v1, v2))
+    dt = oracle.dt(G.a, p, oracle.cmax(G, p.g, th, h, v1, v2), t0, math.inf)
+    hn, v1n, v2n, _ = oracle.step_cells(G, z, th, alpha_p, p, r, dt, t0 + dt, h, v1, v2,
+                                        np.arange(G.n))
+    xs = window / dt
+    return xs * (hn - h), xs * (th * hn * v1n - th * h * v1), xs * (th * hn * v2n - th * h * v2)
+
+
+def features(G, h, v1, v2, z, theta, rain_depth, ext, H, Q, Z, S, dH, dQ):
+    """Network input (N, 11) of a state: h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, depth/H,
+    (dz/dx)/S, (dz/dy)/S, x_h/dH, x_q1/dQ, x_q2/dQ with ext = (x_h, x_q1, x_q2) of
+    :func:`extrapolation`.  All channels but theta are zero on inactive cells (theta = 0).
+
+    Absolute elevation is kept as a channel, but bfloat16 cannot resolve the differences of
+    neighbouring elevations that drive the flow, so the slope enters as channels of its own;
+    likewise the probe step supplies, at full precision, the flux divergence that is a small
+    difference of large discharges."""
     h, v1, v2, z, th = (np.asarray(a, np.float64) for a in (h, v1, v2, z, theta))
     act = th > 0.0
+    sl = terrain_slope(G, z)
     f = np.zeros((h.size, FEATURES))
     f[:, 0] = np.where(act, h / H, 0.0)
     f[:, 1] = np.where(act, th * h * v1 / Q, 0.0)
@@ -160,18 +216,25 @@ def features(h, v1, v2, z, theta, rain_depth, H, Q, Z):
     f[:, 3] = np.where(act, z / Z, 0.0)
     f[:, 4] = th
     f[:, 5] = np.where(act, rain_depth / H, 0.0)
+    f[:, 6] = np.where(act, sl[:, 0] / S, 0.0)
+    f[:, 7] = np.where(act, sl[:, 1] / S, 0.0)
+    f[:, 8] = np.where(act, ext[0] / dH, 0.0)
+    f[:, 9] = np.where(act, ext[1] / dQ, 0.0)
+    f[:, 10] = np.where(act, ext[2] / dQ, 0.0)
     return f
 
 
-def apply_window(h, v1, v2, theta, out, dH, dQ, m_min=1e-6):
-    """State after a predicted window: h' = max(h + dH out0, 0), q' = theta h v + dQ (out1, out2),
-    v' = q' / (theta h') where theta h' > m_min, else 0; inactive cells unchanged."""
+def apply_window(h, v1, v2, theta, out, dH, dQ, ext=None, m_min=1e-6):
+    """State after a predicted window: h' = max(h + x_h + dH out0, 0),
+    q' = theta h v + x_q + dQ (out1, out2), v' = q' / (theta h') where theta h' > m_min, else 0;
+    inactive cells unchanged (x = 0 when ext is None)."""
     h, v1, v2, th = (np.asarray(a, np.float64) for a in (h, v1, v2, theta))
     out = np.asarray(out, np.float64)
+    xh, xq1, xq2 = (0.0, 0.0, 0.0) if ext is None else ext
     act = th > 0.0
-    hn = np.maximum(h + dH * out[:, 0], 0.0)
-    q1 = th * h * v1 + dQ * out[:, 1]
-    q2 = th * h * v2 + dQ * out[:, 2]
+    hn = np.maximum(h + xh + dH * out[:, 0], 0.0)
+    q1 = th * h * v1 + xq1 + dQ * out[:, 1]
+    q2 = th * h * v2 + xq2 + dQ * out[:, 2]
     mn = th * hn
     wet = mn > m_min
     with np.errstate(divide="ignore", invalid="ignore"):

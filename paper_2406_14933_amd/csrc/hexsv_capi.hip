@@ -153,9 +153,16 @@ struct hexsv_sim {
     hipGraph_t graph;
     hipGraphExec_t gexec;
     bool graph_ok, fields_set, state_set;
-    // surrogate windows: features, network output, outflow-rate partials
-    float *d_feat, *d_sout;
-    double *d_opart, *h_opart;
+    // surrogate windows: control record (device + pinned mirror), outflow
+    // partials of both ends, and a graph of WIN_CHAIN chained windows
+    SurWin *d_sw, *h_sw;
+    Part *d_op;
+    void *d_scr;  // probe state: 3 x cells of the state's precision
+    hipGraph_t wgraph;
+    hipGraphExec_t wexec;
+    const hexsv_surrogate *w_sur;
+    uint64_t w_gen;
+    float w_scales[8];
     // optional device timing of graph replays (hipEvents on the run stream)
     bool timing;
     hipEvent_t ev0, ev1;
@@ -182,6 +189,14 @@ static void drop_graph(hexsv_sim *s) {
     s->gexec = nullptr;
     s->graph = nullptr;
     s->graph_ok = false;
+}
+
+static void drop_win_graph(hexsv_sim *s) {
+    if (s->wexec) (void)hipGraphExecDestroy(s->wexec);
+    if (s->wgraph) (void)hipGraphDestroy(s->wgraph);
+    s->wexec = nullptr;
+    s->wgraph = nullptr;
+    s->w_sur = nullptr;
 }
 
 extern "C" int hexsv_tile_count(void) { return NUM_TILES; }
@@ -262,10 +277,11 @@ extern "C" void hexsv_sim_destroy(hexsv_sim *s) {
     if (s->d_chk) (void)hipFree(s->d_chk);
     if (s->h_ctl) (void)hipHostFree(s->h_ctl);
     if (s->h_chk) (void)hipHostFree(s->h_chk);
-    if (s->d_feat) (void)hipFree(s->d_feat);
-    if (s->d_sout) (void)hipFree(s->d_sout);
-    if (s->d_opart) (void)hipFree(s->d_opart);
-    if (s->h_opart) (void)hipHostFree(s->h_opart);
+    drop_win_graph(s);
+    if (s->d_sw) (void)hipFree(s->d_sw);
+    if (s->h_sw) (void)hipHostFree(s->h_sw);
+    if (s->d_op) (void)hipFree(s->d_op);
+    if (s->d_scr) (void)hipFree(s->d_scr);
     delete s;
 }
 
@@ -615,58 +631,150 @@ extern "C" int hexsv_sim_set_books(hexsv_sim *s, const hexsv_books *b, hipStream
 
 // ------------------------------------------------------------ surrogate
 
-static const int OUTFLOW_PARTS = 256;
+// Scratch of the windows (probe state) and their control record.
+static int window_buffers(hexsv_sim *s) {
+    if (!s->d_sw) {
+        HIP_TRY(hipMalloc(&s->d_sw, sizeof(SurWin)));
+        HIP_TRY(hipHostMalloc(&s->h_sw, sizeof(SurWin), hipHostMallocDefault));
+        HIP_TRY(hipMalloc(&s->d_op, sizeof(Part) * 2 * OUTFLOW_PARTS));
+        HIP_TRY(hipMalloc(&s->d_scr, s->esz * 3 * (size_t)s->grid->n));
+    }
+    return HEXSV_OK;
+}
 
-extern "C" int hexsv_surrogate_features(const hexsv_surrogate *sur, int64_t n, const double *d_h,
-                                        const double *d_v1, const double *d_v2, const double *d_z,
-                                        const double *d_theta, double rain_depth, float *d_features,
-                                        hipStream_t stream) {
-    if (!sur || n < 1 || !d_h || !d_v1 || !d_v2 || !d_z || !d_theta || !d_features)
-        return fail(HEXSV_EINVAL, "surrogate_features: bad argument");
-    float sc[5];
-    int rc = hexsv_surrogate_get_scales(sur, sc, 5);
+static void window_record(hexsv_sim *s, double t_stop, double window, int32_t k, double tol,
+                          int project) {
+    SurWin &w = *s->h_sw;
+    memset(&w, 0, sizeof w);
+    w.t_stop = t_stop;
+    w.window = window;
+    w.tol = tol;
+    w.k = k;
+    w.project = project ? 1 : 0;
+    w.perr_cell = -1;
+}
+
+static FeatScale feat_scale(const float *sc) { return FeatScale{sc[0], sc[1], sc[2], sc[5], sc[3], sc[4]}; }
+
+template <typename T>
+static int window_features(hexsv_sim *s, hexsv_surrogate *sur, double window, int32_t k,
+                           float *d_features, hipStream_t st) {
+    int rc = window_buffers(s);
     if (rc) return rc;
-    HIP_TRY(launch_features<double>(n, d_h, d_v1, d_v2, d_z, d_theta, rain_depth, sc[0], sc[1], sc[2],
-                                    d_features, stream));
+    float sc[8];
+    rc = hexsv_surrogate_get_scales(sur, sc, 8);
+    if (rc) return rc;
+    window_record(s, INFINITY, window, k, 0.0, 0);
+    HIP_TRY(hipMemcpyAsync(s->d_sw, s->h_sw, sizeof(SurWin), hipMemcpyHostToDevice, st));
+    const KDom<T> d = dom_of<T>(s);
+    HIP_TRY(launch_win_reset(s->d_sw, st));
+    HIP_TRY(launch_win_begin(s->d_ctl, s->d_sw, s->rn, s->kc, st));
+    HIP_TRY(launch_win_probe<T>(d, s->grid->kg, s->kc, s->rn, s->d_ctl, s->d_sw, (T *)s->d_scr,
+                                s->p.dt_max, st));
+    HIP_TRY(launch_win_features<T>(d, s->grid->kg, s->grid->edge, s->d_ctl, s->d_sw,
+                                   (const T *)s->d_scr, s->p.dt_max, feat_scale(sc), 0, d_features,
+                                   st));
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_surrogate_features(hexsv_sim *s, hexsv_surrogate *sur, double window,
+                                            int32_t k, float *d_features, hipStream_t stream) {
+    if (!s || !sur || !d_features || !(window > 0.0) || !isfinite(window) || k < 1)
+        return fail(HEXSV_EINVAL, "surrogate_features: bad argument");
+    if (!s->state_set) return fail(HEXSV_ESTATE, "surrogate_features: call set_state first");
+    return s->prec == HEXSV_FP64 ? window_features<double>(s, sur, window, k, d_features, stream)
+                                 : window_features<float>(s, sur, window, k, d_features, stream);
+}
+
+// Windows chained in one graph launch (a refused window stops the rest of
+// its chain, whose kernels then return at once).
+static const int WIN_CHAIN = 8;
+
+// One window: begin, outflow rate of the state, features, network, predicted
+// state, its outflow rate and sums, gate.
+template <typename T>
+static int window_body(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float *out,
+                       const float *sc, hipStream_t st) {
+    const KDom<T> d = dom_of<T>(s);
+    const KGrid &g = s->grid->kg;
+    const double l = s->grid->edge;
+    const int64_t n = s->grid->n;
+    T *scr = (T *)s->d_scr;
+    const double dt_max = s->p.dt_max;
+    Part *op0 = s->d_op, *op1 = s->d_op + OUTFLOW_PARTS;
+    HIP_TRY(launch_win_begin(s->d_ctl, s->d_sw, s->rn, s->kc, st));
+    HIP_TRY(launch_win_outflow<T>(d, g, l, s->d_ctl, s->d_sw, 0, op0, st));
+    HIP_TRY(launch_win_probe<T>(d, g, s->kc, s->rn, s->d_ctl, s->d_sw, scr, dt_max, st));
+    HIP_TRY(launch_win_features<T>(d, g, s->grid->edge, s->d_ctl, s->d_sw, scr, dt_max,
+                                   feat_scale(sc), 1, x0, st));
+    int rc = sur_forward_x0(sur, g.nq, g.nr, st);
+    if (rc) return rc;
+    HIP_TRY(launch_win_apply<T>(d, n, s->d_ctl, s->d_sw, scr, dt_max, out, nn::OUT_STRIDE, sc[3],
+                                sc[4], 1e-6, st));
+    HIP_TRY(launch_win_outflow<T>(d, g, l, s->d_ctl, s->d_sw, 1, op1, st));
+    HIP_TRY(launch_win_sums<T>(d, n, s->kc, s->d_ctl, s->d_sw, s->d_part, st));
+    HIP_TRY(launch_win_gate(s->d_ctl, s->d_sw, s->d_part, PRIME_BLOCKS, op0, op1, OUTFLOW_PARTS,
+                            s->kc, st));
+    HIP_TRY(launch_win_scale<T>(d, n, s->d_ctl, s->d_sw, st));
     return HEXSV_OK;
 }
 
 template <typename T>
-static int outflow_rate(hexsv_sim *s, int par, hipStream_t st, double *rate) {
-    HIP_TRY(launch_outflow_rate<T>(dom_of<T>(s), par, s->grid->kg, s->grid->edge, s->d_opart,
-                                   OUTFLOW_PARTS, st));
-    HIP_TRY(hipMemcpyAsync(s->h_opart, s->d_opart, sizeof(double) * OUTFLOW_PARTS,
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    double a = 0.0;
-    for (int k = 0; k < OUTFLOW_PARTS; ++k) a += s->h_opart[k];
-    *rate = a;
+static int window_chain(hexsv_sim *s, hexsv_surrogate *sur, int nwin, void *x0, const float *out,
+                        const float *sc, hipStream_t st) {
+    HIP_TRY(launch_win_reset(s->d_sw, st));
+    for (int w = 0; w < nwin; ++w) {
+        int rc = window_body<T>(s, sur, x0, out, sc, st);
+        if (rc) return rc;
+    }
     return HEXSV_OK;
 }
 
-static double host_rain_rate(const KRain &rn, double t) {
-    if (rn.kind == 0) return (t >= 0.0 && t <= rn.T_d) ? rn.i_a : 0.0;
-    const double gamma = rn.t_a / rn.T_d;
-    if (t >= 0.0 && t <= rn.t_a) return rn.i_a * (t / rn.t_a);
-    if (t > rn.t_a && t <= rn.T_d) return rn.i_a * ((1.0 - t / rn.T_d) / (1.0 - gamma));
-    return 0.0;
+template <typename T>
+static int capture_windows(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float *out,
+                           const float *sc, uint64_t gen) {
+    drop_win_graph(s);
+    HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+    int rc = window_chain<T>(s, sur, WIN_CHAIN, x0, out, sc, s->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s->cap, &g);
+    if (rc || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : fail(HEXSV_EHIP, "window graph capture failed: %s", hipGetErrorString(e2));
+    }
+    s->wgraph = g;
+    HIP_TRY(hipGraphInstantiate(&s->wexec, s->wgraph, nullptr, nullptr, 0));
+    s->w_sur = sur;
+    s->w_gen = gen;
+    return HEXSV_OK;
 }
 
 template <typename T>
 static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, double window,
-                             int32_t k, double tol, int64_t *n_acc, int64_t *n_fb,
+                             int32_t k, double tol, int project, int64_t *n_acc, int64_t *n_fb,
                              hipStream_t st) {
-    const int64_t n = s->grid->n;
-    if (!s->d_feat) {
-        HIP_TRY(hipMalloc(&s->d_feat, sizeof(float) * 6 * n));
-        HIP_TRY(hipMalloc(&s->d_sout, sizeof(float) * 4 * n));
-        HIP_TRY(hipMalloc(&s->d_opart, sizeof(double) * OUTFLOW_PARTS));
-        HIP_TRY(hipHostMalloc(&s->h_opart, sizeof(double) * OUTFLOW_PARTS, hipHostMallocDefault));
-    }
-    float sc[5];
-    int rc = hexsv_surrogate_get_scales(sur, sc, 5);
+    int rc = window_buffers(s);
     if (rc) return rc;
-    const KDom<T> d = dom_of<T>(s);
+    float sc[8];
+    rc = hexsv_surrogate_get_scales(sur, sc, 8);
+    if (rc) return rc;
+    void *x0 = nullptr;
+    const float *out = nullptr;
+    uint64_t gen = 0;
+    rc = sur_window_bind(sur, s->grid->kg.nq, s->grid->kg.nr, &x0, &out, &gen);
+    if (rc) return rc;
+    // the scales are kernel arguments of the graph: rebuild when they change
+    static_assert(sizeof(sc) == 8 * sizeof(float), "scales");
+    bool same = s->wexec && s->w_sur == sur && s->w_gen == gen;
+    for (int j = 0; j < 8 && same; ++j) same = s->w_scales[j] == sc[j];
+    if (!same) {
+        rc = capture_windows<T>(s, sur, x0, out, sc, gen);
+        if (rc) return rc;
+        for (int j = 0; j < 8; ++j) s->w_scales[j] = sc[j];
+    }
+    window_record(s, t_end, window, k, tol, project);
+    const SurWin &w = *s->h_sw;
+    HIP_TRY(hipMemcpyAsync(s->d_sw, s->h_sw, sizeof(SurWin), hipMemcpyHostToDevice, st));
     Ctl &c = *s->h_ctl;
     for (;;) {
         HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -674,49 +782,27 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
         if (c.err) return fail(HEXSV_ENUMERIC, "run_surrogate: non-finite value at cell %d", c.err_cell);
         const double t0 = c.t;
         if (t0 >= t_end) break;
-        if (t_end - t0 < window) {  // last partial window: the plain solver
+        // whole windows left, formed exactly as the device forms them
+        int left = 0;
+        for (double t = t0; left < WIN_CHAIN && t + window <= t_end; t += window) ++left;
+        if (left == 0) {  // last partial span: the plain solver
             rc = hexsv_sim_run(s, t_end, 0, st);
             if (rc) return rc;
             *n_fb += 1;
             break;
         }
-        const int par = c.parity;
-        const double S0 = c.stored;
-        // rain depth of the window by the right-endpoint rule on k sub-steps (as the solver)
-        double depth = 0.0;
-        for (int j = 1; j <= k; ++j) depth += (window / k) * host_rain_rate(s->rn, t0 + j * (window / k));
-        double O0 = 0.0, O1 = 0.0;
-        rc = outflow_rate<T>(s, par, st, &O0);
-        if (rc) return rc;
-        HIP_TRY(launch_features<T>(n, d.buf(par, 0), d.buf(par, 1), d.buf(par, 2), d.z, d.th, depth,
-                                   sc[0], sc[1], sc[2], s->d_feat, st));
-        rc = hexsv_surrogate_forward(sur, 1, s->grid->kg.nq, s->grid->kg.nr, s->d_feat, s->d_sout, st);
-        if (rc) return rc;
-        HIP_TRY(launch_apply_surrogate<T>(d, par, n, s->d_sout, sc[3], sc[4], 1e-6, st));
-        rc = outflow_rate<T>(s, par ^ 1, st, &O1);
-        if (rc) return rc;
-        // stored volume and CFL bound of the predicted state (books kept)
-        const Ctl saved = c;
-        c.parity = par ^ 1;
-        HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
-        HIP_TRY(prime<T>(s, 0, st));
+        if (left == WIN_CHAIN) {
+            HIP_TRY(hipGraphLaunch(s->wexec, st));
+        } else {
+            rc = window_chain<T>(s, sur, left, x0, out, sc, st);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipMemcpyAsync(s->h_sw, s->d_sw, sizeof(SurWin), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        const double R = s->kc.area_active * depth;
-        const double Ow = 0.5 * (O0 + O1) * window;
-        double ref = S0 + R;
-        if (ref < 1e-300) ref = 1e-300;
-        const double rho = fabs(c.stored - S0 - (R - Ow)) / ref;
-        if (isfinite(c.stored) && rho <= tol) {
-            c.t = t0 + window;
-            c.rain += R;
-            c.outflow += Ow;
-            HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
-            *n_acc += 1;
-        } else {
-            c = saved;  // the state at t0 is intact in buffer `par`
-            HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
-            rc = hexsv_sim_run(s, t0 + window, 0, st);
+        *n_acc += w.accepted;
+        if (w.rejected) {  // the refused window's span, by the plain solver from its start
+            rc = hexsv_sim_run(s, c.t + window, 0, st);
             if (rc) return rc;
             *n_fb += 1;
         }
@@ -726,14 +812,16 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
 
 extern "C" int hexsv_sim_run_surrogate(hexsv_sim *s, hexsv_surrogate *sur, double t_end,
                                        double window, int32_t k, double residual_tol,
-                                       int64_t *n_accepted, int64_t *n_fallback, hipStream_t st) {
-    if (!s || !sur || !(window > 0.0) || k < 1 || !(residual_tol >= 0.0))
+                                       int32_t project, int64_t *n_accepted, int64_t *n_fallback,
+                                       hipStream_t st) {
+    if (!s || !sur || !(window > 0.0) || !isfinite(window) || k < 1 || !(residual_tol >= 0.0))
         return fail(HEXSV_EINVAL, "run_surrogate: bad argument");
     if (!s->state_set) return fail(HEXSV_ESTATE, "run_surrogate: call set_state first");
     int64_t a = 0, f = 0;
-    const int rc = s->prec == HEXSV_FP64
-                       ? surrogate_windows<double>(s, sur, t_end, window, k, residual_tol, &a, &f, st)
-                       : surrogate_windows<float>(s, sur, t_end, window, k, residual_tol, &a, &f, st);
+    const int rc =
+        s->prec == HEXSV_FP64
+            ? surrogate_windows<double>(s, sur, t_end, window, k, residual_tol, project, &a, &f, st)
+            : surrogate_windows<float>(s, sur, t_end, window, k, residual_tol, project, &a, &f, st);
     if (n_accepted) *n_accepted = a;
     if (n_fallback) *n_fallback = f;
     return rc;

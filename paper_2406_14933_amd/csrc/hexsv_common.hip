@@ -9,8 +9,6 @@
 namespace hexsv {
 
 // Deterministic reduction of partial records: fixed strided assignment to
-// threads, xor-butterfly within waves, fixed order across waves.
-// Deterministic reduction of partial records: fixed strided assignment to
 // threads (eight independent loads in flight per thread), xor-butterfly within
 // waves, fixed order across waves.
 template <int NT>
@@ -178,6 +176,102 @@ __global__ __launch_bounds__(1024) void k_ens_finalize(const EnsScen *scen, Ctl 
 hipError_t launch_ens_finalize(const EnsScen *scen, Ctl *ctl, const Part *part, int nscen,
                                hipStream_t stream) {
     hipLaunchKernelGGL(k_ens_finalize, dim3(nscen), dim3(1024), 0, stream, scen, ctl, part);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ surrogate windows
+
+__global__ void k_win_reset(SurWin *sw) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sw->live = 0;
+        sw->alive = 1;
+        sw->rejected = 0;
+        sw->accepted = 0;
+        sw->scale_live = 0;
+    }
+}
+
+hipError_t launch_win_reset(SurWin *sw, hipStream_t stream) {
+    hipLaunchKernelGGL(k_win_reset, dim3(1), dim3(64), 0, stream, sw);
+    return hipGetLastError();
+}
+
+// Starts a window if the chain is alive and the span fits before t_stop: its
+// rain depth is the sum over k equal sub-steps of the rate at each sub-step's
+// end (the solver's right-endpoint rule, eq. fvm_2D_eq_frac.05-1).
+__global__ void k_win_begin(Ctl *ctl, SurWin *sw, KRain rn, KConst kc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double t0 = ctl->t;
+    sw->scale_live = 0;
+    if (!sw->alive || ctl->err || !(t0 + sw->window <= sw->t_stop)) {
+        sw->live = 0;
+        return;
+    }
+    const double dt = sw->window / sw->k;
+    double depth = 0.0;
+    for (int j = 1; j <= sw->k; ++j) depth += dt * rain_rate(rn, t0 + j * dt);
+    sw->depth = depth;
+    sw->R = kc.area_active * depth;
+    sw->t0 = t0;
+    sw->S0 = ctl->stored;
+    sw->live = 1;
+}
+
+hipError_t launch_win_begin(Ctl *ctl, SurWin *sw, const KRain &rn, const KConst &kc,
+                            hipStream_t stream) {
+    hipLaunchKernelGGL(k_win_begin, dim3(1), dim3(64), 0, stream, ctl, sw, rn, kc);
+    return hipGetLastError();
+}
+
+// Water-balance gate of a window.  With S0, S1 the stored volumes at both
+// ends, R the rain volume and O the outflow volume by the trapezoid rule on
+// the outflow rates of both states, rho = |S1 - S0 - (R - O)| / max(S0 + R,
+// tiny).  Accepted (finite and rho <= tol): the predicted buffer becomes the
+// state and time, books and CFL bound advance; with `project` the depths are
+// then rescaled (k_win_scale) so that the stored volume is S0 + R - O
+// exactly, which keeps the accepted residuals from adding up over many
+// windows.  Refused: the chain stops and the state at t0 is untouched.
+__global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const Part *part,
+                                                   int nparts, const Part *op0, const Part *op1,
+                                                   int nop, KConst kc) {
+    if (!sw->live) return;
+    const Part p = reduce_parts<1024>(part, nparts);
+    const Part o0 = reduce_parts<1024>(op0, nop);
+    const Part o1 = reduce_parts<1024>(op1, nop);
+    if (threadIdx.x != 0) return;
+    const double Ow = 0.5 * (o0.stored + o1.stored) * sw->window;
+    double ref = sw->S0 + sw->R;
+    if (ref < 1e-300) ref = 1e-300;
+    const double rho = fabs(p.stored - sw->S0 - (sw->R - Ow)) / ref;
+    sw->rho = rho;
+    const bool ok = p.clamp == 0.0 && isfinite(p.stored) && isfinite(Ow) && rho <= sw->tol;
+    if (ok) {
+        const double target = sw->S0 + sw->R - Ow;
+        double stored = p.stored;
+        if (sw->project && p.stored > 0.0 && target > 0.0) {
+            sw->scale = target / p.stored;
+            sw->scale_live = 1;
+            stored = target;
+        }
+        ctl->t = sw->t0 + sw->window;
+        ctl->parity ^= 1;
+        ctl->stored = stored;
+        ctl->rain += sw->R;
+        ctl->outflow += Ow;
+        ctl->last_cmax = p.cmax;
+        ctl->tau = p.cmax > 0.0 ? kc.cfl_phi / p.cmax : INFINITY;
+        sw->accepted += 1;
+    } else {
+        sw->alive = 0;
+        sw->rejected = 1;
+    }
+    sw->live = 0;
+}
+
+hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, int nparts, const Part *op0,
+                           const Part *op1, int nop, const KConst &kc, hipStream_t stream) {
+    hipLaunchKernelGGL(k_win_gate, dim3(1), dim3(1024), 0, stream, ctl, sw, part, nparts, op0, op1,
+                       nop, kc);
     return hipGetLastError();
 }
 

@@ -6,4 +6,5 @@
 namespace hexsv {
 HEXSV_INSTANTIATE(double)
 HEXSV_INSTANTIATE_ENSEMBLE(double)
+
 }

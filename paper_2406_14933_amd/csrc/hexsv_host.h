@@ -41,3 +41,13 @@ int tune_cache_store(const char *path, const char *kernel, int prec, int64_t cel
                      double ms, const double *all_ms, int nvar);
 // Tile recorded for this key in $HEXSV_TUNE_CACHE, else `fallback`.
 int tuned_tile(const char *kernel, int prec, int64_t cells, int fallback);
+
+// ------------------------------------------------ surrogate for the solver
+// Workspace of the surrogate for one nq x nr sample: the packed bf16 input
+// (nn::FEATURES channels per cell) and the FP32 output (nn::OUT_STRIDE per
+// cell); gen changes whenever those buffers move (graphs that captured them
+// must be rebuilt).
+int sur_window_bind(hexsv_surrogate *s, int nq, int nr, void **x0, const float **out,
+                    uint64_t *gen);
+// Network forward over the bound input into the bound output (stream-ordered).
+int sur_forward_x0(hexsv_surrogate *s, int nq, int nr, hipStream_t st);

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "hexsv_device.h"
+#include "hexsv_nn.h"
 
 namespace hexsv {
 
@@ -96,17 +97,65 @@ hipError_t launch_check_fields(const double *z, const double *th, const double *
 hipError_t launch_check_state(const double *h, const double *v1, const double *v2,
                               const uint8_t *active, int64_t n, int32_t *chk, hipStream_t stream);
 
-// Surrogate glue (see hexsv_kernels.h).
-template <typename S>
-hipError_t launch_features(int64_t n, const S *h, const S *v1, const S *v2, const S *z,
-                           const S *th, double rain_depth, float H, float Q, float Z, float *f,
-                           hipStream_t stream);
+// ------------------------------------------------------ surrogate windows
+//
+// A window advances the state by a fixed span with one network call; it is
+// kept only if the predicted state keeps the water balance.  Everything of a
+// window runs on the device (so windows chain inside a graph); the host only
+// reads this record after a chain.
+struct alignas(64) SurWin {
+    double t_stop, window, tol;     // set by the host for a run
+    double depth, R, t0, S0, rho;   // of the current window
+    int32_t k;                      // rain sub-steps of a window
+    int32_t live;                   // the current window runs
+    int32_t alive;                  // every window of this chain so far was accepted
+    int32_t rejected;               // a window of this chain was refused
+    int32_t accepted;               // windows accepted in this chain
+    int32_t project;                // 1: rescale an accepted state onto the balance
+    int32_t scale_live;             // the accepted state waits for its rescaling
+    int32_t perr, perr_cell;        // non-finite value met by a probe step
+    double scale;                   // factor of that rescaling
+};
+
+constexpr int FEATURES = nn::FEATURES;
+constexpr int OUTFLOW_PARTS = 256;
+
+// Feature scales: H (depth), Q (discharge), Z (elevation), S (slope), and the
+// window changes of depth and discharge dH, dQ.
+struct FeatScale {
+    float H, Q, Z, S, dH, dQ;
+};
+
+hipError_t launch_win_reset(SurWin *sw, hipStream_t stream);
+hipError_t launch_win_begin(Ctl *ctl, SurWin *sw, const KRain &rn, const KConst &kc,
+                            hipStream_t stream);
+hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, int nparts, const Part *op0,
+                           const Part *op1, int nop, const KConst &kc, hipStream_t stream);
+// Window kernels on the current state (buffer ctl->parity), each a no-op unless sw->live.
+// scr holds 3 x cells values of T (the probe step's h, v1, v2).
 template <typename T>
-hipError_t launch_apply_surrogate(const KDom<T> &d, int par, int64_t n, const float *out,
-                                  float dH, float dQ, double m_min, hipStream_t stream);
+hipError_t launch_win_probe(const KDom<T> &d, const KGrid &g, const KConst &kc, const KRain &rn,
+                            const Ctl *ctl, SurWin *sw, T *scr, double dt_max, hipStream_t stream);
 template <typename T>
-hipError_t launch_outflow_rate(const KDom<T> &d, int par, const KGrid &g, double l, double *part,
-                               int nparts, hipStream_t stream);
+hipError_t launch_win_features(const KDom<T> &d, const KGrid &g, double a, const Ctl *ctl,
+                               const SurWin *sw, const T *scr, double dt_max, FeatScale sc,
+                               int packed, void *out, hipStream_t stream);
+template <typename T>
+hipError_t launch_win_apply(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,
+                            const T *scr, double dt_max, const float *out, int out_stride, float dH,
+                            float dQ, double m_min, hipStream_t stream);
+// Outflow rate of the current (flip = 0) or the predicted (flip = 1) state.
+template <typename T>
+hipError_t launch_win_outflow(const KDom<T> &d, const KGrid &g, double l, const Ctl *ctl,
+                              const SurWin *sw, int flip, Part *op, hipStream_t stream);
+// Rescaling of an accepted state onto the water balance (no-op unless sw->scale_live).
+template <typename T>
+hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,
+                            hipStream_t stream);
+// Stored volume and c_max of the predicted state (PRIME_BLOCKS partials).
+template <typename T>
+hipError_t launch_win_sums(const KDom<T> &d, int64_t n, const KConst &kc, const Ctl *ctl,
+                           const SurWin *sw, Part *part, hipStream_t stream);
 
 hipError_t launch_tables(const KGrid &g, const uint8_t *active, int32_t *nbr, uint8_t *code,
                          hipStream_t stream);

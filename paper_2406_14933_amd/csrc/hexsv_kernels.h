@@ -148,48 +148,213 @@ hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------ surrogate glue
+// ------------------------------------------------------------ surrogate windows
+//
+// The learned surrogate is not part of the paper's method: a window replaces
+// the explicit steps over a fixed span by one network call and is kept only
+// if the predicted state keeps the water balance of the scheme (stored =
+// initial + rain - outflow - clamped).
 
-// Surrogate input features of every cell (scales {H, Q, Z}):
-// h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, rain_depth/H (0 outside the domain).
+// Is the neighbour of (q, r) in direction k an active raster cell?  (The
+// INTERIOR edge of the tables; periodic sides wrap.)  Sets j to its index.
 template <typename S>
-__global__ void k_features(int64_t n, const S *h, const S *v1, const S *v2, const S *z,
-                           const S *th, double rain_depth, float H, float Q, float Z,
-                           float *__restrict__ f) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const float t = (float)th[i];
-        const float hh = (float)h[i];
-        const bool act = t > 0.f;
-        f[i * 6 + 0] = act ? hh / H : 0.f;
-        f[i * 6 + 1] = act ? t * hh * (float)v1[i] / Q : 0.f;
-        f[i * 6 + 2] = act ? t * hh * (float)v2[i] / Q : 0.f;
-        f[i * 6 + 3] = act ? (float)z[i] / Z : 0.f;
-        f[i * 6 + 4] = t;
-        f[i * 6 + 5] = act ? (float)(rain_depth / H) : 0.f;
+__device__ inline bool active_nbr(const KGrid &g, const S *th, const uint8_t *active, int q, int r,
+                                  int k, int64_t &j) {
+    int qn = q + dq_of(k), rn = r + dr_of(k);
+    if (!wrap_pos(g, qn, rn)) return false;
+    j = (int64_t)rn * g.nq + qn;
+    if (active && !active[j]) return false;
+    return th[j] > S(0);
+}
+
+// Terrain slope of cell i = (q, r): along each axis k < 3 of the hexagon the
+// estimate d_k = D_k / (2 sqrt(3) a) with D_k the central difference of the
+// two neighbours (twice the one-sided one if only one is active); the slope
+// is the least-squares (minimum-norm) fit of n_k . grad z = d_k over the axes
+// present.  Exact for a plane whenever two axes are present.
+template <typename S>
+__device__ inline void terrain_slope(const KGrid &g, double a, const S *z, const S *th,
+                                     const uint8_t *active, int q, int r, int64_t i, double &sx,
+                                     double &sy) {
+    const double S3 = 0.86602540378443864676;
+    const double NX[3] = {1.0, 0.5, -0.5}, NY[3] = {0.0, S3, S3};
+    const double inv = 1.0 / (2.0 * 1.7320508075688772935 * a);
+    double m00 = 0.0, m01 = 0.0, m11 = 0.0, b0 = 0.0, b1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        int64_t j = 0, m = 0;
+        const bool pj = active_nbr(g, th, active, q, r, k, j);
+        const bool pm = active_nbr(g, th, active, q, r, k + 3, m);
+        double D;
+        if (pj && pm) D = (double)z[j] - (double)z[m];
+        else if (pj) D = 2.0 * ((double)z[j] - (double)z[i]);
+        else if (pm) D = 2.0 * ((double)z[i] - (double)z[m]);
+        else continue;
+        m00 += NX[k] * NX[k];
+        m01 += NX[k] * NY[k];
+        m11 += NY[k] * NY[k];
+        b0 += NX[k] * D * inv;
+        b1 += NY[k] * D * inv;
+    }
+    const double det = m00 * m11 - m01 * m01;
+    if (det > 1e-9) {  // two or three axes: M^-1 b
+        sx = (m11 * b0 - m01 * b1) / det;
+        sy = (m00 * b1 - m01 * b0) / det;
+    } else {  // one axis (M = n n^T, b along n: the minimum-norm fit is b) or none
+        sx = b0;
+        sy = b1;
     }
 }
 
-template <typename S>
-hipError_t launch_features(int64_t n, const S *h, const S *v1, const S *v2, const S *z,
-                           const S *th, double rain_depth, float H, float Q, float Z, float *f,
-                           hipStream_t stream) {
-    const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-    hipLaunchKernelGGL((k_features<S>), dim3(nb > 0 ? nb : 1), dim3(256), 0, stream, n, h, v1, v2, z,
-                       th, rain_depth, H, Q, Z, f);
+// Time step of a window's probe step: the solver's next step (CFL bound of
+// the current state, at most dt_max).
+__device__ inline double win_probe_dt(const Ctl *ctl, double dt_max) {
+    const double tau = ctl->tau;
+    return tau < dt_max ? tau : dt_max;
+}
+
+// Probe step of a window: one explicit step of the scheme (rain included)
+// from the current state into the scratch buffers, with the control block
+// untouched.  Its change, scaled to the window, is the extrapolation the
+// network corrects.
+template <typename T, int TQ, int TR, int NT>
+__global__ __launch_bounds__(NT) void k_win_probe(KDom<T> d, KGrid g, KConst kc, KRain rn,
+                                                  const Ctl *ctl, SurWin *sw, T *scr, int ntq,
+                                                  int ntiles, double dt_max) {
+    if (!sw->live) return;
+    const int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const int par = ctl->parity;
+    const int64_t n = (int64_t)g.nq * g.nr;
+    KDom<T> e;
+    for (int f = 0; f < 3; ++f) {
+        e.st[0][f] = par ? d.st[1][f] : d.st[0][f];
+        e.st[1][f] = scr + f * n;
+    }
+    e.z = d.z;
+    e.th = d.th;
+    e.ap = d.ap;
+    const double dt = win_probe_dt(ctl, dt_max);
+    const double r_next = rain_rate(rn, ctl->t + dt);
+    __shared__ TileLDS<T, TQ, TR> L;
+    Acc acc{0.0, 0.0, 0.0, 0.0};
+    const int tr = tile / ntq, tq = tile - tr * ntq;
+    tile_step<T, TQ, TR, NT, false>(L, e, g, kc, 0, tq, tr, dt, r_next, acc, &sw->perr,
+                                    &sw->perr_cell);
+}
+
+template <typename T>
+hipError_t launch_win_probe(const KDom<T> &d, const KGrid &g, const KConst &kc, const KRain &rn,
+                            const Ctl *ctl, SurWin *sw, T *scr, double dt_max, hipStream_t stream) {
+    constexpr TileShape S = TILES[DEFAULT_TILE];
+    int ntq, ntiles;
+    tile_grid(DEFAULT_TILE, g.nq, g.nr, &ntq, &ntiles);
+    hipLaunchKernelGGL((k_win_probe<T, S.tq, S.tr, S.nt>), dim3(ntiles), dim3(S.nt), 0, stream, d, g,
+                       kc, rn, ctl, sw, scr, ntq, ntiles, dt_max);
     return hipGetLastError();
 }
 
-// Apply a predicted window change to state buffer `par` into buffer par^1:
-// h' = max(h + dH*out0, 0), q' = theta h v + dQ*(out1, out2), v' = q' / (theta h')
-// (0 where theta h' <= m_min).  Inactive cells are copied.
+// The network inputs of cell i (all but theta zero on inactive cells):
+//   h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, depth/H, slope/S (2),
+//   and the probe step's change scaled by window/dt: dh/dH, dq1/dQ, dq2/dQ.
 template <typename T>
-__global__ void k_apply_surrogate(KDom<T> d, int par, int64_t n, const float *__restrict__ out,
-                                  float dH, float dQ, double m_min) {
-    const T *h = d.buf(par, 0), *v1 = d.buf(par, 1), *v2 = d.buf(par, 2);
-    T *ho = d.buf(par ^ 1, 0), *v1o = d.buf(par ^ 1, 1), *v2o = d.buf(par ^ 1, 2);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+__device__ inline void win_feature_vec(const KGrid &g, double a, const T *h, const T *v1,
+                                       const T *v2, const T *z, const T *th, const T *hs,
+                                       const T *v1s, const T *v2s, int64_t i, double depth,
+                                       double xs, const FeatScale &sc, float f[FEATURES]) {
+    const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+#pragma unroll
+    for (int c = 0; c < FEATURES; ++c) f[c] = 0.f;
+    if (!(th[i] > T(0))) return;
+    const double t = (double)th[i], hh = (double)h[i];
+    double sx, sy;
+    terrain_slope<T>(g, a, z, th, nullptr, q, r, i, sx, sy);
+    const double q1 = t * hh * (double)v1[i], q2 = t * hh * (double)v2[i];
+    const double xh = xs * ((double)hs[i] - hh);
+    const double xq1 = xs * (t * (double)hs[i] * (double)v1s[i] - q1);
+    const double xq2 = xs * (t * (double)hs[i] * (double)v2s[i] - q2);
+    f[0] = (float)(hh / sc.H);
+    f[1] = (float)(q1 / sc.Q);
+    f[2] = (float)(q2 / sc.Q);
+    f[3] = (float)((double)z[i] / sc.Z);
+    f[4] = (float)t;
+    f[5] = (float)(depth / sc.H);
+    f[6] = (float)(sx / sc.S);
+    f[7] = (float)(sy / sc.S);
+    f[8] = (float)(xh / sc.dH);
+    f[9] = (float)(xq1 / sc.dQ);
+    f[10] = (float)(xq2 / sc.dQ);
+}
+
+// PACKED: bf16, FEATURES_PAD channels per cell (the network's input buffer);
+// otherwise FP32, FEATURES channels per cell.
+template <typename T, bool PACKED>
+__global__ __launch_bounds__(256) void k_win_features(KDom<T> d, KGrid g, double a,
+                                                      const Ctl *ctl, const SurWin *sw,
+                                                      const T *scr, double dt_max, FeatScale sc,
+                                                      void *out) {
+    if (!sw->live) return;
+    const int par = ctl->parity;
+    const double depth = sw->depth;
+    const double xs = sw->window / win_probe_dt(ctl, dt_max);
+    const int64_t n = (int64_t)g.nq * g.nr;
+    const T *h = par ? d.st[1][0] : d.st[0][0];
+    const T *v1 = par ? d.st[1][1] : d.st[0][1];
+    const T *v2 = par ? d.st[1][2] : d.st[0][2];
+    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        float f[FEATURES];
+        win_feature_vec<T>(g, a, h, v1, v2, d.z, d.th, scr, scr + n, scr + 2 * n, i, depth, xs, sc, f);
+        if constexpr (PACKED) {
+            bf16x8 v[nn::FEATURES_PAD / 8];
+#pragma unroll
+            for (int c = 0; c < nn::FEATURES_PAD; ++c)
+                v[c / 8][c % 8] = c < FEATURES ? (__bf16)f[c] : (__bf16)0.f;
+#pragma unroll
+            for (int u = 0; u < nn::FEATURES_PAD / 8; ++u)
+                reinterpret_cast<bf16x8 *>((__bf16 *)out + i * nn::FEATURES_PAD)[u] = v[u];
+        } else {
+#pragma unroll
+            for (int c = 0; c < FEATURES; ++c) ((float *)out)[i * FEATURES + c] = f[c];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_win_features(const KDom<T> &d, const KGrid &g, double a, const Ctl *ctl,
+                               const SurWin *sw, const T *scr, double dt_max, FeatScale sc,
+                               int packed, void *out, hipStream_t stream) {
+    const int64_t n = (int64_t)g.nq * g.nr;
+    const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (packed)
+        hipLaunchKernelGGL((k_win_features<T, true>), dim3(nb), dim3(256), 0, stream, d, g, a, ctl,
+                           sw, scr, dt_max, sc, out);
+    else
+        hipLaunchKernelGGL((k_win_features<T, false>), dim3(nb), dim3(256), 0, stream, d, g, a, ctl,
+                           sw, scr, dt_max, sc, out);
+    return hipGetLastError();
+}
+
+// Predicted state of the window into buffer parity^1, with x the probe's
+// change scaled to the window:
+//   h' = max(h + x_h + dH out0, 0),  q' = theta h v + x_q + dQ (out1, out2),
+//   v' = q' / (theta h') (0 where theta h' <= m_min).  Inactive cells are copied.
+template <typename T>
+__global__ __launch_bounds__(256) void k_win_apply(KDom<T> d, int64_t n, const Ctl *ctl,
+                                                   const SurWin *sw, const T *scr, double dt_max,
+                                                   const float *__restrict__ out, int os, float dH,
+                                                   float dQ, double m_min) {
+    if (!sw->live) return;
+    const int par = ctl->parity;
+    const double xs = sw->window / win_probe_dt(ctl, dt_max);
+    const T *h = par ? d.st[1][0] : d.st[0][0];
+    const T *v1 = par ? d.st[1][1] : d.st[0][1];
+    const T *v2 = par ? d.st[1][2] : d.st[0][2];
+    T *ho = par ? d.st[0][0] : d.st[1][0];
+    T *v1o = par ? d.st[0][1] : d.st[1][1];
+    T *v2o = par ? d.st[0][2] : d.st[1][2];
+    const T *hs = scr, *v1s = scr + n, *v2s = scr + 2 * n;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const T th = d.th[i];
         if (!(th > T(0))) {
             ho[i] = h[i];
@@ -197,60 +362,149 @@ __global__ void k_apply_surrogate(KDom<T> d, int par, int64_t n, const float *__
             v2o[i] = v2[i];
             continue;
         }
-        const T m = th * h[i];
-        T hn = h[i] + (T)dH * (T)out[i * 4 + 0];
-        hn = hn > T(0) ? hn : T(0);
-        const T q1 = m * v1[i] + (T)dQ * (T)out[i * 4 + 1];
-        const T q2 = m * v2[i] + (T)dQ * (T)out[i * 4 + 2];
-        const T mn = th * hn;
-        ho[i] = hn;
-        v1o[i] = mn > (T)m_min ? q1 / mn : T(0);
-        v2o[i] = mn > (T)m_min ? q2 / mn : T(0);
+        const double t = (double)th, hh = (double)h[i];
+        const double q1 = t * hh * (double)v1[i], q2 = t * hh * (double)v2[i];
+        const double xh = xs * ((double)hs[i] - hh);
+        const double xq1 = xs * (t * (double)hs[i] * (double)v1s[i] - q1);
+        const double xq2 = xs * (t * (double)hs[i] * (double)v2s[i] - q2);
+        double hn = hh + xh + (double)dH * (double)out[i * os + 0];
+        hn = hn > 0.0 ? hn : 0.0;
+        const double p1 = q1 + xq1 + (double)dQ * (double)out[i * os + 1];
+        const double p2 = q2 + xq2 + (double)dQ * (double)out[i * os + 2];
+        const double mn = t * hn;
+        ho[i] = (T)hn;
+        v1o[i] = mn > m_min ? (T)(p1 / mn) : T(0);
+        v2o[i] = mn > m_min ? (T)(p2 / mn) : T(0);
     }
 }
 
 template <typename T>
-hipError_t launch_apply_surrogate(const KDom<T> &d, int par, int64_t n, const float *out,
-                                  float dH, float dQ, double m_min, hipStream_t stream) {
+hipError_t launch_win_apply(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,
+                            const T *scr, double dt_max, const float *out, int out_stride, float dH,
+                            float dQ, double m_min, hipStream_t stream) {
     const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-    hipLaunchKernelGGL((k_apply_surrogate<T>), dim3(nb > 0 ? nb : 1), dim3(256), 0, stream, d, par,
-                       n, out, dH, dQ, m_min);
+    hipLaunchKernelGGL((k_win_apply<T>), dim3(nb), dim3(256), 0, stream, d, n, ctl, sw, scr, dt_max,
+                       out, out_stride, dH, dQ, m_min);
     return hipGetLastError();
 }
 
-// Instantaneous volume flux through the OUTFLOW edges of state buffer `par`:
-// with the free-outflow ghost (the cell's own h, v, theta) an edge carries
-// l * theta h * (v . n_k) whatever its sign.  One FP64 partial per workgroup.
+// Volume flux (m^3/s) out of cell (q, r) through its OUTFLOW edges: the ghost
+// carries the cell's own h, v and theta, so each such edge passes
+// l * theta h * (v . n_k) whatever its sign.
 template <typename T>
-__global__ __launch_bounds__(256) void k_outflow_rate(KDom<T> d, int par, KGrid g, double l,
-                                                      double *__restrict__ part) {
-    const T *h = d.buf(par, 0), *v1 = d.buf(par, 1), *v2 = d.buf(par, 2);
+__device__ inline double cell_outflow(const KGrid &g, double l, const T *h, const T *v1,
+                                      const T *v2, const T *th, int q, int r, int64_t i) {
     const double S3 = 0.86602540378443864676;
     const double NX[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
     const double NY[6] = {0.0, S3, S3, 0.0, -S3, -S3};
+    if (!(th[i] > T(0))) return 0.0;
     double acc = 0.0;
-    const int64_t n = (int64_t)g.nq * g.nr;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        if (!(d.th[i] > T(0))) continue;
-        const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
-        for (int k = 0; k < 6; ++k) {
-            int qn = q + dq_of(k), rn = r + dr_of(k);
-            int cd;
-            if (wrap_pos(g, qn, rn)) cd = d.th[(int64_t)rn * g.nq + qn] > T(0) ? CODE_INTERIOR : g.mask_bc;
-            else cd = side_code(g, qn, rn);
-            if (cd != CODE_OUTFLOW) continue;
-            const double m = (double)d.th[i] * (double)h[i];
-            acc += l * m * ((double)v1[i] * NX[k] + (double)v2[i] * NY[k]);
+    for (int k = 0; k < 6; ++k) {
+        int qn = q + dq_of(k), rn = r + dr_of(k);
+        int cd;
+        if (wrap_pos(g, qn, rn)) cd = th[(int64_t)rn * g.nq + qn] > T(0) ? CODE_INTERIOR : g.mask_bc;
+        else cd = side_code(g, qn, rn);
+        if (cd != CODE_OUTFLOW) continue;
+        const double m = (double)th[i] * (double)h[i];
+        acc += l * m * ((double)v1[i] * NX[k] + (double)v2[i] * NY[k]);
+    }
+    return acc;
+}
+
+// One partial per workgroup (gridDim.x == OUTFLOW_PARTS) in Part::stored.  Without an
+// active mask only the raster's rim can hold OUTFLOW edges and only it is visited.
+template <typename T>
+__global__ __launch_bounds__(256) void k_win_outflow(KDom<T> d, KGrid g, double l, const Ctl *ctl,
+                                                     const SurWin *sw, int flip,
+                                                     Part *__restrict__ op) {
+    if (sw && !sw->live) return;
+    const int par = ctl->parity ^ flip;
+    const T *h = d.buf(par, 0), *v1 = d.buf(par, 1), *v2 = d.buf(par, 2);
+    double acc = 0.0;
+    const int nq = g.nq, nr = g.nr;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    if (g.has_mask) {
+        const int64_t n = (int64_t)nq * nr;
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+            const int r = (int)(i / nq), q = (int)(i - (int64_t)r * nq);
+            acc += cell_outflow<T>(g, l, h, v1, v2, d.th, q, r, i);
+        }
+    } else {
+        // rim: row 0, row nr-1 (if nr > 1), then columns 0 and nq-1 (if nq > 1) of rows 1..nr-2
+        const int64_t rows = nr > 1 ? 2 * (int64_t)nq : nq;
+        const int64_t mid = nr > 2 ? nr - 2 : 0;
+        const int64_t cols = nq > 1 ? 2 * mid : mid;
+        for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < rows + cols; p += stride) {
+            int q, r;
+            if (p < rows) {
+                q = (int)(p % nq);
+                r = p < nq ? 0 : nr - 1;
+            } else {
+                const int64_t c = p - rows;
+                r = 1 + (int)(c % mid);
+                q = c < mid ? 0 : nq - 1;
+            }
+            acc += cell_outflow<T>(g, l, h, v1, v2, d.th, q, r, (int64_t)r * nq + q);
         }
     }
     const Part p = block_reduce<256>(0.0, acc, 0.0, 0.0);
-    if (threadIdx.x == 0) part[blockIdx.x] = p.stored;
+    if (threadIdx.x == 0) op[blockIdx.x] = p;
 }
 
 template <typename T>
-hipError_t launch_outflow_rate(const KDom<T> &d, int par, const KGrid &g, double l, double *part,
-                               int nparts, hipStream_t stream) {
-    hipLaunchKernelGGL((k_outflow_rate<T>), dim3(nparts), dim3(256), 0, stream, d, par, g, l, part);
+hipError_t launch_win_outflow(const KDom<T> &d, const KGrid &g, double l, const Ctl *ctl,
+                              const SurWin *sw, int flip, Part *op, hipStream_t stream) {
+    hipLaunchKernelGGL((k_win_outflow<T>), dim3(OUTFLOW_PARTS), dim3(256), 0, stream, d, g, l, ctl,
+                       sw, flip, op);
+    return hipGetLastError();
+}
+
+// h *= scale on the state an accepted window produced (its velocities kept).
+template <typename T>
+__global__ __launch_bounds__(256) void k_win_scale(KDom<T> d, int64_t n, const Ctl *ctl,
+                                                   const SurWin *sw) {
+    if (!sw->scale_live) return;
+    const int par = ctl->parity;
+    const T f = (T)sw->scale;
+    T *h = d.buf(par, 0);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        h[i] = h[i] * f;
+}
+
+template <typename T>
+hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,
+                            hipStream_t stream) {
+    const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    hipLaunchKernelGGL((k_win_scale<T>), dim3(nb), dim3(256), 0, stream, d, n, ctl, sw);
+    return hipGetLastError();
+}
+
+// Stored volume sum sigma theta h and c_max of the predicted state.
+template <typename T>
+__global__ __launch_bounds__(256) void k_win_sums(KDom<T> d, int64_t n, KConst kc, const Ctl *ctl,
+                                                  const SurWin *sw, Part *part) {
+    if (!sw->live) return;
+    const int par = ctl->parity ^ 1;
+    const T *h = d.buf(par, 0), *v1 = d.buf(par, 1), *v2 = d.buf(par, 2);
+    double c = 0.0, s = 0.0, bad = 0.0;
+    const T G = (T)kc.g;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const T th = d.th[i];
+        if (!(th > T(0))) continue;
+        const double cc = (double)(p_sqrt(v1[i] * v1[i] + v2[i] * v2[i]) + p_sqrt(G * h[i]));
+        if (__builtin_isfinite(cc)) c = cc > c ? cc : c;
+        else bad += 1.0;  // counted in Part::clamp; the gate refuses such a window
+        s += kc.sigma * ((double)th * (double)h[i]);
+    }
+    const Part p = block_reduce<256>(c, s, 0.0, bad);
+    if (threadIdx.x == 0) part[blockIdx.x] = p;
+}
+
+template <typename T>
+hipError_t launch_win_sums(const KDom<T> &d, int64_t n, const KConst &kc, const Ctl *ctl,
+                           const SurWin *sw, Part *part, hipStream_t stream) {
+    hipLaunchKernelGGL((k_win_sums<T>), dim3(PRIME_BLOCKS), dim3(256), 0, stream, d, n, kc, ctl, sw,
+                       part);
     return hipGetLastError();
 }
 
@@ -263,13 +517,22 @@ hipError_t launch_outflow_rate(const KDom<T> &d, int par, const KGrid &g, double
                                             hipStream_t);                                     \
     template hipError_t launch_prime<T>(const KDom<T> &, int64_t, const KConst &, Ctl *, Part *, \
                                         int, int, hipStream_t);                               \
-    template hipError_t launch_features<T>(int64_t, const T *, const T *, const T *, const T *, \
-                                           const T *, double, float, float, float, float *,   \
-                                           hipStream_t);                                      \
-    template hipError_t launch_apply_surrogate<T>(const KDom<T> &, int, int64_t, const float *, \
-                                                  float, float, double, hipStream_t);         \
-    template hipError_t launch_outflow_rate<T>(const KDom<T> &, int, const KGrid &, double,   \
-                                               double *, int, hipStream_t);                   \
+    template hipError_t launch_win_probe<T>(const KDom<T> &, const KGrid &, const KConst &,   \
+                                            const KRain &, const Ctl *, SurWin *, T *, double, \
+                                            hipStream_t);                                     \
+    template hipError_t launch_win_features<T>(const KDom<T> &, const KGrid &, double,        \
+                                               const Ctl *, const SurWin *, const T *, double, \
+                                               FeatScale, int, void *, hipStream_t);         \
+    template hipError_t launch_win_apply<T>(const KDom<T> &, int64_t, const Ctl *,            \
+                                            const SurWin *, const T *, double, const float *, \
+                                            int, float, float, double, hipStream_t);          \
+    template hipError_t launch_win_outflow<T>(const KDom<T> &, const KGrid &, double,         \
+                                              const Ctl *, const SurWin *, int, Part *,       \
+                                              hipStream_t);                                   \
+    template hipError_t launch_win_scale<T>(const KDom<T> &, int64_t, const Ctl *,            \
+                                            const SurWin *, hipStream_t);                     \
+    template hipError_t launch_win_sums<T>(const KDom<T> &, int64_t, const KConst &,          \
+                                           const Ctl *, const SurWin *, Part *, hipStream_t); \
     template hipError_t launch_import<T>(const double *, T *, const uint8_t *, int, int64_t,  \
                                          hipStream_t);                                        \
     template hipError_t launch_export<T>(const KDom<T> &, int, int64_t, double *, double *,   \

@@ -9,13 +9,15 @@ namespace nn {
 
 enum { EPI_RELU = 0, EPI_LIN = 1, EPI_MASK = 2 };
 constexpr int OUT_STRIDE = 4;  // floats per cell of the network output (3 used)
+constexpr int FEATURES = 11;     // network input channels
+constexpr int FEATURES_PAD = 16; // stored input channels per cell (bf16, zero padded)
 
 // Workgroups (tiles of 64 x 4 cells) of one conv launch over a batch.
 int conv_tiles(int nq, int nr, int batch);
 
 // Hex convolution of channels-last bf16 x (cinp channels) with the MFMA
 // weight layout wm[t][coutp][cinp]; epilogue per EPI_* (see hexsv_nn.hip).
-// Built for (cinp, coutp, epi) in {(8,32,RELU), (32,32,RELU), (32,16,LIN),
+// Built for (cinp, coutp, epi) in {(16,32,RELU), (32,32,RELU), (32,16,LIN),
 // (16,32,MASK), (32,32,MASK)}.
 hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf16 *wm,
                        const float *bias, void *out, const __bf16 *mask, int nq, int nr,

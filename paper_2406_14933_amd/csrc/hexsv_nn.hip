@@ -360,10 +360,13 @@ __global__ void k_pack_features(const float *__restrict__ f, int64_t ncell,
                                 __bf16 *__restrict__ x) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell;
          i += (int64_t)gridDim.x * blockDim.x) {
-        bf16x8 v = bf16x8{};
+        bf16x8 v[FEATURES_PAD / 8];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] = (__bf16)f[i * 6 + c];
-        *reinterpret_cast<bf16x8 *>(x + i * 8) = v;
+        for (int c = 0; c < FEATURES_PAD; ++c)
+            v[c / 8][c % 8] = c < FEATURES ? (__bf16)f[i * FEATURES + c] : (__bf16)0.f;
+#pragma unroll
+        for (int u = 0; u < FEATURES_PAD / 8; ++u)
+            reinterpret_cast<bf16x8 *>(x + i * FEATURES_PAD)[u] = v[u];
     }
 }
 
@@ -388,7 +391,7 @@ hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf
                            mask, nq, nr, nt, cout_real);                                        \
         return hipGetLastError();                                                               \
     }
-    HEXSV_CONV(8, 32, EPI_RELU)
+    HEXSV_CONV(16, 32, EPI_RELU)
     HEXSV_CONV(32, 32, EPI_RELU)
     HEXSV_CONV(32, 16, EPI_LIN)
     HEXSV_CONV(16, 32, EPI_MASK)
@@ -406,7 +409,7 @@ hipError_t launch_wgrad(int cinp, int coutp, const __bf16 *x, const __bf16 *dy, 
                            nr, nt);                                                            \
         return hipGetLastError();                                                              \
     }
-    HEXSV_WG(8, 32)
+    HEXSV_WG(16, 32)
     HEXSV_WG(32, 32)
     HEXSV_WG(32, 16)
 #undef HEXSV_WG

@@ -27,9 +27,11 @@ struct hexsv_surrogate {
     int adam_step;
     bool weights_ready;
     float scales[8];
-    // workspace sized for ws_cells cells and ws_tiles conv tiles
+    // workspace sized for ws_cells cells and ws_tiles conv tiles; ws_gen
+    // counts reallocations (a captured graph holds the buffer addresses)
     int64_t ws_cells;
     int ws_tiles;
+    uint64_t ws_gen;
     __bf16 *x0;                 // packed features, 8 channels
     std::vector<__bf16 *> act;  // hidden activations, channels each
     float *out;                 // network output, OUT_STRIDE floats per cell
@@ -69,7 +71,7 @@ static int ensure_ws(hexsv_surrogate *s, int64_t cells, int tiles) {
     if (cells <= s->ws_cells && tiles <= s->ws_tiles) return HEXSV_OK;
     free_ws(s);
     const int C = s->channels;
-    hipError_t e = hipMalloc(&s->x0, sizeof(__bf16) * 8 * cells);
+    hipError_t e = hipMalloc(&s->x0, sizeof(__bf16) * nn::FEATURES_PAD * cells);
     for (int l = 0; l + 1 < s->layers && e == hipSuccess; ++l) {
         __bf16 *p = nullptr;
         e = hipMalloc(&p, sizeof(__bf16) * C * cells);
@@ -90,6 +92,7 @@ static int ensure_ws(hexsv_surrogate *s, int64_t cells, int tiles) {
     }
     s->ws_cells = cells;
     s->ws_tiles = tiles;
+    s->ws_gen += 1;
     return HEXSV_OK;
 }
 
@@ -105,9 +108,9 @@ extern "C" int hexsv_surrogate_create(int32_t layers, int32_t channels, hexsv_su
     int64_t off = 0;
     for (int l = 0; l < layers; ++l) {
         SurLayer y{};
-        y.cin = l == 0 ? 6 : channels;
+        y.cin = l == 0 ? nn::FEATURES : channels;
         y.cout = l == layers - 1 ? 3 : channels;
-        y.cinp = l == 0 ? 8 : channels;
+        y.cinp = l == 0 ? nn::FEATURES_PAD : channels;
         y.coutp = l == layers - 1 ? 16 : channels;
         y.off = off;
         off += (int64_t)y.cout * y.cin * 7 + y.cout;
@@ -225,6 +228,23 @@ extern "C" int hexsv_surrogate_forward(hexsv_surrogate *s, int32_t batch, int32_
     HIP_TRY(hipMemcpyAsync(d_out, s->out, sizeof(float) * nn::OUT_STRIDE * cells,
                            hipMemcpyDeviceToDevice, st));
     return HEXSV_OK;
+}
+
+// ---- interface for the solver's surrogate windows (hexsv_capi.hip)
+
+int sur_window_bind(hexsv_surrogate *s, int nq, int nr, void **x0, const float **out,
+                    uint64_t *gen) {
+    int64_t cells;
+    int rc = check_shape(s, 1, nq, nr, &cells);
+    if (rc) return rc;
+    *x0 = s->x0;
+    *out = s->out;
+    *gen = s->ws_gen;
+    return HEXSV_OK;
+}
+
+int sur_forward_x0(hexsv_surrogate *s, int nq, int nr, hipStream_t st) {
+    return forward_packed(s, nq, nr, 1, st);
 }
 
 // Forward + L1 loss + backward into s->d_g; loss in *loss (synchronises).

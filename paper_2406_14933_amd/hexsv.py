@@ -112,10 +112,9 @@ _SIGS = [
                                            C.POINTER(C.c_double), _VP]),
     ("hexsv_surrogate_train_step", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
                                              C.c_float, C.POINTER(C.c_double), _VP]),
-    ("hexsv_surrogate_features", C.c_int, [_VP, C.c_int64, _VP, _VP, _VP, _VP, _VP, C.c_double,
-                                           _VP, _VP]),
+    ("hexsv_sim_surrogate_features", C.c_int, [_VP, _VP, C.c_double, C.c_int32, _VP, _VP]),
     ("hexsv_sim_run_surrogate", C.c_int, [_VP, _VP, C.c_double, C.c_double, C.c_int32,
-                                          C.c_double, C.POINTER(C.c_int64),
+                                          C.c_double, C.c_int32, C.POINTER(C.c_int64),
                                           C.POINTER(C.c_int64), _VP]),
     ("hexsv_tile_count", C.c_int, []),
     ("hexsv_tile_shape", C.c_int, [C.c_int32] + [C.POINTER(C.c_int32)] * 3),
@@ -308,13 +307,20 @@ class Sim:
                                         _stream()))
         return best.value, ms.value
 
-    def run_surrogate(self, sur, t_end, window, k, residual_tol=1e-3):
+    def run_surrogate(self, sur, t_end, window, k, residual_tol=1e-3, project=True):
         """Advance with surrogate windows and solver fallback; returns (accepted, fallback)."""
         a, f = C.c_int64(), C.c_int64()
         _check(lib().hexsv_sim_run_surrogate(self._h, sur._h, float(t_end), float(window), int(k),
-                                             float(residual_tol), C.byref(a), C.byref(f),
-                                             _stream()))
+                                             float(residual_tol), int(bool(project)), C.byref(a),
+                                             C.byref(f), _stream()))
         return a.value, f.value
+
+    def surrogate_features(self, sur, window, k):
+        """(cells, 11) FP32 network inputs of a window starting at the current state."""
+        f = torch.empty((self.grid.cells, Surrogate.FEATURES), dtype=torch.float32, device="cuda")
+        _check(lib().hexsv_sim_surrogate_features(self._h, sur._h, float(window), int(k), _ptr(f),
+                                                  _stream()))
+        return f
 
     def info(self):
         vals = [C.c_int32() for _ in range(5)]
@@ -439,6 +445,8 @@ class Surrogate:
         return t
 
     def set_scales(self, scales):
+        """{H, Q, Z, dH, dQ, S}: input depth, discharge, elevation, output depth and discharge,
+        input slope."""
         a = (C.c_float * len(scales))(*[float(x) for x in scales])
         _check(lib().hexsv_surrogate_set_scales(self._h, a, len(scales)))
 
@@ -447,14 +455,7 @@ class Surrogate:
         _check(lib().hexsv_surrogate_get_scales(self._h, a, n))
         return list(a)
 
-    def features(self, h, v1, v2, z, theta, rain_depth):
-        """(n, 6) FP32 features from FP64 state arrays (device or host)."""
-        arrs = [_dev(x) for x in (h, v1, v2, z, theta)]
-        n = arrs[0].numel()
-        f = torch.empty((n, 6), dtype=torch.float32, device="cuda")
-        _check(lib().hexsv_surrogate_features(self._h, n, *(_ptr(a) for a in arrs),
-                                              float(rain_depth), _ptr(f), _stream()))
-        return f
+    FEATURES = 11
 
     @staticmethod
     def _shape(x, nq, nr, ch):
@@ -465,7 +466,7 @@ class Surrogate:
 
     def forward(self, features, nq, nr):
         f = _dev(features, dtype=torch.float32)
-        batch = self._shape(f, nq, nr, 6)
+        batch = self._shape(f, nq, nr, self.FEATURES)
         out = torch.empty((batch * nq * nr, 4), dtype=torch.float32, device="cuda")
         _check(lib().hexsv_surrogate_forward(self._h, batch, int(nq), int(nr), _ptr(f), _ptr(out),
                                              _stream()))
@@ -474,7 +475,7 @@ class Surrogate:
     def gradient(self, features, target, nq, nr):
         f = _dev(features, dtype=torch.float32)
         t = _dev(target, dtype=torch.float32)
-        batch = self._shape(f, nq, nr, 6)
+        batch = self._shape(f, nq, nr, self.FEATURES)
         g = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
         loss = C.c_double()
         _check(lib().hexsv_surrogate_gradient(self._h, batch, int(nq), int(nr), _ptr(f), _ptr(t),
@@ -482,7 +483,7 @@ class Surrogate:
         return loss.value, g
 
     def train_step(self, features, target, nq, nr, lr):
-        batch = self._shape(features, nq, nr, 6)
+        batch = self._shape(features, nq, nr, self.FEATURES)
         loss = C.c_double()
         _check(lib().hexsv_surrogate_train_step(self._h, batch, int(nq), int(nr), _ptr(features),
                                                 _ptr(target), float(lr), C.byref(loss), _stream()))

@@ -23,7 +23,7 @@ def setup(seed, nq, nr, batch, layers=4):
     rng = np.random.default_rng(seed)
     p = so.init_params(seed, layers, 32, out_scale=1.0)
     p = (p + rng.normal(scale=0.02, size=p.shape)).astype(np.float32)
-    feats = rng.normal(size=(batch, nq * nr, 6)).astype(np.float32)
+    feats = rng.normal(size=(batch, nq * nr, so.FEATURES)).astype(np.float32)
     tgt = rng.normal(size=(batch, nq * nr, 3)).astype(np.float32)
     G = oracle.grid(nq, nr, 1.0)
     return p, feats, tgt, G
@@ -35,7 +35,7 @@ def test_forward_matches_oracle(hx, nq, nr, batch, layers):
     p, feats, _, G = setup(1, nq, nr, batch, layers)
     sur = hx.Surrogate(layers, 32)
     sur.set_params(p)
-    out = sur.forward(feats.reshape(-1, 6), nq, nr).cpu().numpy().reshape(batch, nq * nr, 4)
+    out = sur.forward(feats.reshape(-1, so.FEATURES), nq, nr).cpu().numpy().reshape(batch, nq * nr, 4)
     for b in range(batch):
         ref, _, _ = so.forward(G, p, feats[b].astype(np.float64), layers, 32, bf16=True)
         e = rel_l2(out[b, :, :3], ref)
@@ -49,7 +49,7 @@ def test_gradient_matches_oracle(hx, nq, nr, batch):
     p, feats, tgt, G = setup(2, nq, nr, batch, layers)
     sur = hx.Surrogate(layers, 32)
     sur.set_params(p)
-    loss, g = sur.gradient(feats.reshape(-1, 6), tgt.reshape(-1, 3), nq, nr)
+    loss, g = sur.gradient(feats.reshape(-1, so.FEATURES), tgt.reshape(-1, 3), nq, nr)
     g = g.cpu().numpy()
     rl, rg = so.loss_and_grad(G, p, [f.astype(np.float64) for f in feats],
                               [t.astype(np.float64) for t in tgt], layers, 32, bf16=True)
@@ -69,8 +69,8 @@ def test_adam_step_matches_oracle(hx):
     p, feats, tgt, G = setup(3, nq, nr, 1)
     sur = hx.Surrogate(4, 32)
     sur.set_params(p)
-    _, g = sur.gradient(feats.reshape(-1, 6), tgt.reshape(-1, 3), nq, nr)
-    f = torch.from_numpy(feats.reshape(-1, 6)).cuda()
+    _, g = sur.gradient(feats.reshape(-1, so.FEATURES), tgt.reshape(-1, 3), nq, nr)
+    f = torch.from_numpy(feats.reshape(-1, so.FEATURES)).cuda()
     t = torch.from_numpy(tgt.reshape(-1, 3)).cuda()
     sur.train_step(f, t, nq, nr, 1e-3)
     p1 = sur.params().cpu().numpy()
@@ -85,7 +85,7 @@ def test_training_reduces_loss(hx):
     p = so.init_params(5, 4, 32)
     sur = hx.Surrogate(4, 32)
     sur.set_params(p)
-    feats = rng.normal(size=(batch * nq * nr, 6)).astype(np.float32)
+    feats = rng.normal(size=(batch * nq * nr, so.FEATURES)).astype(np.float32)
     # a smooth target the network can represent: local linear combinations of features
     tgt = np.stack([0.5 * feats[:, 0] - 0.3 * feats[:, 5], 0.2 * feats[:, 1],
                     -0.4 * feats[:, 2] + 0.1 * feats[:, 3]], axis=1).astype(np.float32)

@@ -19,7 +19,8 @@ from tests.test_gpu_parity import hx  # noqa: F401  (fixture)
 
 pytestmark = pytest.mark.gpu
 
-SCALES = (0.05, 0.01, 10.0, 0.01, 0.002)  # H, Q, Z, dH, dQ
+SCALES = (0.05, 0.01, 10.0, 0.01, 0.002, 0.1)  # H, Q, Z, dH, dQ, S
+FS = (SCALES[0], SCALES[1], SCALES[2], SCALES[5], SCALES[3], SCALES[4])  # oracle order
 WINDOW, K = 1.6, 16
 
 
@@ -41,12 +42,36 @@ def make_surrogate(hx, seed=4):
     return sur, p
 
 
-def test_features_kernel(hx):
-    sc = wet_planar()
+def oracle_inputs(sc, t0=0.0):
+    G = oracle.grid(sc.nq, sc.nr, sc.a, sc.side, sc.segs, sc.active, sc.mask_code)
+    p = oracle.params(sc.g, sc.cfl, sc.dt_max, sc.h_dry, sc.alpha_s)
+    r = oracle.rain(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d)
+    th = np.where(G.active, sc.theta, 0.0)
+    depth = so.window_rain_depth(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d, t0, WINDOW, K)
+    ext = so.extrapolation(G, sc.z, th, sc.alpha_p, p, r, t0, WINDOW, sc.h0, sc.v10, sc.v20)
+    f = so.features(G, sc.h0, sc.v10, sc.v20, sc.z, th, depth, ext, *FS)
+    return G, th, depth, ext, f
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_features_kernel(hx, masked):
+    """Window inputs of an FP64 simulation (probe step included) against the oracle's."""
+    if masked:
+        sc = synth.cone(R=9, rim=synth.OUTFLOW)
+        h, v1, v2 = synth.random_state(sc, 3, depth=0.05, speed=0.2)
+        sc = sc.with_(h0=h, v10=v1, v20=v2)
+    else:
+        sc = wet_planar()
+    sim = hx.Sim.from_scenario(sc, "fp64")
     sur, _ = make_surrogate(hx)
-    f = sur.features(sc.h0, sc.v10, sc.v20, sc.z, sc.theta, 3e-4).cpu().numpy()
-    ref = so.features(sc.h0, sc.v10, sc.v20, sc.z, sc.theta, 3e-4, *SCALES[:3])
-    np.testing.assert_allclose(f, ref, rtol=1e-6, atol=1e-12)
+    f = sim.surrogate_features(sur, WINDOW, K).cpu().numpy()
+    _, th, _, _, ref = oracle_inputs(sc)
+    act = th > 0
+    np.testing.assert_allclose(f[act], ref[act], rtol=1e-6, atol=1e-6)
+    np.testing.assert_array_equal(f[~act], 0.0)
+    # the state is untouched
+    st = sim.state_numpy()
+    np.testing.assert_array_equal(st["h"][act], sc.h0[act])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -56,16 +81,15 @@ def test_accepted_window_matches_oracle_chain(hx, prec):
     b0 = sim.books()
     sur, p = make_surrogate(hx)
     print(f"[surrogate window {prec} {sc.nq}x{sc.nr}]", flush=True)
-    acc, fb = sim.run_surrogate(sur, WINDOW, WINDOW, K, residual_tol=math.inf)
+    acc, fb = sim.run_surrogate(sur, WINDOW, WINDOW, K, residual_tol=math.inf, project=False)
     assert (acc, fb) == (1, 0)
     st = sim.state_numpy()
     b = sim.books()
 
-    G = oracle.grid(sc.nq, sc.nr, sc.a, sc.side)
-    depth = so.window_rain_depth(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d, 0.0, WINDOW, K)
-    f = so.features(sc.h0, sc.v10, sc.v20, sc.z, sc.theta, depth, *SCALES[:3])
+    G, _, depth, ext, f = oracle_inputs(sc)
     out, _, _ = so.forward(G, p, f, 4, 32, bf16=True)
-    hn, v1n, v2n = so.apply_window(sc.h0, sc.v10, sc.v20, sc.theta, out, SCALES[3], SCALES[4])
+    hn, v1n, v2n = so.apply_window(sc.h0, sc.v10, sc.v20, sc.theta, out, SCALES[3], SCALES[4],
+                                   ext)
     th = sc.theta
     e_h = rel_l2(st["h"] - sc.h0, hn - sc.h0)
     e_q1 = rel_l2(st["q1"] - th * sc.h0 * sc.v10, th * hn * v1n - th * sc.h0 * sc.v10)
@@ -83,6 +107,30 @@ def test_accepted_window_matches_oracle_chain(hx, prec):
     tol = 1e-12 if prec == "fp64" else 1e-5
     assert b["outflow"] - b0["outflow"] == pytest.approx(0.5 * (o0 + o1) * WINDOW, rel=tol)
     assert b["stored"] == pytest.approx(sigma * float(np.sum(th * st["h"])), rel=tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_projection_closes_the_balance(hx, prec):
+    """With projection the kept state is the unprojected one with every depth scaled by
+    (S0 + R - O) / S', and its stored volume is S0 + R - O."""
+    sc = wet_planar()
+    sur, _ = make_surrogate(hx)
+    runs = {}
+    for proj in (False, True):
+        sim = hx.Sim.from_scenario(sc, prec)
+        b0 = sim.books()
+        assert sim.run_surrogate(sur, WINDOW, WINDOW, K, math.inf, project=proj) == (1, 0)
+        runs[proj] = (sim.state_numpy(), sim.books(), b0)
+    (a, ba, b0), (p, bp, _) = runs[False], runs[True]
+    target = b0["stored"] + (ba["rain"] - b0["rain"]) - (ba["outflow"] - b0["outflow"])
+    f = target / ba["stored"]
+    print(f"[projection {prec}] factor {f:.6f}")
+    assert bp["stored"] == pytest.approx(target, rel=1e-12)
+    tol = 1e-15 if prec == "fp64" else 3e-7
+    np.testing.assert_allclose(p["h"], a["h"] * f, rtol=tol, atol=0)
+    np.testing.assert_array_equal(p["v1"], a["v1"])
+    sigma, _, _ = oracle.geometry(sc.a)
+    assert sigma * float(np.sum(sc.theta * p["h"])) == pytest.approx(target, rel=1e-6)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

@@ -163,9 +163,9 @@ def test_adam_matches_torch():
 
 def test_param_layout():
     shapes = so.layer_shapes(4, 32)
-    assert shapes == [(6, 32), (32, 32), (32, 32), (32, 3)]
+    assert shapes == [(11, 32), (32, 32), (32, 32), (32, 3)]
     n = so.num_params(4, 32)
-    assert n == 6 * 32 * 7 + 32 + 2 * (32 * 32 * 7 + 32) + 32 * 3 * 7 + 3
+    assert n == 11 * 32 * 7 + 32 + 2 * (32 * 32 * 7 + 32) + 32 * 3 * 7 + 3
     p = so.init_params(0)
     assert p.shape == (n,) and p.dtype == np.float32
     back = so.flatten(so.unflatten(p))
@@ -229,15 +229,67 @@ def test_apply_window_zero_change_keeps_the_state():
 
 
 def test_features_definition():
+    G = oracle.grid(3, 1, 1.0)
     h = np.array([0.1, 0.0, 0.2])
     v1 = np.array([1.0, 0.0, -2.0])
     v2 = np.array([0.5, 0.0, 0.0])
     z = np.array([3.0, 4.0, 5.0])
     th = np.array([0.5, 1.0, 0.0])
-    f = so.features(h, v1, v2, z, th, 0.004, 0.1, 0.01, 10.0)
-    np.testing.assert_allclose(f[0], [1.0, 5.0, 2.5, 0.3, 0.5, 0.04])
-    np.testing.assert_allclose(f[1], [0.0, 0.0, 0.0, 0.4, 1.0, 0.04])
-    np.testing.assert_array_equal(f[2], np.zeros(6))  # inactive
+    ext = (np.array([1e-3, 2e-3, 9.0]), np.array([4e-4, 0.0, 9.0]), np.array([-2e-4, 0.0, 9.0]))
+    f = so.features(G, h, v1, v2, z, th, 0.004, ext, 0.1, 0.01, 10.0, 0.5, 1e-3, 2e-4)
+    np.testing.assert_allclose(f[0, :6], [1.0, 5.0, 2.5, 0.3, 0.5, 0.04])
+    np.testing.assert_allclose(f[0, 8:], [1.0, 2.0, -1.0])
+    np.testing.assert_allclose(f[1, :6], [0.0, 0.0, 0.0, 0.4, 1.0, 0.04])
+    np.testing.assert_array_equal(f[2], np.zeros(so.FEATURES))  # inactive
+
+
+def test_extrapolation_of_still_water():
+    """Lake at rest: the probe step changes nothing (well-balanced scheme, Sec. 2.2), so the
+    extrapolation is exactly zero; with rain r on a flat lake only the depth grows, by
+    window * r / theta."""
+    sc = synth.lake_at_rest(nq=12, nr=10)
+    G = oracle.grid(sc.nq, sc.nr, sc.a, sc.side, sc.segs, sc.active, sc.mask_code)
+    p = oracle.params(sc.g, sc.cfl, sc.dt_max, sc.h_dry, sc.alpha_s)
+    x = so.extrapolation(G, sc.z, sc.theta, sc.alpha_p, p, oracle.rain(), 0.0, 1.6,
+                         sc.h0, sc.v10, sc.v20)
+    for a in x:
+        np.testing.assert_array_equal(a, 0.0)
+    n = sc.n
+    z = np.zeros(n)
+    th = np.full(n, 0.8)
+    r = 50.0 / 3.6e6
+    x = so.extrapolation(G, z, th, np.full(n, 73.39), p, oracle.rain(0, r), 0.0, 1.6,
+                         np.full(n, 0.3), np.zeros(n), np.zeros(n))
+    np.testing.assert_allclose(x[0], 1.6 * r / 0.8, rtol=1e-9)
+    np.testing.assert_array_equal(x[1], 0.0)
+    np.testing.assert_array_equal(x[2], 0.0)
+
+
+@pytest.mark.parametrize("side", [(oracle.WALL,) * 4, (oracle.WALL, oracle.PERIODIC) * 2])
+def test_terrain_slope_is_exact_on_a_plane(side):
+    """Every cell, also at the raster's edges and corners (one-sided differences), recovers
+    the gradient of a plane; with a periodic side the wrap makes the plane non-planar across
+    the seam, so only cells away from it are checked there."""
+    nq, nr, a = 9, 7, 1.3
+    G = oracle.grid(nq, nr, a, side=side)
+    x, y = synth.centres(nq, nr, a)
+    z = 0.07 * x - 0.13 * y + 2.0
+    s = so.terrain_slope(G, z)
+    q = np.tile(np.arange(nq), nr)
+    keep = np.ones(G.n, bool) if side[1] == oracle.WALL else (q > 0) & (q < nq - 1)
+    np.testing.assert_allclose(s[keep], np.tile([0.07, -0.13], (keep.sum(), 1)), rtol=1e-12)
+
+
+def test_terrain_slope_of_a_cone_points_outward():
+    sc = synth.cone(R=6, H=2.0)
+    G = oracle.grid(sc.nq, sc.nr, sc.a, sc.side, sc.segs, sc.active, sc.mask_code)
+    s = so.terrain_slope(G, sc.z)
+    x, y = synth.centres(sc.nq, sc.nr, sc.a)
+    c = (sc.nr // 2) * sc.nq + sc.nq // 2
+    dx, dy = x - x[c], y - y[c]
+    inner = G.active & (np.hypot(dx, dy) > 1.0) & (G.nbr >= 0).all(axis=1)
+    # the cone falls away from its centre: the gradient points inward
+    assert np.all(s[inner, 0] * dx[inner] + s[inner, 1] * dy[inner] < 0)
 
 
 def test_window_rain_depth():
