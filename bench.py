@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -139,6 +140,49 @@ def time_ensemble(precision, launches, ksteps, n_scen, tune):
             "info": info}
 
 
+def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=1e-5, seed=1):
+    """Train the window surrogate on solver trajectories (all on the GPU, the library's own
+    kernels) and time it against the plain FP32 solver on held-out scenarios to t_end."""
+    import numpy as np
+
+    import synth
+    from paper_2406_14933_amd import hexsv
+    from paper_2406_14933_amd import surrogate as S
+    t_end = 1800.0
+    train_sc = [synth.ensemble_member(s, size=size, config=5, t_end=t_end) for s in range(n_train)]
+    test_sc = [synth.ensemble_member(1000 + s, size=size, config=5, t_end=t_end)
+               for s in range(n_test)]
+    t0 = time.perf_counter()
+    dt_fix = 0.8 * min(S.pilot_dt(sc) for sc in train_sc[:2])
+    window = k * dt_fix
+    sur = hexsv.Surrogate(4, 32)
+    rng = np.random.default_rng(seed)
+    # He-normal start, last layer scaled down: the network starts near the probe extrapolation
+    p = []
+    for li, (ci, co) in enumerate([(hexsv.Surrogate.FEATURES, 32), (32, 32), (32, 32), (32, 3)]):
+        std = math.sqrt(2.0 / (7 * ci)) * (0.1 if li == 3 else 1.0)
+        p.append(rng.normal(scale=std, size=co * ci * 7))
+        p.append(np.zeros(co))
+    sur.set_params(np.concatenate(p).astype(np.float32))
+    times = list(np.linspace(window, t_end - 2 * window, 32))
+    data, scales = S.collect(train_sc, times, window, k, sur)
+    S.train(sur, data, 3000, batch=4, lr=1e-3, lr_end=5e-5, seed=seed)
+    ro = S.rollout_pairs(sur, train_sc, list(np.linspace(2 * window, t_end - 2 * window, 16)),
+                         window, k, scales, tol=tol)
+    data = S.merge(data, ro)
+    S.train(sur, data, 3000, batch=4, lr=5e-4, lr_end=2e-5, seed=seed + 1)
+    train_s = time.perf_counter() - t0
+    ev = S.evaluate(sur, test_sc, window, k, tol, project=True)
+    plain_steps = sum(r["plain_steps"] for r in ev["rows"])
+    sur_steps = sum(r["surrogate_steps"] for r in ev["rows"])
+    return {"workload": f"surrogate-{n_test}-heldout-{size}x{size}-edge1m-to-{t_end:.0f}s",
+            "speedup": ev["speedup"], "err_h_max": ev["err_h_max"],
+            "err_h_mean": ev["err_h_mean"], "tol": tol, "accept_frac": ev["accept_frac"],
+            "solver_steps_avoided": 1.0 - sur_steps / max(plain_steps, 1),
+            "plain_s": ev["plain_s"], "surrogate_s": ev["surrogate_s"], "window_s": window,
+            "k": k, "train_pairs": data.pairs, "train_scenarios": n_train, "train_s": train_s}
+
+
 def cpu_baseline(sc, budget_s=12.0):
     """The FP64 oracle as it stands, on the host cores, over a bounded number of steps."""
     import numpy as np
@@ -180,6 +224,8 @@ def main():
     ap.add_argument("--ensemble-ksteps", type=int, default=25)
     ap.add_argument("--ensemble-scenarios", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
+                    help="skip training and timing the window surrogate")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for counter calibration)")
@@ -252,6 +298,12 @@ def main():
                            "value": er["value"], "cells": er["cells"],
                            "steps_per_scenario": er["steps_per_scenario"],
                            "roofline": er["roofline"], "config": er["info"]}
+    if args.surrogate:
+        print("[bench] surrogate: training on solver trajectories", file=sys.stderr, flush=True)
+        sr = surrogate_block()
+        print(f"[bench] surrogate: speed-up {sr['speedup']:.2f}x at rel L1 error "
+              f"{sr['err_h_max']:.2e} (max over held-out)", file=sys.stderr, flush=True)
+        line["surrogate"] = sr
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(line), flush=True)

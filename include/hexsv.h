@@ -339,11 +339,14 @@ int hexsv_sim_surrogate_features(hexsv_sim *sim, hexsv_surrogate *sur, double wi
  * (S, S' stored volume sum sigma theta h at both ends, R = rain volume of the
  * window as k equal sub-steps each taking the rate at its end, O the outflow
  * volume by the trapezoid rule on the outflow rates of both states).  A
- * finite window with rho <= residual_tol is kept (time, rain and outflow books
- * and the CFL bound advance; steps does not); with project != 0 its depths are
- * then scaled by (S + R - O) / S' so that the kept state closes the balance
- * exactly (small residuals would otherwise add up over many windows).  A
- * refused window is discarded and the plain solver advances that span.  A last span shorter than `window` is
+ * finite window with rho <= residual_tol whose largest wave speed
+ * |v| + sqrt(g h) is at most twice that of its start state is kept (time,
+ * rain and outflow books and the CFL bound advance; steps does not; an
+ * infinite residual_tol keeps every finite window); with project != 0 its
+ * depths are then scaled by (S + R - O) / S' so that the kept state closes
+ * the balance exactly (small residuals would otherwise add up over many
+ * windows).  A refused window is discarded and the plain solver advances
+ * that span (ENUMERIC if it stalls).  A last span shorter than `window` is
  * always solved.  Windows are chained several to a graph launch; the host
  * synchronises once per chain.  Counts of kept and solved windows are
  * returned.  The surrogate must not be used by another simulation while this

@@ -191,8 +191,10 @@ def extrapolation(G, z, theta, alpha_p, p, r, t0, window, h, v1, v2):
     th = np.where(G.active, np.asarray(theta, np.float64), 0.0)
     h, v1, v2 = (np.asarray(a, np.float64) for a in (h, v1, v2))
     dt = oracle.dt(G.a, p, oracle.cmax(G, p.g, th, h, v1, v2), t0, math.inf)
-    hn, v1n, v2n, _ = oracle.step_cells(G, z, th, alpha_p, p, r, dt, t0 + dt, h, v1, v2,
-                                        np.arange(G.n))
+    cells = np.nonzero(G.active)[0]
+    hn, v1n, v2n = h.copy(), v1.copy(), v2.copy()  # inactive cells: no change
+    hn[cells], v1n[cells], v2n[cells], _ = oracle.step_cells(G, z, th, alpha_p, p, r, dt, t0 + dt,
+                                                            h, v1, v2, cells)
     xs = window / dt
     return xs * (hn - h), xs * (th * hn * v1n - th * h * v1), xs * (th * hn * v2n - th * h * v2)
 

@@ -152,12 +152,16 @@ struct hexsv_sim {
     hipStream_t cap;
     hipGraph_t graph;
     hipGraphExec_t gexec;
+    hipGraph_t sgraph;      // short graph (SHORT_STEPS steps) for spans of a few steps
+    hipGraphExec_t sexec;
     bool graph_ok, fields_set, state_set;
     // surrogate windows: control record (device + pinned mirror), outflow
     // partials of both ends, and a graph of WIN_CHAIN chained windows
     SurWin *d_sw, *h_sw;
-    Part *d_op;
+    Part *d_op;   // window partial records: start-state outflow, predicted-state sums
     void *d_scr;  // probe state: 3 x cells of the state's precision
+    float2 *d_slope;  // terrain slope per cell (static; rebuilt after set_fields)
+    bool slope_ok;
     hipGraph_t wgraph;
     hipGraphExec_t wexec;
     const hexsv_surrogate *w_sur;
@@ -186,8 +190,12 @@ static KDom<T> dom_of(const hexsv_sim *s) {
 static void drop_graph(hexsv_sim *s) {
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->sexec) (void)hipGraphExecDestroy(s->sexec);
+    if (s->sgraph) (void)hipGraphDestroy(s->sgraph);
     s->gexec = nullptr;
     s->graph = nullptr;
+    s->sexec = nullptr;
+    s->sgraph = nullptr;
     s->graph_ok = false;
 }
 
@@ -282,6 +290,7 @@ extern "C" void hexsv_sim_destroy(hexsv_sim *s) {
     if (s->h_sw) (void)hipHostFree(s->h_sw);
     if (s->d_op) (void)hipFree(s->d_op);
     if (s->d_scr) (void)hipFree(s->d_scr);
+    if (s->d_slope) (void)hipFree(s->d_slope);
     delete s;
 }
 
@@ -336,6 +345,7 @@ extern "C" int hexsv_sim_set_fields(hexsv_sim *s, const double *d_z, const doubl
     }
     s->kc.alpha_s = alpha_s;
     s->fields_set = true;
+    s->slope_ok = false;
     drop_graph(s);
     return HEXSV_OK;
 }
@@ -404,11 +414,11 @@ extern "C" int hexsv_sim_set_state(hexsv_sim *s, double t0, const double *d_h, c
     return HEXSV_OK;
 }
 
-static int capture(hexsv_sim *s) {
-    drop_graph(s);
+// Capture nsteps steps (tile kernel + finalize each) into one executable graph.
+static int capture_steps(hexsv_sim *s, int nsteps, hipGraph_t *graph, hipGraphExec_t *exec) {
     HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < s->gsteps && e == hipSuccess; ++k) {
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
         if (s->prec == HEXSV_FP64)
             e = launch_step<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
                                     s->d_part, s->ntq, s->ntiles, s->nwg, s->cap);
@@ -423,13 +433,33 @@ static int capture(hexsv_sim *s) {
         return fail(HEXSV_EHIP, "graph capture failed: %s",
                     hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    s->graph = g;
-    HIP_TRY(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+    *graph = g;
+    HIP_TRY(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
+    return HEXSV_OK;
+}
+
+// Steps per replay of the short graph used for spans of a few steps (the
+// fallback of a refused surrogate window): the long graph would replay its
+// whole length of no-op steps past the span's end.
+static const int SHORT_STEPS = 8;
+
+static int capture(hexsv_sim *s) {
+    drop_graph(s);
+    int rc = capture_steps(s, s->gsteps, &s->graph, &s->gexec);
+    if (rc) return rc;
+    rc = capture_steps(s, SHORT_STEPS, &s->sgraph, &s->sexec);
+    if (rc) return rc;
     s->graph_ok = true;
     return HEXSV_OK;
 }
 
+static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, hipStream_t stream);
+
 extern "C" int hexsv_sim_run(hexsv_sim *s, double t_end, int64_t max_steps, hipStream_t stream) {
+    return sim_run(s, t_end, max_steps, false, stream);
+}
+
+static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, hipStream_t stream) {
     if (!s) return fail(HEXSV_EINVAL, "run: null sim");
     if (!s->state_set) return fail(HEXSV_ESTATE, "run: call set_state first");
     HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
@@ -449,7 +479,7 @@ extern "C" int hexsv_sim_run(hexsv_sim *s, double t_end, int64_t max_steps, hipS
     for (;;) {
         const int64_t before = c.steps;
         if (s->timing) HIP_TRY(hipEventRecord(s->ev0, stream));
-        HIP_TRY(hipGraphLaunch(s->gexec, stream));
+        HIP_TRY(hipGraphLaunch(shortg ? s->sexec : s->gexec, stream));
         if (s->timing) HIP_TRY(hipEventRecord(s->ev1, stream));
         HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -636,8 +666,18 @@ static int window_buffers(hexsv_sim *s) {
     if (!s->d_sw) {
         HIP_TRY(hipMalloc(&s->d_sw, sizeof(SurWin)));
         HIP_TRY(hipHostMalloc(&s->h_sw, sizeof(SurWin), hipHostMallocDefault));
-        HIP_TRY(hipMalloc(&s->d_op, sizeof(Part) * 2 * OUTFLOW_PARTS));
+        HIP_TRY(hipMalloc(&s->d_op, sizeof(Part) * 2 * WIN_PARTS));
         HIP_TRY(hipMalloc(&s->d_scr, s->esz * 3 * (size_t)s->grid->n));
+        HIP_TRY(hipMalloc(&s->d_slope, sizeof(float2) * (size_t)s->grid->n));
+    }
+    return HEXSV_OK;
+}
+
+template <typename T>
+static int window_slope(hexsv_sim *s, hipStream_t st) {
+    if (!s->slope_ok) {
+        HIP_TRY(launch_win_slope<T>(dom_of<T>(s), s->grid->kg, s->grid->edge, s->d_slope, st));
+        s->slope_ok = true;
     }
     return HEXSV_OK;
 }
@@ -664,16 +704,17 @@ static int window_features(hexsv_sim *s, hexsv_surrogate *sur, double window, in
     float sc[8];
     rc = hexsv_surrogate_get_scales(sur, sc, 8);
     if (rc) return rc;
+    rc = window_slope<T>(s, st);
+    if (rc) return rc;
     window_record(s, INFINITY, window, k, 0.0, 0);
     HIP_TRY(hipMemcpyAsync(s->d_sw, s->h_sw, sizeof(SurWin), hipMemcpyHostToDevice, st));
     const KDom<T> d = dom_of<T>(s);
     HIP_TRY(launch_win_reset(s->d_sw, st));
-    HIP_TRY(launch_win_begin(s->d_ctl, s->d_sw, s->rn, s->kc, st));
     HIP_TRY(launch_win_probe<T>(d, s->grid->kg, s->kc, s->rn, s->d_ctl, s->d_sw, (T *)s->d_scr,
                                 s->p.dt_max, st));
     HIP_TRY(launch_win_features<T>(d, s->grid->kg, s->grid->edge, s->d_ctl, s->d_sw,
-                                   (const T *)s->d_scr, s->p.dt_max, feat_scale(sc), 0, d_features,
-                                   st));
+                                   (const T *)s->d_scr, s->d_slope, s->p.dt_max, feat_scale(sc), 0,
+                                   d_features, s->d_op, st));
     return HEXSV_OK;
 }
 
@@ -688,10 +729,13 @@ extern "C" int hexsv_sim_surrogate_features(hexsv_sim *s, hexsv_surrogate *sur, 
 
 // Windows chained in one graph launch (a refused window stops the rest of
 // its chain, whose kernels then return at once).
-static const int WIN_CHAIN = 8;
+static const int WIN_CHAIN = 16;
+// Most plain steps one refused window may take before the run reports a stall.
+static const int64_t FALLBACK_STEP_LIMIT = 1 << 20;
 
-// One window: begin, outflow rate of the state, features, network, predicted
-// state, its outflow rate and sums, gate.
+// One window: probe step (which starts the window), features (with the start
+// state's outflow rate), network, predicted state (with its sums and outflow
+// rate), gate, and the optional projection.
 template <typename T>
 static int window_body(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float *out,
                        const float *sc, hipStream_t st) {
@@ -701,20 +745,15 @@ static int window_body(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float
     const int64_t n = s->grid->n;
     T *scr = (T *)s->d_scr;
     const double dt_max = s->p.dt_max;
-    Part *op0 = s->d_op, *op1 = s->d_op + OUTFLOW_PARTS;
-    HIP_TRY(launch_win_begin(s->d_ctl, s->d_sw, s->rn, s->kc, st));
-    HIP_TRY(launch_win_outflow<T>(d, g, l, s->d_ctl, s->d_sw, 0, op0, st));
+    Part *op0 = s->d_op, *part = s->d_op + WIN_PARTS;
     HIP_TRY(launch_win_probe<T>(d, g, s->kc, s->rn, s->d_ctl, s->d_sw, scr, dt_max, st));
-    HIP_TRY(launch_win_features<T>(d, g, s->grid->edge, s->d_ctl, s->d_sw, scr, dt_max,
-                                   feat_scale(sc), 1, x0, st));
-    int rc = sur_forward_x0(sur, g.nq, g.nr, st);
+    HIP_TRY(launch_win_features<T>(d, g, l, s->d_ctl, s->d_sw, scr, s->d_slope, dt_max,
+                                   feat_scale(sc), 1, x0, op0, st));
+    int rc = sur_forward_x0(sur, g.nq, g.nr, st, &s->d_sw->live);
     if (rc) return rc;
-    HIP_TRY(launch_win_apply<T>(d, n, s->d_ctl, s->d_sw, scr, dt_max, out, nn::OUT_STRIDE, sc[3],
-                                sc[4], 1e-6, st));
-    HIP_TRY(launch_win_outflow<T>(d, g, l, s->d_ctl, s->d_sw, 1, op1, st));
-    HIP_TRY(launch_win_sums<T>(d, n, s->kc, s->d_ctl, s->d_sw, s->d_part, st));
-    HIP_TRY(launch_win_gate(s->d_ctl, s->d_sw, s->d_part, PRIME_BLOCKS, op0, op1, OUTFLOW_PARTS,
-                            s->kc, st));
+    HIP_TRY(launch_win_apply<T>(d, g, l, s->kc, s->d_ctl, s->d_sw, scr, dt_max, out,
+                                nn::OUT_STRIDE, sc[3], sc[4], 1e-6, part, st));
+    HIP_TRY(launch_win_gate(s->d_ctl, s->d_sw, part, op0, s->kc, st));
     HIP_TRY(launch_win_scale<T>(d, n, s->d_ctl, s->d_sw, st));
     return HEXSV_OK;
 }
@@ -763,6 +802,8 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
     uint64_t gen = 0;
     rc = sur_window_bind(sur, s->grid->kg.nq, s->grid->kg.nr, &x0, &out, &gen);
     if (rc) return rc;
+    rc = window_slope<T>(s, st);
+    if (rc) return rc;
     // the scales are kernel arguments of the graph: rebuild when they change
     static_assert(sizeof(sc) == 8 * sizeof(float), "scales");
     bool same = s->wexec && s->w_sur == sur && s->w_gen == gen;
@@ -786,7 +827,7 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
         int left = 0;
         for (double t = t0; left < WIN_CHAIN && t + window <= t_end; t += window) ++left;
         if (left == 0) {  // last partial span: the plain solver
-            rc = hexsv_sim_run(s, t_end, 0, st);
+            rc = sim_run(s, t_end, 0, true, st);
             if (rc) return rc;
             *n_fb += 1;
             break;
@@ -802,8 +843,12 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
         HIP_TRY(hipStreamSynchronize(st));
         *n_acc += w.accepted;
         if (w.rejected) {  // the refused window's span, by the plain solver from its start
-            rc = hexsv_sim_run(s, c.t + window, 0, st);
+            const double target = c.t + window;
+            rc = sim_run(s, target, FALLBACK_STEP_LIMIT, true, st);
             if (rc) return rc;
+            if (!(c.t >= target))
+                return fail(HEXSV_ENUMERIC, "run_surrogate: the solver stalled at t=%g before %g",
+                            c.t, target);
             *n_fb += 1;
         }
     }

@@ -196,33 +196,6 @@ hipError_t launch_win_reset(SurWin *sw, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// Starts a window if the chain is alive and the span fits before t_stop: its
-// rain depth is the sum over k equal sub-steps of the rate at each sub-step's
-// end (the solver's right-endpoint rule, eq. fvm_2D_eq_frac.05-1).
-__global__ void k_win_begin(Ctl *ctl, SurWin *sw, KRain rn, KConst kc) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double t0 = ctl->t;
-    sw->scale_live = 0;
-    if (!sw->alive || ctl->err || !(t0 + sw->window <= sw->t_stop)) {
-        sw->live = 0;
-        return;
-    }
-    const double dt = sw->window / sw->k;
-    double depth = 0.0;
-    for (int j = 1; j <= sw->k; ++j) depth += dt * rain_rate(rn, t0 + j * dt);
-    sw->depth = depth;
-    sw->R = kc.area_active * depth;
-    sw->t0 = t0;
-    sw->S0 = ctl->stored;
-    sw->live = 1;
-}
-
-hipError_t launch_win_begin(Ctl *ctl, SurWin *sw, const KRain &rn, const KConst &kc,
-                            hipStream_t stream) {
-    hipLaunchKernelGGL(k_win_begin, dim3(1), dim3(64), 0, stream, ctl, sw, rn, kc);
-    return hipGetLastError();
-}
-
 // Water-balance gate of a window.  With S0, S1 the stored volumes at both
 // ends, R the rain volume and O the outflow volume by the trapezoid rule on
 // the outflow rates of both states, rho = |S1 - S0 - (R - O)| / max(S0 + R,
@@ -230,21 +203,24 @@ hipError_t launch_win_begin(Ctl *ctl, SurWin *sw, const KRain &rn, const KConst 
 // state and time, books and CFL bound advance; with `project` the depths are
 // then rescaled (k_win_scale) so that the stored volume is S0 + R - O
 // exactly, which keeps the accepted residuals from adding up over many
-// windows.  Refused: the chain stops and the state at t0 is untouched.
+// windows.  A window is also refused if its fastest wave speed more than
+// doubles.  Refused: the chain stops and the state at t0 is untouched.
 __global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const Part *part,
-                                                   int nparts, const Part *op0, const Part *op1,
-                                                   int nop, KConst kc) {
+                                                   const Part *op0, KConst kc) {
     if (!sw->live) return;
-    const Part p = reduce_parts<1024>(part, nparts);
-    const Part o0 = reduce_parts<1024>(op0, nop);
-    const Part o1 = reduce_parts<1024>(op1, nop);
+    const Part p = reduce_parts<1024>(part, WIN_PARTS);
+    const Part o0 = reduce_parts<1024>(op0, WIN_PARTS);
     if (threadIdx.x != 0) return;
-    const double Ow = 0.5 * (o0.stored + o1.stored) * sw->window;
+    const double Ow = 0.5 * (o0.stored + p.outflow) * sw->window;
     double ref = sw->S0 + sw->R;
     if (ref < 1e-300) ref = 1e-300;
     const double rho = fabs(p.stored - sw->S0 - (sw->R - Ow)) / ref;
     sw->rho = rho;
-    const bool ok = p.clamp == 0.0 && isfinite(p.stored) && isfinite(Ow) && rho <= sw->tol;
+    // also refused: a prediction whose fastest wave more than doubles within the
+    // window (it would shrink the solver's next steps for no physical reason)
+    // (an infinite tolerance keeps every finite window)
+    const bool calm = !(sw->c0 > 0.0) || p.cmax <= 2.0 * sw->c0 || isinf(sw->tol);
+    const bool ok = p.clamp == 0.0 && isfinite(p.stored) && isfinite(Ow) && rho <= sw->tol && calm;
     if (ok) {
         const double target = sw->S0 + sw->R - Ow;
         double stored = p.stored;
@@ -268,10 +244,9 @@ __global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const P
     sw->live = 0;
 }
 
-hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, int nparts, const Part *op0,
-                           const Part *op1, int nop, const KConst &kc, hipStream_t stream) {
-    hipLaunchKernelGGL(k_win_gate, dim3(1), dim3(1024), 0, stream, ctl, sw, part, nparts, op0, op1,
-                       nop, kc);
+hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, const Part *op0,
+                           const KConst &kc, hipStream_t stream) {
+    hipLaunchKernelGGL(k_win_gate, dim3(1), dim3(1024), 0, stream, ctl, sw, part, op0, kc);
     return hipGetLastError();
 }
 

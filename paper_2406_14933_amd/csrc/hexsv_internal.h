@@ -115,10 +115,11 @@ struct alignas(64) SurWin {
     int32_t scale_live;             // the accepted state waits for its rescaling
     int32_t perr, perr_cell;        // non-finite value met by a probe step
     double scale;                   // factor of that rescaling
+    double c0;                      // c_max of the window's start state
 };
 
 constexpr int FEATURES = nn::FEATURES;
-constexpr int OUTFLOW_PARTS = 256;
+constexpr int WIN_PARTS = 256;  // partial records of the window reductions
 
 // Feature scales: H (depth), Q (discharge), Z (elevation), S (slope), and the
 // window changes of depth and discharge dH, dQ.
@@ -127,36 +128,35 @@ struct FeatScale {
 };
 
 hipError_t launch_win_reset(SurWin *sw, hipStream_t stream);
-hipError_t launch_win_begin(Ctl *ctl, SurWin *sw, const KRain &rn, const KConst &kc,
-                            hipStream_t stream);
-hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, int nparts, const Part *op0,
-                           const Part *op1, int nop, const KConst &kc, hipStream_t stream);
-// Window kernels on the current state (buffer ctl->parity), each a no-op unless sw->live.
+hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, const Part *op0,
+                           const KConst &kc, hipStream_t stream);
+// Window kernels on the current state (buffer ctl->parity), each a no-op unless sw->live
+// (which the probe, the first of them, decides).
 // scr holds 3 x cells values of T (the probe step's h, v1, v2).
 template <typename T>
 hipError_t launch_win_probe(const KDom<T> &d, const KGrid &g, const KConst &kc, const KRain &rn,
                             const Ctl *ctl, SurWin *sw, T *scr, double dt_max, hipStream_t stream);
+// Terrain slope of every cell (float2), static for a simulation.
 template <typename T>
-hipError_t launch_win_features(const KDom<T> &d, const KGrid &g, double a, const Ctl *ctl,
-                               const SurWin *sw, const T *scr, double dt_max, FeatScale sc,
-                               int packed, void *out, hipStream_t stream);
+hipError_t launch_win_slope(const KDom<T> &d, const KGrid &g, double a, float2 *slope,
+                            hipStream_t stream);
+// Features of the current state (packed bf16 network input, or FP32) and the
+// outflow rate of the current state (WIN_PARTS partials in op0[].stored).
 template <typename T>
-hipError_t launch_win_apply(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,
-                            const T *scr, double dt_max, const float *out, int out_stride, float dH,
-                            float dQ, double m_min, hipStream_t stream);
-// Outflow rate of the current (flip = 0) or the predicted (flip = 1) state.
+hipError_t launch_win_features(const KDom<T> &d, const KGrid &g, double l, const Ctl *ctl,
+                               const SurWin *sw, const T *scr, const float2 *slope, double dt_max,
+                               FeatScale sc, int packed, void *out, Part *op0, hipStream_t stream);
+// Predicted state into the other buffer, with its reductions (WIN_PARTS partials
+// {c_max, stored, outflow rate, non-finite count}).
 template <typename T>
-hipError_t launch_win_outflow(const KDom<T> &d, const KGrid &g, double l, const Ctl *ctl,
-                              const SurWin *sw, int flip, Part *op, hipStream_t stream);
+hipError_t launch_win_apply(const KDom<T> &d, const KGrid &g, double l, const KConst &kc,
+                            const Ctl *ctl, const SurWin *sw, const T *scr, double dt_max,
+                            const float *out, int out_stride, float dH, float dQ, double m_min,
+                            Part *part, hipStream_t stream);
 // Rescaling of an accepted state onto the water balance (no-op unless sw->scale_live).
 template <typename T>
 hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,
                             hipStream_t stream);
-// Stored volume and c_max of the predicted state (PRIME_BLOCKS partials).
-template <typename T>
-hipError_t launch_win_sums(const KDom<T> &d, int64_t n, const KConst &kc, const Ctl *ctl,
-                           const SurWin *sw, Part *part, hipStream_t stream);
-
 hipError_t launch_tables(const KGrid &g, const uint8_t *active, int32_t *nbr, uint8_t *code,
                          hipStream_t stream);
 

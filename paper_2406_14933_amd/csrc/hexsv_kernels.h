@@ -217,11 +217,33 @@ __device__ inline double win_probe_dt(const Ctl *ctl, double dt_max) {
 // from the current state into the scratch buffers, with the control block
 // untouched.  Its change, scaled to the window, is the extrapolation the
 // network corrects.
+//
+// The probe also starts the window: every workgroup decides (identically)
+// whether it runs -- the chain is alive and the span fits before t_stop -- and
+// workgroup 0 records that and the window's rain depth (k equal sub-steps,
+// each at the rate of its end: the solver's right-endpoint rule), rain volume,
+// start time, stored volume and c_max for the kernels that follow.
 template <typename T, int TQ, int TR, int NT>
 __global__ __launch_bounds__(NT) void k_win_probe(KDom<T> d, KGrid g, KConst kc, KRain rn,
                                                   const Ctl *ctl, SurWin *sw, T *scr, int ntq,
                                                   int ntiles, double dt_max) {
-    if (!sw->live) return;
+    const double t0 = ctl->t;
+    const bool live = sw->alive && !ctl->err && t0 + sw->window <= sw->t_stop;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sw->scale_live = 0;
+        sw->live = live ? 1 : 0;
+        if (live) {
+            const double dts = sw->window / sw->k;
+            double depth = 0.0;
+            for (int j = 1; j <= sw->k; ++j) depth += dts * rain_rate(rn, t0 + j * dts);
+            sw->depth = depth;
+            sw->R = kc.area_active * depth;
+            sw->t0 = t0;
+            sw->S0 = ctl->stored;
+            sw->c0 = ctl->last_cmax;
+        }
+    }
+    if (!live) return;
     const int tile = blockIdx.x;
     if (tile >= ntiles) return;
     const int par = ctl->parity;
@@ -254,137 +276,25 @@ hipError_t launch_win_probe(const KDom<T> &d, const KGrid &g, const KConst &kc, 
     return hipGetLastError();
 }
 
-// The network inputs of cell i (all but theta zero on inactive cells):
-//   h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, depth/H, slope/S (2),
-//   and the probe step's change scaled by window/dt: dh/dH, dq1/dQ, dq2/dQ.
+// Terrain slope of every cell (static: computed once per run of windows).
 template <typename T>
-__device__ inline void win_feature_vec(const KGrid &g, double a, const T *h, const T *v1,
-                                       const T *v2, const T *z, const T *th, const T *hs,
-                                       const T *v1s, const T *v2s, int64_t i, double depth,
-                                       double xs, const FeatScale &sc, float f[FEATURES]) {
-    const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
-#pragma unroll
-    for (int c = 0; c < FEATURES; ++c) f[c] = 0.f;
-    if (!(th[i] > T(0))) return;
-    const double t = (double)th[i], hh = (double)h[i];
-    double sx, sy;
-    terrain_slope<T>(g, a, z, th, nullptr, q, r, i, sx, sy);
-    const double q1 = t * hh * (double)v1[i], q2 = t * hh * (double)v2[i];
-    const double xh = xs * ((double)hs[i] - hh);
-    const double xq1 = xs * (t * (double)hs[i] * (double)v1s[i] - q1);
-    const double xq2 = xs * (t * (double)hs[i] * (double)v2s[i] - q2);
-    f[0] = (float)(hh / sc.H);
-    f[1] = (float)(q1 / sc.Q);
-    f[2] = (float)(q2 / sc.Q);
-    f[3] = (float)((double)z[i] / sc.Z);
-    f[4] = (float)t;
-    f[5] = (float)(depth / sc.H);
-    f[6] = (float)(sx / sc.S);
-    f[7] = (float)(sy / sc.S);
-    f[8] = (float)(xh / sc.dH);
-    f[9] = (float)(xq1 / sc.dQ);
-    f[10] = (float)(xq2 / sc.dQ);
-}
-
-// PACKED: bf16, FEATURES_PAD channels per cell (the network's input buffer);
-// otherwise FP32, FEATURES channels per cell.
-template <typename T, bool PACKED>
-__global__ __launch_bounds__(256) void k_win_features(KDom<T> d, KGrid g, double a,
-                                                      const Ctl *ctl, const SurWin *sw,
-                                                      const T *scr, double dt_max, FeatScale sc,
-                                                      void *out) {
-    if (!sw->live) return;
-    const int par = ctl->parity;
-    const double depth = sw->depth;
-    const double xs = sw->window / win_probe_dt(ctl, dt_max);
+__global__ __launch_bounds__(256) void k_win_slope(KDom<T> d, KGrid g, double a,
+                                                   float2 *__restrict__ slope) {
     const int64_t n = (int64_t)g.nq * g.nr;
-    const T *h = par ? d.st[1][0] : d.st[0][0];
-    const T *v1 = par ? d.st[1][1] : d.st[0][1];
-    const T *v2 = par ? d.st[1][2] : d.st[0][2];
-    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        float f[FEATURES];
-        win_feature_vec<T>(g, a, h, v1, v2, d.z, d.th, scr, scr + n, scr + 2 * n, i, depth, xs, sc, f);
-        if constexpr (PACKED) {
-            bf16x8 v[nn::FEATURES_PAD / 8];
-#pragma unroll
-            for (int c = 0; c < nn::FEATURES_PAD; ++c)
-                v[c / 8][c % 8] = c < FEATURES ? (__bf16)f[c] : (__bf16)0.f;
-#pragma unroll
-            for (int u = 0; u < nn::FEATURES_PAD / 8; ++u)
-                reinterpret_cast<bf16x8 *>((__bf16 *)out + i * nn::FEATURES_PAD)[u] = v[u];
-        } else {
-#pragma unroll
-            for (int c = 0; c < FEATURES; ++c) ((float *)out)[i * FEATURES + c] = f[c];
-        }
+        const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+        double sx = 0.0, sy = 0.0;
+        if (d.th[i] > T(0)) terrain_slope<T>(g, a, d.z, d.th, nullptr, q, r, i, sx, sy);
+        slope[i] = make_float2((float)sx, (float)sy);
     }
 }
 
 template <typename T>
-hipError_t launch_win_features(const KDom<T> &d, const KGrid &g, double a, const Ctl *ctl,
-                               const SurWin *sw, const T *scr, double dt_max, FeatScale sc,
-                               int packed, void *out, hipStream_t stream) {
+hipError_t launch_win_slope(const KDom<T> &d, const KGrid &g, double a, float2 *slope,
+                            hipStream_t stream) {
     const int64_t n = (int64_t)g.nq * g.nr;
     const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-    if (packed)
-        hipLaunchKernelGGL((k_win_features<T, true>), dim3(nb), dim3(256), 0, stream, d, g, a, ctl,
-                           sw, scr, dt_max, sc, out);
-    else
-        hipLaunchKernelGGL((k_win_features<T, false>), dim3(nb), dim3(256), 0, stream, d, g, a, ctl,
-                           sw, scr, dt_max, sc, out);
-    return hipGetLastError();
-}
-
-// Predicted state of the window into buffer parity^1, with x the probe's
-// change scaled to the window:
-//   h' = max(h + x_h + dH out0, 0),  q' = theta h v + x_q + dQ (out1, out2),
-//   v' = q' / (theta h') (0 where theta h' <= m_min).  Inactive cells are copied.
-template <typename T>
-__global__ __launch_bounds__(256) void k_win_apply(KDom<T> d, int64_t n, const Ctl *ctl,
-                                                   const SurWin *sw, const T *scr, double dt_max,
-                                                   const float *__restrict__ out, int os, float dH,
-                                                   float dQ, double m_min) {
-    if (!sw->live) return;
-    const int par = ctl->parity;
-    const double xs = sw->window / win_probe_dt(ctl, dt_max);
-    const T *h = par ? d.st[1][0] : d.st[0][0];
-    const T *v1 = par ? d.st[1][1] : d.st[0][1];
-    const T *v2 = par ? d.st[1][2] : d.st[0][2];
-    T *ho = par ? d.st[0][0] : d.st[1][0];
-    T *v1o = par ? d.st[0][1] : d.st[1][1];
-    T *v2o = par ? d.st[0][2] : d.st[1][2];
-    const T *hs = scr, *v1s = scr + n, *v2s = scr + 2 * n;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const T th = d.th[i];
-        if (!(th > T(0))) {
-            ho[i] = h[i];
-            v1o[i] = v1[i];
-            v2o[i] = v2[i];
-            continue;
-        }
-        const double t = (double)th, hh = (double)h[i];
-        const double q1 = t * hh * (double)v1[i], q2 = t * hh * (double)v2[i];
-        const double xh = xs * ((double)hs[i] - hh);
-        const double xq1 = xs * (t * (double)hs[i] * (double)v1s[i] - q1);
-        const double xq2 = xs * (t * (double)hs[i] * (double)v2s[i] - q2);
-        double hn = hh + xh + (double)dH * (double)out[i * os + 0];
-        hn = hn > 0.0 ? hn : 0.0;
-        const double p1 = q1 + xq1 + (double)dQ * (double)out[i * os + 1];
-        const double p2 = q2 + xq2 + (double)dQ * (double)out[i * os + 2];
-        const double mn = t * hn;
-        ho[i] = (T)hn;
-        v1o[i] = mn > m_min ? (T)(p1 / mn) : T(0);
-        v2o[i] = mn > m_min ? (T)(p2 / mn) : T(0);
-    }
-}
-
-template <typename T>
-hipError_t launch_win_apply(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,
-                            const T *scr, double dt_max, const float *out, int out_stride, float dH,
-                            float dQ, double m_min, hipStream_t stream) {
-    const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-    hipLaunchKernelGGL((k_win_apply<T>), dim3(nb), dim3(256), 0, stream, d, n, ctl, sw, scr, dt_max,
-                       out, out_stride, dH, dQ, m_min);
+    hipLaunchKernelGGL((k_win_slope<T>), dim3(nb), dim3(256), 0, stream, d, g, a, slope);
     return hipGetLastError();
 }
 
@@ -411,51 +321,158 @@ __device__ inline double cell_outflow(const KGrid &g, double l, const T *h, cons
     return acc;
 }
 
-// One partial per workgroup (gridDim.x == OUTFLOW_PARTS) in Part::stored.  Without an
-// active mask only the raster's rim can hold OUTFLOW edges and only it is visited.
+// Can cell (q, r) have an OUTFLOW edge?  Without an active mask only the rim can.
+__device__ inline bool may_outflow(const KGrid &g, int q, int r) {
+    return g.has_mask || q == 0 || r == 0 || q == g.nq - 1 || r == g.nr - 1;
+}
+
+// The network inputs of one cell (all but theta zero on inactive cells):
+//   h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, depth/H, slope/S (2),
+//   and the probe step's change scaled by xs = window/dt: x_h/dH, x_q1/dQ, x_q2/dQ.
 template <typename T>
-__global__ __launch_bounds__(256) void k_win_outflow(KDom<T> d, KGrid g, double l, const Ctl *ctl,
-                                                     const SurWin *sw, int flip,
-                                                     Part *__restrict__ op) {
-    if (sw && !sw->live) return;
-    const int par = ctl->parity ^ flip;
-    const T *h = d.buf(par, 0), *v1 = d.buf(par, 1), *v2 = d.buf(par, 2);
-    double acc = 0.0;
-    const int nq = g.nq, nr = g.nr;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    if (g.has_mask) {
-        const int64_t n = (int64_t)nq * nr;
-        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-            const int r = (int)(i / nq), q = (int)(i - (int64_t)r * nq);
-            acc += cell_outflow<T>(g, l, h, v1, v2, d.th, q, r, i);
+__device__ inline void win_feature_vec(T h, T v1, T v2, T z, T th, T hs, T v1s, T v2s, float2 sl,
+                                       double depth, double xs, const FeatScale &sc,
+                                       float f[FEATURES]) {
+#pragma unroll
+    for (int c = 0; c < FEATURES; ++c) f[c] = 0.f;
+    if (!(th > T(0))) return;
+    const T q1 = th * h * v1, q2 = th * h * v2;
+    f[0] = (float)h / sc.H;
+    f[1] = (float)q1 / sc.Q;
+    f[2] = (float)q2 / sc.Q;
+    f[3] = (float)z / sc.Z;
+    f[4] = (float)th;
+    f[5] = (float)(depth / sc.H);
+    f[6] = sl.x / sc.S;
+    f[7] = sl.y / sc.S;
+    f[8] = (float)(xs * (double)(hs - h)) / sc.dH;
+    f[9] = (float)(xs * (double)(th * hs * v1s - q1)) / sc.dQ;
+    f[10] = (float)(xs * (double)(th * hs * v2s - q2)) / sc.dQ;
+}
+
+// Features of the current state (PACKED: bf16, FEATURES_PAD channels per cell,
+// the network's input buffer; otherwise FP32, FEATURES channels per cell),
+// and the outflow rate of the current state: one partial per workgroup in
+// op0[b].stored (WIN_PARTS workgroups).
+template <typename T, bool PACKED>
+__global__ __launch_bounds__(256) void k_win_features(KDom<T> d, KGrid g, double l,
+                                                      const Ctl *ctl, const SurWin *sw,
+                                                      const T *scr, const float2 *slope,
+                                                      double dt_max, FeatScale sc, void *out,
+                                                      Part *op0) {
+    if (!sw->live) return;
+    const int par = ctl->parity;
+    const double depth = sw->depth;
+    const double xs = sw->window / win_probe_dt(ctl, dt_max);
+    const int64_t n = (int64_t)g.nq * g.nr;
+    const T *h = par ? d.st[1][0] : d.st[0][0];
+    const T *v1 = par ? d.st[1][1] : d.st[0][1];
+    const T *v2 = par ? d.st[1][2] : d.st[0][2];
+    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+    double o = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        float f[FEATURES];
+        win_feature_vec<T>(h[i], v1[i], v2[i], d.z[i], d.th[i], scr[i], scr[n + i], scr[2 * n + i],
+                           slope[i], depth, xs, sc, f);
+        if constexpr (PACKED) {
+            bf16x8 v[nn::FEATURES_PAD / 8];
+#pragma unroll
+            for (int c = 0; c < nn::FEATURES_PAD; ++c)
+                v[c / 8][c % 8] = c < FEATURES ? (__bf16)f[c] : (__bf16)0.f;
+#pragma unroll
+            for (int u = 0; u < nn::FEATURES_PAD / 8; ++u)
+                reinterpret_cast<bf16x8 *>((__bf16 *)out + i * nn::FEATURES_PAD)[u] = v[u];
+        } else {
+#pragma unroll
+            for (int c = 0; c < FEATURES; ++c) ((float *)out)[i * FEATURES + c] = f[c];
         }
-    } else {
-        // rim: row 0, row nr-1 (if nr > 1), then columns 0 and nq-1 (if nq > 1) of rows 1..nr-2
-        const int64_t rows = nr > 1 ? 2 * (int64_t)nq : nq;
-        const int64_t mid = nr > 2 ? nr - 2 : 0;
-        const int64_t cols = nq > 1 ? 2 * mid : mid;
-        for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < rows + cols; p += stride) {
-            int q, r;
-            if (p < rows) {
-                q = (int)(p % nq);
-                r = p < nq ? 0 : nr - 1;
-            } else {
-                const int64_t c = p - rows;
-                r = 1 + (int)(c % mid);
-                q = c < mid ? 0 : nq - 1;
-            }
-            acc += cell_outflow<T>(g, l, h, v1, v2, d.th, q, r, (int64_t)r * nq + q);
-        }
+        const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+        if (may_outflow(g, q, r)) o += cell_outflow<T>(g, l, h, v1, v2, d.th, q, r, i);
     }
-    const Part p = block_reduce<256>(0.0, acc, 0.0, 0.0);
-    if (threadIdx.x == 0) op[blockIdx.x] = p;
+    const Part p = block_reduce<256>(0.0, o, 0.0, 0.0);
+    if (threadIdx.x == 0) op0[blockIdx.x] = p;
 }
 
 template <typename T>
-hipError_t launch_win_outflow(const KDom<T> &d, const KGrid &g, double l, const Ctl *ctl,
-                              const SurWin *sw, int flip, Part *op, hipStream_t stream) {
-    hipLaunchKernelGGL((k_win_outflow<T>), dim3(OUTFLOW_PARTS), dim3(256), 0, stream, d, g, l, ctl,
-                       sw, flip, op);
+hipError_t launch_win_features(const KDom<T> &d, const KGrid &g, double l, const Ctl *ctl,
+                               const SurWin *sw, const T *scr, const float2 *slope, double dt_max,
+                               FeatScale sc, int packed, void *out, Part *op0, hipStream_t stream) {
+    if (packed)
+        hipLaunchKernelGGL((k_win_features<T, true>), dim3(WIN_PARTS), dim3(256), 0, stream, d, g, l,
+                           ctl, sw, scr, slope, dt_max, sc, out, op0);
+    else
+        hipLaunchKernelGGL((k_win_features<T, false>), dim3(WIN_PARTS), dim3(256), 0, stream, d, g, l,
+                           ctl, sw, scr, slope, dt_max, sc, out, op0);
+    return hipGetLastError();
+}
+
+// Predicted state of the window into buffer parity^1, with x the probe's
+// change scaled to the window:
+//   h' = max(h + x_h + dH out0, 0),  q' = theta h v + x_q + dQ (out1, out2),
+//   v' = q' / (theta h') (0 where theta h' <= m_min).  Inactive cells are copied.
+// Also reduces, per workgroup (WIN_PARTS workgroups), the predicted state's
+// c_max, stored volume sum sigma theta h', outflow rate and count of
+// non-finite wave speeds into part[b] = {cmax, stored, outflow, bad}.
+template <typename T>
+__global__ __launch_bounds__(256) void k_win_apply(KDom<T> d, KGrid g, double l, KConst kc,
+                                                   const Ctl *ctl, const SurWin *sw, const T *scr,
+                                                   double dt_max, const float *__restrict__ out,
+                                                   int os, float dH, float dQ, double m_min,
+                                                   Part *part) {
+    if (!sw->live) return;
+    const int par = ctl->parity;
+    const int64_t n = (int64_t)g.nq * g.nr;
+    const double xs = sw->window / win_probe_dt(ctl, dt_max);
+    const T *h = par ? d.st[1][0] : d.st[0][0];
+    const T *v1 = par ? d.st[1][1] : d.st[0][1];
+    const T *v2 = par ? d.st[1][2] : d.st[0][2];
+    T *ho = par ? d.st[0][0] : d.st[1][0];
+    T *v1o = par ? d.st[0][1] : d.st[1][1];
+    T *v2o = par ? d.st[0][2] : d.st[1][2];
+    const T *hs = scr, *v1s = scr + n, *v2s = scr + 2 * n;
+    const T G = (T)kc.g;
+    double c = 0.0, s = 0.0, o = 0.0, bad = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const T th = d.th[i];
+        if (!(th > T(0))) {
+            ho[i] = h[i];
+            v1o[i] = v1[i];
+            v2o[i] = v2[i];
+            continue;
+        }
+        const T q1 = th * h[i] * v1[i], q2 = th * h[i] * v2[i];
+        const double xh = xs * (double)(hs[i] - h[i]);
+        const double xq1 = xs * (double)(th * hs[i] * v1s[i] - q1);
+        const double xq2 = xs * (double)(th * hs[i] * v2s[i] - q2);
+        double hn = (double)h[i] + xh + (double)dH * (double)out[i * os + 0];
+        hn = hn > 0.0 ? hn : 0.0;
+        const double p1 = (double)q1 + xq1 + (double)dQ * (double)out[i * os + 1];
+        const double p2 = (double)q2 + xq2 + (double)dQ * (double)out[i * os + 2];
+        const double mn = (double)th * hn;
+        const T hT = (T)hn;
+        const T a1 = mn > m_min ? (T)(p1 / mn) : T(0);
+        const T a2 = mn > m_min ? (T)(p2 / mn) : T(0);
+        ho[i] = hT;
+        v1o[i] = a1;
+        v2o[i] = a2;
+        const double cc = (double)(p_sqrt(a1 * a1 + a2 * a2) + p_sqrt(G * hT));
+        if (__builtin_isfinite(cc)) c = cc > c ? cc : c;
+        else bad += 1.0;  // the gate refuses such a window
+        s += kc.sigma * ((double)th * (double)hT);
+        const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+        if (may_outflow(g, q, r)) o += cell_outflow<T>(g, l, ho, v1o, v2o, d.th, q, r, i);
+    }
+    const Part p = block_reduce<256>(c, s, o, bad);
+    if (threadIdx.x == 0) part[blockIdx.x] = p;
+}
+
+template <typename T>
+hipError_t launch_win_apply(const KDom<T> &d, const KGrid &g, double l, const KConst &kc,
+                            const Ctl *ctl, const SurWin *sw, const T *scr, double dt_max,
+                            const float *out, int out_stride, float dH, float dQ, double m_min,
+                            Part *part, hipStream_t stream) {
+    hipLaunchKernelGGL((k_win_apply<T>), dim3(WIN_PARTS), dim3(256), 0, stream, d, g, l, kc, ctl, sw,
+                       scr, dt_max, out, out_stride, dH, dQ, m_min, part);
     return hipGetLastError();
 }
 
@@ -479,35 +496,6 @@ hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const S
     return hipGetLastError();
 }
 
-// Stored volume sum sigma theta h and c_max of the predicted state.
-template <typename T>
-__global__ __launch_bounds__(256) void k_win_sums(KDom<T> d, int64_t n, KConst kc, const Ctl *ctl,
-                                                  const SurWin *sw, Part *part) {
-    if (!sw->live) return;
-    const int par = ctl->parity ^ 1;
-    const T *h = d.buf(par, 0), *v1 = d.buf(par, 1), *v2 = d.buf(par, 2);
-    double c = 0.0, s = 0.0, bad = 0.0;
-    const T G = (T)kc.g;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const T th = d.th[i];
-        if (!(th > T(0))) continue;
-        const double cc = (double)(p_sqrt(v1[i] * v1[i] + v2[i] * v2[i]) + p_sqrt(G * h[i]));
-        if (__builtin_isfinite(cc)) c = cc > c ? cc : c;
-        else bad += 1.0;  // counted in Part::clamp; the gate refuses such a window
-        s += kc.sigma * ((double)th * (double)h[i]);
-    }
-    const Part p = block_reduce<256>(c, s, 0.0, bad);
-    if (threadIdx.x == 0) part[blockIdx.x] = p;
-}
-
-template <typename T>
-hipError_t launch_win_sums(const KDom<T> &d, int64_t n, const KConst &kc, const Ctl *ctl,
-                           const SurWin *sw, Part *part, hipStream_t stream) {
-    hipLaunchKernelGGL((k_win_sums<T>), dim3(PRIME_BLOCKS), dim3(256), 0, stream, d, n, kc, ctl, sw,
-                       part);
-    return hipGetLastError();
-}
-
 #define HEXSV_INSTANTIATE(T)                                                                  \
     template hipError_t launch_step<T>(int, const KDom<T> &, const KGrid &, const KConst &,   \
                                        const KRain &, Ctl *, Part *, int, int, int,           \
@@ -520,19 +508,18 @@ hipError_t launch_win_sums(const KDom<T> &d, int64_t n, const KConst &kc, const 
     template hipError_t launch_win_probe<T>(const KDom<T> &, const KGrid &, const KConst &,   \
                                             const KRain &, const Ctl *, SurWin *, T *, double, \
                                             hipStream_t);                                     \
+    template hipError_t launch_win_slope<T>(const KDom<T> &, const KGrid &, double, float2 *, \
+                                            hipStream_t);                                     \
     template hipError_t launch_win_features<T>(const KDom<T> &, const KGrid &, double,        \
-                                               const Ctl *, const SurWin *, const T *, double, \
-                                               FeatScale, int, void *, hipStream_t);         \
-    template hipError_t launch_win_apply<T>(const KDom<T> &, int64_t, const Ctl *,            \
-                                            const SurWin *, const T *, double, const float *, \
-                                            int, float, float, double, hipStream_t);          \
-    template hipError_t launch_win_outflow<T>(const KDom<T> &, const KGrid &, double,         \
-                                              const Ctl *, const SurWin *, int, Part *,       \
-                                              hipStream_t);                                   \
+                                               const Ctl *, const SurWin *, const T *,        \
+                                               const float2 *, double, FeatScale, int, void *, \
+                                               Part *, hipStream_t);                          \
+    template hipError_t launch_win_apply<T>(const KDom<T> &, const KGrid &, double,           \
+                                            const KConst &, const Ctl *, const SurWin *,      \
+                                            const T *, double, const float *, int, float,     \
+                                            float, double, Part *, hipStream_t);              \
     template hipError_t launch_win_scale<T>(const KDom<T> &, int64_t, const Ctl *,            \
                                             const SurWin *, hipStream_t);                     \
-    template hipError_t launch_win_sums<T>(const KDom<T> &, int64_t, const KConst &,          \
-                                           const Ctl *, const SurWin *, Part *, hipStream_t); \
     template hipError_t launch_import<T>(const double *, T *, const uint8_t *, int, int64_t,  \
                                          hipStream_t);                                        \
     template hipError_t launch_export<T>(const KDom<T> &, int, int64_t, double *, double *,   \

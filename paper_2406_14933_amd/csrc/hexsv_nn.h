@@ -19,9 +19,10 @@ int conv_tiles(int nq, int nr, int batch);
 // weight layout wm[t][coutp][cinp]; epilogue per EPI_* (see hexsv_nn.hip).
 // Built for (cinp, coutp, epi) in {(16,32,RELU), (32,32,RELU), (32,16,LIN),
 // (16,32,MASK), (32,32,MASK)}.
+// live (nullable, device): the launch does nothing unless *live != 0.
 hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf16 *wm,
                        const float *bias, void *out, const __bf16 *mask, int nq, int nr,
-                       int batch, int cout_real, hipStream_t st);
+                       int batch, int cout_real, hipStream_t st, const int32_t *live = nullptr);
 // Per-tile weight-gradient partials (7*coutp*cinp + coutp floats per tile).
 hipError_t launch_wgrad(int cinp, int coutp, const __bf16 *x, const __bf16 *dy, float *part,
                         int nq, int nr, int batch, hipStream_t st);

@@ -69,7 +69,8 @@ __global__ __launch_bounds__(NT) void k_hexconv(const __bf16 *__restrict__ x,
                                                 const __bf16 *__restrict__ wm,
                                                 const float *__restrict__ bias, void *out,
                                                 const __bf16 *__restrict__ mask, int nq, int nr,
-                                                int ntiles_total, int cout_real) {
+                                                int ntiles_total, int cout_real,
+                                                const int32_t *live) {
     constexpr int CH = CIN / 8;
     constexpr int MB = COUT / 16;                 // output-channel blocks
     constexpr int TPK = 32 / CIN;                 // taps per K step of 32
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(NT) void k_hexconv(const __bf16 *__restrict__ x,
     const int ntq = (nq + TQ - 1) / TQ, ntr = (nr + TR - 1) / TR;
     const int tile = blockIdx.x;
     if (tile >= ntiles_total) return;
+    if (live && !*live) return;  // a surrogate window that does not run
     int b, q0, r0;
     tile_of(tile, ntq, ntr, b, q0, r0);
     const int64_t soff = (int64_t)b * nq * nr;
@@ -383,12 +385,12 @@ int conv_tiles(int nq, int nr, int batch) {
 
 hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf16 *wm,
                        const float *bias, void *out, const __bf16 *mask, int nq, int nr,
-                       int batch, int cout_real, hipStream_t st) {
+                       int batch, int cout_real, hipStream_t st, const int32_t *live) {
     const int nt = conv_tiles(nq, nr, batch);
 #define HEXSV_CONV(CI, CO, E)                                                                   \
     if (cinp == CI && coutp == CO && epi == E) {                                                \
         hipLaunchKernelGGL((k_hexconv<CI, CO, E>), dim3(nt), dim3(NT), 0, st, x, wm, bias, out, \
-                           mask, nq, nr, nt, cout_real);                                        \
+                           mask, nq, nr, nt, cout_real, live);                                  \
         return hipGetLastError();                                                               \
     }
     HEXSV_CONV(16, 32, EPI_RELU)

@@ -196,14 +196,15 @@ extern "C" int hexsv_surrogate_get_scales(const hexsv_surrogate *s, float *scale
 }
 
 // Forward over the packed features already in s->x0; output in s->out.
-static int forward_packed(hexsv_surrogate *s, int nq, int nr, int batch, hipStream_t st) {
+static int forward_packed(hexsv_surrogate *s, int nq, int nr, int batch, hipStream_t st,
+                          const int32_t *live = nullptr) {
     const __bf16 *x = s->x0;
     for (int l = 0; l < s->layers; ++l) {
         const SurLayer &y = s->L[l];
         const bool last = l == s->layers - 1;
         void *o = last ? (void *)s->out : (void *)s->act[l];
         HIP_TRY(nn::launch_conv(y.cinp, y.coutp, last ? nn::EPI_LIN : nn::EPI_RELU, x, y.wm, y.bias,
-                                o, nullptr, nq, nr, batch, y.cout, st));
+                                o, nullptr, nq, nr, batch, y.cout, st, live));
         if (!last) x = s->act[l];
     }
     return HEXSV_OK;
@@ -243,8 +244,8 @@ int sur_window_bind(hexsv_surrogate *s, int nq, int nr, void **x0, const float *
     return HEXSV_OK;
 }
 
-int sur_forward_x0(hexsv_surrogate *s, int nq, int nr, hipStream_t st) {
-    return forward_packed(s, nq, nr, 1, st);
+int sur_forward_x0(hexsv_surrogate *s, int nq, int nr, hipStream_t st, const int32_t *live) {
+    return forward_packed(s, nq, nr, 1, st, live);
 }
 
 // Forward + L1 loss + backward into s->d_g; loss in *loss (synchronises).

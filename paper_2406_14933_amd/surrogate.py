@@ -166,6 +166,42 @@ def collect(scenarios, times, window, k, sur, scales=None):
     return WindowData(nq, nr, feats, target), scales
 
 
+def rollout_pairs(sur, scenarios, times, window, k, scales, tol=1e-5):
+    """Pairs whose start states come from surrogate runs of the scenarios, i.e. the states the
+    network meets once it drives a simulation, with the plain solver's change over the
+    window from each such state as the target (the same correction form as ``collect``).
+    Training on them as well keeps a run from drifting away from the data it was fitted on."""
+    nq, nr = scenarios[0].nq, scenarios[0].nr
+    F = hexsv.Surrogate.FEATURES
+    n = len(scenarios) * len(times)
+    feats = torch.empty((n, nq * nr, F), dtype=torch.float32, device="cuda")
+    target = torch.empty((n, nq * nr, 3), dtype=torch.float32, device="cuda")
+    p = 0
+    for sc in scenarios:
+        run = hexsv.Sim.from_scenario(sc, "fp32")
+        probe = hexsv.Sim.from_scenario(sc, "fp32")
+        th = torch.as_tensor(np.asarray(sc.theta, np.float64), device="cuda")
+        for t in times:
+            run.run_surrogate(sur, t, window, k, tol)
+            a = run.state()
+            probe.set_state(a["h"], a["v1"], a["v2"], t)
+            f = probe.surrogate_features(sur, window, k)
+            probe.run(t + window)
+            b = probe.state()
+            feats[p] = f
+            target[p, :, 0] = ((b["h"] - a["h"]) / scales.dH).float() - f[:, 8]
+            target[p, :, 1] = ((b["q1"] - a["q1"]) / scales.dQ).float() - f[:, 9]
+            target[p, :, 2] = ((b["q2"] - a["q2"]) / scales.dQ).float() - f[:, 10]
+            p += 1
+    del th
+    return WindowData(nq, nr, feats, target)
+
+
+def merge(*sets: WindowData) -> WindowData:
+    return WindowData(sets[0].nq, sets[0].nr, torch.cat([d.feats for d in sets]),
+                      torch.cat([d.target for d in sets]))
+
+
 def train(sur, data: WindowData, steps, batch=2, lr=2e-3, lr_end=1e-4, seed=0, log=None):
     """Adam on the mean L1 loss over random mini-batches, cosine decay lr -> lr_end.
     Returns the loss of every step."""
