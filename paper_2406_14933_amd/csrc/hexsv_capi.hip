@@ -229,6 +229,9 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
         return fail(HEXSV_EINVAL, "sim_create: precision %d unknown", p.precision);
     if (p.tile >= NUM_TILES) return fail(HEXSV_EINVAL, "sim_create: tile %d not built", p.tile);
     if (p.wg_per_cu != 0) return fail(HEXSV_EUNSUPPORTED, "sim_create: wg_per_cu must be 0");
+    if ((uint64_t)grid->n * (p.precision == HEXSV_FP64 ? 8u : 4u) >= (1ull << 32))
+        return fail(HEXSV_EUNSUPPORTED, "sim_create: %lld cells exceed 4 GiB per field",
+                    (long long)grid->n);
     hexsv_sim *s = new (std::nothrow) hexsv_sim();
     if (!s) return fail(HEXSV_ENOMEM, "sim_create: out of host memory");
     s->grid = grid;

@@ -73,6 +73,19 @@ struct KDom {
 
 // ------------------------------------------------------------- helpers
 
+// Element i of a field through a 32-bit byte offset from the field's base
+// (a uniform register pair), so each access needs no 64-bit address
+// arithmetic.  Valid while a field holds less than 4 GiB, which sim and
+// ensemble creation check.
+template <typename T>
+__device__ inline T ld(const T *p, uint32_t i) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ inline T *at(T *p, uint32_t i) {
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(p) + i * (uint32_t)sizeof(T));
+}
+
 __device__ __host__ inline int dq_of(int k) {
     return k == 0 ? 1 : (k == 1 ? 0 : (k == 2 ? -1 : (k == 3 ? -1 : (k == 4 ? 0 : 1))));
 }

@@ -143,8 +143,11 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         return fail(HEXSV_EINVAL, "ensemble_create: precision %d unknown", p.precision);
     if (p.ensemble_mode < HEXSV_ENS_AUTO || p.ensemble_mode > HEXSV_ENS_BATCHED)
         return fail(HEXSV_EINVAL, "ensemble_create: mode %d unknown", p.ensemble_mode);
-    for (int s = 0; s < n; ++s)
+    for (int s = 0; s < n; ++s) {
         if (!grids[s]) return fail(HEXSV_EINVAL, "ensemble_create: grid %d is null", s);
+        if ((uint64_t)grids[s]->n * (p.precision == HEXSV_FP64 ? 8u : 4u) >= (1ull << 32))
+            return fail(HEXSV_EUNSUPPORTED, "ensemble_create: scenario %d exceeds 4 GiB per field", s);
+    }
     hexsv_ensemble *e = new (std::nothrow) hexsv_ensemble();
     if (!e) return fail(HEXSV_ENOMEM, "ensemble_create: out of host memory");
     e->n = n;

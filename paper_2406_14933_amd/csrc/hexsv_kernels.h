@@ -41,7 +41,7 @@ static hipError_t launch_step_v(const KDom<T> &d, const KGrid &g, const KConst &
                        part, ntq, ntiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !finalize) return e;
-    return launch_finalize(ctl, part, nwg, kc, rn, stream);
+    return launch_finalize(ctl, part, ntiles, kc, rn, stream);
 }
 
 template <typename T>

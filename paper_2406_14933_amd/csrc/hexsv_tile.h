@@ -120,13 +120,13 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
             pos = wrap_pos(g, q, r) ? POS_NEIGHBOUR : POS_OUTSIDE;
         R.pos[k] = pos;
         if (pos != POS_OUTSIDE) {
-            const int64_t i = (int64_t)r * g.nq + q;
-            R.h[k] = hin[i];
-            R.th[k] = d.th[i];
-            R.ap[k] = d.ap[i];
-            R.z[k] = d.z[i];
-            R.v1[k] = v1in[i];
-            R.v2[k] = v2in[i];
+            const uint32_t i = (uint32_t)(r * g.nq + q);
+            R.h[k] = ld(hin, i);
+            R.th[k] = ld(d.th, i);
+            R.ap[k] = ld(d.ap, i);
+            R.z[k] = ld(d.z, i);
+            R.v1[k] = ld(v1in, i);
+            R.v2[k] = ld(v2in, i);
         }
     }
 #pragma unroll
@@ -139,12 +139,12 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
             int q = q0 + lq - 1, r = r0 + lr - 1;
             if (inner || wrap_pos(g, q, r)) {
                 R.rpos[k] = POS_NEIGHBOUR;
-                const int64_t i = (int64_t)r * g.nq + q;
-                R.rh[k] = hin[i];
-                R.rth[k] = d.th[i];
-                R.rz[k] = d.z[i];
-                R.rv1[k] = v1in[i];
-                R.rv2[k] = v2in[i];
+                const uint32_t i = (uint32_t)(r * g.nq + q);
+                R.rh[k] = ld(hin, i);
+                R.rth[k] = ld(d.th, i);
+                R.rz[k] = ld(d.z, i);
+                R.rv1[k] = ld(v1in, i);
+                R.rv2[k] = ld(v2in, i);
             }
         }
     }
@@ -239,6 +239,8 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
     const T NYh[6] = {T(0), T(0.5) * S3H, T(0.5) * S3H, T(0), -T(0.5) * S3H, -T(0.5) * S3H};
     constexpr int OFF[6] = {1, W, W - 1, -1, -W, -W + 1};
 
+    float cmax32 = 0.f, m32 = 0.f;  // FP32 path: c_max and sum theta h of this thread's cells
+    float wsum = 0.f;
     auto cell = [&](int k, auto gen_tag) {
         constexpr bool GEN = decltype(gen_tag)::value;
         const int cc = threadIdx.x + k * NT;
@@ -285,14 +287,17 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
             if constexpr (F32) {
                 // mj holds l*theta_j*h_j
                 const T vn = (e == 0) ? vb1 : ((e == 3) ? -vb1 : vb1 * NX[e] + vb2 * NY[e]);
-                const bool up = vn > T(0);
-                const T F = (up ? Mi : mj) * vn;
+                const T dw = wj - wi;
+                // one selected mass serves both terms: the upwind mass of the flux
+                // (at vn = 0 the flux vanishes whatever it is) and the pressure mass,
+                // which at vn = 0 follows the free-surface tie rule
+                const T key = (vn != T(0)) ? vn : -dw;  // w_i > w_j decides at vn = 0
+                const T msel = key > T(0) ? Mi : mj;
+                const T F = msel * vn;
                 Ls -= F;
                 A1 -= F * vb1;
                 A2 -= F * vb2;
-                const T dw = wj - wi;
-                const bool take_i = up || (vn == T(0) && dw < T(0));
-                const T Q = dw * (take_i ? Mi : mj);
+                const T Q = dw * msel;
                 A1 -= Q * NXh[e];
                 if (e != 0 && e != 3) A2 -= Q * NYh[e];
                 if (GEN && cd == CODE_OUTFLOW) Fout += F;
@@ -343,17 +348,25 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
         T mu = (D == T(0)) ? T(0) : p_div(T(2), D);
         if (h_dry > T(0) && h1 < h_dry) mu = T(0);
         const T v1n = mu * g1, v2n = mu * g2;
-        const int64_t i = (int64_t)r * g.nq + q;
-        put<T, NT_STORE>(hout + i, h1);
-        put<T, NT_STORE>(v1out + i, v1n);
-        put<T, NT_STORE>(v2out + i, v2n);
+        const uint32_t i = (uint32_t)(r * g.nq + q);
+        put<T, NT_STORE>(at(hout, i), h1);
+        put<T, NT_STORE>(at(v1out, i), v1n);
+        put<T, NT_STORE>(at(v2out, i), v2n);
         const T cc2 = p_sqrt(v1n * v1n + v2n * v2n) + p_sqrt(G * h1);
-        acc.c = (double)cc2 > acc.c ? (double)cc2 : acc.c;
-        acc.s += kc.sigma * ((double)thi * (double)h1);
-        if (GEN) acc.o += dt * (double)Fout;
-        if (!__builtin_isfinite(h1) || !__builtin_isfinite(v1n) || !__builtin_isfinite(v2n)) {
-            if (atomicOr(err_flag, 1) == 0) *err_cell = (int32_t)i;
+        if constexpr (F32) {
+            // FP32 partials over this thread's cells, folded into the FP64 books below;
+            // wsum carries any non-finite h or v of the thread's cells to one check
+            cmax32 = cc2 > cmax32 ? cc2 : cmax32;
+            m32 += thi * h1;
+            wsum += cc2;
+        } else {
+            acc.c = (double)cc2 > acc.c ? (double)cc2 : acc.c;
+            acc.s += kc.sigma * ((double)thi * (double)h1);
+            if (!__builtin_isfinite(h1) || !__builtin_isfinite(v1n) || !__builtin_isfinite(v2n)) {
+                if (atomicOr(err_flag, 1) == 0) *err_cell = (int32_t)i;
+            }
         }
+        if (GEN) acc.o += dt * (double)Fout;
     };
 
     if (general) {
@@ -363,6 +376,24 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
     } else {
 #pragma unroll
         for (int k = 0; k < Regs::CPT; ++k) cell(k, std::false_type{});
+    }
+    if constexpr (F32) {
+        acc.c = (double)cmax32 > acc.c ? (double)cmax32 : acc.c;
+        acc.s += kc.sigma * (double)m32;
+        if (!__builtin_isfinite(m32 + wsum)) {
+            // rare: find the offending cell among the values this thread just stored
+#pragma unroll
+            for (int k = 0; k < Regs::CPT; ++k) {
+                if (R.pos[k] != POS_OWN) continue;
+                const int cc = threadIdx.x + k * NT;
+                const int lr = cc / TQ, lq = cc - lr * TQ;
+                const uint32_t i = (uint32_t)((r0 + lr) * g.nq + q0 + lq);
+                if (!__builtin_isfinite(ld(hout, i)) || !__builtin_isfinite(ld(v1out, i)) ||
+                    !__builtin_isfinite(ld(v2out, i))) {
+                    if (atomicOr(err_flag, 1) == 0) *err_cell = (int32_t)i;
+                }
+            }
+        }
     }
 }
 
