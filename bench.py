@@ -35,7 +35,7 @@ BYTES_PER_CELL = {"fp32": 9 * 4, "fp64": 9 * 8}
 # was taken on (digest below); otherwise the line reports null.
 TRAFFIC = {
     ("catchment-4096x4096-edge2m-storm150mmh", "fp32", 2): {
-        "bytes": 606614109, "digest": "21c9adbd738eeb33"},
+        "bytes": 606359372, "digest": "7476a07c73281bd9"},
 }
 
 
@@ -183,6 +183,40 @@ def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=1e-5, seed=1):
             "k": k, "train_pairs": data.pairs, "train_scenarios": n_train, "train_s": train_s}
 
 
+def window_cost(size=512, nwin=256, window=0.69, k=16):
+    """Device cost of one surrogate window against the plain steps it replaces, on still
+    water (every window is kept, so chains run unbroken): 512 x 512 dyadic lake at rest."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2406_14933_amd import hexsv
+    sc = synth.lake_at_rest(nq=size, nr=size)
+    sur = hexsv.Surrogate(4, 32)
+    sur.set_params(np.zeros(sur.num_params, np.float32))
+    sur.set_scales([0.03, 0.015, 100.0, 2e-5, 1.5e-5, 0.2])
+    t0 = 8 * window
+    s = hexsv.Sim.from_scenario(sc, "fp32")
+    s.run_surrogate(sur, t0, window, k, math.inf)  # captures the window graph
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    acc, _ = s.run_surrogate(sur, t0 + nwin * window, window, k, math.inf)
+    torch.cuda.synchronize()
+    tw = time.perf_counter() - w0
+    p = hexsv.Sim.from_scenario(sc, "fp32")
+    p.run(t0)
+    b0 = p.books()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    p.run(t0 + nwin * window)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - w0
+    steps = p.books()["steps"] - b0["steps"]
+    return {"workload": f"still-water-{size}x{size}", "windows": acc,
+            "window_us": 1e6 * tw / nwin, "plain_step_us": 1e6 * tp / steps,
+            "plain_steps_per_window": steps / nwin}
+
+
 def cpu_baseline(sc, budget_s=12.0):
     """The FP64 oracle as it stands, on the host cores, over a bounded number of steps."""
     import numpy as np
@@ -227,6 +261,8 @@ def main():
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="skip training and timing the window surrogate")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--window-cost", action="store_true",
+                    help="only time surrogate windows against plain steps on still water")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -238,6 +274,9 @@ def main():
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.window_cost:
+        print(json.dumps(window_cost()))
+        return
     if args.copy_calibration:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -301,6 +340,7 @@ def main():
     if args.surrogate:
         print("[bench] surrogate: training on solver trajectories", file=sys.stderr, flush=True)
         sr = surrogate_block()
+        sr["window_cost"] = window_cost()
         print(f"[bench] surrogate: speed-up {sr['speedup']:.2f}x at rel L1 error "
               f"{sr['err_h_max']:.2e} (max over held-out)", file=sys.stderr, flush=True)
         line["surrogate"] = sr

@@ -119,7 +119,7 @@ struct alignas(64) SurWin {
 };
 
 constexpr int FEATURES = nn::FEATURES;
-constexpr int WIN_PARTS = 256;  // partial records of the window reductions
+constexpr int WIN_PARTS = 1024;  // partial records of the window reductions
 
 // Feature scales: H (depth), Q (discharge), Z (elevation), S (slope), and the
 // window changes of depth and discharge dH, dQ.
