@@ -167,10 +167,11 @@ def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=1e-5, seed=1):
     times = list(np.linspace(window, t_end - 2 * window, 32))
     data, scales = S.collect(train_sc, times, window, k, sur)
     S.train(sur, data, 3000, batch=4, lr=1e-3, lr_end=5e-5, seed=seed)
-    ro = S.rollout_pairs(sur, train_sc, list(np.linspace(2 * window, t_end - 2 * window, 16)),
-                         window, k, scales, tol=tol)
-    data = S.merge(data, ro)
-    S.train(sur, data, 3000, batch=4, lr=5e-4, lr_end=2e-5, seed=seed + 1)
+    for rnd in range(2):  # pairs from the network's own runs, then more training
+        ro = S.rollout_pairs(sur, train_sc, list(np.linspace(2 * window, t_end - 2 * window, 16)),
+                             window, k, scales, tol=tol)
+        data = S.merge(data, ro)
+        S.train(sur, data, 3000, batch=4, lr=5e-4, lr_end=2e-5, seed=seed + 1 + rnd)
     train_s = time.perf_counter() - t0
     ev = S.evaluate(sur, test_sc, window, k, tol, project=True)
     plain_steps = sum(r["plain_steps"] for r in ev["rows"])

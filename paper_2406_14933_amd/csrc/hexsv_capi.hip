@@ -162,8 +162,8 @@ struct hexsv_sim {
     void *d_scr;  // probe state: 3 x cells of the state's precision
     float2 *d_slope;  // terrain slope per cell (static; rebuilt after set_fields)
     bool slope_ok;
-    hipGraph_t wgraph;
-    hipGraphExec_t wexec;
+    hipGraph_t wgraph[4];     // chains of WIN_CHAINS[j] windows
+    hipGraphExec_t wexec[4];
     const hexsv_surrogate *w_sur;
     uint64_t w_gen;
     float w_scales[8];
@@ -200,10 +200,12 @@ static void drop_graph(hexsv_sim *s) {
 }
 
 static void drop_win_graph(hexsv_sim *s) {
-    if (s->wexec) (void)hipGraphExecDestroy(s->wexec);
-    if (s->wgraph) (void)hipGraphDestroy(s->wgraph);
-    s->wexec = nullptr;
-    s->wgraph = nullptr;
+    for (int j = 0; j < 4; ++j) {
+        if (s->wexec[j]) (void)hipGraphExecDestroy(s->wexec[j]);
+        if (s->wgraph[j]) (void)hipGraphDestroy(s->wgraph[j]);
+        s->wexec[j] = nullptr;
+        s->wgraph[j] = nullptr;
+    }
     s->w_sur = nullptr;
 }
 
@@ -456,17 +458,23 @@ static int capture(hexsv_sim *s) {
     return HEXSV_OK;
 }
 
-static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, hipStream_t stream);
+static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, bool ctl_fresh,
+                   hipStream_t stream);
 
 extern "C" int hexsv_sim_run(hexsv_sim *s, double t_end, int64_t max_steps, hipStream_t stream) {
-    return sim_run(s, t_end, max_steps, false, stream);
+    return sim_run(s, t_end, max_steps, false, false, stream);
 }
 
-static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, hipStream_t stream) {
+// ctl_fresh: the pinned host copy of the control block is already current
+// (the caller has just read it), which saves a round trip.
+static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, bool ctl_fresh,
+                   hipStream_t stream) {
     if (!s) return fail(HEXSV_EINVAL, "run: null sim");
     if (!s->state_set) return fail(HEXSV_ESTATE, "run: call set_state first");
-    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
+    if (!ctl_fresh) {
+        HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+    }
     Ctl &c = *s->h_ctl;
     if (!(t_end >= c.t)) return fail(HEXSV_EDOMAIN, "run: t_end=%g before t=%g", t_end, c.t);
     c.t_end = t_end;
@@ -481,8 +489,16 @@ static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, h
     int64_t last_steps = -1;
     for (;;) {
         const int64_t before = c.steps;
+        // the short graph is replayed as often as the span should need (steps past
+        // its end are no-ops), so a span of a few steps costs one host round trip
+        int reps = 1;
+        if (shortg) {
+            const double dt = c.tau < s->p.dt_max ? c.tau : s->p.dt_max;
+            const double need = dt > 0.0 ? (t_end - c.t) / dt + 1.0 : 1.0;
+            reps = need < SHORT_STEPS ? 1 : (int)fmin(64.0, ceil(need / SHORT_STEPS));
+        }
         if (s->timing) HIP_TRY(hipEventRecord(s->ev0, stream));
-        HIP_TRY(hipGraphLaunch(shortg ? s->sexec : s->gexec, stream));
+        for (int k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(shortg ? s->sexec : s->gexec, stream));
         if (s->timing) HIP_TRY(hipEventRecord(s->ev1, stream));
         HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -731,8 +747,10 @@ extern "C" int hexsv_sim_surrogate_features(hexsv_sim *s, hexsv_surrogate *sur, 
 }
 
 // Windows chained in one graph launch (a refused window stops the rest of
-// its chain, whose kernels then return at once).
-static const int WIN_CHAIN = 16;
+// its chain, whose kernels then return at once).  The chain length adapts: it
+// shrinks after a chain with a refusal (fewer dead windows launched) and grows
+// after a chain without one (fewer host round trips).
+static const int WIN_CHAINS[4] = {2, 4, 8, 16};
 // Most plain steps one refused window may take before the run reports a stall.
 static const int64_t FALLBACK_STEP_LIMIT = 1 << 20;
 
@@ -776,16 +794,19 @@ template <typename T>
 static int capture_windows(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float *out,
                            const float *sc, uint64_t gen) {
     drop_win_graph(s);
-    HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
-    int rc = window_chain<T>(s, sur, WIN_CHAIN, x0, out, sc, s->cap);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(s->cap, &g);
-    if (rc || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return rc ? rc : fail(HEXSV_EHIP, "window graph capture failed: %s", hipGetErrorString(e2));
+    for (int j = 0; j < 4; ++j) {
+        HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+        int rc = window_chain<T>(s, sur, WIN_CHAINS[j], x0, out, sc, s->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s->cap, &g);
+        if (rc || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc
+                      : fail(HEXSV_EHIP, "window graph capture failed: %s", hipGetErrorString(e2));
+        }
+        s->wgraph[j] = g;
+        HIP_TRY(hipGraphInstantiate(&s->wexec[j], g, nullptr, nullptr, 0));
     }
-    s->wgraph = g;
-    HIP_TRY(hipGraphInstantiate(&s->wexec, s->wgraph, nullptr, nullptr, 0));
     s->w_sur = sur;
     s->w_gen = gen;
     return HEXSV_OK;
@@ -809,7 +830,7 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
     if (rc) return rc;
     // the scales are kernel arguments of the graph: rebuild when they change
     static_assert(sizeof(sc) == 8 * sizeof(float), "scales");
-    bool same = s->wexec && s->w_sur == sur && s->w_gen == gen;
+    bool same = s->wexec[3] && s->w_sur == sur && s->w_gen == gen;
     for (int j = 0; j < 8 && same; ++j) same = s->w_scales[j] == sc[j];
     if (!same) {
         rc = capture_windows<T>(s, sur, x0, out, sc, gen);
@@ -820,23 +841,25 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
     const SurWin &w = *s->h_sw;
     HIP_TRY(hipMemcpyAsync(s->d_sw, s->h_sw, sizeof(SurWin), hipMemcpyHostToDevice, st));
     Ctl &c = *s->h_ctl;
-    for (;;) {
-        HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int level = 3;  // index into WIN_CHAINS
+    for (;;) {  // c is current here
         if (c.err) return fail(HEXSV_ENUMERIC, "run_surrogate: non-finite value at cell %d", c.err_cell);
         const double t0 = c.t;
         if (t0 >= t_end) break;
         // whole windows left, formed exactly as the device forms them
+        const int want = WIN_CHAINS[level];
         int left = 0;
-        for (double t = t0; left < WIN_CHAIN && t + window <= t_end; t += window) ++left;
+        for (double t = t0; left < want && t + window <= t_end; t += window) ++left;
         if (left == 0) {  // last partial span: the plain solver
-            rc = sim_run(s, t_end, 0, true, st);
+            rc = sim_run(s, t_end, 0, true, true, st);
             if (rc) return rc;
             *n_fb += 1;
             break;
         }
-        if (left == WIN_CHAIN) {
-            HIP_TRY(hipGraphLaunch(s->wexec, st));
+        if (left == want) {
+            HIP_TRY(hipGraphLaunch(s->wexec[level], st));
         } else {
             rc = window_chain<T>(s, sur, left, x0, out, sc, st);
             if (rc) return rc;
@@ -846,13 +869,17 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
         HIP_TRY(hipStreamSynchronize(st));
         *n_acc += w.accepted;
         if (w.rejected) {  // the refused window's span, by the plain solver from its start
+            if (level > 0) --level;
+            if (c.err) continue;
             const double target = c.t + window;
-            rc = sim_run(s, target, FALLBACK_STEP_LIMIT, true, st);
+            rc = sim_run(s, target, FALLBACK_STEP_LIMIT, true, true, st);
             if (rc) return rc;
             if (!(c.t >= target))
                 return fail(HEXSV_ENUMERIC, "run_surrogate: the solver stalled at t=%g before %g",
                             c.t, target);
             *n_fb += 1;
+        } else if (level < 3) {
+            ++level;
         }
     }
     return HEXSV_OK;

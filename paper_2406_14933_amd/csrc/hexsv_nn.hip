@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hexsv_device.h"
 #include "hexsv_nn.h"
 
 namespace hexsv {
@@ -41,20 +42,30 @@ __device__ inline int tile_of(int tile, int ntq, int ntr, int &b, int &q0, int &
 
 // Stage the (TQ+2) x (TR+2) halo of channels-last bf16 activations of one
 // sample into LDS as 16-byte chunks; positions outside the raster are zero.
+// All of a thread's loads are issued before any LDS store, so the staging
+// costs one memory latency rather than one per chunk.
 template <int C>
 __device__ inline void stage_act(uint4 *lds, const __bf16 *__restrict__ x, int nq, int nr,
                                  int64_t sample_off, int q0, int r0) {
     constexpr int CH = C / 8;  // 16-byte chunks per cell
-    for (int e = threadIdx.x; e < NSLOT * CH; e += NT) {
+    constexpr int ITERS = (NSLOT * CH + NT - 1) / NT;
+    uint4 v[ITERS];
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const int e = threadIdx.x + it * NT;
         const int s = e / CH, ch = e - s * CH;
         const int lr = s / SW, lq = s - lr * SW;
         const int q = q0 + lq - 1, r = r0 + lr - 1;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (q >= 0 && q < nq && r >= 0 && r < nr) {
+        v[it] = make_uint4(0u, 0u, 0u, 0u);
+        if (e < NSLOT * CH && q >= 0 && q < nq && r >= 0 && r < nr) {
             const int64_t i = sample_off + (int64_t)r * nq + q;
-            v = reinterpret_cast<const uint4 *>(x + i * C)[ch];
+            v[it] = reinterpret_cast<const uint4 *>(x + i * C)[ch];
         }
-        lds[e] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const int e = threadIdx.x + it * NT;
+        if (e < NSLOT * CH) lds[e] = v[it];
     }
 }
 
@@ -77,8 +88,10 @@ __global__ __launch_bounds__(NT) void k_hexconv(const __bf16 *__restrict__ x,
     constexpr int KSTEPS = (7 + TPK - 1) / TPK;
     __shared__ uint4 lds[NSLOT * CH];
     const int ntq = (nq + TQ - 1) / TQ, ntr = (nr + TR - 1) / TR;
-    const int tile = blockIdx.x;
-    if (tile >= ntiles_total) return;
+    // XCD-banded tile order: every layer gives a tile to the same XCD, so the
+    // activations a layer writes are mostly read back from that XCD's L2
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles_total, 0);
+    if (tile < 0) return;
     if (live && !*live) return;  // a surrogate window that does not run
     int b, q0, r0;
     tile_of(tile, ntq, ntr, b, q0, r0);
@@ -182,20 +195,30 @@ __global__ __launch_bounds__(NT) void k_hexconv_wgrad(const __bf16 *__restrict__
     __shared__ uint4 lds[NSLOT * CH];
     __shared__ __bf16 sdy[TQ * TR * COUT];
     const int ntq = (nq + TQ - 1) / TQ, ntr = (nr + TR - 1) / TR;
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles_total, 0);
+    if (tile < 0) return;
     float *P = part + (int64_t)tile * PSZ;
     int b, q0, r0;
     tile_of(tile, ntq, ntr, b, q0, r0);
     const int64_t soff = (int64_t)b * nq * nr;
     stage_act<CIN>(lds, x, nq, nr, soff, q0, r0);
-    // dy of the tile's cells (zero outside the raster), channels-last
-    for (int e = threadIdx.x; e < TQ * TR * COUT / 8; e += NT) {
+    // dy of the tile's cells (zero outside the raster), channels-last; loads first
+    constexpr int DITERS = (TQ * TR * COUT / 8 + NT - 1) / NT;
+    uint4 dv[DITERS];
+#pragma unroll
+    for (int it = 0; it < DITERS; ++it) {
+        const int e = threadIdx.x + it * NT;
         const int c = e / (COUT / 8), ch = e - c * (COUT / 8);
         const int lr = c / TQ, lq = c - lr * TQ;
         const int q = q0 + lq, r = r0 + lr;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (q < nq && r < nr) v = reinterpret_cast<const uint4 *>(dy + (soff + (int64_t)r * nq + q) * COUT)[ch];
-        reinterpret_cast<uint4 *>(sdy)[e] = v;
+        dv[it] = make_uint4(0u, 0u, 0u, 0u);
+        if (e < TQ * TR * COUT / 8 && q < nq && r < nr)
+            dv[it] = reinterpret_cast<const uint4 *>(dy + (soff + (int64_t)r * nq + q) * COUT)[ch];
+    }
+#pragma unroll
+    for (int it = 0; it < DITERS; ++it) {
+        const int e = threadIdx.x + it * NT;
+        if (e < TQ * TR * COUT / 8) reinterpret_cast<uint4 *>(sdy)[e] = dv[it];
     }
     __syncthreads();
     const uint16_t *sx16 = reinterpret_cast<const uint16_t *>(lds);
