@@ -180,6 +180,8 @@ def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=1e-5, seed=1):
             "speedup": ev["speedup"], "err_h_max": ev["err_h_max"],
             "err_h_mean": ev["err_h_mean"], "tol": tol, "accept_frac": ev["accept_frac"],
             "solver_steps_avoided": 1.0 - sur_steps / max(plain_steps, 1),
+            "refused": {k: ev[k] for k in ("refused_residual", "refused_wave_speed",
+                                           "refused_nonfinite")},
             "plain_s": ev["plain_s"], "surrogate_s": ev["surrogate_s"], "window_s": window,
             "k": k, "train_pairs": data.pairs, "train_scenarios": n_train, "train_s": train_s}
 

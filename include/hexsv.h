@@ -355,6 +355,11 @@ int hexsv_sim_run_surrogate(hexsv_sim *sim, hexsv_surrogate *sur, double t_end, 
                             int32_t k, double residual_tol, int32_t project, int64_t *n_accepted,
                             int64_t *n_fallback, hipStream_t stream);
 
+/* Window counts of every run_surrogate call on this simulation so far:
+ * counts[0] kept, counts[1] refused for the water-balance residual, counts[2]
+ * refused for the wave-speed growth, counts[3] refused as non-finite. */
+int hexsv_sim_surrogate_stats(const hexsv_sim *sim, int64_t *counts);
+
 /* Number of tile variants built, and the shape of variant v. */
 int hexsv_tile_count(void);
 int hexsv_tile_shape(int32_t v, int32_t *tq, int32_t *tr, int32_t *threads);

@@ -167,6 +167,7 @@ struct hexsv_sim {
     const hexsv_surrogate *w_sur;
     uint64_t w_gen;
     float w_scales[8];
+    int64_t w_stats[4];  // windows kept; refused for the residual, the wave speed, non-finite
     // optional device timing of graph replays (hipEvents on the run stream)
     bool timing;
     hipEvent_t ev0, ev1;
@@ -868,6 +869,8 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
         HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         *n_acc += w.accepted;
+        s->w_stats[0] += w.accepted;
+        if (w.rejected) s->w_stats[w.why == 1 ? 1 : (w.why == 2 ? 2 : 3)] += 1;
         if (w.rejected) {  // the refused window's span, by the plain solver from its start
             if (level > 0) --level;
             if (c.err) continue;
@@ -882,6 +885,12 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
             ++level;
         }
     }
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_surrogate_stats(const hexsv_sim *s, int64_t *counts) {
+    if (!s || !counts) return fail(HEXSV_EINVAL, "surrogate_stats: null argument");
+    for (int j = 0; j < 4; ++j) counts[j] = s->w_stats[j];
     return HEXSV_OK;
 }
 

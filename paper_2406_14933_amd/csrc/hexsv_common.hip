@@ -240,6 +240,8 @@ __global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const P
     } else {
         sw->alive = 0;
         sw->rejected = 1;
+        const bool finite = p.clamp == 0.0 && isfinite(p.stored) && isfinite(Ow);
+        sw->why = !finite ? 4 : (rho > sw->tol ? 1 : 2);
     }
     sw->live = 0;
 }

@@ -116,6 +116,8 @@ struct alignas(64) SurWin {
     int32_t perr, perr_cell;        // non-finite value met by a probe step
     double scale;                   // factor of that rescaling
     double c0;                      // c_max of the window's start state
+    int32_t why;                    // reason of the last refusal: 1 residual, 2 wave speed, 4 non-finite
+    int32_t pad2;
 };
 
 constexpr int FEATURES = nn::FEATURES;

@@ -116,6 +116,7 @@ _SIGS = [
     ("hexsv_sim_run_surrogate", C.c_int, [_VP, _VP, C.c_double, C.c_double, C.c_int32,
                                           C.c_double, C.c_int32, C.POINTER(C.c_int64),
                                           C.POINTER(C.c_int64), _VP]),
+    ("hexsv_sim_surrogate_stats", C.c_int, [_VP, C.POINTER(C.c_int64)]),
     ("hexsv_tile_count", C.c_int, []),
     ("hexsv_tile_shape", C.c_int, [C.c_int32] + [C.POINTER(C.c_int32)] * 3),
 ]
@@ -314,6 +315,13 @@ class Sim:
                                              float(residual_tol), int(bool(project)), C.byref(a),
                                              C.byref(f), _stream()))
         return a.value, f.value
+
+    def surrogate_stats(self):
+        """Windows of all run_surrogate calls: kept and refused (by reason)."""
+        a = (C.c_int64 * 4)()
+        _check(lib().hexsv_sim_surrogate_stats(self._h, a))
+        return dict(zip(("kept", "refused_residual", "refused_wave_speed", "refused_nonfinite"),
+                        list(a)))
 
     def surrogate_features(self, sur, window, k):
         """(cells, 11) FP32 network inputs of a window starting at the current state."""

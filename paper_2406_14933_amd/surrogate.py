@@ -242,14 +242,20 @@ def evaluate(sur, scenarios, window, k, tol=1e-3, t_end=None, project=True):
         hp = plain.state()["h"]
         hs = surr.state()["h"]
         err = float((hs - hp).abs().sum() / hp.abs().sum().clamp_min(1e-300))
+        st = surr.surrogate_stats()
         rows.append({"scenario": sc.name, "err_h": err, "accepted": acc, "fallback": fb,
+                     "refused_residual": st["refused_residual"],
+                     "refused_wave_speed": st["refused_wave_speed"],
+                     "refused_nonfinite": st["refused_nonfinite"],
                      "plain_s": tp, "surrogate_s": ts, "plain_steps": plain.books()["steps"],
                      "surrogate_steps": surr.books()["steps"]})
     tp = sum(r["plain_s"] for r in rows)
     ts = sum(r["surrogate_s"] for r in rows)
     acc = sum(r["accepted"] for r in rows)
     fb = sum(r["fallback"] for r in rows)
-    return {"rows": rows, "speedup": tp / ts, "plain_s": tp, "surrogate_s": ts,
+    refused = {k: sum(r[k] for r in rows)
+               for k in ("refused_residual", "refused_wave_speed", "refused_nonfinite")}
+    return {"rows": rows, "speedup": tp / ts, "plain_s": tp, "surrogate_s": ts, **refused,
             "err_h_max": max(r["err_h"] for r in rows),
             "err_h_mean": sum(r["err_h"] for r in rows) / len(rows),
             "accepted": acc, "fallback": fb, "accept_frac": acc / max(acc + fb, 1)}

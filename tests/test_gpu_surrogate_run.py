@@ -83,6 +83,7 @@ def test_accepted_window_matches_oracle_chain(hx, prec):
     print(f"[surrogate window {prec} {sc.nq}x{sc.nr}]", flush=True)
     acc, fb = sim.run_surrogate(sur, WINDOW, WINDOW, K, residual_tol=math.inf, project=False)
     assert (acc, fb) == (1, 0)
+    assert sim.surrogate_stats()["kept"] == 1
     st = sim.state_numpy()
     b = sim.books()
 
@@ -142,6 +143,9 @@ def test_zero_tolerance_falls_back_to_the_solver(hx, prec):
     print(f"[surrogate fallback {prec}]", flush=True)
     acc, fb = sim.run_surrogate(sur, t_end, WINDOW, K, residual_tol=0.0)
     assert (acc, fb) == (0, 6)
+    st = sim.surrogate_stats()  # 5 whole windows refused on their residual, then a short span
+    assert st == {"kept": 0, "refused_residual": 5, "refused_wave_speed": 0,
+                  "refused_nonfinite": 0}, st
     ref = hx.Sim.from_scenario(sc, prec)
     t = 0.0
     for _ in range(5):  # the window ends as the surrogate loop forms them
