@@ -134,6 +134,14 @@ extern "C" int hexsv_grid_tables(const hexsv_grid *grid, int32_t *d_nbr, uint8_t
 
 // ------------------------------------------------------------- simulation
 
+// Steps per replay of the short graph used for spans of a few steps (the
+// fallback of a refused surrogate window): the long graph would replay its
+// whole length of no-op steps past the span's end.
+static const int SHORT_STEPS = 8;
+// Most closed steps whose books wait in the step ring before a fold.
+static const int RING_MAX = 128;
+static const size_t ACC_BYTES = sizeof(unsigned long long) * ACC_SLOTS * ACC_STRIDE;
+
 struct hexsv_sim {
     const hexsv_grid *grid;
     hexsv_params p;
@@ -144,16 +152,23 @@ struct hexsv_sim {
     KRain rn;
     Ctl *d_ctl;
     Ctl *h_ctl;  // pinned mirror
-    Part *d_part;
+    Part *d_part;  // partial records of the priming pass (PRIME_BLOCKS)
+    // step results (see KClose): ring of ring_len steps x ntiles tile records,
+    // per-slot totals and the wave-speed maximum; the ring is sized for the
+    // current tile variant when a graph is captured or a kernel timed
+    Part *d_ring, *d_slots;
+    unsigned long long *d_acc;
+    size_t ring_cap;  // tile records the ring holds
+    int ring_len;
     int32_t *d_chk;
     int32_t *h_chk;  // pinned
     int tile, ntq, ntiles, nwg;
     int gsteps;
     hipStream_t cap;
-    hipGraph_t graph;
-    hipGraphExec_t gexec;
-    hipGraph_t sgraph;      // short graph (SHORT_STEPS steps) for spans of a few steps
-    hipGraphExec_t sexec;
+    hipGraph_t graph[2];    // gsteps steps, starting from buffer parity 0 / 1
+    hipGraphExec_t gexec[2];
+    hipGraph_t sgraph[2];   // short graphs (SHORT_STEPS steps) for spans of a few steps
+    hipGraphExec_t sexec[2];
     bool graph_ok, fields_set, state_set;
     // surrogate windows: control record (device + pinned mirror), outflow
     // partials of both ends, and a graph of WIN_CHAIN chained windows
@@ -189,14 +204,16 @@ static KDom<T> dom_of(const hexsv_sim *s) {
 }
 
 static void drop_graph(hexsv_sim *s) {
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
-    if (s->sexec) (void)hipGraphExecDestroy(s->sexec);
-    if (s->sgraph) (void)hipGraphDestroy(s->sgraph);
-    s->gexec = nullptr;
-    s->graph = nullptr;
-    s->sexec = nullptr;
-    s->sgraph = nullptr;
+    for (int p = 0; p < 2; ++p) {
+        if (s->gexec[p]) (void)hipGraphExecDestroy(s->gexec[p]);
+        if (s->graph[p]) (void)hipGraphDestroy(s->graph[p]);
+        if (s->sexec[p]) (void)hipGraphExecDestroy(s->sexec[p]);
+        if (s->sgraph[p]) (void)hipGraphDestroy(s->sgraph[p]);
+        s->gexec[p] = nullptr;
+        s->graph[p] = nullptr;
+        s->sexec[p] = nullptr;
+        s->sgraph[p] = nullptr;
+    }
     s->graph_ok = false;
 }
 
@@ -244,6 +261,8 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->tile = p.tile >= 0 ? p.tile : tuned_tile("step", p.precision, grid->n, DEFAULT_TILE);
     tile_grid(s->tile, grid->kg.nq, grid->kg.nr, &s->ntq, &s->ntiles);
     s->gsteps = p.steps_per_graph > 0 ? p.steps_per_graph : 100;
+    s->ring_len = s->gsteps < RING_MAX ? s->gsteps : RING_MAX;
+    if (s->ring_len < SHORT_STEPS) s->ring_len = SHORT_STEPS;
     const double a = grid->edge;
     s->kc.g = p.g;
     s->kc.a = a;
@@ -256,17 +275,13 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->rn.t_a = 0.0;
     s->rn.T_d = INFINITY;
     s->nwg = s->ntiles;
-    // room for the partial records of every tile variant (the autotuner switches)
-    size_t nparts = PRIME_BLOCKS;
-    for (int v = 0; v < NUM_TILES; ++v) {
-        int nq_t, nt_t;
-        tile_grid(v, grid->kg.nq, grid->kg.nr, &nq_t, &nt_t);
-        if ((size_t)nt_t > nparts) nparts = (size_t)nt_t;
-    }
     hipError_t e = hipMalloc(&s->buf, s->esz * 9 * (size_t)grid->n);
     if (e == hipSuccess) e = hipMalloc(&s->d_ctl, sizeof(Ctl));
-    if (e == hipSuccess) e = hipMalloc(&s->d_part, sizeof(Part) * nparts);
+    if (e == hipSuccess) e = hipMalloc(&s->d_part, sizeof(Part) * PRIME_BLOCKS);
     if (e == hipSuccess) e = hipMalloc(&s->d_chk, 4 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&s->d_acc, ACC_BYTES);
+    if (e == hipSuccess) e = hipMalloc(&s->d_slots, sizeof(Part) * s->ring_len);
+    if (e == hipSuccess) e = hipMemset(s->d_acc, 0, ACC_BYTES);
     if (e == hipSuccess) e = hipHostMalloc(&s->h_ctl, sizeof(Ctl), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&s->h_chk, 4 * sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
@@ -288,6 +303,9 @@ extern "C" void hexsv_sim_destroy(hexsv_sim *s) {
     if (s->buf) (void)hipFree(s->buf);
     if (s->d_ctl) (void)hipFree(s->d_ctl);
     if (s->d_part) (void)hipFree(s->d_part);
+    if (s->d_ring) (void)hipFree(s->d_ring);
+    if (s->d_slots) (void)hipFree(s->d_slots);
+    if (s->d_acc) (void)hipFree(s->d_acc);
     if (s->d_chk) (void)hipFree(s->d_chk);
     if (s->h_ctl) (void)hipHostFree(s->h_ctl);
     if (s->h_chk) (void)hipHostFree(s->h_chk);
@@ -413,6 +431,7 @@ extern "C" int hexsv_sim_set_state(hexsv_sim *s, double t0, const double *d_h, c
     c.parity = 0;
     c.err_cell = -1;
     HIP_TRY(hipMemcpyAsync(s->d_ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemsetAsync(s->d_acc, 0, ACC_BYTES, stream));
     HIP_TRY(s->prec == HEXSV_FP64 ? prime<double>(s, 1, stream) : prime<float>(s, 1, stream));
     HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -420,17 +439,44 @@ extern "C" int hexsv_sim_set_state(hexsv_sim *s, double t0, const double *d_h, c
     return HEXSV_OK;
 }
 
-// Capture nsteps steps (tile kernel + finalize each) into one executable graph.
-static int capture_steps(hexsv_sim *s, int nsteps, hipGraph_t *graph, hipGraphExec_t *exec) {
+// The step ring sized for the current tile variant.
+static int ensure_ring(hexsv_sim *s) {
+    const size_t need = (size_t)s->ntiles * s->ring_len;
+    if (s->d_ring && s->ring_cap >= need) return HEXSV_OK;
+    if (s->d_ring) HIP_TRY(hipFree(s->d_ring));
+    s->d_ring = nullptr;
+    s->ring_cap = 0;
+    if (hipMalloc(&s->d_ring, sizeof(Part) * need) != hipSuccess) {
+        s->d_ring = nullptr;
+        return fail(HEXSV_ENOMEM, "step ring of %zu records: allocation failed", need);
+    }
+    s->ring_cap = need;
+    return HEXSV_OK;
+}
+
+static KClose close_of(const hexsv_sim *s) { return KClose{s->d_ring, s->d_slots, s->d_acc, s->ring_len}; }
+
+// Capture nsteps steps (tile kernel + finalize each, a fold of the books every
+// ring_len steps and at the end) into one executable graph.  Step k of the
+// graph reads buffer parity (par0 + k) % 2 (live steps are consecutive from
+// the start of a replay).
+static int capture_steps(hexsv_sim *s, int nsteps, int par0, hipGraph_t *graph,
+                         hipGraphExec_t *exec) {
+    int rc = ensure_ring(s);
+    if (rc) return rc;
+    const KClose cl = close_of(s);
     HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+        const int hint = (par0 + k) & 1;
         if (s->prec == HEXSV_FP64)
             e = launch_step<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
-                                    s->d_part, s->ntq, s->ntiles, s->nwg, s->cap);
+                                    cl, s->ntq, s->ntiles, s->nwg, hint, s->cap);
         else
             e = launch_step<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
-                                   s->d_part, s->ntq, s->ntiles, s->nwg, s->cap);
+                                   cl, s->ntq, s->ntiles, s->nwg, hint, s->cap);
+        if (e == hipSuccess && ((k + 1) % s->ring_len == 0 || k + 1 == nsteps))
+            e = launch_fold(s->d_ctl, cl, s->ntiles, s->cap);
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->cap, &g);
@@ -444,17 +490,14 @@ static int capture_steps(hexsv_sim *s, int nsteps, hipGraph_t *graph, hipGraphEx
     return HEXSV_OK;
 }
 
-// Steps per replay of the short graph used for spans of a few steps (the
-// fallback of a refused surrogate window): the long graph would replay its
-// whole length of no-op steps past the span's end.
-static const int SHORT_STEPS = 8;
-
 static int capture(hexsv_sim *s) {
     drop_graph(s);
-    int rc = capture_steps(s, s->gsteps, &s->graph, &s->gexec);
-    if (rc) return rc;
-    rc = capture_steps(s, SHORT_STEPS, &s->sgraph, &s->sexec);
-    if (rc) return rc;
+    for (int p = 0; p < 2; ++p) {
+        int rc = capture_steps(s, s->gsteps, p, &s->graph[p], &s->gexec[p]);
+        if (rc) return rc;
+        rc = capture_steps(s, SHORT_STEPS, p, &s->sgraph[p], &s->sexec[p]);
+        if (rc) return rc;
+    }
     s->graph_ok = true;
     return HEXSV_OK;
 }
@@ -499,7 +542,12 @@ static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, b
             reps = need < SHORT_STEPS ? 1 : (int)fmin(64.0, ceil(need / SHORT_STEPS));
         }
         if (s->timing) HIP_TRY(hipEventRecord(s->ev0, stream));
-        for (int k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(shortg ? s->sexec : s->gexec, stream));
+        // replays after the first start from a parity the host no longer knows: for
+        // a live step the graph's hint is still right whenever its step count is even
+        for (int k = 0; k < reps; ++k) {
+            const int p = (c.parity + k * (shortg ? SHORT_STEPS : s->gsteps)) & 1;
+            HIP_TRY(hipGraphLaunch(shortg ? s->sexec[p] : s->gexec[p], stream));
+        }
         if (s->timing) HIP_TRY(hipEventRecord(s->ev1, stream));
         HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -571,20 +619,26 @@ extern "C" int hexsv_sim_time_kernel(hexsv_sim *s, int32_t nlaunch, double *avg_
         HIP_TRY(hipEventCreate(&s->ev0));
         HIP_TRY(hipEventCreate(&s->ev1));
     }
+    int rc = ensure_ring(s);
+    if (rc) return rc;
+    const KClose cl = close_of(s);
     hipError_t e = hipSuccess;
     HIP_TRY(hipEventRecord(s->ev0, stream));
     for (int k = 0; k < nlaunch && e == hipSuccess; ++k) {
         if (s->prec == HEXSV_FP64)
             e = launch_step_only<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn,
-                                         s->d_ctl, s->d_part, s->ntq, s->ntiles, s->nwg,
+                                         s->d_ctl, cl, s->ntq, s->ntiles, s->nwg, c.parity,
                                          stream);
         else
             e = launch_step_only<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn,
-                                        s->d_ctl, s->d_part, s->ntq, s->ntiles, s->nwg,
+                                        s->d_ctl, cl, s->ntq, s->ntiles, s->nwg, c.parity,
                                         stream);
     }
     HIP_TRY(e);
     HIP_TRY(hipEventRecord(s->ev1, stream));
+    // the timed launches left their wave speeds in the accumulator and their
+    // records in the (empty) ring's first slot: clear the accumulator
+    HIP_TRY(hipMemsetAsync(s->d_acc, 0, ACC_BYTES, stream));
     HIP_TRY(hipEventSynchronize(s->ev1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));

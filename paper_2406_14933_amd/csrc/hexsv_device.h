@@ -42,13 +42,15 @@ struct KRain {
 };
 
 // Device-resident control block: time, CFL bound, step counters, the buffer
-// parity and the FP64 books.  Read by every step kernel, written only by the
-// single-workgroup kernel that closes each step.
+// parity and the FP64 books.  Read by every step kernel; written by the
+// kernels that close a step and fold the books (and by the ensemble's
+// per-scenario close).
 struct alignas(128) Ctl {
     double t, tau, t_end, dt_max;
     int64_t steps, step_limit;
     int32_t parity, err;
-    int32_t err_cell, pad0;
+    int32_t err_cell;
+    int32_t open;  // closed steps whose water books still wait in the step ring
     double initial, stored, rain, outflow, clamp, dt_min, dt_max_seen, last_cmax;
 };
 static_assert(sizeof(Ctl) == 128, "control block is 128 bytes");
@@ -56,6 +58,24 @@ static_assert(sizeof(Ctl) == 128, "control block is 128 bytes");
 // Per-tile partial results of one step.
 struct alignas(32) Part {
     double cmax, stored, outflow, clamp;
+};
+
+// Where the tile kernel of a single-domain step leaves its results: the
+// largest wave speed goes into one of ACC_SLOTS accumulators (an atomic
+// maximum over the bit patterns of non-negative doubles, which order like the
+// values; tile t uses slot t % ACC_SLOTS, ACC_STRIDE words apart, so that the
+// atomics of concurrent tiles do not queue on one address), the tile's water
+// books into slot ctl->open of the ring (ring[slot * ntiles + tile]).  The
+// finalize kernel closes the step from the accumulators alone; the fold
+// kernels add the ring's records to the books, step by step in order, every
+// ring_len steps at most.
+constexpr int ACC_SLOTS = 256;
+constexpr int ACC_STRIDE = 16;  // 128 bytes
+struct KClose {
+    Part *ring;
+    Part *slots;  // per-slot totals (fold scratch)
+    unsigned long long *acc;
+    int ring_len;
 };
 
 // Static geometry and parameters of one domain.
@@ -204,6 +224,21 @@ __device__ inline Part block_reduce(double c, double s, double o, double cl) {
 
 // Close one step on the device (Appendix A, eqs. .12-.13 for the next bound):
 // FP64 books, t^{n+1}, step count, buffer parity and tau = CFL*phi_min/c_max.
+// Time, step count and CFL bound of a closed step (its books are folded in
+// later from the step ring).
+__device__ inline void close_time(Ctl *ctl, double cmax, const StepTime &st, const KConst &kc,
+                                  double r_next) {
+    ctl->rain += kc.area_active * st.dt * r_next;
+    ctl->t = st.t_next;
+    ctl->steps += 1;
+    if (st.dt < ctl->dt_min) ctl->dt_min = st.dt;
+    if (st.dt > ctl->dt_max_seen) ctl->dt_max_seen = st.dt;
+    ctl->last_cmax = cmax;
+    ctl->tau = cmax > 0.0 ? kc.cfl_phi / cmax : __builtin_inf();
+    ctl->parity ^= 1;
+    ctl->open += 1;
+}
+
 __device__ inline void close_step(Ctl *ctl, const Part &p, const StepTime &st, const KConst &kc,
                                   double r_next) {
     ctl->stored = p.stored;

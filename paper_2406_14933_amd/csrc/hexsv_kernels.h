@@ -17,43 +17,64 @@ namespace hexsv {
 // XCD bands, see xcd_tile); every workgroup writes its tile's partial record
 // and the single-workgroup finalize kernel launched right after folds the
 // records into the control block, so the next step sees the new dt.
+//
+// par_hint is the buffer parity the launcher expects this step to read (a
+// graph of consecutive live steps alternates it).  The tile's loads are issued
+// from that buffer before the control block has arrived, so they do not wait
+// for it; a wrong hint (never for a live step of a graph replayed from the
+// parity it was captured for) only costs a reload.
 template <typename T, int TQ, int TR, int NT>
 __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRain rn, Ctl *ctl,
-                                             Part *part, int ntq, int ntiles) {
-    const StepTime st = step_time(ctl);
-    if (!st.live) return;
+                                             KClose cl, int ntq, int ntiles, int par_hint) {
     __shared__ TileLDS<T, TQ, TR> L;
-    const double r_next = rain_rate(rn, st.t_next);
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
     const int tr = tile / ntq, tq = tile - tr * ntq;
+    TileRegs<T, TQ, TR, NT> R;
+    tile_load<T, TQ, TR, NT>(R, d, g, par_hint, tq, tr);
+    const StepTime st = step_time(ctl);
+    if (!st.live) return;
+    const int par = ctl->parity;
+    const int slot = ctl->open;
+    if (par != par_hint) tile_load<T, TQ, TR, NT>(R, d, g, par, tq, tr);
+    const double r_next = rain_rate(rn, st.t_next);
+    const bool bad = tile_stage<T, TQ, TR, NT>(L, R, g, kc, tq, tr);
+    const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
+    const bool general = __syncthreads_or((!inner) || bad) != 0;
     Acc acc{0.0, 0.0, 0.0, 0.0};
-    tile_step<T, TQ, TR, NT, true>(L, d, g, kc, ctl->parity, tq, tr, st.dt, r_next, acc,
-                                   &ctl->err, &ctl->err_cell);
+    tile_compute<T, TQ, TR, NT, true>(L, R, general, d, g, kc, par, tq, tr, st.dt, r_next, acc,
+                                      &ctl->err, &ctl->err_cell);
     const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
-    if (threadIdx.x == 0) part[tile] = p;
+    if (threadIdx.x == 0) {
+        // the host folds the ring before it fills; the clamp only keeps a
+        // broken invariant from writing out of bounds
+        const int s = (unsigned)slot < (unsigned)cl.ring_len ? slot : cl.ring_len - 1;
+        cl.ring[(size_t)s * ntiles + tile] = p;
+        atomicMax(cl.acc + (tile % ACC_SLOTS) * ACC_STRIDE,
+                  (unsigned long long)__double_as_longlong(p.cmax));
+    }
 }
 
 template <typename T, int TQ, int TR, int NT>
 static hipError_t launch_step_v(const KDom<T> &d, const KGrid &g, const KConst &kc,
-                                const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles,
-                                int nwg, bool finalize, hipStream_t stream) {
+                                const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles,
+                                int nwg, int par_hint, bool finalize, hipStream_t stream) {
     hipLaunchKernelGGL((k_step<T, TQ, TR, NT>), dim3(nwg), dim3(NT), 0, stream, d, g, kc, rn, ctl,
-                       part, ntq, ntiles);
+                       cl, ntq, ntiles, par_hint);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !finalize) return e;
-    return launch_finalize(ctl, part, ntiles, kc, rn, stream);
+    return launch_finalize(ctl, cl.acc, kc, rn, stream);
 }
 
 template <typename T>
 static hipError_t launch_step_any(int variant, const KDom<T> &d, const KGrid &g,
-                                  const KConst &kc, const KRain &rn, Ctl *ctl, Part *part,
-                                  int ntq, int ntiles, int nwg, bool finalize,
+                                  const KConst &kc, const KRain &rn, Ctl *ctl, const KClose &cl,
+                                  int ntq, int ntiles, int nwg, int par_hint, bool finalize,
                                   hipStream_t stream) {
     switch (variant) {
 #define HEXSV_CASE(V)                                                                          \
     case V:                                                                                    \
         return launch_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(                        \
-            d, g, kc, rn, ctl, part, ntq, ntiles, nwg, finalize, stream);
+            d, g, kc, rn, ctl, cl, ntq, ntiles, nwg, par_hint, finalize, stream);
         HEXSV_TILE_SWITCH(HEXSV_CASE)
 #undef HEXSV_CASE
         default:
@@ -63,16 +84,18 @@ static hipError_t launch_step_any(int variant, const KDom<T> &d, const KGrid &g,
 
 template <typename T>
 hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                       const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles, int nwg,
-                       hipStream_t stream) {
-    return launch_step_any<T>(variant, d, g, kc, rn, ctl, part, ntq, ntiles, nwg, true, stream);
+                       const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles, int nwg,
+                       int par_hint, hipStream_t stream) {
+    return launch_step_any<T>(variant, d, g, kc, rn, ctl, cl, ntq, ntiles, nwg, par_hint, true,
+                              stream);
 }
 
 template <typename T>
 hipError_t launch_step_only(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                            const KRain &rn, Ctl *ctl, Part *part, int ntq, int ntiles, int nwg,
-                            hipStream_t stream) {
-    return launch_step_any<T>(variant, d, g, kc, rn, ctl, part, ntq, ntiles, nwg, false, stream);
+                            const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles,
+                            int nwg, int par_hint, hipStream_t stream) {
+    return launch_step_any<T>(variant, d, g, kc, rn, ctl, cl, ntq, ntiles, nwg, par_hint, false,
+                              stream);
 }
 
 // Initial c_max and stored volume of the current buffer.
@@ -498,11 +521,11 @@ hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const S
 
 #define HEXSV_INSTANTIATE(T)                                                                  \
     template hipError_t launch_step<T>(int, const KDom<T> &, const KGrid &, const KConst &,   \
-                                       const KRain &, Ctl *, Part *, int, int, int,           \
-                                       hipStream_t);                                          \
+                                       const KRain &, Ctl *, const KClose &, int, int, int,   \
+                                       int, hipStream_t);                                     \
     template hipError_t launch_step_only<T>(int, const KDom<T> &, const KGrid &, const KConst &, \
-                                            const KRain &, Ctl *, Part *, int, int, int,      \
-                                            hipStream_t);                                     \
+                                            const KRain &, Ctl *, const KClose &, int, int,   \
+                                            int, int, hipStream_t);                           \
     template hipError_t launch_prime<T>(const KDom<T> &, int64_t, const KConst &, Ctl *, Part *, \
                                         int, int, hipStream_t);                               \
     template hipError_t launch_win_probe<T>(const KDom<T> &, const KGrid &, const KConst &,   \
