@@ -140,7 +140,7 @@ extern "C" int hexsv_grid_tables(const hexsv_grid *grid, int32_t *d_nbr, uint8_t
 static const int SHORT_STEPS = 8;
 // Most closed steps whose books wait in the step ring before a fold.
 static const int RING_MAX = 128;
-static const size_t ACC_BYTES = sizeof(unsigned long long) * ACC_SLOTS * ACC_STRIDE;
+static const size_t ACC_BYTES = sizeof(unsigned long long) * ACC_SETS * ACC_SET_WORDS;
 
 struct hexsv_sim {
     const hexsv_grid *grid;
@@ -276,7 +276,7 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->rn.T_d = INFINITY;
     s->nwg = s->ntiles;
     hipError_t e = hipMalloc(&s->buf, s->esz * 9 * (size_t)grid->n);
-    if (e == hipSuccess) e = hipMalloc(&s->d_ctl, sizeof(Ctl));
+    if (e == hipSuccess) e = hipMalloc(&s->d_ctl, 2 * sizeof(Ctl));  // two control slots
     if (e == hipSuccess) e = hipMalloc(&s->d_part, sizeof(Part) * PRIME_BLOCKS);
     if (e == hipSuccess) e = hipMalloc(&s->d_chk, 4 * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&s->d_acc, ACC_BYTES);
@@ -456,10 +456,20 @@ static int ensure_ring(hexsv_sim *s) {
 
 static KClose close_of(const hexsv_sim *s) { return KClose{s->d_ring, s->d_slots, s->d_acc, s->ring_len}; }
 
-// Capture nsteps steps (tile kernel + finalize each, a fold of the books every
-// ring_len steps and at the end) into one executable graph.  Step k of the
-// graph reads buffer parity (par0 + k) % 2 (live steps are consecutive from
-// the start of a replay).
+static hipError_t step_launch(hexsv_sim *s, const KClose &cl, int hint, int in, int set,
+                              hipStream_t stream) {
+    if (s->prec == HEXSV_FP64)
+        return launch_step<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
+                                   cl, s->ntq, s->ntiles, s->nwg, hint, in, set, stream);
+    return launch_step<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn, s->d_ctl, cl,
+                              s->ntq, s->ntiles, s->nwg, hint, in, set, stream);
+}
+
+// Capture nsteps step launches (with a fold after every ring_len of them and
+// at the end) into one executable graph.  Step k of the graph reads buffer
+// parity (par0 + k) % 2 (live steps are consecutive from the start of a
+// replay); the j-th launch after a fold reads control slot j % 2 and
+// accumulates into set j % 3.
 static int capture_steps(hexsv_sim *s, int nsteps, int par0, hipGraph_t *graph,
                          hipGraphExec_t *exec) {
     int rc = ensure_ring(s);
@@ -467,16 +477,14 @@ static int capture_steps(hexsv_sim *s, int nsteps, int par0, hipGraph_t *graph,
     const KClose cl = close_of(s);
     HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
-        const int hint = (par0 + k) & 1;
-        if (s->prec == HEXSV_FP64)
-            e = launch_step<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
-                                    cl, s->ntq, s->ntiles, s->nwg, hint, s->cap);
-        else
-            e = launch_step<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn, s->d_ctl,
-                                   cl, s->ntq, s->ntiles, s->nwg, hint, s->cap);
-        if (e == hipSuccess && ((k + 1) % s->ring_len == 0 || k + 1 == nsteps))
-            e = launch_fold(s->d_ctl, cl, s->ntiles, s->cap);
+    int j = 0;  // launches since the last fold
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k, ++j) {
+        e = step_launch(s, cl, (par0 + k) & 1, j & 1, j % ACC_SETS, s->cap);
+        if (e == hipSuccess && (j + 1 == s->ring_len || k + 1 == nsteps)) {
+            e = launch_fold(s->d_ctl, cl, s->ntiles, s->kc, s->rn, (j + 1) & 1, j % ACC_SETS,
+                            s->cap);
+            j = -1;
+        }
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->cap, &g);
@@ -624,20 +632,13 @@ extern "C" int hexsv_sim_time_kernel(hexsv_sim *s, int32_t nlaunch, double *avg_
     const KClose cl = close_of(s);
     hipError_t e = hipSuccess;
     HIP_TRY(hipEventRecord(s->ev0, stream));
-    for (int k = 0; k < nlaunch && e == hipSuccess; ++k) {
-        if (s->prec == HEXSV_FP64)
-            e = launch_step_only<double>(s->tile, dom_of<double>(s), s->grid->kg, s->kc, s->rn,
-                                         s->d_ctl, cl, s->ntq, s->ntiles, s->nwg, c.parity,
-                                         stream);
-        else
-            e = launch_step_only<float>(s->tile, dom_of<float>(s), s->grid->kg, s->kc, s->rn,
-                                        s->d_ctl, cl, s->ntq, s->ntiles, s->nwg, c.parity,
-                                        stream);
-    }
+    // every launch reads slot 0 (no step pending) and recomputes the same step;
+    // what it writes (slot 1, the ring's first slot, accumulator sets 0 and 1)
+    // is scratch until the next run
+    for (int k = 0; k < nlaunch && e == hipSuccess; ++k)
+        e = step_launch(s, cl, c.parity, 0, 0, stream);
     HIP_TRY(e);
     HIP_TRY(hipEventRecord(s->ev1, stream));
-    // the timed launches left their wave speeds in the accumulator and their
-    // records in the (empty) ring's first slot: clear the accumulator
     HIP_TRY(hipMemsetAsync(s->d_acc, 0, ACC_BYTES, stream));
     HIP_TRY(hipEventSynchronize(s->ev1));
     float ms = 0.f;

@@ -33,56 +33,47 @@ __device__ inline Part reduce_parts(const Part *part, int nparts) {
     return block_reduce<NT>(c, s, o, cl);
 }
 
-// Closes one step of a single domain: time, step count and the CFL bound of
-// the next step from the largest wave speed the tile kernel left in the
-// accumulators (each read and reset with one atomic exchange).  One wave.
-__global__ __launch_bounds__(64) void k_finalize(Ctl *ctl, unsigned long long *acc, KConst kc,
-                                                 KRain rn) {
-    const StepTime st = step_time(ctl);
-    if (!st.live && ctl->err == 0) return;  // past the end: the tile kernel did nothing
-    unsigned long long m = 0;
-    for (int i = threadIdx.x; i < ACC_SLOTS; i += 64) {
-        const unsigned long long v = atomicExch(acc + i * ACC_STRIDE, 0ull);
-        m = v > m ? v : m;
-    }
-    m = wave_max(m);
-    if (threadIdx.x == 0 && st.live)
-        close_time(ctl, __longlong_as_double((long long)m), st, kc, rain_rate(rn, st.t_next));
-}
-
-hipError_t launch_finalize(Ctl *ctl, unsigned long long *acc, const KConst &kc, const KRain &rn,
-                           hipStream_t stream) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, stream, ctl, acc, kc, rn);
-    return hipGetLastError();
-}
-
 // Totals of one ring slot (one closed step) over its tile records, in the
-// same order as a whole-domain reduction of that step.
-__global__ __launch_bounds__(1024) void k_fold_slots(const Ctl *ctl, KClose cl, int ntiles) {
+// same order as a whole-domain reduction of that step.  The slots in use are
+// the closed steps of slot `in` plus its pending step.
+__global__ __launch_bounds__(1024) void k_fold_slots(const Ctl *ctl, KClose cl, int ntiles,
+                                                     int in) {
     const int j = blockIdx.x;
-    if (j >= ctl->open) return;
+    const Ctl *c = ctl + in;
+    const int n = c->open + ((c->p_live != 0 && ctl[0].err == 0) ? 1 : 0);
+    if (j >= n) return;
     const Part p = reduce_parts<1024>(cl.ring + (size_t)j * ntiles, ntiles);
     if (threadIdx.x == 0) cl.slots[j] = p;
 }
 
-// The slots' books added to the control block in step order.
-__global__ __launch_bounds__(64) void k_fold_close(Ctl *ctl, KClose cl) {
-    if (threadIdx.x != 0) return;
-    const int n = ctl->open < cl.ring_len ? ctl->open : cl.ring_len;
-    for (int j = 0; j < n; ++j) {
-        const Part p = cl.slots[j];
-        ctl->stored = p.stored;
-        ctl->outflow += p.outflow;
-        ctl->clamp += p.clamp;
+// The pending step of slot `in` closed into ctl[0], the slots' books added in
+// step order, the ring emptied and every accumulator cleared.  One wave.
+__global__ __launch_bounds__(64) void k_fold_close(Ctl *ctl, KClose cl, KConst kc, KRain rn,
+                                                   int in, int set) {
+    const OpenStep o = open_step(ctl, in, cl.acc + set * ACC_SET_WORDS, kc);
+    if (threadIdx.x == 0) {
+        write_slot(ctl, ctl + in, o, kc, rn, false);
+        const int n = o.open < cl.ring_len ? o.open : cl.ring_len;
+        for (int j = 0; j < n; ++j) {
+            const Part p = cl.slots[j];
+            ctl->stored = p.stored;
+            ctl->outflow += p.outflow;
+            ctl->clamp += p.clamp;
+        }
+        ctl->open = 0;
     }
-    ctl->open = 0;
+    for (int i = threadIdx.x; i < ACC_SETS * ACC_SLOTS; i += 64)
+        __hip_atomic_store(cl.acc + i * ACC_STRIDE, 0ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
-hipError_t launch_fold(Ctl *ctl, const KClose &cl, int ntiles, hipStream_t stream) {
-    hipLaunchKernelGGL(k_fold_slots, dim3(cl.ring_len), dim3(1024), 0, stream, ctl, cl, ntiles);
+hipError_t launch_fold(Ctl *ctl, const KClose &cl, int ntiles, const KConst &kc, const KRain &rn,
+                       int in, int set, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fold_slots, dim3(cl.ring_len), dim3(1024), 0, stream, ctl, cl, ntiles,
+                       in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fold_close, dim3(1), dim3(64), 0, stream, ctl, cl);
+    hipLaunchKernelGGL(k_fold_close, dim3(1), dim3(64), 0, stream, ctl, cl, kc, rn, in, set);
     return hipGetLastError();
 }
 

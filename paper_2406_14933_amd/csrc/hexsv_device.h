@@ -42,9 +42,17 @@ struct KRain {
 };
 
 // Device-resident control block: time, CFL bound, step counters, the buffer
-// parity and the FP64 books.  Read by every step kernel; written by the
-// kernels that close a step and fold the books (and by the ensemble's
-// per-scenario close).
+// parity and the FP64 books.
+//
+// A single domain keeps two of them.  ctl[0] is the one the host and every
+// other kernel see between graph replays; inside a run of step launches the
+// two alternate: a launch reads slot `in` and its workgroup 0 writes slot
+// in ^ 1 for the next launch.  The step a launch starts is closed by the next
+// launch (its wave-speed maximum is only complete once the launch has ended),
+// so a slot carries that pending step (p_live, p_dt, p_tnext) beside the state
+// after the last closed one; a fold kernel closes the last pending step and
+// brings ctl[0] up to date.  err and err_cell are only used in ctl[0].
+// The ensemble keeps one block per scenario and closes each step at once.
 struct alignas(128) Ctl {
     double t, tau, t_end, dt_max;
     int64_t steps, step_limit;
@@ -52,8 +60,10 @@ struct alignas(128) Ctl {
     int32_t err_cell;
     int32_t open;  // closed steps whose water books still wait in the step ring
     double initial, stored, rain, outflow, clamp, dt_min, dt_max_seen, last_cmax;
+    double p_dt, p_tnext;  // the pending step's dt and end time
+    int32_t p_live, pad0;  // a step was started and is not closed yet
 };
-static_assert(sizeof(Ctl) == 128, "control block is 128 bytes");
+static_assert(sizeof(Ctl) == 256, "control block is 256 bytes");
 
 // Per-tile partial results of one step.
 struct alignas(32) Part {
@@ -61,16 +71,19 @@ struct alignas(32) Part {
 };
 
 // Where the tile kernel of a single-domain step leaves its results: the
-// largest wave speed goes into one of ACC_SLOTS accumulators (an atomic
-// maximum over the bit patterns of non-negative doubles, which order like the
-// values; tile t uses slot t % ACC_SLOTS, ACC_STRIDE words apart, so that the
-// atomics of concurrent tiles do not queue on one address), the tile's water
-// books into slot ctl->open of the ring (ring[slot * ntiles + tile]).  The
-// finalize kernel closes the step from the accumulators alone; the fold
-// kernels add the ring's records to the books, step by step in order, every
-// ring_len steps at most.
-constexpr int ACC_SLOTS = 256;
-constexpr int ACC_STRIDE = 16;  // 128 bytes
+// largest wave speed goes into one of ACC_SLOTS accumulators of the launch's
+// set (an atomic maximum over the bit patterns of non-negative doubles, which
+// order like the values; tile t uses slot t % ACC_SLOTS, ACC_STRIDE words
+// apart, so that the atomics of concurrent tiles do not queue on one
+// address), the tile's water books into slot `open` of the ring
+// (ring[slot * ntiles + tile]).  Launch k of a run accumulates into set k % 3,
+// reads set (k - 1) % 3 to close the previous step and clears set (k + 1) % 3
+// for the next launch.  The fold kernels add the ring's records to the books,
+// step by step in order, every ring_len steps at most.
+constexpr int ACC_SLOTS = 16;
+constexpr int ACC_STRIDE = 32;  // 256 bytes
+constexpr int ACC_SETS = 3;
+constexpr int ACC_SET_WORDS = ACC_SLOTS * ACC_STRIDE;
 struct KClose {
     Part *ring;
     Part *slots;  // per-slot totals (fold scratch)
@@ -224,19 +237,100 @@ __device__ inline Part block_reduce(double c, double s, double o, double cl) {
 
 // Close one step on the device (Appendix A, eqs. .12-.13 for the next bound):
 // FP64 books, t^{n+1}, step count, buffer parity and tau = CFL*phi_min/c_max.
-// Time, step count and CFL bound of a closed step (its books are folded in
-// later from the step ring).
-__device__ inline void close_time(Ctl *ctl, double cmax, const StepTime &st, const KConst &kc,
-                                  double r_next) {
-    ctl->rain += kc.area_active * st.dt * r_next;
-    ctl->t = st.t_next;
-    ctl->steps += 1;
-    if (st.dt < ctl->dt_min) ctl->dt_min = st.dt;
-    if (st.dt > ctl->dt_max_seen) ctl->dt_max_seen = st.dt;
-    ctl->last_cmax = cmax;
-    ctl->tau = cmax > 0.0 ? kc.cfl_phi / cmax : __builtin_inf();
-    ctl->parity ^= 1;
-    ctl->open += 1;
+// Largest wave speed in one accumulator set (see KClose).  The addresses are
+// uniform and nothing is stored before, so these are scalar loads, which do
+// not wait for the tile's vector loads.  The set was last written by the
+// previous launch: the kernel boundary makes it visible, as it does for the
+// control slots.
+__device__ inline double acc_max(const unsigned long long *set) {
+    unsigned long long m = 0;
+#pragma unroll
+    for (int i = 0; i < ACC_SLOTS; ++i) {
+        const unsigned long long v = set[i * ACC_STRIDE];
+        m = v > m ? v : m;
+    }
+    return __longlong_as_double((long long)m);
+}
+
+// A launch's view of the run: control slot `in` with its pending step
+// closed (when there is one and no error was flagged), and the step this
+// launch starts from there.
+struct OpenStep {
+    double t, tau, cmax;  // after the close (cmax: of the closed step)
+    double dt, t_next;    // of the step this launch starts
+    int64_t steps;
+    int parity, open;
+    bool closed, live;
+};
+
+// prev_set: the accumulator set the pending step of slot `in` accumulated
+// into (read whether or not a step is pending, so the loads start at once).
+__device__ inline OpenStep open_step(const Ctl *ctl, int in, const unsigned long long *prev_set,
+                                     const KConst &kc) {
+    const double prev_max = acc_max(prev_set);
+    const Ctl *c = ctl + in;
+    const int err = ctl[0].err;
+    OpenStep o;
+    o.closed = c->p_live != 0 && err == 0;
+    o.t = c->t;
+    o.tau = c->tau;
+    o.steps = c->steps;
+    o.parity = c->parity;
+    o.open = c->open;
+    o.cmax = 0.0;
+    if (o.closed) {
+        o.cmax = prev_max;
+        o.t = c->p_tnext;
+        o.tau = o.cmax > 0.0 ? kc.cfl_phi / o.cmax : __builtin_inf();
+        o.steps += 1;
+        o.parity ^= 1;
+        o.open += 1;
+    }
+    const double t_end = c->t_end;
+    double dt = c->dt_max;
+    if (o.tau < dt) dt = o.tau;
+    if (t_end - o.t < dt) dt = t_end - o.t;
+    o.dt = dt;
+    o.live = (dt > 0.0) && (o.steps < c->step_limit) && (err == 0);
+    o.t_next = (dt == t_end - o.t) ? t_end : o.t + dt;
+    return o;
+}
+
+// Slot `out` of the control block from slot `in` and the launch's view: the
+// pending step of `in` closed (time, counters, CFL bound, rain book, dt range)
+// and the launch's own step pending.  err and err_cell are left alone.
+__device__ inline void write_slot(Ctl *out, const Ctl *in, const OpenStep o, const KConst &kc,
+                                  const KRain &rn, bool pending) {
+    double rain = in->rain, dmin = in->dt_min, dmax = in->dt_max_seen, lc = in->last_cmax;
+    if (o.closed) {
+        const double pdt = in->p_dt;
+        rain += kc.area_active * pdt * rain_rate(rn, in->p_tnext);
+        if (pdt < dmin) dmin = pdt;
+        if (pdt > dmax) dmax = pdt;
+        lc = o.cmax;
+    }
+    const double t_end = in->t_end, dt_max = in->dt_max, initial = in->initial;
+    const double stored = in->stored, outflow = in->outflow, clamp = in->clamp;
+    const int64_t limit = in->step_limit;
+    out->t = o.t;
+    out->tau = o.tau;
+    out->t_end = t_end;
+    out->dt_max = dt_max;
+    out->steps = o.steps;
+    out->step_limit = limit;
+    out->parity = o.parity;
+    out->open = o.open;
+    out->initial = initial;
+    out->stored = stored;
+    out->rain = rain;
+    out->outflow = outflow;
+    out->clamp = clamp;
+    out->dt_min = dmin;
+    out->dt_max_seen = dmax;
+    out->last_cmax = lc;
+    out->p_live = pending && o.live ? 1 : 0;
+    out->p_dt = o.dt;
+    out->p_tnext = o.t_next;
 }
 
 __device__ inline void close_step(Ctl *ctl, const Part &p, const StepTime &st, const KConst &kc,

@@ -53,28 +53,23 @@ inline void tile_grid(int v, int nq, int nr, int *ntq, int *ntiles) {
     *ntiles = *ntq * ((nr + s.tr - 1) / s.tr);
 }
 
-// One step: the tile kernel (nwg == ntiles workgroups; results as KClose
-// describes) followed by the one-thread finalize kernel.  par_hint: the
-// buffer parity the step is expected to read (its loads start before the
-// control block is read; a wrong hint only costs a reload).
+// One step launch (nwg == ntiles workgroups): closes the step of the
+// previous launch and starts the next (see k_step, Ctl and KClose).  ctl
+// points at the two control slots; `in` is the slot this launch reads and
+// `set` its accumulator set (launch k after a fold: in = k % 2, set = k % 3).
+// par_hint: the buffer parity the step is expected to read (its loads start
+// before the control block is read; a wrong hint only costs a reload).
 template <typename T>
 hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
                        const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles, int nwg,
-                       int par_hint, hipStream_t stream);
+                       int par_hint, int in, int set, hipStream_t stream);
 
-// The tile kernel alone (no finalize): used to time the kernel in isolation.
-template <typename T>
-hipError_t launch_step_only(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                            const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles,
-                            int nwg, int par_hint, hipStream_t stream);
-
-// Close a step from the largest wave speed in acc (which it resets).
-hipError_t launch_finalize(Ctl *ctl, unsigned long long *acc, const KConst &kc, const KRain &rn,
-                           hipStream_t stream);
-// Add the books of the ctl->open closed steps in the ring to the control
-// block, step by step in order, and empty the ring (one workgroup per slot,
-// then one thread).
-hipError_t launch_fold(Ctl *ctl, const KClose &cl, int ntiles, hipStream_t stream);
+// After a run of step launches whose last one read slot `in` with
+// accumulator set `set`: close its pending step, add the books of every
+// closed step in the ring to ctl[0] in step order, empty the ring and clear
+// the accumulators (one workgroup per ring slot, then one wave).
+hipError_t launch_fold(Ctl *ctl, const KClose &cl, int ntiles, const KConst &kc, const KRain &rn,
+                       int in, int set, hipStream_t stream);
 // Close a priming pass over nparts partial records: tau (and, with
 // reset_books, the initial books) of the current state.
 hipError_t launch_prime_finalize(Ctl *ctl, const Part *part, int nparts, const KConst &kc,

@@ -1,4 +1,4 @@
-// hexsv_kernels.h — step, finalize and state-transfer kernels, templated on
+// hexsv_kernels.h — step, priming and state-transfer kernels, templated on
 // the state precision T.  Included by one translation unit per precision.
 #pragma once
 
@@ -9,14 +9,14 @@
 
 namespace hexsv {
 
-// One explicit step of one tile (see tile_step).  Every workgroup first
-// recomputes the step's dt from the control block; a step past t_end or
-// past the step limit does nothing, so a captured graph of many steps can
-// overrun the end of a run safely.
 // One explicit step over the raster, one workgroup per tile (tiles mapped to
-// XCD bands, see xcd_tile); every workgroup writes its tile's partial record
-// and the single-workgroup finalize kernel launched right after folds the
-// records into the control block, so the next step sees the new dt.
+// XCD bands, see xcd_tile).  Every workgroup first closes the step the
+// previous launch started (from control slot `in` and the wave-speed maximum
+// that launch accumulated, see open_step) and derives this step's dt from it;
+// workgroup 0 also writes the control slot the next launch reads.  A step
+// past t_end or past the step limit computes nothing, so a captured graph of
+// many steps can overrun the end of a run safely.  Each tile adds its wave
+// speed to the launch's accumulator set and its water books to the step ring.
 //
 // par_hint is the buffer parity the launcher expects this step to read (a
 // graph of consecutive live steps alternates it).  The tile's loads are issued
@@ -25,31 +25,37 @@ namespace hexsv {
 // parity it was captured for) only costs a reload.
 template <typename T, int TQ, int TR, int NT>
 __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRain rn, Ctl *ctl,
-                                             KClose cl, int ntq, int ntiles, int par_hint) {
+                                             KClose cl, int ntq, int ntiles, int par_hint, int in,
+                                             int set) {
     __shared__ TileLDS<T, TQ, TR> L;
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
     const int tr = tile / ntq, tq = tile - tr * ntq;
     TileRegs<T, TQ, TR, NT> R;
     tile_load<T, TQ, TR, NT>(R, d, g, par_hint, tq, tr);
-    const StepTime st = step_time(ctl);
-    if (!st.live) return;
-    const int par = ctl->parity;
-    const int slot = ctl->open;
-    if (par != par_hint) tile_load<T, TQ, TR, NT>(R, d, g, par, tq, tr);
-    const double r_next = rain_rate(rn, st.t_next);
+    const OpenStep o = open_step(ctl, in, cl.acc + ((set + 2) % ACC_SETS) * ACC_SET_WORDS, kc);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) write_slot(ctl + (in ^ 1), ctl + in, o, kc, rn, true);
+        unsigned long long *next = cl.acc + ((set + 1) % ACC_SETS) * ACC_SET_WORDS;
+        if (threadIdx.x < ACC_SLOTS)
+            __hip_atomic_store(next + threadIdx.x * ACC_STRIDE, 0ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!o.live) return;
+    if (o.parity != par_hint) tile_load<T, TQ, TR, NT>(R, d, g, o.parity, tq, tr);
+    const double r_next = rain_rate(rn, o.t_next);
     const bool bad = tile_stage<T, TQ, TR, NT>(L, R, g, kc, tq, tr);
     const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
     const bool general = __syncthreads_or((!inner) || bad) != 0;
     Acc acc{0.0, 0.0, 0.0, 0.0};
-    tile_compute<T, TQ, TR, NT, true>(L, R, general, d, g, kc, par, tq, tr, st.dt, r_next, acc,
-                                      &ctl->err, &ctl->err_cell);
+    tile_compute<T, TQ, TR, NT, true>(L, R, general, d, g, kc, o.parity, tq, tr, o.dt, r_next,
+                                      acc, &ctl->err, &ctl->err_cell);
     const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
     if (threadIdx.x == 0) {
         // the host folds the ring before it fills; the clamp only keeps a
         // broken invariant from writing out of bounds
-        const int s = (unsigned)slot < (unsigned)cl.ring_len ? slot : cl.ring_len - 1;
+        const int s = (unsigned)o.open < (unsigned)cl.ring_len ? o.open : cl.ring_len - 1;
         cl.ring[(size_t)s * ntiles + tile] = p;
-        atomicMax(cl.acc + (tile % ACC_SLOTS) * ACC_STRIDE,
+        atomicMax(cl.acc + set * ACC_SET_WORDS + (tile % ACC_SLOTS) * ACC_STRIDE,
                   (unsigned long long)__double_as_longlong(p.cmax));
     }
 }
@@ -57,24 +63,22 @@ __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRai
 template <typename T, int TQ, int TR, int NT>
 static hipError_t launch_step_v(const KDom<T> &d, const KGrid &g, const KConst &kc,
                                 const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles,
-                                int nwg, int par_hint, bool finalize, hipStream_t stream) {
+                                int nwg, int par_hint, int in, int set, hipStream_t stream) {
     hipLaunchKernelGGL((k_step<T, TQ, TR, NT>), dim3(nwg), dim3(NT), 0, stream, d, g, kc, rn, ctl,
-                       cl, ntq, ntiles, par_hint);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !finalize) return e;
-    return launch_finalize(ctl, cl.acc, kc, rn, stream);
+                       cl, ntq, ntiles, par_hint, in, set);
+    return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_step_any(int variant, const KDom<T> &d, const KGrid &g,
                                   const KConst &kc, const KRain &rn, Ctl *ctl, const KClose &cl,
-                                  int ntq, int ntiles, int nwg, int par_hint, bool finalize,
+                                  int ntq, int ntiles, int nwg, int par_hint, int in, int set,
                                   hipStream_t stream) {
     switch (variant) {
 #define HEXSV_CASE(V)                                                                          \
     case V:                                                                                    \
         return launch_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(                        \
-            d, g, kc, rn, ctl, cl, ntq, ntiles, nwg, par_hint, finalize, stream);
+            d, g, kc, rn, ctl, cl, ntq, ntiles, nwg, par_hint, in, set, stream);
         HEXSV_TILE_SWITCH(HEXSV_CASE)
 #undef HEXSV_CASE
         default:
@@ -85,16 +89,8 @@ static hipError_t launch_step_any(int variant, const KDom<T> &d, const KGrid &g,
 template <typename T>
 hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
                        const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles, int nwg,
-                       int par_hint, hipStream_t stream) {
-    return launch_step_any<T>(variant, d, g, kc, rn, ctl, cl, ntq, ntiles, nwg, par_hint, true,
-                              stream);
-}
-
-template <typename T>
-hipError_t launch_step_only(int variant, const KDom<T> &d, const KGrid &g, const KConst &kc,
-                            const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles,
-                            int nwg, int par_hint, hipStream_t stream) {
-    return launch_step_any<T>(variant, d, g, kc, rn, ctl, cl, ntq, ntiles, nwg, par_hint, false,
+                       int par_hint, int in, int set, hipStream_t stream) {
+    return launch_step_any<T>(variant, d, g, kc, rn, ctl, cl, ntq, ntiles, nwg, par_hint, in, set,
                               stream);
 }
 
@@ -522,10 +518,7 @@ hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const S
 #define HEXSV_INSTANTIATE(T)                                                                  \
     template hipError_t launch_step<T>(int, const KDom<T> &, const KGrid &, const KConst &,   \
                                        const KRain &, Ctl *, const KClose &, int, int, int,   \
-                                       int, hipStream_t);                                     \
-    template hipError_t launch_step_only<T>(int, const KDom<T> &, const KGrid &, const KConst &, \
-                                            const KRain &, Ctl *, const KClose &, int, int,   \
-                                            int, int, hipStream_t);                           \
+                                       int, int, int, hipStream_t);                           \
     template hipError_t launch_prime<T>(const KDom<T> &, int64_t, const KConst &, Ctl *, Part *, \
                                         int, int, hipStream_t);                               \
     template hipError_t launch_win_probe<T>(const KDom<T> &, const KGrid &, const KConst &,   \
