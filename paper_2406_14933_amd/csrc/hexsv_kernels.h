@@ -19,10 +19,12 @@ namespace hexsv {
 // speed to the launch's accumulator set and its water books to the step ring.
 //
 // par_hint is the buffer parity the launcher expects this step to read (a
-// graph of consecutive live steps alternates it).  The tile's loads are issued
-// from that buffer before the control block has arrived, so they do not wait
-// for it; a wrong hint (never for a live step of a graph replayed from the
-// parity it was captured for) only costs a reload.
+// graph of consecutive live steps alternates it).  The launcher passes the
+// buffers of that parity as d.st[0], so the tile's loads use fixed argument
+// offsets and are issued before the control block has arrived; the kernel
+// works in parities relative to the hint.  A wrong hint (never for a live
+// step of a graph replayed from the parity it was captured for) only costs a
+// reload.
 template <typename T, int TQ, int TR, int NT>
 __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRain rn, Ctl *ctl,
                                              KClose cl, int ntq, int ntiles, int par_hint, int in,
@@ -31,7 +33,7 @@ __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRai
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
     const int tr = tile / ntq, tq = tile - tr * ntq;
     TileRegs<T, TQ, TR, NT> R;
-    tile_load<T, TQ, TR, NT>(R, d, g, par_hint, tq, tr);
+    tile_load<T, TQ, TR, NT>(R, d, g, 0, tq, tr);
     const OpenStep o = open_step(ctl, in, cl.acc + ((set + 2) % ACC_SETS) * ACC_SET_WORDS, kc);
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) write_slot(ctl + (in ^ 1), ctl + in, o, kc, rn, true);
@@ -41,14 +43,15 @@ __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRai
                                __HIP_MEMORY_SCOPE_AGENT);
     }
     if (!o.live) return;
-    if (o.parity != par_hint) tile_load<T, TQ, TR, NT>(R, d, g, o.parity, tq, tr);
+    const int rel = o.parity ^ par_hint;  // buffer parity relative to d
+    if (rel) tile_load<T, TQ, TR, NT>(R, d, g, 1, tq, tr);
     const double r_next = rain_rate(rn, o.t_next);
     const bool bad = tile_stage<T, TQ, TR, NT>(L, R, g, kc, tq, tr);
     const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
     const bool general = __syncthreads_or((!inner) || bad) != 0;
     Acc acc{0.0, 0.0, 0.0, 0.0};
-    tile_compute<T, TQ, TR, NT, true>(L, R, general, d, g, kc, o.parity, tq, tr, o.dt, r_next,
-                                      acc, &ctl->err, &ctl->err_cell);
+    tile_compute<T, TQ, TR, NT, true>(L, R, general, d, g, kc, rel, tq, tr, o.dt, r_next, acc,
+                                      &ctl->err, &ctl->err_cell);
     const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
     if (threadIdx.x == 0) {
         // the host folds the ring before it fills; the clamp only keeps a
@@ -64,8 +67,14 @@ template <typename T, int TQ, int TR, int NT>
 static hipError_t launch_step_v(const KDom<T> &d, const KGrid &g, const KConst &kc,
                                 const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles,
                                 int nwg, int par_hint, int in, int set, hipStream_t stream) {
-    hipLaunchKernelGGL((k_step<T, TQ, TR, NT>), dim3(nwg), dim3(NT), 0, stream, d, g, kc, rn, ctl,
-                       cl, ntq, ntiles, par_hint, in, set);
+    KDom<T> dh = d;  // buffers of the hinted parity first
+    if (par_hint & 1)
+        for (int f = 0; f < 3; ++f) {
+            dh.st[0][f] = d.st[1][f];
+            dh.st[1][f] = d.st[0][f];
+        }
+    hipLaunchKernelGGL((k_step<T, TQ, TR, NT>), dim3(nwg), dim3(NT), 0, stream, dh, g, kc, rn,
+                       ctl, cl, ntq, ntiles, par_hint & 1, in, set);
     return hipGetLastError();
 }
 
