@@ -541,20 +541,27 @@ static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, b
     int64_t last_steps = -1;
     for (;;) {
         const int64_t before = c.steps;
-        // the short graph is replayed as often as the span should need (steps past
-        // its end are no-ops), so a span of a few steps costs one host round trip
-        int reps = 1;
-        if (shortg) {
-            const double dt = c.tau < s->p.dt_max ? c.tau : s->p.dt_max;
-            const double need = dt > 0.0 ? (t_end - c.t) / dt + 1.0 : 1.0;
-            reps = need < SHORT_STEPS ? 1 : (int)fmin(64.0, ceil(need / SHORT_STEPS));
-        }
+        // A launch past the end of the run still issues its tile loads before it
+        // finds out, so each batch of replays is sized from the steps expected to
+        // remain (the current dt bound, or the step limit): whole long graphs
+        // while two or more of them remain, then the short graph as often as the
+        // rest should need (a span of a few steps costs one host round trip).
+        const double dt = c.tau < s->p.dt_max ? c.tau : s->p.dt_max;
+        double need = dt > 0.0 ? (t_end - c.t) / dt + 1.0 : 1.0;
+        if ((double)(limit - c.steps) < need) need = (double)(limit - c.steps);
+        const bool use_short = shortg || need < 2.0 * s->gsteps;
+        int reps;
+        if (use_short)
+            reps = need <= SHORT_STEPS ? 1 : (int)fmin(64.0, ceil(need / SHORT_STEPS));
+        else
+            reps = (int)fmin(64.0, floor(need / s->gsteps) - 1.0);
+        const int per = use_short ? SHORT_STEPS : s->gsteps;
         if (s->timing) HIP_TRY(hipEventRecord(s->ev0, stream));
         // replays after the first start from a parity the host no longer knows: for
         // a live step the graph's hint is still right whenever its step count is even
         for (int k = 0; k < reps; ++k) {
-            const int p = (c.parity + k * (shortg ? SHORT_STEPS : s->gsteps)) & 1;
-            HIP_TRY(hipGraphLaunch(shortg ? s->sexec[p] : s->gexec[p], stream));
+            const int p = (int)((c.parity + (int64_t)k * per) & 1);
+            HIP_TRY(hipGraphLaunch(use_short ? s->sexec[p] : s->gexec[p], stream));
         }
         if (s->timing) HIP_TRY(hipEventRecord(s->ev1, stream));
         HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
