@@ -30,12 +30,15 @@ BYTES_PER_CELL = {"fp32": 9 * 4, "fp64": 9 * 8}
 
 # Measured HBM bytes of one step-kernel launch: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB
 # per dispatch, in runs of their own) scaled by what the same counters read for a plain 1 GiB
-# device copy (x2.000 and x1.000); the summary with its commands is
-# profiles/k_step_catchment-4096x4096_fp32.md.  A figure holds only for the kernel source it
-# was taken on (digest below); otherwise the line reports null.
+# device copy (x2.000 and x1.000); the summaries with their commands are
+# profiles/k_step_catchment-{4096x4096,1024x1024}_fp32.md (at 1024 x 1024 the working set sits
+# in the Infinity Cache, whose hits these counters include).  A figure holds only for the
+# kernel source it was taken on (digest below); otherwise the line reports null.
 TRAFFIC = {
     ("catchment-4096x4096-edge2m-storm150mmh", "fp32", 2): {
-        "bytes": 606359372, "digest": "7476a07c73281bd9"},
+        "bytes": 607152846, "digest": "0d9f2f60d2da7b29"},
+    ("catchment-1024x1024-edge2m-rain100mmh", "fp32", 2): {
+        "bytes": 38556881, "digest": "0d9f2f60d2da7b29"},
 }
 
 

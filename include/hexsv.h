@@ -181,8 +181,9 @@ int hexsv_sim_set_state(hexsv_sim *sim, double t0, const double *d_h, const doub
  * no limit).  Each step: dt = min(dt_max, CFL*phi_min/c_max, t_end - t),
  * then eq. fvm_2D_eq_frac.07 on every active cell, then c_max and the FP64
  * books of the new state; the last step lands on t_end exactly.  Runs as
- * replays of a captured graph of steps_per_graph steps on `stream`, reading
- * a 128-byte control block back after each replay.  EDOMAIN: t_end < t.
+ * replays of captured graphs of steps_per_graph (and of 8) steps on `stream`,
+ * batched by the steps expected to remain, reading the 256-byte control block
+ * back after each batch.  EDOMAIN: t_end < t.
  * ENUMERIC: a non-finite value appeared (state left at the failing step). */
 int hexsv_sim_run(hexsv_sim *sim, double t_end, int64_t max_steps, hipStream_t stream);
 

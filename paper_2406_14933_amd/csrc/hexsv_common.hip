@@ -54,12 +54,17 @@ __global__ __launch_bounds__(64) void k_fold_close(Ctl *ctl, KClose cl, KConst k
     if (threadIdx.x == 0) {
         write_slot(ctl, ctl + in, o, kc, rn, false);
         const int n = o.open < cl.ring_len ? o.open : cl.ring_len;
+        // in registers: stores to ctl inside the loop would serialise its loads
+        double stored = ctl->stored, outflow = ctl->outflow, clamp = ctl->clamp;
         for (int j = 0; j < n; ++j) {
             const Part p = cl.slots[j];
-            ctl->stored = p.stored;
-            ctl->outflow += p.outflow;
-            ctl->clamp += p.clamp;
+            stored = p.stored;
+            outflow += p.outflow;
+            clamp += p.clamp;
         }
+        ctl->stored = stored;
+        ctl->outflow = outflow;
+        ctl->clamp = clamp;
         ctl->open = 0;
     }
     for (int i = threadIdx.x; i < ACC_SETS * ACC_SLOTS; i += 64)
