@@ -143,7 +143,7 @@ def time_ensemble(precision, launches, ksteps, n_scen, tune):
             "info": info}
 
 
-def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=1e-5, seed=1):
+def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=3e-5, seed=1, dt_scale=2.4):
     """Train the window surrogate on solver trajectories (all on the GPU, the library's own
     kernels) and time it against the plain FP32 solver on held-out scenarios to t_end."""
     import numpy as np
@@ -156,7 +156,7 @@ def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=1e-5, seed=1):
     test_sc = [synth.ensemble_member(1000 + s, size=size, config=5, t_end=t_end)
                for s in range(n_test)]
     t0 = time.perf_counter()
-    dt_fix = 0.8 * min(S.pilot_dt(sc) for sc in train_sc[:2])
+    dt_fix = dt_scale * min(S.pilot_dt(sc) for sc in train_sc[:2])
     window = k * dt_fix
     sur = hexsv.Surrogate(4, 32)
     rng = np.random.default_rng(seed)

@@ -774,6 +774,7 @@ static void window_record(hexsv_sim *s, double t_stop, double window, int32_t k,
     w.k = k;
     w.project = project ? 1 : 0;
     w.perr_cell = -1;
+    w.c0 = -1.0;
 }
 
 static FeatScale feat_scale(const float *sc) { return FeatScale{sc[0], sc[1], sc[2], sc[5], sc[3], sc[4]}; }
@@ -943,6 +944,10 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
                 return fail(HEXSV_ENUMERIC, "run_surrogate: the solver stalled at t=%g before %g",
                             c.t, target);
             *n_fb += 1;
+            // the solver's state is the new reference wave speed of the windows that follow
+            static const double fresh = -1.0;
+            HIP_TRY(hipMemcpyAsync((char *)s->d_sw + offsetof(SurWin, c0), &fresh, sizeof fresh,
+                                   hipMemcpyHostToDevice, st));
         } else if (level < 3) {
             ++level;
         }

@@ -115,7 +115,9 @@ struct alignas(64) SurWin {
     int32_t scale_live;             // the accepted state waits for its rescaling
     int32_t perr, perr_cell;        // non-finite value met by a probe step
     double scale;                   // factor of that rescaling
-    double c0;                      // c_max of the window's start state
+    double c0;                      // reference c_max: of the last state the solver made
+                                    // (run start, end of a refused span); < 0: take it
+                                    // from the next window's start state
     int32_t why;                    // reason of the last refusal: 1 residual, 2 wave speed, 4 non-finite
     int32_t pad2;
 };

@@ -268,7 +268,7 @@ __global__ __launch_bounds__(NT) void k_win_probe(KDom<T> d, KGrid g, KConst kc,
             sw->R = kc.area_active * depth;
             sw->t0 = t0;
             sw->S0 = ctl->stored;
-            sw->c0 = ctl->last_cmax;
+            if (!(sw->c0 >= 0.0)) sw->c0 = ctl->last_cmax;
         }
     }
     if (!live) return;
