@@ -206,6 +206,41 @@ def test_graph_length_does_not_change_results(hx):
     assert a["books"]["steps"] == b["books"]["steps"]
 
 
+BOOK_KEYS = ("t", "steps", "stored", "rain", "outflow", "clamp", "dt_min", "dt_max_seen")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_step_protocol_is_invariant_to_graph_and_run_shape(hx, precision):
+    """Each step launch closes the previous launch's step (two alternating control slots,
+    rotating accumulator sets, books in a step ring folded per replay and every 128 steps):
+    graphs of odd and even lengths, graphs longer than the ring, runs cut into uneven pieces
+    by max_steps, and isolated kernel timings in between must all give the same bits."""
+    sc = synth.catchment(72, 64, 2.0, config=2, t_end=80.0)
+    ref = gpu_run(hx, sc, precision, steps_per_graph=100)
+    nsteps = ref["books"]["steps"]
+    assert nsteps > 300, nsteps  # graphs of 300 steps fold mid-graph
+    for spg in (1, 3, 8, 300):
+        got = gpu_run(hx, sc, precision, steps_per_graph=spg)
+        for f in ("h", "v1", "v2"):
+            np.testing.assert_array_equal(got[f], ref[f], err_msg=f"{f} steps_per_graph={spg}")
+        for k in BOOK_KEYS:
+            assert got["books"][k] == ref["books"][k], (spg, k, got["books"][k], ref["books"][k])
+    sim = hx.Sim.from_scenario(sc, precision, steps_per_graph=16)
+    done = 0
+    for piece in (1, 13, 2, 29, 200):
+        sim.run(sc.t_end, max_steps=piece)
+        done += piece
+        assert sim.books()["steps"] == done
+        sim.time_kernel(5)  # recomputes the current step in place: no effect on the run
+    sim.run(sc.t_end)
+    got = sim.state_numpy()
+    for f in ("h", "v1", "v2"):
+        np.testing.assert_array_equal(got[f], ref[f], err_msg=f)
+    bk = sim.books()
+    for k in BOOK_KEYS:
+        assert bk[k] == ref["books"][k], (k, bk[k], ref["books"][k])
+
+
 def test_max_steps_and_resume(hx):
     sc = synth.c1_planar(nq=40, nr=30, t_end=120.0)
     full = gpu_run(hx, sc, "fp64")
