@@ -308,9 +308,9 @@ hipError_t launch_win_probe(const KDom<T> &d, const KGrid &g, const KConst &kc, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_win_slope(KDom<T> d, KGrid g, double a,
                                                    float2 *__restrict__ slope) {
-    const int64_t n = (int64_t)g.nq * g.nr;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+    const int n = g.nq * g.nr;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const int r = i / g.nq, q = i - r * g.nq;
         double sx = 0.0, sy = 0.0;
         if (d.th[i] > T(0)) terrain_slope<T>(g, a, d.z, d.th, nullptr, q, r, i, sx, sy);
         slope[i] = make_float2((float)sx, (float)sy);
@@ -392,13 +392,14 @@ __global__ __launch_bounds__(256) void k_win_features(KDom<T> d, KGrid g, double
     const int par = ctl->parity;
     const double depth = sw->depth;
     const double xs = sw->window / win_probe_dt(ctl, dt_max);
-    const int64_t n = (int64_t)g.nq * g.nr;
+    // 32-bit cell indices: creation limits a field to 4 GiB
+    const int n = g.nq * g.nr;
     const T *h = par ? d.st[1][0] : d.st[0][0];
     const T *v1 = par ? d.st[1][1] : d.st[0][1];
     const T *v2 = par ? d.st[1][2] : d.st[0][2];
     typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
     double o = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         float f[FEATURES];
         win_feature_vec<T>(h[i], v1[i], v2[i], d.z[i], d.th[i], scr[i], scr[n + i], scr[2 * n + i],
                            slope[i], depth, xs, sc, f);
@@ -409,12 +410,12 @@ __global__ __launch_bounds__(256) void k_win_features(KDom<T> d, KGrid g, double
                 v[c / 8][c % 8] = c < FEATURES ? (__bf16)f[c] : (__bf16)0.f;
 #pragma unroll
             for (int u = 0; u < nn::FEATURES_PAD / 8; ++u)
-                reinterpret_cast<bf16x8 *>((__bf16 *)out + i * nn::FEATURES_PAD)[u] = v[u];
+                reinterpret_cast<bf16x8 *>((__bf16 *)out + (size_t)i * nn::FEATURES_PAD)[u] = v[u];
         } else {
 #pragma unroll
-            for (int c = 0; c < FEATURES; ++c) ((float *)out)[i * FEATURES + c] = f[c];
+            for (int c = 0; c < FEATURES; ++c) ((float *)out)[(size_t)i * FEATURES + c] = f[c];
         }
-        const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+        const int r = i / g.nq, q = i - r * g.nq;
         if (may_outflow(g, q, r)) o += cell_outflow<T>(g, l, h, v1, v2, d.th, q, r, i);
     }
     const Part p = block_reduce<256>(0.0, o, 0.0, 0.0);
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(256) void k_win_apply(KDom<T> d, KGrid g, double l,
                                                    Part *part) {
     if (!sw->live) return;
     const int par = ctl->parity;
-    const int64_t n = (int64_t)g.nq * g.nr;
+    const int n = g.nq * g.nr;  // 32-bit cell indices: creation limits a field to 4 GiB
     const double xs = sw->window / win_probe_dt(ctl, dt_max);
     const T *h = par ? d.st[1][0] : d.st[0][0];
     const T *v1 = par ? d.st[1][1] : d.st[0][1];
@@ -460,7 +461,7 @@ __global__ __launch_bounds__(256) void k_win_apply(KDom<T> d, KGrid g, double l,
     const T *hs = scr, *v1s = scr + n, *v2s = scr + 2 * n;
     const T G = (T)kc.g;
     double c = 0.0, s = 0.0, o = 0.0, bad = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const T th = d.th[i];
         if (!(th > T(0))) {
             ho[i] = h[i];
@@ -472,10 +473,10 @@ __global__ __launch_bounds__(256) void k_win_apply(KDom<T> d, KGrid g, double l,
         const double xh = xs * (double)(hs[i] - h[i]);
         const double xq1 = xs * (double)(th * hs[i] * v1s[i] - q1);
         const double xq2 = xs * (double)(th * hs[i] * v2s[i] - q2);
-        double hn = (double)h[i] + xh + (double)dH * (double)out[i * os + 0];
+        double hn = (double)h[i] + xh + (double)dH * (double)out[(size_t)i * os + 0];
         hn = hn > 0.0 ? hn : 0.0;
-        const double p1 = (double)q1 + xq1 + (double)dQ * (double)out[i * os + 1];
-        const double p2 = (double)q2 + xq2 + (double)dQ * (double)out[i * os + 2];
+        const double p1 = (double)q1 + xq1 + (double)dQ * (double)out[(size_t)i * os + 1];
+        const double p2 = (double)q2 + xq2 + (double)dQ * (double)out[(size_t)i * os + 2];
         const double mn = (double)th * hn;
         const T hT = (T)hn;
         const T a1 = mn > m_min ? (T)(p1 / mn) : T(0);
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(256) void k_win_apply(KDom<T> d, KGrid g, double l,
         if (__builtin_isfinite(cc)) c = cc > c ? cc : c;
         else bad += 1.0;  // the gate refuses such a window
         s += kc.sigma * ((double)th * (double)hT);
-        const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+        const int r = i / g.nq, q = i - r * g.nq;
         if (may_outflow(g, q, r)) o += cell_outflow<T>(g, l, ho, v1o, v2o, d.th, q, r, i);
     }
     const Part p = block_reduce<256>(c, s, o, bad);
