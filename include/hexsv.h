@@ -170,6 +170,14 @@ int hexsv_sim_set_fields(hexsv_sim *sim, const double *d_z, const double *d_thet
 /* Rain forcing.  EDOMAIN: i_a < 0, kind 1 with t_a <= 0 or T_d <= t_a. */
 int hexsv_sim_set_rain(hexsv_sim *sim, const hexsv_rain *rain);
 
+/* Linear soil resistance -tau*h*v (1/s), the law of the Thacker test
+ * (Sec. 3.2.2, Appendix B), added to the friction terms of the momentum step
+ * and, like them, implicit in v^{n+1} (weighted by theta like the soil term):
+ * the coefficient of v becomes m^{n+1} (1 + dt*tau), m = theta*h.  tau = 0
+ * (the default) leaves the paper's Darcy-Weisbach scheme unchanged bit for bit.
+ * Takes effect from the next run.  EDOMAIN: tau < 0 or non-finite. */
+int hexsv_sim_set_linear_friction(hexsv_sim *sim, double tau);
+
 /* Initial state (the paper's "initial water layer", Sec. 3) at time t0:
  * h, v1, v2 per cell (device FP64 arrays of nq*nr).  Resets the books and
  * the step count, and computes the first CFL bound.  EDOMAIN: h < 0 or a

@@ -255,7 +255,10 @@ static void step_one(const int32_t *nbr, const uint8_t *code, double a,
     /* eq. fvm_2D_eq_frac.06-2 solved by the miu-formula, with eq_K_h_theta */
     double K = alpha_p[i] * h1 * (1.0 - th) + th * p->alpha_s;
     double beta = dt * K;
-    double mu = ref_mu(m1, beta, g1, g2);
+    /* the linear soil term theta*tau*h*v (Thacker test), implicit in v^{n+1}:
+     * it adds dt*tau*theta*h^{n+1} = dt*tau*m^{n+1} to the coefficient of v */
+    double alpha = m1 * (1.0 + dt * p->tau_lin);
+    double mu = ref_mu(alpha, beta, g1, g2);
     if (p->h_dry > 0.0 && h1 < p->h_dry) mu = 0.0;
     *hn = h1;
     *v1n = mu * g1;

@@ -61,7 +61,10 @@ int ref_tables(int32_t nq, int32_t nr, const int32_t side[4], int32_t nseg,
 double ref_rain_rate(int32_t kind, double i_a, double t_a, double T_d, double t);
 
 /* Closed-form implicit friction solve (Appendix A, miu-formula):
- * alpha*v + beta*|v|*v = gamma.  Returns mu with v = mu*gamma (0 if D = 0). */
+ * alpha*v + beta*|v|*v = gamma.  Returns mu with v = mu*gamma (0 if D = 0).
+ * alpha is the new mass m = theta*h^{n+1}, times (1 + dt*tau) when a linear
+ * soil resistance theta*tau*h*v is on (it is implicit in v like the quadratic
+ * terms). */
 double ref_mu(double alpha, double beta, double g1, double g2);
 
 typedef struct {
@@ -70,6 +73,8 @@ typedef struct {
     double dt_max; /* maximum time step */
     double h_dry;  /* depth below which v is set to 0 (0 disables) */
     double alpha_s;/* Darcy-Weisbach soil coefficient (uniform) */
+    double tau_lin;/* linear soil resistance -tau*h*v of the Thacker test (Sec. 3.2.2,
+                      Appendix B), in 1/s; 0 for the paper's Darcy-Weisbach runs */
 } ref_params;
 
 typedef struct {

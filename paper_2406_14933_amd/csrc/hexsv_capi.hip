@@ -269,6 +269,7 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     hexsv_geometry(a, p.cfl, &s->kc.sigma, &s->kc.cfl_phi);
     s->kc.h_dry = p.h_dry;
     s->kc.alpha_s = 0.0;
+    s->kc.tau_lin = 0.0;
     s->kc.area_active = s->kc.sigma * (double)grid->n_active;
     s->rn.kind = 0;
     s->rn.i_a = 0.0;
@@ -371,6 +372,17 @@ extern "C" int hexsv_sim_set_fields(hexsv_sim *s, const double *d_z, const doubl
     s->fields_set = true;
     s->slope_ok = false;
     drop_graph(s);
+    drop_win_graph(s);
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_set_linear_friction(hexsv_sim *s, double tau) {
+    if (!s) return fail(HEXSV_EINVAL, "set_linear_friction: null sim");
+    if (!(tau >= 0.0) || !isfinite(tau))
+        return fail(HEXSV_EDOMAIN, "set_linear_friction: tau=%g must be finite and >= 0", tau);
+    s->kc.tau_lin = tau;
+    drop_graph(s);
+    drop_win_graph(s);
     return HEXSV_OK;
 }
 
@@ -386,6 +398,7 @@ extern "C" int hexsv_sim_set_rain(hexsv_sim *s, const hexsv_rain *rain) {
     s->rn.t_a = rain->t_a;
     s->rn.T_d = rain->T_d;
     drop_graph(s);
+    drop_win_graph(s);
     return HEXSV_OK;
 }
 

@@ -95,6 +95,7 @@ struct KClose {
 struct KConst {
     double g, a, sigma, cfl_phi, h_dry, alpha_s;
     double area_active;  // sigma * number of active cells
+    double tau_lin;      // linear soil resistance -tau h v (Thacker test), 1/s; 0: off
 };
 
 template <typename T>

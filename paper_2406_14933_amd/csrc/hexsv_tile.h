@@ -231,6 +231,10 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
     const T dts = (T)(dt / kc.sigma);
     const T rT = (T)r_next;
     const T alpha_s = (T)kc.alpha_s;
+    // linear soil resistance theta tau h v, implicit in v^{n+1}: the coefficient of
+    // v is m^{n+1} + dt tau m^{n+1} = m^{n+1} (1 + dt tau) (exactly m^{n+1} at tau = 0)
+    const bool lin = kc.tau_lin != 0.0;
+    const T ftau = T(1) + dtT * (T)kc.tau_lin;
     const T h_dry = (T)kc.h_dry;
     const T S3H = (T)0.86602540378443864676;
     const T NX[6] = {T(1), T(0.5), T(-0.5), T(-1), T(-0.5), T(0.5)};
@@ -344,7 +348,9 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
         const T K = R.ap[k] * h1 * (T(1) - thi) + thi * alpha_s;
         const T beta = dtT * K;
         const T Gm = p_sqrt(g1 * g1 + g2 * g2);
-        const T D = m1 + p_sqrt(m1 * m1 + T(4) * beta * Gm);
+        T alpha = m1;
+        if (lin) alpha = m1 * ftau;
+        const T D = alpha + p_sqrt(alpha * alpha + T(4) * beta * Gm);
         T mu = (D == T(0)) ? T(0) : p_div(T(2), D);
         if (h_dry > T(0) && h1 < h_dry) mu = T(0);
         const T v1n = mu * g1, v2n = mu * g2;

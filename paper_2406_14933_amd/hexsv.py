@@ -74,6 +74,7 @@ _SIGS = [
     ("hexsv_sim_destroy", None, [_VP]),
     ("hexsv_sim_set_fields", C.c_int, [_VP, _VP, _VP, _VP, C.c_double, _VP]),
     ("hexsv_sim_set_rain", C.c_int, [_VP, C.POINTER(Rain)]),
+    ("hexsv_sim_set_linear_friction", C.c_int, [_VP, C.c_double]),
     ("hexsv_sim_set_state", C.c_int, [_VP, C.c_double, _VP, _VP, _VP, _VP]),
     ("hexsv_sim_run", C.c_int, [_VP, C.c_double, C.c_int64, _VP]),
     ("hexsv_sim_get_state", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -242,6 +243,8 @@ class Sim:
         s = cls(grid, precision, g=sc.g, cfl=sc.cfl, dt_max=sc.dt_max, h_dry=sc.h_dry, **kw)
         s.set_fields(sc.z, sc.theta, sc.alpha_p, sc.alpha_s)
         s.set_rain(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d)
+        if getattr(sc, "tau_lin", 0.0):
+            s.set_linear_friction(sc.tau_lin)
         s.set_state(sc.h0, sc.v10, sc.v20, 0.0)
         return s
 
@@ -250,6 +253,10 @@ class Sim:
         z, th, ap = (_dev(x, n=n) for x in (z, theta, alpha_p))
         _check(lib().hexsv_sim_set_fields(self._h, _ptr(z), _ptr(th), _ptr(ap), float(alpha_s),
                                           _stream()))
+
+    def set_linear_friction(self, tau):
+        """Linear soil resistance -tau h v (1/s), the Thacker test's law; 0 turns it off."""
+        _check(lib().hexsv_sim_set_linear_friction(self._h, float(tau)))
 
     def set_rain(self, kind=0, i_a=0.0, t_a=0.0, T_d=float("inf")):
         r = Rain(int(kind), float(i_a), float(t_a), float(T_d))

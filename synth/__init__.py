@@ -61,6 +61,7 @@ class Scenario:
     cfl: float = 0.5
     dt_max: float = 1.0
     h_dry: float = 0.0
+    tau_lin: float = 0.0  # linear soil resistance -tau*h*v (1/s); 0: the paper's Darcy-Weisbach law
     meta: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -303,6 +304,40 @@ def lake_at_rest(nq=24, nr=20, a=1.0, level=1.0, emerged=False, seed=7):
     return Scenario(
         name="lake", nq=nq, nr=nr, a=a, z=z, theta=th, alpha_p=np.full(n, ALPHA_P),
         side=(WALL, WALL, WALL, WALL), rain_kind=0, i_a=0.0, h0=h, t_end=50.0)
+
+
+def thacker(a=0.888231, half_x=200.0, half_y=150.0, t_end=330.0, tau=0.7, curv=(1.25e-3, 5e-3),
+            centre=(500.0, 500.0), w0=15.0, du0=0.02 * G_ACCEL, dv0=-0.1 * G_ACCEL, h_dry=1e-3,
+            cfl=0.25):
+    """The non-oscillating Thacker problem of Sec. 3.2.2 / Appendix B: paraboloid bed
+    z = A (x-x0)^2 + B (y-y0)^2, no vegetation (theta = 1), no rain, linear soil resistance
+    -tau h v, velocity initially zero with accelerations (du0, dv0), free surface
+    w(0,x,y) = w0 - (x-x0) du0/g - (y-y0) dv0/g (the exact solution at t = 0), h = [w - z]_+.
+
+    The raster is a parallelogram of edge a covering x0 +- half_x, y0 +- half_y (the water
+    stays well inside; the extra cells are dry), walls all round.  Below h_dry (1 mm) the
+    velocity is set to zero: with only a linear resistance a thin film at the wet/dry front
+    would otherwise be accelerated without bound.  The Courant number is 0.25: at 0.5 a mode
+    in the 15 m deep centre of the bowl grows slowly and takes over after about 60 s (the
+    paper does not give its value for this test).  meta carries the exact solution's
+    parameters and the centre coordinates' offset (ox, oy)."""
+    A, B = curv
+    x0, y0 = centre
+    nr = int(math.ceil(2.0 * half_y / (1.5 * a))) + 1
+    shift = a * math.sqrt(3.0) * 0.5 * (nr - 1)
+    nq = int(math.ceil((2.0 * half_x + shift) / (a * math.sqrt(3.0)))) + 1
+    ox, oy = x0 - half_x - shift, y0 - half_y
+    x, y = centres(nq, nr, a)
+    x, y = x + ox, y + oy
+    z = A * (x - x0) ** 2 + B * (y - y0) ** 2
+    w = w0 - (x - x0) * du0 / G_ACCEL - (y - y0) * dv0 / G_ACCEL
+    n = nq * nr
+    return Scenario(
+        name=f"thacker-a{a:g}", nq=nq, nr=nr, a=a, z=z, theta=np.ones(n), alpha_p=np.zeros(n),
+        alpha_s=0.0, side=(WALL, WALL, WALL, WALL), h0=np.maximum(w - z, 0.0), t_end=t_end,
+        tau_lin=tau, h_dry=h_dry, cfl=cfl,
+        meta={"A": A, "B": B, "x0": x0, "y0": y0, "ox": ox, "oy": oy, "tau": tau, "w0": w0,
+              "u0": 0.0, "v0": 0.0, "du0": du0, "dv0": dv0, "g": G_ACCEL})
 
 
 def random_state(sc: Scenario, seed: int, depth=0.05, speed=0.3, dry_frac=0.2):
