@@ -170,6 +170,15 @@ int hexsv_sim_set_fields(hexsv_sim *sim, const double *d_z, const double *d_thet
 /* Rain forcing.  EDOMAIN: i_a < 0, kind 1 with t_a <= 0 or T_d <= t_a. */
 int hexsv_sim_set_rain(hexsv_sim *sim, const hexsv_rain *rain);
 
+/* Momentum flux with artificial viscosity (on = 1), for shocks and the
+ * Riemann problem (Sec. 3.2.3, Appendix A, eqs. eq_artif_visc and eq_visc1):
+ * J^v_a,i = J_a,i + sum over the interior edges of l c_ij mu_ij ((v_a)_j -
+ * (v_a)_i), c_ij = max(c_i, c_j), c = |v| + sqrt(g h), mu_ij =
+ * 2 m_i m_j / (m_i + m_j), m = theta*h; explicit, like J.  Off (0) by default.
+ * Takes effect from the next run; surrogate windows refuse a viscous sim
+ * (EUNSUPPORTED).  EINVAL: on not 0 or 1. */
+int hexsv_sim_set_viscosity(hexsv_sim *sim, int32_t on);
+
 /* Linear soil resistance -tau*h*v (1/s), the law of the Thacker test
  * (Sec. 3.2.2, Appendix B), added to the friction terms of the momentum step
  * and, like them, implicit in v^{n+1} (weighted by theta like the soil term):

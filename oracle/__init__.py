@@ -36,7 +36,8 @@ def build(quiet: bool = True) -> str:
 
 class RefParams(C.Structure):
     _fields_ = [("g", C.c_double), ("cfl", C.c_double), ("dt_max", C.c_double),
-                ("h_dry", C.c_double), ("alpha_s", C.c_double), ("tau_lin", C.c_double)]
+                ("h_dry", C.c_double), ("alpha_s", C.c_double), ("tau_lin", C.c_double),
+                ("visc", C.c_int32)]
 
 
 class RefRain(C.Structure):
@@ -76,6 +77,8 @@ def lib():
         L.ref_mu.restype = C.c_double
         L.ref_cell_sums.argtypes = [C.c_int32, ip, up, C.c_double, C.c_double, dp, dp, dp, dp,
                                     dp, C.c_int32, dp]
+        L.ref_visc_sums.argtypes = [C.c_int32, ip, up, C.c_double, C.c_double, dp, dp, dp, dp,
+                                    C.c_int32, dp]
         L.ref_cmax.argtypes = [C.c_int32, dp, C.c_double, dp, dp, dp]
         L.ref_cmax.restype = C.c_double
         L.ref_dt.argtypes = [C.c_double, C.POINTER(RefParams), C.c_double, C.c_double, C.c_double]
@@ -177,8 +180,8 @@ def mu(alpha, beta, g1, g2):
     return lib().ref_mu(alpha, beta, g1, g2)
 
 
-def params(g=9.81, cfl=0.5, dt_max=1.0, h_dry=0.0, alpha_s=0.0, tau_lin=0.0):
-    return RefParams(g, cfl, dt_max, h_dry, alpha_s, tau_lin)
+def params(g=9.81, cfl=0.5, dt_max=1.0, h_dry=0.0, alpha_s=0.0, tau_lin=0.0, visc=False):
+    return RefParams(g, cfl, dt_max, h_dry, alpha_s, tau_lin, int(bool(visc)))
 
 
 def rain(kind=0, i_a=0.0, t_a=0.0, T_d=float("inf")):
@@ -197,6 +200,15 @@ def cell_sums(G: RefGrid, g, z, theta, h, v1, v2, i):
     z, th, h, v1, v2 = (_f64(x, G.n) for x in (z, _theta_masked(G, theta), h, v1, v2))
     lib().ref_cell_sums(G.n, _i(G.nbr), _u(G.code), G.a, g, _d(z), _d(th), _d(h), _d(v1),
                         _d(v2), int(i), _d(out))
+    return out
+
+
+def visc_sums(G: RefGrid, g, theta, h, v1, v2, i):
+    """The artificial-viscosity part {V1, V2} of the augmented flux J^v for cell i."""
+    out = np.zeros(2)
+    th, h, v1, v2 = (_f64(x, G.n) for x in (_theta_masked(G, theta), h, v1, v2))
+    lib().ref_visc_sums(G.n, _i(G.nbr), _u(G.code), G.a, g, _d(th), _d(h), _d(v1), _d(v2),
+                        int(i), _d(out))
     return out
 
 

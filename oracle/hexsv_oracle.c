@@ -201,6 +201,29 @@ void ref_cell_sums(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
     out[5] = Fout;
 }
 
+void ref_visc_sums(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
+                   double g, const double *theta, const double *h, const double *v1,
+                   const double *v2, int32_t i, double out[2]) {
+    (void)N;
+    double l = a;
+    double V1 = 0.0, V2 = 0.0;
+    double mi = theta[i] * h[i];
+    double ci = sqrt(v1[i] * v1[i] + v2[i] * v2[i]) + sqrt(g * h[i]);
+    for (int k = 0; k < 6; ++k) {
+        if (code[(int64_t)i * 6 + k] != REF_INTERIOR) continue;
+        int32_t j = nbr[(int64_t)i * 6 + k];
+        double mj = theta[j] * h[j];
+        double cj = sqrt(v1[j] * v1[j] + v2[j] * v2[j]) + sqrt(g * h[j]);
+        double c = ci > cj ? ci : cj;
+        double ms = mi + mj;
+        double mu = ms > 0.0 ? 2.0 * mi * mj / ms : 0.0;
+        V1 += l * c * mu * (v1[j] - v1[i]);
+        V2 += l * c * mu * (v2[j] - v2[i]);
+    }
+    out[0] = V1;
+    out[1] = V2;
+}
+
 /* Cells outside the domain carry theta == 0; theta of a cell of the domain
  * lies in (0,1] (eq. eq_theta, and theta*h must determine h). */
 static int is_active_cell(const double *theta, int64_t i) { return theta[i] > 0.0; }
@@ -249,9 +272,17 @@ static void step_one(const int32_t *nbr, const uint8_t *code, double a,
         m1 = 0.0;
     }
     double h1 = m1 / th;
-    /* eq. fvm_2D_eq_frac.05-2: (theta h v)^* */
-    double g1 = mi * v1[i] + dts * (s[1] + s[3]);
-    double g2 = mi * v2[i] + dts * (s[2] + s[4]);
+    /* eq. fvm_2D_eq_frac.05-2: (theta h v)^*, with J^v = J + viscous sums when on */
+    double g1, g2;
+    if (p->visc) {
+        double vs[2];
+        ref_visc_sums(0, nbr, code, a, p->g, theta, h, v1, v2, i, vs);
+        g1 = mi * v1[i] + dts * ((s[1] + vs[0]) + s[3]);
+        g2 = mi * v2[i] + dts * ((s[2] + vs[1]) + s[4]);
+    } else {
+        g1 = mi * v1[i] + dts * (s[1] + s[3]);
+        g2 = mi * v2[i] + dts * (s[2] + s[4]);
+    }
     /* eq. fvm_2D_eq_frac.06-2 solved by the miu-formula, with eq_K_h_theta */
     double K = alpha_p[i] * h1 * (1.0 - th) + th * p->alpha_s;
     double beta = dt * K;

@@ -75,6 +75,8 @@ typedef struct {
     double alpha_s;/* Darcy-Weisbach soil coefficient (uniform) */
     double tau_lin;/* linear soil resistance -tau*h*v of the Thacker test (Sec. 3.2.2,
                       Appendix B), in 1/s; 0 for the paper's Darcy-Weisbach runs */
+    int32_t visc;  /* 1: augmented momentum flux J^v with artificial viscosity
+                      (eqs. eq_artif_visc, eq_visc1), for shocks */
 } ref_params;
 
 typedef struct {
@@ -101,6 +103,16 @@ void ref_cell_sums(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
                    double g, const double *z, const double *theta,
                    const double *h, const double *v1, const double *v2,
                    int32_t i, double out[6]);
+
+/* The artificial-viscosity part of the augmented flux J^v (eq. eq_artif_visc):
+ * out = sum over the INTERIOR edges of cell i, in direction order, of
+ * l * c_ij * mu_ij * ((v_a)_j - (v_a)_i) (eq. eq_visc1), with c_ij the larger
+ * of c = |v| + sqrt(g h) of the two cells and mu_ij = 2 m_i m_j / (m_i + m_j),
+ * m = theta*h (0 when both are dry).  OUTFLOW ghosts carry the cell's own
+ * velocity and WALL edges carry nothing, so neither contributes. */
+void ref_visc_sums(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
+                   double g, const double *theta, const double *h, const double *v1,
+                   const double *v2, int32_t i, double out[2]);
 
 /* Largest c_i = |v_i| + sqrt(g h_i) over active cells (eq. fvm_2D_eq_frac.13). */
 double ref_cmax(int32_t N, const double *theta, double g, const double *h,

@@ -270,6 +270,7 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->kc.h_dry = p.h_dry;
     s->kc.alpha_s = 0.0;
     s->kc.tau_lin = 0.0;
+    s->kc.visc = 0;
     s->kc.area_active = s->kc.sigma * (double)grid->n_active;
     s->rn.kind = 0;
     s->rn.i_a = 0.0;
@@ -371,6 +372,15 @@ extern "C" int hexsv_sim_set_fields(hexsv_sim *s, const double *d_z, const doubl
     s->kc.alpha_s = alpha_s;
     s->fields_set = true;
     s->slope_ok = false;
+    drop_graph(s);
+    drop_win_graph(s);
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_set_viscosity(hexsv_sim *s, int32_t on) {
+    if (!s) return fail(HEXSV_EINVAL, "set_viscosity: null sim");
+    if (on != 0 && on != 1) return fail(HEXSV_EINVAL, "set_viscosity: on must be 0 or 1");
+    s->kc.visc = on;
     drop_graph(s);
     drop_win_graph(s);
     return HEXSV_OK;
@@ -981,6 +991,8 @@ extern "C" int hexsv_sim_run_surrogate(hexsv_sim *s, hexsv_surrogate *sur, doubl
     if (!s || !sur || !(window > 0.0) || !isfinite(window) || k < 1 || !(residual_tol >= 0.0))
         return fail(HEXSV_EINVAL, "run_surrogate: bad argument");
     if (!s->state_set) return fail(HEXSV_ESTATE, "run_surrogate: call set_state first");
+    if (s->kc.visc)
+        return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for the viscous flux");
     int64_t a = 0, f = 0;
     const int rc =
         s->prec == HEXSV_FP64

@@ -96,6 +96,7 @@ struct KConst {
     double g, a, sigma, cfl_phi, h_dry, alpha_s;
     double area_active;  // sigma * number of active cells
     double tau_lin;      // linear soil resistance -tau h v (Thacker test), 1/s; 0: off
+    int32_t visc;        // 1: augmented momentum flux with artificial viscosity
 };
 
 template <typename T>

@@ -25,11 +25,15 @@ namespace hexsv {
 // works in parities relative to the hint.  A wrong hint (never for a live
 // step of a graph replayed from the parity it was captured for) only costs a
 // reload.
-template <typename T, int TQ, int TR, int NT>
+//
+// VISC: the momentum flux is the augmented J^v with artificial viscosity
+// (eqs. eq_artif_visc, eq_visc1), an instance of its own so that the plain
+// scheme pays nothing for it.
+template <typename T, int TQ, int TR, int NT, bool VISC>
 __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRain rn, Ctl *ctl,
                                              KClose cl, int ntq, int ntiles, int par_hint, int in,
                                              int set) {
-    __shared__ TileLDS<T, TQ, TR> L;
+    __shared__ TileLDS<T, TQ, TR, VISC> L;
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
     const int tr = tile / ntq, tq = tile - tr * ntq;
     TileRegs<T, TQ, TR, NT> R;
@@ -73,8 +77,12 @@ static hipError_t launch_step_v(const KDom<T> &d, const KGrid &g, const KConst &
             dh.st[0][f] = d.st[1][f];
             dh.st[1][f] = d.st[0][f];
         }
-    hipLaunchKernelGGL((k_step<T, TQ, TR, NT>), dim3(nwg), dim3(NT), 0, stream, dh, g, kc, rn,
-                       ctl, cl, ntq, ntiles, par_hint & 1, in, set);
+    if (kc.visc)
+        hipLaunchKernelGGL((k_step<T, TQ, TR, NT, true>), dim3(nwg), dim3(NT), 0, stream, dh, g,
+                           kc, rn, ctl, cl, ntq, ntiles, par_hint & 1, in, set);
+    else
+        hipLaunchKernelGGL((k_step<T, TQ, TR, NT, false>), dim3(nwg), dim3(NT), 0, stream, dh, g,
+                           kc, rn, ctl, cl, ntq, ntiles, par_hint & 1, in, set);
     return hipGetLastError();
 }
 

@@ -40,11 +40,15 @@ struct Rec<double> {
     using type = double4;
 };
 
-template <typename T, int TQ, int TR>
+// V: the step adds the artificial viscosity of the augmented momentum flux
+// (eqs. eq_artif_visc, eq_visc1), which needs c = |v| + sqrt(g h) of every
+// staged position as well.
+template <typename T, int TQ, int TR, bool V = false>
 struct TileLDS {
     static constexpr int W = TQ + 2, H = TR + 2, NS = W * H;
     typename Rec<T>::type rec[NS];
     uint8_t code[NS];
+    T c[V ? NS : 1];
 };
 
 // Map ring index t (0 <= t < 2*(TQ+2) + 2*TR) to a halo slot (lq, lr) in
@@ -153,8 +157,8 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
 // ----------------------------------------------------------------- stage
 
 // Write the LDS records; returns true if a staged raster cell is inactive.
-template <typename T, int TQ, int TR, int NT>
-__device__ inline bool tile_stage(TileLDS<T, TQ, TR> &L, const TileRegs<T, TQ, TR, NT> &R,
+template <typename T, int TQ, int TR, int NT, bool V>
+__device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ, TR, NT> &R,
                                   const KGrid &g, const KConst &kc, int tq, int tr) {
     using Regs = TileRegs<T, TQ, TR, NT>;
     constexpr int W = TQ + 2;
@@ -174,6 +178,8 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR> &L, const TileRegs<T, TQ, T
             const T m = R.th[k] * R.h[k];
             L.rec[s] = make_rec<T>(mscale * m, G * (R.z[k] + R.h[k]), R.v1[k] * T(0.5),
                                    R.v2[k] * T(0.5));
+            if constexpr (V)
+                L.c[s] = p_sqrt(R.v1[k] * R.v1[k] + R.v2[k] * R.v2[k]) + p_sqrt(G * R.h[k]);
             const bool act = R.th[k] > T(0);
             bad |= !act;
             if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
@@ -181,6 +187,7 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR> &L, const TileRegs<T, TQ, T
             int q = q0 + lq, r = r0 + lr;
             wrap_pos(g, q, r);
             L.rec[s] = make_rec<T>(T(0), T(0), T(0), T(0));
+            if constexpr (V) L.c[s] = T(0);
             L.code[s] = (uint8_t)side_code(g, q, r);
         }
     }
@@ -195,6 +202,8 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR> &L, const TileRegs<T, TQ, T
             const T m = R.rth[k] * R.rh[k];
             L.rec[s] = make_rec<T>(mscale * m, G * (R.rz[k] + R.rh[k]), R.rv1[k] * T(0.5),
                                    R.rv2[k] * T(0.5));
+            if constexpr (V)
+                L.c[s] = p_sqrt(R.rv1[k] * R.rv1[k] + R.rv2[k] * R.rv2[k]) + p_sqrt(G * R.rh[k]);
             const bool act = R.rth[k] > T(0);
             bad |= !act;
             if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
@@ -202,6 +211,7 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR> &L, const TileRegs<T, TQ, T
             int q = q0 + lq - 1, r = r0 + lr - 1;
             wrap_pos(g, q, r);
             L.rec[s] = make_rec<T>(T(0), T(0), T(0), T(0));
+            if constexpr (V) L.c[s] = T(0);
             L.code[s] = (uint8_t)side_code(g, q, r);
         }
     }
@@ -210,8 +220,8 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR> &L, const TileRegs<T, TQ, T
 
 // --------------------------------------------------------------- compute
 
-template <typename T, int TQ, int TR, int NT, bool NT_STORE>
-__device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<T, TQ, TR, NT> &R,
+template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V>
+__device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ, TR, NT> &R,
                                     bool general, const KDom<T> &d, const KGrid &g,
                                     const KConst &kc, int par, int tq, int tr, double dt,
                                     double r_next, Acc &acc, int32_t *err_flag,
@@ -257,6 +267,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
         const T vh1i = R.v1[k] * T(0.5), vh2i = R.v2[k] * T(0.5);
         const T Mi = mscale * mi;
         T Ls = T(0), A1 = T(0), A2 = T(0), S1 = T(0), S2 = T(0), Fout = T(0);
+        T V1 = T(0), V2 = T(0);  // viscous part of J^v (V only)
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
             const int sn = s + OFF[e];
@@ -318,6 +329,20 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
                 S2 -= P * NY[e];
                 if (GEN && cd == CODE_OUTFLOW) Fout += F;
             }
+            if constexpr (V) {
+                // artificial viscosity l c_ij mu_ij (v_j - v_i) of an interior edge (an
+                // outflow ghost carries the cell's own velocity); (v_j - v_i) is twice the
+                // difference of the staged halves, exactly.  FP32 masses carry the l.
+                if (!GEN || cd == CODE_INTERIOR) {
+                    const T ci = L.c[s], cj = L.c[sn];
+                    const T cij = ci > cj ? ci : cj;
+                    const T ms = Mi + mj;
+                    const T mu = ms > T(0) ? p_div(T(2) * Mi * mj, ms) : T(0);
+                    const T lc = F32 ? cij : l * cij;
+                    V1 += lc * mu * (T(2) * (vh1j - vh1i));
+                    V2 += lc * mu * (T(2) * (vh2j - vh2i));
+                }
+            }
         }
         const T v1i = R.v1[k], v2i = R.v2[k];
         T m1, h1, g1, g2;
@@ -332,8 +357,13 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
                 h1 = hi + p_div(dm, thi);
                 h1 = h1 > T(0) ? h1 : T(0);
             }
-            g1 = mi * v1i + dts * A1;
-            g2 = mi * v2i + dts * A2;
+            if constexpr (V) {
+                g1 = mi * v1i + dts * (A1 + V1);
+                g2 = mi * v2i + dts * (A2 + V2);
+            } else {
+                g1 = mi * v1i + dts * A1;
+                g2 = mi * v2i + dts * A2;
+            }
         } else {
             const T ms = mi + dts * Ls;
             m1 = ms + dtT * rT;
@@ -342,8 +372,13 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
                 m1 = T(0);
             }
             h1 = p_div(m1, thi);
-            g1 = mi * v1i + dts * (A1 + S1);
-            g2 = mi * v2i + dts * (A2 + S2);
+            if constexpr (V) {  // J^v = J + viscous sums, then the pressure part
+                g1 = mi * v1i + dts * ((A1 + V1) + S1);
+                g2 = mi * v2i + dts * ((A2 + V2) + S2);
+            } else {
+                g1 = mi * v1i + dts * (A1 + S1);
+                g2 = mi * v2i + dts * (A2 + S2);
+            }
         }
         const T K = R.ap[k] * h1 * (T(1) - thi) + thi * alpha_s;
         const T beta = dtT * K;
@@ -405,8 +440,8 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR> &L, const TileRegs<
 
 // All three phases for one tile (the caller separates consecutive tiles on
 // the same LDS with a barrier).
-template <typename T, int TQ, int TR, int NT, bool NT_STORE>
-__device__ inline void tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const KGrid &g,
+template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V = false>
+__device__ inline void tile_step(TileLDS<T, TQ, TR, V> &L, const KDom<T> &d, const KGrid &g,
                                  const KConst &kc, int par, int tq, int tr, double dt,
                                  double r_next, Acc &acc, int32_t *err_flag, int32_t *err_cell) {
     TileRegs<T, TQ, TR, NT> R;
@@ -414,8 +449,8 @@ __device__ inline void tile_step(TileLDS<T, TQ, TR> &L, const KDom<T> &d, const 
     const bool bad = tile_stage<T, TQ, TR, NT>(L, R, g, kc, tq, tr);
     const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
     const bool general = __syncthreads_or((!inner) || bad) != 0;
-    tile_compute<T, TQ, TR, NT, NT_STORE>(L, R, general, d, g, kc, par, tq, tr, dt, r_next, acc,
-                                          err_flag, err_cell);
+    tile_compute<T, TQ, TR, NT, NT_STORE, V>(L, R, general, d, g, kc, par, tq, tr, dt, r_next,
+                                             acc, err_flag, err_cell);
 }
 
 }  // namespace hexsv

@@ -75,6 +75,7 @@ _SIGS = [
     ("hexsv_sim_set_fields", C.c_int, [_VP, _VP, _VP, _VP, C.c_double, _VP]),
     ("hexsv_sim_set_rain", C.c_int, [_VP, C.POINTER(Rain)]),
     ("hexsv_sim_set_linear_friction", C.c_int, [_VP, C.c_double]),
+    ("hexsv_sim_set_viscosity", C.c_int, [_VP, C.c_int32]),
     ("hexsv_sim_set_state", C.c_int, [_VP, C.c_double, _VP, _VP, _VP, _VP]),
     ("hexsv_sim_run", C.c_int, [_VP, C.c_double, C.c_int64, _VP]),
     ("hexsv_sim_get_state", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -245,6 +246,8 @@ class Sim:
         s.set_rain(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d)
         if getattr(sc, "tau_lin", 0.0):
             s.set_linear_friction(sc.tau_lin)
+        if getattr(sc, "visc", False):
+            s.set_viscosity(True)
         s.set_state(sc.h0, sc.v10, sc.v20, 0.0)
         return s
 
@@ -253,6 +256,10 @@ class Sim:
         z, th, ap = (_dev(x, n=n) for x in (z, theta, alpha_p))
         _check(lib().hexsv_sim_set_fields(self._h, _ptr(z), _ptr(th), _ptr(ap), float(alpha_s),
                                           _stream()))
+
+    def set_viscosity(self, on):
+        """Momentum flux with artificial viscosity (for shocks); off by default."""
+        _check(lib().hexsv_sim_set_viscosity(self._h, int(bool(on))))
 
     def set_linear_friction(self, tau):
         """Linear soil resistance -tau h v (1/s), the Thacker test's law; 0 turns it off."""

@@ -62,6 +62,7 @@ class Scenario:
     dt_max: float = 1.0
     h_dry: float = 0.0
     tau_lin: float = 0.0  # linear soil resistance -tau*h*v (1/s); 0: the paper's Darcy-Weisbach law
+    visc: bool = False    # augmented momentum flux with artificial viscosity (for shocks)
     meta: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -338,6 +339,38 @@ def thacker(a=0.888231, half_x=200.0, half_y=150.0, t_end=330.0, tau=0.7, curv=(
         tau_lin=tau, h_dry=h_dry, cfl=cfl,
         meta={"A": A, "B": B, "x0": x0, "y0": y0, "ox": ox, "oy": oy, "tau": tau, "w0": w0,
               "u0": 0.0, "v0": 0.0, "du0": du0, "dv0": dv0, "g": G_ACCEL})
+
+
+def riemann(n_section=1122, length=18.0, width=1.0, x_jump=9.0, t_end=1.5,
+            left=(0.8, 1.0, 0.2, 5.00), right=(1.0, 1.2, 0.6, 1.33), cfl=0.5):
+    """The Riemann problem with vegetation of Sec. 3.2.3: a horizontal channel of the given
+    length and width with a jump of porosity, bed, depth and velocity at x_jump; each side
+    is (theta, z, h, u) of the paper's data table (v = 0).  Pointy-top hexes whose rows
+    run along the channel, n_section centres per row (the paper's longitudinal section
+    has 1122); the rectangle is cut from the axial parallelogram by the active mask.  The
+    channel walls are the raster's S and N sides; the cut ends are OUTFLOW (ghost cells
+    copy the cell, so the supercritical inflow at x = 0 keeps its state).  No friction
+    (the paper gives no coefficients for this test) and the artificial-viscosity flux."""
+    a = length / (n_section * math.sqrt(3.0))
+    s3a = a * math.sqrt(3.0)
+    nr = int(math.floor((width - a) / (1.5 * a))) + 1
+    oy = 0.5 * (width - 1.5 * a * (nr - 1))
+    ox = 0.5 * s3a - 0.5 * s3a * (nr - 1)
+    nq = n_section + (nr - 1 + 1) // 2 + 1
+    x, y = centres(nq, nr, a)
+    x, y = x + ox, y + oy
+    eps = 1e-9 * length
+    act = ((x >= 0.5 * s3a - eps) & (x <= length - 0.5 * s3a + eps)).astype(np.uint8)
+    L = x <= x_jump
+    pick = lambda k: np.where(L, left[k], right[k]).astype(np.float64)
+    n = nq * nr
+    h0 = np.where(act > 0, pick(2), 0.0)
+    v10 = np.where(act > 0, pick(3), 0.0)
+    return Scenario(
+        name=f"riemann-{n_section}", nq=nq, nr=nr, a=a, z=pick(1), theta=pick(0),
+        alpha_p=np.zeros(n), alpha_s=0.0, side=(WALL, OUTFLOW, WALL, OUTFLOW), active=act,
+        mask_code=OUTFLOW, h0=h0, v10=v10, t_end=t_end, cfl=cfl, visc=True,
+        meta={"ox": ox, "oy": oy, "x_jump": x_jump, "left": left, "right": right})
 
 
 def random_state(sc: Scenario, seed: int, depth=0.05, speed=0.3, dry_frac=0.2):

@@ -9,7 +9,7 @@ def ref_grid(sc):
 
 
 def ref_params(sc):
-    return oracle.params(sc.g, sc.cfl, sc.dt_max, sc.h_dry, sc.alpha_s, sc.tau_lin)
+    return oracle.params(sc.g, sc.cfl, sc.dt_max, sc.h_dry, sc.alpha_s, sc.tau_lin, sc.visc)
 
 
 def ref_rain(sc):
