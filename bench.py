@@ -36,9 +36,9 @@ BYTES_PER_CELL = {"fp32": 9 * 4, "fp64": 9 * 8}
 # kernel source it was taken on (digest below); otherwise the line reports null.
 TRAFFIC = {
     ("catchment-4096x4096-edge2m-storm150mmh", "fp32", 2): {
-        "bytes": 607152846, "digest": "0d9f2f60d2da7b29"},
+        "bytes": 607001391, "digest": "d88fe01fa94dd0ad"},
     ("catchment-1024x1024-edge2m-rain100mmh", "fp32", 2): {
-        "bytes": 38556881, "digest": "0d9f2f60d2da7b29"},
+        "bytes": 38558300, "digest": "d88fe01fa94dd0ad"},
 }
 
 
