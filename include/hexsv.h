@@ -26,6 +26,15 @@
  *    mask_bc.  WALL edges carry no flux or pressure term; OUTFLOW edges see a
  *    ghost with the cell's h, v, theta and the terrain extrapolated linearly
  *    through the opposite neighbour.
+ *  - Dirichlet cells (active == 2; the prescribed inflow state of Sec. 3.2.1,
+ *    eq. numerics-bc): a band of cells outside the domain held at the state
+ *    set_state gives them.  They are never updated and are not in the books
+ *    or c_max.  An edge from an updated cell into one (code DIRICHLET) reads
+ *    it like a neighbour, but the interface velocity is the prescribed
+ *    velocity itself rather than the mean of eq. fvm_2D_eq.04, so the inflow
+ *    flux is l h_D (v_D . n); that flux enters the books as negative outflow.
+ *    Viscous sums (set_viscosity) run over INTERIOR edges only.  Ensembles
+ *    and surrogate windows refuse grids with Dirichlet cells.
  *  - Every d_* pointer is caller-owned device memory (e.g. a torch tensor's
  *    data_ptr()), read or written only during the call (stream-ordered on
  *    `stream`); the library copies inputs into its own buffers and never frees
@@ -59,7 +68,8 @@ typedef enum {
 typedef enum { HEXSV_FP64 = 0, HEXSV_FP32 = 1 } hexsv_precision;
 
 /* edge codes and side kinds */
-enum { HEXSV_INTERIOR = 0, HEXSV_WALL = 1, HEXSV_OUTFLOW = 2, HEXSV_PERIODIC = 3 };
+enum { HEXSV_INTERIOR = 0, HEXSV_WALL = 1, HEXSV_OUTFLOW = 2, HEXSV_PERIODIC = 3,
+       HEXSV_DIRICHLET = 4 /* edge codes only: the neighbour is a Dirichlet cell */ };
 /* sides */
 enum { HEXSV_S = 0, HEXSV_E = 1, HEXSV_N = 2, HEXSV_W = 3 };
 
@@ -79,7 +89,8 @@ typedef struct {
                                 E/W (and S/N) must agree on PERIODIC */
     int32_t nseg;            /* number of valid entries in seg (<= 8) */
     hexsv_segment seg[HEXSV_MAX_SEGMENTS];
-    const uint8_t *active;   /* host, nq*nr, nullable (all active): 1 = in the domain */
+    const uint8_t *active;   /* host, nq*nr, nullable (all 1): 0 = outside the domain,
+                                1 = in the domain, 2 = Dirichlet cell; other values EINVAL */
     int32_t mask_bc;         /* code of edges into inactive cells: WALL or OUTFLOW */
 } hexsv_grid_desc;
 
@@ -121,7 +132,8 @@ typedef struct {
     double rain;      /* rain volume added */
     double outflow;   /* volume that left through OUTFLOW edges */
     double clamp;     /* volume added by clamping negative theta*h to zero */
-    double residual;  /* |stored - (initial + rain - outflow + clamp)| / (initial + rain) */
+    double residual;  /* |stored - (initial + rain - outflow + clamp)| /
+                         (initial + rain + max(-outflow, 0)) */
     int64_t steps;    /* steps taken since set_state */
     double dt_min, dt_max_seen;
 } hexsv_books;
@@ -141,12 +153,13 @@ const char *hexsv_last_error(void);
  * EINVAL: sizes, codes or segments malformed.  ENOMEM. */
 int hexsv_grid_create(const hexsv_grid_desc *desc, hexsv_grid **out);
 void hexsv_grid_destroy(hexsv_grid *grid);
-/* Number of cells nq*nr and of active cells. */
+/* Number of cells nq*nr and of updated cells (active == 1). */
 int hexsv_grid_counts(const hexsv_grid *grid, int64_t *cells, int64_t *active);
 
 /* Neighbour and edge-code tables computed on the device (one thread per cell):
- * d_nbr[i*6+k] = index of the neighbour across edge k for INTERIOR edges, -1
- * otherwise; d_code[i*6+k] = edge code; inactive cells get six WALL codes.
+ * d_nbr[i*6+k] = index of the neighbour across edge k for INTERIOR and
+ * DIRICHLET edges, -1 otherwise; d_code[i*6+k] = edge code; cells outside the
+ * domain (active == 0) get six WALL codes.
  * Caller-allocated device arrays of nq*nr*6 int32 and uint8. */
 int hexsv_grid_tables(const hexsv_grid *grid, int32_t *d_nbr, uint8_t *d_code,
                       hipStream_t stream);

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhexsv_oracle.so")
 SRC_PATH = os.path.join(HERE, "hexsv_oracle.c")
 
-INTERIOR, WALL, OUTFLOW, PERIODIC = 0, 1, 2, 3
+INTERIOR, WALL, OUTFLOW, PERIODIC, DIRICHLET = 0, 1, 2, 3, 4
 S, E, N, W = 0, 1, 2, 3
 DQ = (1, 0, -1, -1, 0, 1)
 DR = (0, 1, 1, 0, -1, -1)
@@ -140,7 +140,8 @@ class RefGrid:
     a: float
     nbr: np.ndarray   # (N, 6) int32, -1 where the edge is not INTERIOR
     code: np.ndarray  # (N, 6) uint8
-    active: np.ndarray  # (N,) bool
+    active: np.ndarray  # (N,) bool: computational cells
+    dirichlet: np.ndarray = None  # (N,) bool: boundary cells whose state is held fixed
 
     @property
     def n(self):
@@ -164,8 +165,12 @@ def tables(nq, nr, side=(WALL, WALL, WALL, WALL), segs=(), active=None, mask_cod
 
 def grid(nq, nr, a, side=(WALL, WALL, WALL, WALL), segs=(), active=None, mask_code=WALL):
     nbr, code = tables(nq, nr, side, segs, active, mask_code)
-    act = np.ones(nq * nr, bool) if active is None else np.asarray(active, bool).reshape(-1)
-    return RefGrid(nq, nr, float(a), nbr, code, act)
+    if active is None:
+        act, dch = np.ones(nq * nr, bool), np.zeros(nq * nr, bool)
+    else:
+        raw = np.asarray(active).reshape(-1)
+        act, dch = raw == 1, raw == 2
+    return RefGrid(nq, nr, float(a), nbr, code, act, dch)
 
 
 # ------------------------------------------------------------ small pieces
@@ -190,7 +195,9 @@ def rain(kind=0, i_a=0.0, t_a=0.0, T_d=float("inf")):
 
 def _theta_masked(G: RefGrid, theta):
     th = _f64(theta, G.n).copy()
-    th[~G.active] = 0.0
+    dch = G.dirichlet if G.dirichlet is not None else np.zeros(G.n, bool)
+    th[~(G.active | dch)] = 0.0
+    th[dch] = -th[dch]  # held fixed: not updated, not booked, read with |theta| by neighbours
     return th
 
 
@@ -248,7 +255,7 @@ def run(G: RefGrid, z, theta, alpha_p, p: RefParams, r: RefRain, h, v1, v2, t_en
     z, th, ap = (_f64(x, G.n) for x in (z, _theta_masked(G, theta), alpha_p))
     h, v1, v2 = (_f64(x, G.n).copy() for x in (h, v1, v2))
     if books is None:
-        books = books_init(G, th, h, t0)
+        books = books_init(G, theta, h, t0)
     cap = int(min(max_steps, 10 ** 7))
     dlog = np.zeros(cap) if log_dt else None
     rc = lib().ref_run(G.n, _i(G.nbr), _u(G.code), G.a, _d(z), _d(th), _d(ap), C.byref(p),

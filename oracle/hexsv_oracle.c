@@ -98,6 +98,9 @@ int ref_tables(int32_t nq, int32_t nr, const int32_t side[4], int32_t nseg,
                     int64_t j = (int64_t)rn * nq + qn;
                     if (active && !active[j]) {
                         code[i * 6 + k] = (uint8_t)mask_code;
+                    } else if (active && active[j] == 2) {
+                        code[i * 6 + k] = REF_DIRICHLET;
+                        nbr[i * 6 + k] = (int32_t)j;
                     } else {
                         code[i * 6 + k] = REF_INTERIOR;
                         nbr[i * 6 + k] = (int32_t)j;
@@ -147,13 +150,14 @@ void ref_cell_sums(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
         int c = code[(int64_t)i * 6 + k];
         if (c == REF_WALL) continue; /* impermeable wall: no flux, no pressure term */
         double hj, v1j, v2j, zj, thj;
-        if (c == REF_INTERIOR) {
+        if (c == REF_INTERIOR || c == REF_DIRICHLET) {
             int32_t j = nbr[(int64_t)i * 6 + k];
             hj = h[j];
             v1j = v1[j];
             v2j = v2[j];
             zj = z[j];
-            thj = theta[j];
+            /* a Dirichlet cell carries its porosity negated (it is not updated) */
+            thj = c == REF_DIRICHLET ? -theta[j] : theta[j];
         } else { /* OUTFLOW: zero-gradient ghost, terrain extrapolated linearly */
             int ko = (k + 3) % 6;
             hj = h[i];
@@ -169,9 +173,10 @@ void ref_cell_sums(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
         ref_normal(k, n);
         double mj = thj * hj;
         double wj = g * (zj + hj);
-        /* eq. fvm_2D_eq.04: interface velocity and its normal component */
-        double vb1 = (v1[i] + v1j) * 0.5;
-        double vb2 = (v2[i] + v2j) * 0.5;
+        /* eq. fvm_2D_eq.04: interface velocity and its normal component; on an edge
+         * to a Dirichlet cell the edge carries the prescribed velocity itself */
+        double vb1 = c == REF_DIRICHLET ? v1j : (v1[i] + v1j) * 0.5;
+        double vb2 = c == REF_DIRICHLET ? v2j : (v2[i] + v2j) * 0.5;
         double vn = vb1 * n[0] + vb2 * n[1];
         /* eq. fvm_2D_eq.06: upwind theta*h */
         double mup;
@@ -191,7 +196,7 @@ void ref_cell_sums(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
         double P = 0.5 * l * (wj - wi) * mhat;
         S1 -= P * n[0];
         S2 -= P * n[1];
-        if (c == REF_OUTFLOW) Fout += F;
+        if (c == REF_OUTFLOW || c == REF_DIRICHLET) Fout += F;
     }
     out[0] = L;
     out[1] = J1;
@@ -228,11 +233,15 @@ void ref_visc_sums(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
  * lies in (0,1] (eq. eq_theta, and theta*h must determine h). */
 static int is_active_cell(const double *theta, int64_t i) { return theta[i] > 0.0; }
 
+/* The wave speeds of eq. .12 run over the updated cells and the Dirichlet cells
+ * (theta < 0): a prescribed state enters its neighbours' fluxes as well. */
+static int enters_cfl(const double *theta, int64_t i) { return theta[i] != 0.0; }
+
 double ref_cmax(int32_t N, const double *theta, double g, const double *h,
                 const double *v1, const double *v2) {
     double cmax = 0.0;
     for (int32_t i = 0; i < N; ++i) {
-        if (!is_active_cell(theta, i)) continue;
+        if (!enters_cfl(theta, i)) continue;
         double c = sqrt(v1[i] * v1[i] + v2[i] * v2[i]) + sqrt(g * h[i]);
         if (c > cmax) cmax = c;
     }
@@ -368,10 +377,10 @@ int64_t ref_run(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
     int64_t taken = 0;
     int64_t status = 0;
     while (taken < max_steps) {
-        /* eqs. fvm_2D_eq_frac.12-13 over the active cells */
+        /* eqs. fvm_2D_eq_frac.12-13 over the updated and the Dirichlet cells */
         double cmax = 0.0;
         for (int32_t i = 0; i < N; ++i) {
-            if (!is_active_cell(theta, i)) continue;
+            if (!enters_cfl(theta, i)) continue;
             double c = sqrt(v1[i] * v1[i] + v2[i] * v2[i]) + sqrt(p->g * h[i]);
             if (c > cmax) cmax = c;
         }
@@ -418,7 +427,8 @@ int64_t ref_run(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
         b->steps += 1;
         if (dt < b->dt_min) b->dt_min = dt;
         if (dt > b->dt_max_seen) b->dt_max_seen = dt;
-        double ref = b->initial + b->rain;
+        /* water supplied: initial, rain and any net inflow (Dirichlet edges) */
+        double ref = b->initial + b->rain + (b->outflow < 0.0 ? -b->outflow : 0.0);
         if (ref < 1e-300) ref = 1e-300;
         b->residual = fabs(S - (b->initial + b->rain - b->outflow + b->clamp)) / ref;
         if (dt_log) dt_log[taken] = dt;

@@ -86,15 +86,24 @@ extern "C" int hexsv_grid_create(const hexsv_grid_desc *desc, hexsv_grid **out) 
     gr->edge = desc->edge;
     gr->n = n;
     gr->n_active = n;
+    gr->n_dirichlet = 0;
     gr->d_active = nullptr;
     if (desc->active) {
-        int64_t na = 0;
-        for (int64_t i = 0; i < n; ++i) na += desc->active[i] != 0;
+        int64_t na = 0, nd = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const uint8_t v = desc->active[i];
+            if (v > 2) {
+                delete gr;
+                return fail(HEXSV_EINVAL, "grid_create: active[%lld]=%d is not 0, 1 or 2", (long long)i, v);
+            }
+            na += v == 1;
+            nd += v == 2;
+        }
         gr->n_active = na;
+        gr->n_dirichlet = nd;
         if (na < n) {
             gr->kg.has_mask = 1;
-            std::vector<uint8_t> a01(n);
-            for (int64_t i = 0; i < n; ++i) a01[i] = desc->active[i] != 0;
+            std::vector<uint8_t> a01(desc->active, desc->active + n);
             hipError_t e = hipMalloc(&gr->d_active, n);
             if (e != hipSuccess) {
                 delete gr;
@@ -270,6 +279,7 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->kc.h_dry = p.h_dry;
     s->kc.alpha_s = 0.0;
     s->kc.tau_lin = 0.0;
+    s->kc.c_floor = 0.0;
     s->kc.visc = 0;
     s->kc.area_active = s->kc.sigma * (double)grid->n_active;
     s->rn.kind = 0;
@@ -280,12 +290,12 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     hipError_t e = hipMalloc(&s->buf, s->esz * 9 * (size_t)grid->n);
     if (e == hipSuccess) e = hipMalloc(&s->d_ctl, 2 * sizeof(Ctl));  // two control slots
     if (e == hipSuccess) e = hipMalloc(&s->d_part, sizeof(Part) * PRIME_BLOCKS);
-    if (e == hipSuccess) e = hipMalloc(&s->d_chk, 4 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&s->d_chk, 8 * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&s->d_acc, ACC_BYTES);
     if (e == hipSuccess) e = hipMalloc(&s->d_slots, sizeof(Part) * s->ring_len);
     if (e == hipSuccess) e = hipMemset(s->d_acc, 0, ACC_BYTES);
     if (e == hipSuccess) e = hipHostMalloc(&s->h_ctl, sizeof(Ctl), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc(&s->h_chk, 4 * sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_chk, 8 * sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         hexsv_sim_destroy(s);
@@ -328,19 +338,22 @@ extern "C" int hexsv_sim_info(const hexsv_sim *s, int32_t *workgroups, int32_t *
     return hexsv_tile_shape(s->tile, tq, tr, threads);
 }
 
-// Run a device check; returns the count of offending cells (chk[0]).
+// Run a device check; returns the count of offending cells (chk[0]) and, for a
+// state check, the largest wave speed of the Dirichlet cells (c_dirichlet, nullable).
 static int run_check(hexsv_sim *s, hipStream_t stream, bool fields, const double *a, const double *b,
-                     const double *c, int32_t *count, int32_t *first, int32_t *reason) {
-    const int32_t init[4] = {0, 0x7fffffff, 0, 0};
+                     const double *c, int32_t *count, int32_t *first, int32_t *reason,
+                     double *c_dirichlet = nullptr) {
+    const int32_t init[8] = {0, 0x7fffffff, 0, 0, 0, 0, 0, 0};
     memcpy(s->h_chk, init, sizeof init);
     HIP_TRY(hipMemcpyAsync(s->d_chk, s->h_chk, sizeof init, hipMemcpyHostToDevice, stream));
     if (fields) HIP_TRY(launch_check_fields(a, b, c, s->grid->d_active, s->grid->n, s->d_chk, stream));
-    else HIP_TRY(launch_check_state(a, b, c, s->grid->d_active, s->grid->n, s->d_chk, stream));
+    else HIP_TRY(launch_check_state(a, b, c, s->grid->d_active, s->grid->n, s->kc.g, s->d_chk, stream));
     HIP_TRY(hipMemcpyAsync(s->h_chk, s->d_chk, sizeof init, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     *count = s->h_chk[0];
     *first = s->h_chk[1];
     *reason = s->h_chk[2];
+    if (c_dirichlet) memcpy(c_dirichlet, s->h_chk + 4, sizeof(double));
     return HEXSV_OK;
 }
 
@@ -361,12 +374,12 @@ extern "C" int hexsv_sim_set_fields(hexsv_sim *s, const double *d_z, const doubl
     if (s->prec == HEXSV_FP64) {
         KDom<double> d = dom_of<double>(s);
         HIP_TRY(launch_import<double>(d_z, (double *)d.z, act, 0, n, stream));
-        HIP_TRY(launch_import<double>(d_theta, (double *)d.th, act, 1, n, stream));
+        HIP_TRY(launch_import<double>(d_theta, (double *)d.th, act, 2, n, stream));
         HIP_TRY(launch_import<double>(d_alpha_p, (double *)d.ap, act, 0, n, stream));
     } else {
         KDom<float> d = dom_of<float>(s);
         HIP_TRY(launch_import<float>(d_z, (float *)d.z, act, 0, n, stream));
-        HIP_TRY(launch_import<float>(d_theta, (float *)d.th, act, 1, n, stream));
+        HIP_TRY(launch_import<float>(d_theta, (float *)d.th, act, 2, n, stream));
         HIP_TRY(launch_import<float>(d_alpha_p, (float *)d.ap, act, 0, n, stream));
     }
     s->kc.alpha_s = alpha_s;
@@ -424,11 +437,17 @@ extern "C" int hexsv_sim_set_state(hexsv_sim *s, double t0, const double *d_h, c
     if (!s->fields_set) return fail(HEXSV_ESTATE, "set_state: call set_fields first");
     if (!isfinite(t0)) return fail(HEXSV_EDOMAIN, "set_state: t0 must be finite");
     int32_t cnt, first, why;
-    int rc = run_check(s, stream, false, d_h, d_v1, d_v2, &cnt, &first, &why);
+    double c_dirichlet = 0.0;
+    int rc = run_check(s, stream, false, d_h, d_v1, d_v2, &cnt, &first, &why, &c_dirichlet);
     if (rc) return rc;
     if (cnt)
         return fail(HEXSV_EDOMAIN, "set_state: %d active cells invalid; first cell %d (%s%s)", cnt,
                     first, (why & 1) ? "h < 0 or not finite " : "", (why & 2) ? "v not finite" : "");
+    if (c_dirichlet != s->kc.c_floor) {  // captured launches hold the old value
+        s->kc.c_floor = c_dirichlet;
+        drop_graph(s);
+        drop_win_graph(s);
+    }
     const int64_t n = s->grid->n;
     const uint8_t *act = s->grid->d_active;
     for (int p = 0; p < 2; ++p) {
@@ -732,7 +751,8 @@ extern "C" int hexsv_sim_get_books(hexsv_sim *s, hexsv_books *out, hipStream_t s
     out->rain = c.rain;
     out->outflow = c.outflow;
     out->clamp = c.clamp;
-    double ref = c.initial + c.rain;
+    // water supplied: initial, rain and any net inflow through Dirichlet edges
+    double ref = c.initial + c.rain + (c.outflow < 0.0 ? -c.outflow : 0.0);
     if (ref < 1e-300) ref = 1e-300;
     out->residual = fabs(c.stored - (c.initial + c.rain - c.outflow + c.clamp)) / ref;
     out->steps = c.steps;
@@ -829,6 +849,8 @@ extern "C" int hexsv_sim_surrogate_features(hexsv_sim *s, hexsv_surrogate *sur, 
     if (!s || !sur || !d_features || !(window > 0.0) || !isfinite(window) || k < 1)
         return fail(HEXSV_EINVAL, "surrogate_features: bad argument");
     if (!s->state_set) return fail(HEXSV_ESTATE, "surrogate_features: call set_state first");
+    if (s->grid->n_dirichlet)
+        return fail(HEXSV_EUNSUPPORTED, "surrogate_features: windows are not built for Dirichlet cells");
     return s->prec == HEXSV_FP64 ? window_features<double>(s, sur, window, k, d_features, stream)
                                  : window_features<float>(s, sur, window, k, d_features, stream);
 }
@@ -993,6 +1015,8 @@ extern "C" int hexsv_sim_run_surrogate(hexsv_sim *s, hexsv_surrogate *sur, doubl
     if (!s->state_set) return fail(HEXSV_ESTATE, "run_surrogate: call set_state first");
     if (s->kc.visc)
         return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for the viscous flux");
+    if (s->grid->n_dirichlet)
+        return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for Dirichlet cells");
     int64_t a = 0, f = 0;
     const int rc =
         s->prec == HEXSV_FP64

@@ -86,8 +86,9 @@ __global__ __launch_bounds__(1024) void k_prime_finalize(Ctl *ctl, const Part *p
                                                          KConst kc, int reset_books) {
     const Part p = reduce_parts<1024>(part, nparts);
     if (threadIdx.x == 0) {
-        ctl->last_cmax = p.cmax;
-        ctl->tau = p.cmax > 0.0 ? kc.cfl_phi / p.cmax : INFINITY;
+        const double cm = p.cmax > kc.c_floor ? p.cmax : kc.c_floor;  // Dirichlet cells too
+        ctl->last_cmax = cm;
+        ctl->tau = cm > 0.0 ? kc.cfl_phi / cm : INFINITY;
         ctl->stored = p.stored;
         if (reset_books) {
             ctl->initial = p.stored;
@@ -111,7 +112,8 @@ hipError_t launch_prime_finalize(Ctl *ctl, const Part *part, int nparts, const K
 }
 
 // chk[0] = number of offending active cells, chk[1] = lowest offending index,
-// chk[2] = reason of that cell (bit mask).
+// chk[2] = reason of that cell (bit mask); chk[4..5] (8-byte aligned) = bits of the
+// largest |v| + sqrt(g h) over valid Dirichlet cells (state check only).
 __device__ inline void flag_bad(int32_t *chk, int64_t i, int reason) {
     atomicAdd(&chk[0], 1);
     atomicMin(&chk[1], (int32_t)i);
@@ -132,14 +134,20 @@ __global__ void k_check_fields(const double *z, const double *th, const double *
 }
 
 __global__ void k_check_state(const double *h, const double *v1, const double *v2,
-                              const uint8_t *active, int64_t n, int32_t *chk) {
+                              const uint8_t *active, int64_t n, double g, int32_t *chk) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (active && !active[i]) continue;
         int reason = 0;
         if (!(h[i] >= 0.0) || !__builtin_isfinite(h[i])) reason |= 1;
         if (!__builtin_isfinite(v1[i]) || !__builtin_isfinite(v2[i])) reason |= 2;
-        if (reason) flag_bad(chk, i, reason);
+        if (reason) {
+            flag_bad(chk, i, reason);
+        } else if (active && active[i] == 2) {
+            // non-negative doubles order like their bit patterns
+            const double c = __builtin_sqrt(v1[i] * v1[i] + v2[i] * v2[i]) + __builtin_sqrt(g * h[i]);
+            atomicMax((unsigned long long *)(chk + 4), (unsigned long long)__double_as_longlong(c));
+        }
     }
 }
 
@@ -157,10 +165,10 @@ hipError_t launch_check_fields(const double *z, const double *th, const double *
 }
 
 hipError_t launch_check_state(const double *h, const double *v1, const double *v2,
-                              const uint8_t *active, int64_t n, int32_t *chk,
+                              const uint8_t *active, int64_t n, double g, int32_t *chk,
                               hipStream_t stream) {
     hipLaunchKernelGGL(k_check_state, dim3(grid_blocks(n)), dim3(256), 0, stream, h, v1, v2,
-                       active, n, chk);
+                       active, n, g, chk);
     return hipGetLastError();
 }
 
@@ -180,12 +188,9 @@ __global__ void k_tables(KGrid g, const uint8_t *active, int32_t *nbr, uint8_t *
                 cd = CODE_WALL;
             } else if (wrap_pos(g, qn, rn)) {
                 const int64_t jj = (int64_t)rn * g.nq + qn;
-                if (active && !active[jj]) {
-                    cd = g.mask_bc;
-                } else {
-                    cd = CODE_INTERIOR;
-                    j = (int32_t)jj;
-                }
+                const int aj = active ? (int)active[jj] : 1;
+                cd = aj == 0 ? g.mask_bc : (aj == 2 ? (int)CODE_DIRICHLET : (int)CODE_INTERIOR);
+                j = aj == 0 ? -1 : (int32_t)jj;
             } else {
                 cd = side_code(g, qn, rn);
             }

@@ -20,7 +20,10 @@
 
 namespace hexsv {
 
-enum { CODE_INTERIOR = 0, CODE_WALL = 1, CODE_OUTFLOW = 2, CODE_PERIODIC = 3 };
+// CODE_DIRICHLET: the neighbour is a cell held at a prescribed state (inflow of
+// Sec. 3.2.1, eq. numerics-bc); it is read like a cell, the edge carries its velocity
+// and the flux across is booked with the outflow.
+enum { CODE_INTERIOR = 0, CODE_WALL = 1, CODE_OUTFLOW = 2, CODE_PERIODIC = 3, CODE_DIRICHLET = 4 };
 enum { SIDE_S = 0, SIDE_E = 1, SIDE_N = 2, SIDE_W = 3 };
 
 constexpr int MAX_SEG = 8;
@@ -96,6 +99,7 @@ struct KConst {
     double g, a, sigma, cfl_phi, h_dry, alpha_s;
     double area_active;  // sigma * number of active cells
     double tau_lin;      // linear soil resistance -tau h v (Thacker test), 1/s; 0: off
+    double c_floor;      // largest |v| + sqrt(g h) of the Dirichlet cells (fixed), 0 if none
     int32_t visc;        // 1: augmented momentum flux with artificial viscosity
 };
 
@@ -281,7 +285,9 @@ __device__ inline OpenStep open_step(const Ctl *ctl, int in, const unsigned long
     o.open = c->open;
     o.cmax = 0.0;
     if (o.closed) {
-        o.cmax = prev_max;
+        // c_max of eq. .12 over the updated cells and the Dirichlet cells, whose
+        // prescribed states enter the fluxes of their neighbours as well
+        o.cmax = prev_max > kc.c_floor ? prev_max : kc.c_floor;
         o.t = c->p_tnext;
         o.tau = o.cmax > 0.0 ? kc.cfl_phi / o.cmax : __builtin_inf();
         o.steps += 1;

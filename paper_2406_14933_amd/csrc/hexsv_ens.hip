@@ -147,6 +147,8 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         if (!grids[s]) return fail(HEXSV_EINVAL, "ensemble_create: grid %d is null", s);
         if ((uint64_t)grids[s]->n * (p.precision == HEXSV_FP64 ? 8u : 4u) >= (1ull << 32))
             return fail(HEXSV_EUNSUPPORTED, "ensemble_create: scenario %d exceeds 4 GiB per field", s);
+        if (grids[s]->n_dirichlet)
+            return fail(HEXSV_EUNSUPPORTED, "ensemble_create: scenario %d has Dirichlet cells", s);
     }
     hexsv_ensemble *e = new (std::nothrow) hexsv_ensemble();
     if (!e) return fail(HEXSV_ENOMEM, "ensemble_create: out of host memory");
@@ -210,7 +212,7 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
     if (err == hipSuccess) err = hipMalloc(&e->d_scen, sizeof(EnsScen) * n);
     if (err == hipSuccess) err = hipMalloc(&e->d_ctl, sizeof(Ctl) * n);
     if (err == hipSuccess) err = hipMalloc(&e->d_part, sizeof(Part) * PRIME_BLOCKS);
-    if (err == hipSuccess) err = hipMalloc(&e->d_chk, 4 * sizeof(int32_t));
+    if (err == hipSuccess) err = hipMalloc(&e->d_chk, 8 * sizeof(int32_t));
     if (err == hipSuccess) err = hipMalloc(&e->d_order, sizeof(int32_t) * n);
     if (err == hipSuccess) err = hipMalloc(&e->d_queue, sizeof(uint32_t));
     // records for the batched tile variant with the most tiles
@@ -227,7 +229,7 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
     if (err == hipSuccess) err = hipMalloc(&e->d_bpart, sizeof(Part) * (size_t)maxtiles);
     if (err == hipSuccess) err = hipMalloc(&e->d_tile_scen, sizeof(int32_t) * (size_t)maxtiles);
     if (err == hipSuccess) err = hipHostMalloc(&e->h_ctl, sizeof(Ctl) * n, hipHostMallocDefault);
-    if (err == hipSuccess) err = hipHostMalloc(&e->h_chk, 4 * sizeof(int32_t), hipHostMallocDefault);
+    if (err == hipSuccess) err = hipHostMalloc(&e->h_chk, 8 * sizeof(int32_t), hipHostMallocDefault);
     if (err == hipSuccess) err = hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking);
     if (err == hipSuccess) err = hipMemcpy(e->d_scen, e->scen.data(), sizeof(EnsScen) * n, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(e->d_order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
@@ -245,12 +247,12 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
 
 static int ens_check(hexsv_ensemble *e, int s, bool fields, const double *a, const double *b,
                      const double *c, hipStream_t stream, int32_t *cnt, int32_t *first, int32_t *why) {
-    const int32_t init[4] = {0, 0x7fffffff, 0, 0};
+    const int32_t init[8] = {0, 0x7fffffff, 0, 0, 0, 0, 0, 0};
     memcpy(e->h_chk, init, sizeof init);
     HIP_TRY(hipMemcpyAsync(e->d_chk, e->h_chk, sizeof init, hipMemcpyHostToDevice, stream));
     const hexsv_grid *g = e->grids[s];
     if (fields) HIP_TRY(launch_check_fields(a, b, c, g->d_active, g->n, e->d_chk, stream));
-    else HIP_TRY(launch_check_state(a, b, c, g->d_active, g->n, e->d_chk, stream));
+    else HIP_TRY(launch_check_state(a, b, c, g->d_active, g->n, e->scen[s].kc.g, e->d_chk, stream));
     HIP_TRY(hipMemcpyAsync(e->h_chk, e->d_chk, sizeof init, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     *cnt = e->h_chk[0];
@@ -431,7 +433,8 @@ extern "C" int hexsv_ensemble_get_books(hexsv_ensemble *e, int32_t s, hexsv_book
     out->rain = c.rain;
     out->outflow = c.outflow;
     out->clamp = c.clamp;
-    double ref = c.initial + c.rain;
+    // water supplied: initial, rain and any net inflow through Dirichlet edges
+    double ref = c.initial + c.rain + (c.outflow < 0.0 ? -c.outflow : 0.0);
     if (ref < 1e-300) ref = 1e-300;
     out->residual = fabs(c.stored - (c.initial + c.rain - c.outflow + c.clamp)) / ref;
     out->steps = c.steps;

@@ -95,7 +95,8 @@ hipError_t launch_check_fields(const double *z, const double *th, const double *
                                const uint8_t *active, int64_t n, int32_t *chk,
                                hipStream_t stream);
 hipError_t launch_check_state(const double *h, const double *v1, const double *v2,
-                              const uint8_t *active, int64_t n, int32_t *chk, hipStream_t stream);
+                              const uint8_t *active, int64_t n, double g, int32_t *chk,
+                              hipStream_t stream);
 
 // ------------------------------------------------------ surrogate windows
 //

@@ -139,13 +139,17 @@ hipError_t launch_prime(const KDom<T> &d, int64_t n, const KConst &kc, Ctl *ctl,
     return launch_prime_finalize(ctl, part, nblocks, kc, reset_books, stream);
 }
 
+// zero_inactive: 0 copies, 1 writes zero outside the domain, 2 also negates the
+// value on Dirichlet cells (theta: the step kernel tells such a cell by theta < 0).
 template <typename T>
 __global__ void k_import(const double *src, T *dst, const uint8_t *active, int zero_inactive,
                          int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const bool act = active ? active[i] != 0 : true;
-        dst[i] = (zero_inactive && !act) ? T(0) : (T)src[i];
+        const uint8_t a = active ? active[i] : (uint8_t)1;
+        T v = (zero_inactive && a == 0) ? T(0) : (T)src[i];
+        if (zero_inactive == 2 && a == 2) v = -v;
+        dst[i] = v;
     }
 }
 
@@ -166,7 +170,7 @@ __global__ void k_export(KDom<T> d, int par, int64_t n, double *h, double *v1, d
         const double hh = (double)d.buf(par, 0)[i];
         const double a = (double)d.buf(par, 1)[i];
         const double b = (double)d.buf(par, 2)[i];
-        const double th = (double)d.th[i];
+        const double th = __builtin_fabs((double)d.th[i]);  // Dirichlet cells hold -theta
         if (h) h[i] = hh;
         if (v1) v1[i] = a;
         if (v2) v2[i] = b;

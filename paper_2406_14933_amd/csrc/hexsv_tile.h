@@ -175,14 +175,17 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
         const int lr = cc / TQ, lq = cc - lr * TQ;
         const int s = (lr + 1) * W + (lq + 1);
         if (R.pos[k] != POS_OUTSIDE) {
-            const T m = R.th[k] * R.h[k];
+            // a Dirichlet cell holds -theta: its record carries |theta| h
+            const T m = __builtin_fabs(R.th[k]) * R.h[k];
             L.rec[s] = make_rec<T>(mscale * m, G * (R.z[k] + R.h[k]), R.v1[k] * T(0.5),
                                    R.v2[k] * T(0.5));
             if constexpr (V)
                 L.c[s] = p_sqrt(R.v1[k] * R.v1[k] + R.v2[k] * R.v2[k]) + p_sqrt(G * R.h[k]);
             const bool act = R.th[k] > T(0);
             bad |= !act;
-            if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
+            if (need_codes)
+                L.code[s] = act ? (uint8_t)CODE_INTERIOR
+                                : (R.th[k] < T(0) ? (uint8_t)CODE_DIRICHLET : (uint8_t)g.mask_bc);
         } else {
             int q = q0 + lq, r = r0 + lr;
             wrap_pos(g, q, r);
@@ -199,14 +202,16 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
         ring_slot<TQ, TR>(t, lq, lr);
         const int s = lr * W + lq;
         if (R.rpos[k] != POS_OUTSIDE) {
-            const T m = R.rth[k] * R.rh[k];
+            const T m = __builtin_fabs(R.rth[k]) * R.rh[k];
             L.rec[s] = make_rec<T>(mscale * m, G * (R.rz[k] + R.rh[k]), R.rv1[k] * T(0.5),
                                    R.rv2[k] * T(0.5));
             if constexpr (V)
                 L.c[s] = p_sqrt(R.rv1[k] * R.rv1[k] + R.rv2[k] * R.rv2[k]) + p_sqrt(G * R.rh[k]);
             const bool act = R.rth[k] > T(0);
             bad |= !act;
-            if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
+            if (need_codes)
+                L.code[s] = act ? (uint8_t)CODE_INTERIOR
+                                : (R.rth[k] < T(0) ? (uint8_t)CODE_DIRICHLET : (uint8_t)g.mask_bc);
         } else {
             int q = q0 + lq - 1, r = r0 + lr - 1;
             wrap_pos(g, q, r);
@@ -277,7 +282,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 cd = L.code[sn];
                 if (cd == CODE_WALL) continue;
             }
-            if (!GEN || cd == CODE_INTERIOR) {
+            if (!GEN || cd != CODE_OUTFLOW) {  // a cell: interior or Dirichlet
                 const typename Rec<T>::type nb = L.rec[sn];
                 mj = nb.x;
                 wj = nb.y;
@@ -297,8 +302,13 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 vh1j = vh1i;
                 vh2j = vh2i;
             }
-            const T vb1 = vh1i + vh1j;
-            const T vb2 = vh2i + vh2j;
+            // interface velocity; an edge to a Dirichlet cell carries the prescribed one
+            T vb1 = vh1i + vh1j;
+            T vb2 = vh2i + vh2j;
+            if (GEN && cd == CODE_DIRICHLET) {
+                vb1 = vh1j + vh1j;
+                vb2 = vh2j + vh2j;
+            }
             if constexpr (F32) {
                 // mj holds l*theta_j*h_j
                 const T vn = (e == 0) ? vb1 : ((e == 3) ? -vb1 : vb1 * NX[e] + vb2 * NY[e]);
@@ -315,7 +325,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 const T Q = dw * msel;
                 A1 -= Q * NXh[e];
                 if (e != 0 && e != 3) A2 -= Q * NYh[e];
-                if (GEN && cd == CODE_OUTFLOW) Fout += F;
+                if (GEN && cd != CODE_INTERIOR) Fout += F;  // outflow or Dirichlet edge
             } else {
                 const T vn = vb1 * NX[e] + vb2 * NY[e];
                 const T mup = vn > T(0) ? mi : (vn < T(0) ? mj : T(0));
@@ -327,7 +337,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 const T P = half_l * (wj - wi) * mhat;
                 S1 -= P * NX[e];
                 S2 -= P * NY[e];
-                if (GEN && cd == CODE_OUTFLOW) Fout += F;
+                if (GEN && cd != CODE_INTERIOR) Fout += F;  // outflow or Dirichlet edge
             }
             if constexpr (V) {
                 // artificial viscosity l c_ij mu_ij (v_j - v_i) of an interior edge (an

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "lib", "libhexsv.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ENUMERIC, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
-INTERIOR, WALL, OUTFLOW, PERIODIC = 0, 1, 2, 3
+INTERIOR, WALL, OUTFLOW, PERIODIC, DIRICHLET = 0, 1, 2, 3, 4
 S, E, N, W = 0, 1, 2, 3
 MAX_SEGMENTS = 8
 
@@ -195,7 +195,11 @@ class Grid:
             d.seg[k] = Segment(int(s_), int(lo), int(hi), int(code))
         self._active = None
         if active is not None:
-            self._active = np.ascontiguousarray(np.asarray(active).reshape(-1) != 0, dtype=np.uint8)
+            # per cell: 0 outside the domain, 1 updated, 2 Dirichlet (held at its state)
+            a = np.asarray(active).reshape(-1)
+            if a.dtype != bool and a.size and (a.min() < 0 or a.max() > 2):
+                raise ValueError("active holds values other than 0, 1, 2")
+            self._active = np.ascontiguousarray(a, dtype=np.uint8)
             d.active = self._active.ctypes.data_as(C.POINTER(C.c_uint8))
         d.mask_bc = int(mask_bc)
         h = C.c_void_p()

@@ -373,6 +373,46 @@ def riemann(n_section=1122, length=18.0, width=1.0, x_jump=9.0, t_end=1.5,
         meta={"ox": ox, "oy": oy, "x_jump": x_jump, "left": left, "right": right})
 
 
+def radial(kind="crater", a=0.5, r0=10.0, r1=100.0, A=10.0, h0=0.05, v0=1.0, t_end=40.0,
+           cfl=0.5, h_dry=1e-5):
+    """Flow on a radially symmetric surface (Sec. 3.2.1): an annulus r0 <= r <= r1 with bed
+    z = A + s A cos(pi (r - r0) / (r1 - r0)), s = -1 for the crater (its rim r1 is the top)
+    and +1 for the hillock (its inner edge r0 is the top).  Water enters through the top
+    edge with depth h0 and speed v0 along -n (n the domain's outward normal there) and
+    leaves freely through the bottom edge.  The inflow is a ring of Dirichlet cells (active
+    code 2) one cell thick just outside the top edge, holding that state; the bottom edge's
+    masked neighbours are OUTFLOW.  theta = 1, no friction (the paper gives no coefficients
+    for this test), no rain; the annulus starts dry."""
+    s = -1.0 if kind == "crater" else 1.0
+    R = r1 + 3.0 * a
+    nr = int(math.ceil(2.0 * R / (1.5 * a))) + 1
+    shift = a * math.sqrt(3.0) * 0.5 * (nr - 1)
+    nq = int(math.ceil((2.0 * R + shift) / (a * math.sqrt(3.0)))) + 1
+    x, y = centres(nq, nr, a)
+    x = x - R - shift
+    y = y - R
+    rr = np.hypot(x, y)
+    ring = a * math.sqrt(3.0)
+    act = ((rr >= r0) & (rr <= r1)).astype(np.uint8)
+    if kind == "crater":
+        inflow, rin = (rr > r1) & (rr <= r1 + ring), r1
+    else:
+        inflow, rin = (rr < r0) & (rr >= r0 - ring), r0
+    act[inflow] = 2
+    z = A + s * A * np.cos(math.pi * (rr - r0) / (r1 - r0))
+    n = nq * nr
+    ux, uy = x / np.maximum(rr, 1e-12), y / np.maximum(rr, 1e-12)
+    vdir = -1.0 if kind == "crater" else 1.0  # -v0 n: inward at the rim, outward at r0
+    h = np.where(inflow, h0, 0.0)
+    return Scenario(
+        name=f"radial-{kind}-a{a:g}", nq=nq, nr=nr, a=a, z=z, theta=np.ones(n),
+        alpha_p=np.zeros(n), alpha_s=0.0, side=(WALL, WALL, WALL, WALL), active=act,
+        mask_code=OUTFLOW, h0=h, v10=np.where(inflow, vdir * v0 * ux, 0.0),
+        v20=np.where(inflow, vdir * v0 * uy, 0.0), t_end=t_end, cfl=cfl, h_dry=h_dry,
+        meta={"kind": kind, "r0": r0, "r1": r1, "A": A, "s": s, "h0": h0, "v0": v0,
+              "r_in": rin, "ox": -R - shift, "oy": -R, "g": G_ACCEL})
+
+
 def random_state(sc: Scenario, seed: int, depth=0.05, speed=0.3, dry_frac=0.2):
     """A rough wet/dry state on sc's raster (for one-step checks)."""
     rng = np.random.Generator(np.random.PCG64(seed))
