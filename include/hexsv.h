@@ -33,8 +33,17 @@
  *    it like a neighbour, but the interface velocity is the prescribed
  *    velocity itself rather than the mean of eq. fvm_2D_eq.04, so the inflow
  *    flux is l h_D (v_D . n); that flux enters the books as negative outflow.
- *    Viscous sums (set_viscosity) run over INTERIOR edges only.  Ensembles
- *    and surrogate windows refuse grids with Dirichlet cells.
+ *    Viscous sums (set_viscosity) run over INTERIOR edges only.
+ *  - Given-flux cells (active == 3; the given mass flux of Sec. 2.2's boundary
+ *    conditions, e.g. the flume inflow u h = q_L of Sec. 3.3.2): held like
+ *    Dirichlet cells, but what they prescribe is the discharge h v across the
+ *    edge (their theta is not used).  An edge into one (code FLUX) carries the
+ *    mass flux l h_F (v_F . n) and momentum flux l h_F (v_F . n) v_F, and its
+ *    pressure term sees the updated cell's own depth over the flux cell's bed:
+ *    0.5 l g (z_F + h_i - z_i - h_i) theta_i h_i.  The flux is booked with the
+ *    outflow.
+ *  - The wave speeds |v| + sqrt(g h) of Dirichlet and flux cells enter c_max
+ *    (eq. .12).  Surrogate windows refuse grids with either kind.
  *  - Every d_* pointer is caller-owned device memory (e.g. a torch tensor's
  *    data_ptr()), read or written only during the call (stream-ordered on
  *    `stream`); the library copies inputs into its own buffers and never frees
@@ -69,7 +78,8 @@ typedef enum { HEXSV_FP64 = 0, HEXSV_FP32 = 1 } hexsv_precision;
 
 /* edge codes and side kinds */
 enum { HEXSV_INTERIOR = 0, HEXSV_WALL = 1, HEXSV_OUTFLOW = 2, HEXSV_PERIODIC = 3,
-       HEXSV_DIRICHLET = 4 /* edge codes only: the neighbour is a Dirichlet cell */ };
+       HEXSV_DIRICHLET = 4, /* edge codes only: the neighbour is a Dirichlet cell */
+       HEXSV_FLUX = 5       /* edge codes only: the neighbour is a given-flux cell */ };
 /* sides */
 enum { HEXSV_S = 0, HEXSV_E = 1, HEXSV_N = 2, HEXSV_W = 3 };
 
@@ -90,7 +100,8 @@ typedef struct {
     int32_t nseg;            /* number of valid entries in seg (<= 8) */
     hexsv_segment seg[HEXSV_MAX_SEGMENTS];
     const uint8_t *active;   /* host, nq*nr, nullable (all 1): 0 = outside the domain,
-                                1 = in the domain, 2 = Dirichlet cell; other values EINVAL */
+                                1 = in the domain, 2 = Dirichlet cell, 3 = given-flux
+                                cell; other values EINVAL */
     int32_t mask_bc;         /* code of edges into inactive cells: WALL or OUTFLOW */
 } hexsv_grid_desc;
 
@@ -157,8 +168,8 @@ void hexsv_grid_destroy(hexsv_grid *grid);
 int hexsv_grid_counts(const hexsv_grid *grid, int64_t *cells, int64_t *active);
 
 /* Neighbour and edge-code tables computed on the device (one thread per cell):
- * d_nbr[i*6+k] = index of the neighbour across edge k for INTERIOR and
- * DIRICHLET edges, -1 otherwise; d_code[i*6+k] = edge code; cells outside the
+ * d_nbr[i*6+k] = index of the neighbour across edge k for INTERIOR, DIRICHLET
+ * and FLUX edges, -1 otherwise; d_code[i*6+k] = edge code; cells outside the
  * domain (active == 0) get six WALL codes.
  * Caller-allocated device arrays of nq*nr*6 int32 and uint8. */
 int hexsv_grid_tables(const hexsv_grid *grid, int32_t *d_nbr, uint8_t *d_code,
@@ -280,6 +291,13 @@ int hexsv_ensemble_set_scenario(hexsv_ensemble *ens, int32_t s, const double *d_
                                 const double *d_theta, const double *d_alpha_p, double alpha_s,
                                 const hexsv_rain *rain, double t0, const double *d_h,
                                 const double *d_v1, const double *d_v2, hipStream_t stream);
+
+/* The momentum flux with artificial viscosity (eqs. eq_artif_visc, eq_visc1;
+ * as hexsv_sim_set_viscosity) for every scenario: on = 1 or 0 (EINVAL
+ * otherwise).  It is built for the batched-step mode only: turning it on
+ * switches a persistent ensemble to batched steps, and the autotuner then
+ * times batched variants only. */
+int hexsv_ensemble_set_viscosity(hexsv_ensemble *ens, int32_t on);
 
 /* Advance every scenario s to t_end[s] (host array of n), or by at most
  * max_steps steps (<= 0: no limit).  Replays a captured graph of one

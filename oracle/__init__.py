@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhexsv_oracle.so")
 SRC_PATH = os.path.join(HERE, "hexsv_oracle.c")
 
-INTERIOR, WALL, OUTFLOW, PERIODIC, DIRICHLET = 0, 1, 2, 3, 4
+INTERIOR, WALL, OUTFLOW, PERIODIC, DIRICHLET, FLUX = 0, 1, 2, 3, 4, 5
 S, E, N, W = 0, 1, 2, 3
 DQ = (1, 0, -1, -1, 0, 1)
 DR = (0, 1, 1, 0, -1, -1)
@@ -142,6 +142,7 @@ class RefGrid:
     code: np.ndarray  # (N, 6) uint8
     active: np.ndarray  # (N,) bool: computational cells
     dirichlet: np.ndarray = None  # (N,) bool: boundary cells whose state is held fixed
+    flux: np.ndarray = None       # (N,) bool: boundary cells prescribing the discharge h v
 
     @property
     def n(self):
@@ -166,11 +167,11 @@ def tables(nq, nr, side=(WALL, WALL, WALL, WALL), segs=(), active=None, mask_cod
 def grid(nq, nr, a, side=(WALL, WALL, WALL, WALL), segs=(), active=None, mask_code=WALL):
     nbr, code = tables(nq, nr, side, segs, active, mask_code)
     if active is None:
-        act, dch = np.ones(nq * nr, bool), np.zeros(nq * nr, bool)
+        act, dch, flx = np.ones(nq * nr, bool), np.zeros(nq * nr, bool), np.zeros(nq * nr, bool)
     else:
         raw = np.asarray(active).reshape(-1)
-        act, dch = raw == 1, raw == 2
-    return RefGrid(nq, nr, float(a), nbr, code, act, dch)
+        act, dch, flx = raw == 1, raw == 2, raw == 3
+    return RefGrid(nq, nr, float(a), nbr, code, act, dch, flx)
 
 
 # ------------------------------------------------------------ small pieces
@@ -196,8 +197,10 @@ def rain(kind=0, i_a=0.0, t_a=0.0, T_d=float("inf")):
 def _theta_masked(G: RefGrid, theta):
     th = _f64(theta, G.n).copy()
     dch = G.dirichlet if G.dirichlet is not None else np.zeros(G.n, bool)
-    th[~(G.active | dch)] = 0.0
+    flx = G.flux if G.flux is not None else np.zeros(G.n, bool)
+    th[~(G.active | dch | flx)] = 0.0
     th[dch] = -th[dch]  # held fixed: not updated, not booked, read with |theta| by neighbours
+    th[flx] = -1.0      # held fixed, not booked; its edges read h, v and z only
     return th
 
 

@@ -101,6 +101,9 @@ int ref_tables(int32_t nq, int32_t nr, const int32_t side[4], int32_t nseg,
                     } else if (active && active[j] == 2) {
                         code[i * 6 + k] = REF_DIRICHLET;
                         nbr[i * 6 + k] = (int32_t)j;
+                    } else if (active && active[j] == 3) {
+                        code[i * 6 + k] = REF_FLUX;
+                        nbr[i * 6 + k] = (int32_t)j;
                     } else {
                         code[i * 6 + k] = REF_INTERIOR;
                         nbr[i * 6 + k] = (int32_t)j;
@@ -150,6 +153,24 @@ void ref_cell_sums(int32_t N, const int32_t *nbr, const uint8_t *code, double a,
         int c = code[(int64_t)i * 6 + k];
         if (c == REF_WALL) continue; /* impermeable wall: no flux, no pressure term */
         double hj, v1j, v2j, zj, thj;
+        if (c == REF_FLUX) {
+            /* given mass flux: the neighbour prescribes the discharge h_j v_j across the
+             * edge; the depth seen by the pressure term is the cell's own (zero gradient) */
+            int32_t j = nbr[(int64_t)i * 6 + k];
+            double n[2];
+            ref_normal(k, n);
+            double vn = v1[j] * n[0] + v2[j] * n[1];
+            double F = l * h[j] * vn;
+            L -= F;
+            J1 -= F * v1[j];
+            J2 -= F * v2[j];
+            double wg = g * (z[j] + h[i]);
+            double P = 0.5 * l * (wg - wi) * mi;
+            S1 -= P * n[0];
+            S2 -= P * n[1];
+            Fout += F;
+            continue;
+        }
         if (c == REF_INTERIOR || c == REF_DIRICHLET) {
             int32_t j = nbr[(int64_t)i * 6 + k];
             hj = h[j];

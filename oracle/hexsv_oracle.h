@@ -30,6 +30,8 @@ extern "C" {
 #define REF_PERIODIC 3 /* side kind only; a wrapped edge is INTERIOR */
 #define REF_DIRICHLET 4 /* edge to a boundary cell whose state is held fixed (Sec. 2.2,
                            boundary conditions: Dirichlet); its flux is booked as outflow */
+#define REF_FLUX 5      /* edge to a boundary cell prescribing the mass flux h v (given
+                           mass flux); its flux is booked as outflow */
 
 /* sides */
 #define REF_S 0 /* r < 0   */

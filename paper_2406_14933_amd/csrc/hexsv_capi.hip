@@ -92,12 +92,12 @@ extern "C" int hexsv_grid_create(const hexsv_grid_desc *desc, hexsv_grid **out) 
         int64_t na = 0, nd = 0;
         for (int64_t i = 0; i < n; ++i) {
             const uint8_t v = desc->active[i];
-            if (v > 2) {
+            if (v > 3) {
                 delete gr;
-                return fail(HEXSV_EINVAL, "grid_create: active[%lld]=%d is not 0, 1 or 2", (long long)i, v);
+                return fail(HEXSV_EINVAL, "grid_create: active[%lld]=%d is not 0, 1, 2 or 3", (long long)i, v);
             }
             na += v == 1;
-            nd += v == 2;
+            nd += v >= 2;
         }
         gr->n_active = na;
         gr->n_dirichlet = nd;

@@ -113,7 +113,7 @@ hipError_t launch_prime_finalize(Ctl *ctl, const Part *part, int nparts, const K
 
 // chk[0] = number of offending active cells, chk[1] = lowest offending index,
 // chk[2] = reason of that cell (bit mask); chk[4..5] (8-byte aligned) = bits of the
-// largest |v| + sqrt(g h) over valid Dirichlet cells (state check only).
+// largest |v| + sqrt(g h) over valid Dirichlet and flux cells (state check only).
 __device__ inline void flag_bad(int32_t *chk, int64_t i, int reason) {
     atomicAdd(&chk[0], 1);
     atomicMin(&chk[1], (int32_t)i);
@@ -143,7 +143,7 @@ __global__ void k_check_state(const double *h, const double *v1, const double *v
         if (!__builtin_isfinite(v1[i]) || !__builtin_isfinite(v2[i])) reason |= 2;
         if (reason) {
             flag_bad(chk, i, reason);
-        } else if (active && active[i] == 2) {
+        } else if (active && active[i] >= 2) {
             // non-negative doubles order like their bit patterns
             const double c = __builtin_sqrt(v1[i] * v1[i] + v2[i] * v2[i]) + __builtin_sqrt(g * h[i]);
             atomicMax((unsigned long long *)(chk + 4), (unsigned long long)__double_as_longlong(c));
@@ -189,7 +189,10 @@ __global__ void k_tables(KGrid g, const uint8_t *active, int32_t *nbr, uint8_t *
             } else if (wrap_pos(g, qn, rn)) {
                 const int64_t jj = (int64_t)rn * g.nq + qn;
                 const int aj = active ? (int)active[jj] : 1;
-                cd = aj == 0 ? g.mask_bc : (aj == 2 ? (int)CODE_DIRICHLET : (int)CODE_INTERIOR);
+                cd = aj == 0   ? g.mask_bc
+                     : aj == 2 ? (int)CODE_DIRICHLET
+                     : aj == 3 ? (int)CODE_FLUX
+                               : (int)CODE_INTERIOR;
                 j = aj == 0 ? -1 : (int32_t)jj;
             } else {
                 cd = side_code(g, qn, rn);
@@ -207,8 +210,10 @@ __global__ __launch_bounds__(1024) void k_ens_finalize(const EnsScen *scen, Ctl 
     const int s = blockIdx.x;
     const StepTime st = step_time(&ctl[s]);
     if (!st.live) return;
-    const Part p = reduce_parts<1024>(part + scen[s].bbase, scen[s].bntiles);
-    if (threadIdx.x == 0) close_step(&ctl[s], p, st, scen[s].kc, rain_rate(scen[s].rn, st.t_next));
+    Part p = reduce_parts<1024>(part + scen[s].bbase, scen[s].bntiles);
+    const KConst &kc = scen[s].kc;
+    if (p.cmax < kc.c_floor) p.cmax = kc.c_floor;  // the Dirichlet cells' wave speed
+    if (threadIdx.x == 0) close_step(&ctl[s], p, st, kc, rain_rate(scen[s].rn, st.t_next));
 }
 
 hipError_t launch_ens_finalize(const EnsScen *scen, Ctl *ctl, const Part *part, int nscen,

@@ -22,8 +22,13 @@ namespace hexsv {
 
 // CODE_DIRICHLET: the neighbour is a cell held at a prescribed state (inflow of
 // Sec. 3.2.1, eq. numerics-bc); it is read like a cell, the edge carries its velocity
-// and the flux across is booked with the outflow.
-enum { CODE_INTERIOR = 0, CODE_WALL = 1, CODE_OUTFLOW = 2, CODE_PERIODIC = 3, CODE_DIRICHLET = 4 };
+// and the flux across is booked with the outflow.  CODE_FLUX: the neighbour prescribes
+// the discharge h v across the edge (given mass flux); the pressure term sees the cell's
+// own depth over the neighbour's bed.  Both kinds hold theta negated (flux cells: -2).
+enum {
+    CODE_INTERIOR = 0, CODE_WALL = 1, CODE_OUTFLOW = 2, CODE_PERIODIC = 3, CODE_DIRICHLET = 4,
+    CODE_FLUX = 5
+};
 enum { SIDE_S = 0, SIDE_E = 1, SIDE_N = 2, SIDE_W = 3 };
 
 constexpr int MAX_SEG = 8;

@@ -21,6 +21,7 @@ struct hexsv_ensemble {
     size_t esz;
     int tile, ksteps, nwg;
     int mode;                   // HEXSV_ENS_PERSISTENT or HEXSV_ENS_BATCHED
+    int visc;                   // 1: artificial viscosity (batched mode only)
     int btile, btotal;          // batched mode: tile variant and total tiles
     int32_t *d_tile_scen;       // batched mode: scenario of every global tile
     Part *d_bpart;              // batched mode: one record per global tile
@@ -147,12 +148,11 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         if (!grids[s]) return fail(HEXSV_EINVAL, "ensemble_create: grid %d is null", s);
         if ((uint64_t)grids[s]->n * (p.precision == HEXSV_FP64 ? 8u : 4u) >= (1ull << 32))
             return fail(HEXSV_EUNSUPPORTED, "ensemble_create: scenario %d exceeds 4 GiB per field", s);
-        if (grids[s]->n_dirichlet)
-            return fail(HEXSV_EUNSUPPORTED, "ensemble_create: scenario %d has Dirichlet cells", s);
     }
     hexsv_ensemble *e = new (std::nothrow) hexsv_ensemble();
     if (!e) return fail(HEXSV_ENOMEM, "ensemble_create: out of host memory");
     e->n = n;
+    e->visc = 0;
     e->prec = p.precision;
     e->esz = p.precision == HEXSV_FP64 ? sizeof(double) : sizeof(float);
     e->tile = 0;
@@ -246,7 +246,8 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
 }
 
 static int ens_check(hexsv_ensemble *e, int s, bool fields, const double *a, const double *b,
-                     const double *c, hipStream_t stream, int32_t *cnt, int32_t *first, int32_t *why) {
+                     const double *c, hipStream_t stream, int32_t *cnt, int32_t *first, int32_t *why,
+                     double *c_dirichlet = nullptr) {
     const int32_t init[8] = {0, 0x7fffffff, 0, 0, 0, 0, 0, 0};
     memcpy(e->h_chk, init, sizeof init);
     HIP_TRY(hipMemcpyAsync(e->d_chk, e->h_chk, sizeof init, hipMemcpyHostToDevice, stream));
@@ -258,6 +259,7 @@ static int ens_check(hexsv_ensemble *e, int s, bool fields, const double *a, con
     *cnt = e->h_chk[0];
     *first = e->h_chk[1];
     *why = e->h_chk[2];
+    if (c_dirichlet) memcpy(c_dirichlet, e->h_chk + 4, sizeof(double));
     return HEXSV_OK;
 }
 
@@ -267,7 +269,7 @@ static int ens_import(hexsv_ensemble *e, int s, const double *z, const double *t
     const KDom<T> d = ens_dom<T>(e, s);
     const hexsv_grid *g = e->grids[s];
     HIP_TRY(launch_import<T>(z, (T *)d.z, g->d_active, 0, g->n, stream));
-    HIP_TRY(launch_import<T>(th, (T *)d.th, g->d_active, 1, g->n, stream));
+    HIP_TRY(launch_import<T>(th, (T *)d.th, g->d_active, 2, g->n, stream));
     HIP_TRY(launch_import<T>(ap, (T *)d.ap, g->d_active, 0, g->n, stream));
     for (int p = 0; p < 2; ++p) {
         HIP_TRY(launch_import<T>(h, d.st[p][0], g->d_active, 1, g->n, stream));
@@ -294,11 +296,13 @@ extern "C" int hexsv_ensemble_set_scenario(hexsv_ensemble *e, int32_t s, const d
     int rc = ens_check(e, s, true, d_z, d_theta, d_alpha_p, stream, &cnt, &first, &why);
     if (rc) return rc;
     if (cnt) return fail(HEXSV_EDOMAIN, "ensemble_set_scenario %d: %d invalid cells; first cell %d", s, cnt, first);
-    rc = ens_check(e, s, false, d_h, d_v1, d_v2, stream, &cnt, &first, &why);
+    double c_dirichlet = 0.0;
+    rc = ens_check(e, s, false, d_h, d_v1, d_v2, stream, &cnt, &first, &why, &c_dirichlet);
     if (rc) return rc;
     if (cnt) return fail(HEXSV_EDOMAIN, "ensemble_set_scenario %d: %d invalid state cells; first cell %d", s, cnt, first);
     EnsScen &sc = e->scen[s];
     sc.kc.alpha_s = alpha_s;
+    sc.kc.c_floor = c_dirichlet;  // read by the kernels from the device copy below
     sc.rn.kind = rain->kind;
     sc.rn.i_a = rain->i_a;
     sc.rn.t_a = rain->t_a;
@@ -331,10 +335,10 @@ static hipError_t ens_launch(hexsv_ensemble *e, int mode, int v, int ksteps, hip
     hipError_t err = hipSuccess;
     for (int k = 0; k < ksteps && err == hipSuccess; ++k)
         err = e->prec == HEXSV_FP64
-                  ? launch_ens_step<double>(v, ens_base<double>(e), e->d_scen, e->d_tile_scen,
-                                            e->d_ctl, e->d_bpart, e->btotal, e->n, st)
-                  : launch_ens_step<float>(v, ens_base<float>(e), e->d_scen, e->d_tile_scen,
-                                           e->d_ctl, e->d_bpart, e->btotal, e->n, st);
+                  ? launch_ens_step<double>(v, e->visc != 0, ens_base<double>(e), e->d_scen,
+                                            e->d_tile_scen, e->d_ctl, e->d_bpart, e->btotal, e->n, st)
+                  : launch_ens_step<float>(v, e->visc != 0, ens_base<float>(e), e->d_scen,
+                                           e->d_tile_scen, e->d_ctl, e->d_bpart, e->btotal, e->n, st);
     return err;
 }
 
@@ -443,6 +447,15 @@ extern "C" int hexsv_ensemble_get_books(hexsv_ensemble *e, int32_t s, hexsv_book
     return HEXSV_OK;
 }
 
+extern "C" int hexsv_ensemble_set_viscosity(hexsv_ensemble *e, int32_t on) {
+    if (!e) return fail(HEXSV_EINVAL, "ensemble_set_viscosity: null ensemble");
+    if (on != 0 && on != 1) return fail(HEXSV_EINVAL, "ensemble_set_viscosity: on must be 0 or 1");
+    e->visc = on;
+    if (on && e->mode == HEXSV_ENS_PERSISTENT) e->mode = HEXSV_ENS_BATCHED;
+    ens_drop_graph(e);
+    return HEXSV_OK;
+}
+
 extern "C" int hexsv_ensemble_timing(hexsv_ensemble *e, int32_t enable, double *gpu_ms,
                                      int64_t *cell_updates, int64_t *launches) {
     if (!e) return fail(HEXSV_EINVAL, "ensemble_timing: null ensemble");
@@ -486,6 +499,7 @@ extern "C" int hexsv_ensemble_autotune(hexsv_ensemble *e, int32_t ksteps, const 
     for (int c = 0; c < nvar && he == hipSuccess; ++c) {
         const int mode = c < NUM_ENS_TILES ? HEXSV_ENS_PERSISTENT : HEXSV_ENS_BATCHED;
         const int v = c < NUM_ENS_TILES ? c : c - NUM_ENS_TILES;
+        if (e->visc && mode == HEXSV_ENS_PERSISTENT) continue;  // not built with viscosity
         if (mode == HEXSV_ENS_PERSISTENT) ens_set_tile(e, v);
         else if (ens_set_btile(e, v) != HEXSV_OK) he = hipErrorUnknown;
         std::vector<Ctl> cc = c0;

@@ -21,8 +21,9 @@ int hexsv_fail(int code, const char *fmt, ...);
 struct hexsv_grid {
     hexsv::KGrid kg;
     double edge;
-    int64_t n, n_active, n_dirichlet;
-    uint8_t *d_active;  // per cell 0 / 1 / 2 (outside, updated, Dirichlet); nullptr when all are 1
+    int64_t n, n_active, n_dirichlet;  // n_dirichlet: boundary cells (Dirichlet or given flux)
+    uint8_t *d_active;  // per cell 0 / 1 / 2 / 3 (outside, updated, Dirichlet, given flux);
+                        // nullptr when all are 1
 };
 
 // Geometry constants of a raster of edge a (regular hexagon area, CFL bound).

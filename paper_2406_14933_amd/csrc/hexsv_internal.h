@@ -31,7 +31,7 @@ struct EnsScen;
 // Batched-step mode of the ensemble: the tile kernel over the tiles of all
 // scenarios (one workgroup each) followed by the per-scenario finalize.
 template <typename T>
-hipError_t launch_ens_step(int variant, const KDom<T> &base, const EnsScen *scen,
+hipError_t launch_ens_step(int variant, bool visc, const KDom<T> &base, const EnsScen *scen,
                            const int32_t *tile_scen, Ctl *ctl, Part *part, int ntiles_total,
                            int nscen, hipStream_t stream);
 hipError_t launch_ens_finalize(const EnsScen *scen, Ctl *ctl, const Part *part, int nscen,

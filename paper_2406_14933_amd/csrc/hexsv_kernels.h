@@ -140,7 +140,8 @@ hipError_t launch_prime(const KDom<T> &d, int64_t n, const KConst &kc, Ctl *ctl,
 }
 
 // zero_inactive: 0 copies, 1 writes zero outside the domain, 2 also negates the
-// value on Dirichlet cells (theta: the step kernel tells such a cell by theta < 0).
+// value on Dirichlet cells and writes -2 on flux cells (theta: the step kernel tells
+// such cells by theta < 0 and theta < -1.5).
 template <typename T>
 __global__ void k_import(const double *src, T *dst, const uint8_t *active, int zero_inactive,
                          int64_t n) {
@@ -149,6 +150,7 @@ __global__ void k_import(const double *src, T *dst, const uint8_t *active, int z
         const uint8_t a = active ? active[i] : (uint8_t)1;
         T v = (zero_inactive && a == 0) ? T(0) : (T)src[i];
         if (zero_inactive == 2 && a == 2) v = -v;
+        if (zero_inactive == 2 && a == 3) v = T(-2);
         dst[i] = v;
     }
 }
@@ -170,7 +172,9 @@ __global__ void k_export(KDom<T> d, int par, int64_t n, double *h, double *v1, d
         const double hh = (double)d.buf(par, 0)[i];
         const double a = (double)d.buf(par, 1)[i];
         const double b = (double)d.buf(par, 2)[i];
-        const double th = __builtin_fabs((double)d.th[i]);  // Dirichlet cells hold -theta
+        // Dirichlet cells hold -theta; flux cells hold -2 and carry the discharge h v
+        const double ts = (double)d.th[i];
+        const double th = ts < -1.5 ? 1.0 : __builtin_fabs(ts);
         if (h) h[i] = hh;
         if (v1) v1[i] = a;
         if (v2) v2[i] = b;

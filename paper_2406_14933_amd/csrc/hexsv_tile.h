@@ -175,17 +175,26 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
         const int lr = cc / TQ, lq = cc - lr * TQ;
         const int s = (lr + 1) * W + (lq + 1);
         if (R.pos[k] != POS_OUTSIDE) {
-            // a Dirichlet cell holds -theta: its record carries |theta| h
-            const T m = __builtin_fabs(R.th[k]) * R.h[k];
-            L.rec[s] = make_rec<T>(mscale * m, G * (R.z[k] + R.h[k]), R.v1[k] * T(0.5),
-                                   R.v2[k] * T(0.5));
+            T m = R.th[k] * R.h[k];
+            T w = G * (R.z[k] + R.h[k]);
+            if (R.th[k] < T(0)) {  // boundary cells: Dirichlet (-theta) or given flux (-2)
+                if (R.th[k] < T(-1.5)) {
+                    m = R.h[k];  // the discharge's depth
+                    w = R.z[k];  // the bed only: the edge adds the cell's own depth
+                } else {
+                    m = -R.th[k] * R.h[k];
+                }
+            }
+            L.rec[s] = make_rec<T>(mscale * m, w, R.v1[k] * T(0.5), R.v2[k] * T(0.5));
             if constexpr (V)
                 L.c[s] = p_sqrt(R.v1[k] * R.v1[k] + R.v2[k] * R.v2[k]) + p_sqrt(G * R.h[k]);
             const bool act = R.th[k] > T(0);
             bad |= !act;
             if (need_codes)
                 L.code[s] = act ? (uint8_t)CODE_INTERIOR
-                                : (R.th[k] < T(0) ? (uint8_t)CODE_DIRICHLET : (uint8_t)g.mask_bc);
+                                : (R.th[k] < T(-1.5) ? (uint8_t)CODE_FLUX
+                                   : R.th[k] < T(0) ? (uint8_t)CODE_DIRICHLET
+                                                    : (uint8_t)g.mask_bc);
         } else {
             int q = q0 + lq, r = r0 + lr;
             wrap_pos(g, q, r);
@@ -202,16 +211,26 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
         ring_slot<TQ, TR>(t, lq, lr);
         const int s = lr * W + lq;
         if (R.rpos[k] != POS_OUTSIDE) {
-            const T m = __builtin_fabs(R.rth[k]) * R.rh[k];
-            L.rec[s] = make_rec<T>(mscale * m, G * (R.rz[k] + R.rh[k]), R.rv1[k] * T(0.5),
-                                   R.rv2[k] * T(0.5));
+            T m = R.rth[k] * R.rh[k];
+            T w = G * (R.rz[k] + R.rh[k]);
+            if (R.rth[k] < T(0)) {
+                if (R.rth[k] < T(-1.5)) {
+                    m = R.rh[k];
+                    w = R.rz[k];
+                } else {
+                    m = -R.rth[k] * R.rh[k];
+                }
+            }
+            L.rec[s] = make_rec<T>(mscale * m, w, R.rv1[k] * T(0.5), R.rv2[k] * T(0.5));
             if constexpr (V)
                 L.c[s] = p_sqrt(R.rv1[k] * R.rv1[k] + R.rv2[k] * R.rv2[k]) + p_sqrt(G * R.rh[k]);
             const bool act = R.rth[k] > T(0);
             bad |= !act;
             if (need_codes)
                 L.code[s] = act ? (uint8_t)CODE_INTERIOR
-                                : (R.rth[k] < T(0) ? (uint8_t)CODE_DIRICHLET : (uint8_t)g.mask_bc);
+                                : (R.rth[k] < T(-1.5) ? (uint8_t)CODE_FLUX
+                                   : R.rth[k] < T(0) ? (uint8_t)CODE_DIRICHLET
+                                                     : (uint8_t)g.mask_bc);
         } else {
             int q = q0 + lq - 1, r = r0 + lr - 1;
             wrap_pos(g, q, r);
@@ -302,12 +321,38 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 vh1j = vh1i;
                 vh2j = vh2i;
             }
-            // interface velocity; an edge to a Dirichlet cell carries the prescribed one
+            // interface velocity; an edge to a Dirichlet or flux cell carries the prescribed one
             T vb1 = vh1i + vh1j;
             T vb2 = vh2i + vh2j;
-            if (GEN && cd == CODE_DIRICHLET) {
+            if (GEN && cd >= CODE_DIRICHLET) {
                 vb1 = vh1j + vh1j;
                 vb2 = vh2j + vh2j;
+            }
+            if (GEN && cd == CODE_FLUX) {
+                // given mass flux: the discharge h_j v_j crosses the edge whatever the cell
+                // holds; the pressure term sees the cell's own depth over the neighbour's
+                // bed (wj holds that bed level)
+                const T vn = vb1 * NX[e] + vb2 * NY[e];
+                if constexpr (F32) {
+                    const T F = mj * vn;  // mj holds l h_j
+                    Ls -= F;
+                    A1 -= F * vb1;
+                    A2 -= F * vb2;
+                    const T Q = (G * (wj + hi) - wi) * Mi;
+                    A1 -= Q * NXh[e];
+                    A2 -= Q * NYh[e];
+                    Fout += F;
+                } else {
+                    const T F = l * mj * vn;
+                    Ls -= F;
+                    A1 -= F * vb1;
+                    A2 -= F * vb2;
+                    const T P = half_l * (G * (wj + hi) - wi) * mi;
+                    S1 -= P * NX[e];
+                    S2 -= P * NY[e];
+                    Fout += F;
+                }
+                continue;
             }
             if constexpr (F32) {
                 // mj holds l*theta_j*h_j

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "lib", "libhexsv.so")
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ENUMERIC, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
-INTERIOR, WALL, OUTFLOW, PERIODIC, DIRICHLET = 0, 1, 2, 3, 4
+INTERIOR, WALL, OUTFLOW, PERIODIC, DIRICHLET, FLUX = 0, 1, 2, 3, 4, 5
 S, E, N, W = 0, 1, 2, 3
 MAX_SEGMENTS = 8
 
@@ -91,6 +91,7 @@ _SIGS = [
     ("hexsv_ensemble_set_scenario", C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_double,
                                               C.POINTER(Rain), C.c_double, _VP, _VP, _VP, _VP]),
     ("hexsv_ensemble_run", C.c_int, [_VP, C.POINTER(C.c_double), C.c_int64, _VP]),
+    ("hexsv_ensemble_set_viscosity", C.c_int, [_VP, C.c_int32]),
     ("hexsv_ensemble_get_state", C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("hexsv_ensemble_get_books", C.c_int, [_VP, C.c_int32, C.POINTER(Books), _VP]),
     ("hexsv_ensemble_timing", C.c_int, [_VP, C.c_int32, C.POINTER(C.c_double),
@@ -195,10 +196,11 @@ class Grid:
             d.seg[k] = Segment(int(s_), int(lo), int(hi), int(code))
         self._active = None
         if active is not None:
-            # per cell: 0 outside the domain, 1 updated, 2 Dirichlet (held at its state)
+            # per cell: 0 outside the domain, 1 updated, 2 Dirichlet (held at its state),
+            # 3 given flux (prescribes the discharge h v)
             a = np.asarray(active).reshape(-1)
-            if a.dtype != bool and a.size and (a.min() < 0 or a.max() > 2):
-                raise ValueError("active holds values other than 0, 1, 2")
+            if a.dtype != bool and a.size and (a.min() < 0 or a.max() > 3):
+                raise ValueError("active holds values other than 0, 1, 2, 3")
             self._active = np.ascontiguousarray(a, dtype=np.uint8)
             d.active = self._active.ctypes.data_as(C.POINTER(C.c_uint8))
         d.mask_bc = int(mask_bc)
@@ -382,9 +384,15 @@ class Ensemble:
         s0 = scs[0]
         ens = cls([Grid.from_scenario(sc) for sc in scs], precision, g=s0.g, cfl=s0.cfl,
                   dt_max=s0.dt_max, h_dry=s0.h_dry, **kw)
+        if getattr(s0, "visc", False):
+            ens.set_viscosity(True)
         for i, sc in enumerate(scs):
             ens.set_scenario(i, sc)
         return ens
+
+    def set_viscosity(self, on):
+        """Artificial viscosity for every scenario (batched-step mode only)."""
+        _check(lib().hexsv_ensemble_set_viscosity(self._h, int(bool(on))))
 
     def set_scenario(self, s, sc, t0=0.0):
         n = self.grids[s].cells

@@ -413,6 +413,40 @@ def radial(kind="crater", a=0.5, r0=10.0, r1=100.0, A=10.0, h0=0.05, v0=1.0, t_e
               "r_in": rin, "ox": -R - shift, "oy": -R, "g": G_ACCEL})
 
 
+def flume(q=0.007, h_in=0.03, theta_v=0.99364, m=0.00105, alpha_s=ALPHA_S, alpha_p=ALPHA_P,
+          a=0.05, length=18.0, width=1.0, vegetated="lower", t_end=300.0, inflow="flux"):
+    """The sloping laboratory flume of Sec. 3.3.2 (18 m x 1 m, bed z = -m (x - 18), emergent
+    vegetation of porosity theta_v on the lower half x in [9, 18] ("lower", theta_1) or the
+    upper half ("upper", theta_2)), fed at x = 0 with the discharge q per unit width and
+    draining freely at x = 18.  The inflow is a column of boundary cells just upstream of
+    x = 0 holding depth h_in and velocity q / h_in along x: given-mass-flux cells (active code
+    3, inflow="flux": every edge into one carries the discharge l q cos(angle) and sees the
+    cell's own depth) or Dirichlet cells (code 2, inflow="dirichlet": the state h_in is
+    imposed).  The channel walls are the raster's S and N sides; the masked cells past
+    x = 18 are OUTFLOW.  The channel starts at depth h_in with the same discharge."""
+    s3 = math.sqrt(3.0)
+    nr = max(2, int(round(width / (1.5 * a))))
+    ox = -s3 * a * (2.0 + 0.5 * (nr - 1))
+    nq = int(math.ceil((length + 2.0 * s3 * a - ox) / (s3 * a))) + 1
+    x, y = centres(nq, nr, a)
+    x = x + ox
+    act = np.zeros(nq * nr, np.uint8)
+    act[(x >= 0.0) & (x <= length)] = 1
+    act[(x < 0.0) & (x >= -s3 * a)] = 3 if inflow == "flux" else 2
+    veg = (x >= 0.5 * length) if vegetated == "lower" else (x < 0.5 * length)
+    theta = np.where(veg, theta_v, 1.0)
+    if inflow != "flux":
+        theta = np.where(act == 2, 1.0, theta)  # the imposed state carries q = h_in v
+    h = np.where(act > 0, h_in, 0.0)
+    v1 = np.where(act == 1, q / (theta * h_in), np.where(act > 1, q / h_in, 0.0))
+    return Scenario(
+        name=f"flume-{vegetated}-q{q:g}", nq=nq, nr=nr, a=a, z=-m * (x - length), theta=theta,
+        alpha_p=np.full(nq * nr, float(alpha_p)), alpha_s=float(alpha_s), side=(WALL,) * 4,
+        active=act, mask_code=OUTFLOW, h0=h, v10=v1, v20=np.zeros(nq * nr), t_end=t_end,
+        meta={"x": x, "q": q, "h_in": h_in, "theta_v": theta_v, "m": m, "length": length,
+              "vegetated": vegetated, "veg_zone": (act == 1) & (x >= 0.5 * length)})
+
+
 def random_state(sc: Scenario, seed: int, depth=0.05, speed=0.3, dry_frac=0.2):
     """A rough wet/dry state on sc's raster (for one-step checks)."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -21,7 +21,7 @@ def ref_run(sc, t_end=None, max_steps=10 ** 9, nthreads=0, log_dt=False):
     h, v1, v2, b, dl = oracle.run(G, sc.z, sc.theta, sc.alpha_p, ref_params(sc), ref_rain(sc),
                                   sc.h0, sc.v10, sc.v20, sc.t_end if t_end is None else t_end,
                                   max_steps=max_steps, nthreads=nthreads, log_dt=log_dt)
-    th = np.where(G.active | G.dirichlet, sc.theta, 0.0)
+    th = np.where(G.active | G.dirichlet, sc.theta, np.where(G.flux, 1.0, 0.0))
     return {"h": h, "v1": v1, "v2": v2, "q1": th * h * v1, "q2": th * h * v2,
             "books": b.as_dict(), "dt": dl}
 
