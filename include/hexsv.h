@@ -43,7 +43,8 @@
  *    0.5 l g (z_F + h_i - z_i - h_i) theta_i h_i.  The flux is booked with the
  *    outflow.
  *  - The wave speeds |v| + sqrt(g h) of Dirichlet and flux cells enter c_max
- *    (eq. .12).  Surrogate windows refuse grids with either kind.
+ *    (eq. .12).  Surrogate windows refuse grids with either kind; an ensemble
+ *    holding either kind runs in the batched-step mode.
  *  - Every d_* pointer is caller-owned device memory (e.g. a torch tensor's
  *    data_ptr()), read or written only during the call (stream-ordered on
  *    `stream`); the library copies inputs into its own buffers and never frees

@@ -280,6 +280,7 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->kc.alpha_s = 0.0;
     s->kc.tau_lin = 0.0;
     s->kc.c_floor = 0.0;
+    s->kc.bc = grid->n_dirichlet > 0 ? 1 : 0;
     s->kc.visc = 0;
     s->kc.area_active = s->kc.sigma * (double)grid->n_active;
     s->rn.kind = 0;

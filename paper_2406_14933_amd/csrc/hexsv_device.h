@@ -106,6 +106,7 @@ struct KConst {
     double tau_lin;      // linear soil resistance -tau h v (Thacker test), 1/s; 0: off
     double c_floor;      // largest |v| + sqrt(g h) of the Dirichlet cells (fixed), 0 if none
     int32_t visc;        // 1: augmented momentum flux with artificial viscosity
+    int32_t bc;          // 1: the raster holds Dirichlet or given-flux cells
 };
 
 template <typename T>

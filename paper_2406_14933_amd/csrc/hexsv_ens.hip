@@ -22,6 +22,7 @@ struct hexsv_ensemble {
     int tile, ksteps, nwg;
     int mode;                   // HEXSV_ENS_PERSISTENT or HEXSV_ENS_BATCHED
     int visc;                   // 1: artificial viscosity (batched mode only)
+    int bc;                     // 1: a scenario holds Dirichlet or flux cells (batched mode only)
     int btile, btotal;          // batched mode: tile variant and total tiles
     int32_t *d_tile_scen;       // batched mode: scenario of every global tile
     Part *d_bpart;              // batched mode: one record per global tile
@@ -153,6 +154,9 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
     if (!e) return fail(HEXSV_ENOMEM, "ensemble_create: out of host memory");
     e->n = n;
     e->visc = 0;
+    e->bc = 0;
+    for (int s = 0; s < n; ++s)
+        if (grids[s]->n_dirichlet) e->bc = 1;
     e->prec = p.precision;
     e->esz = p.precision == HEXSV_FP64 ? sizeof(double) : sizeof(float);
     e->tile = 0;
@@ -198,6 +202,8 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         }
         ens_set_tile(e, e->mode == HEXSV_ENS_PERSISTENT ? v : 0);
         ens_set_btile(e, e->mode == HEXSV_ENS_BATCHED ? v : DEFAULT_TILE);
+        // the persistent kernel is not built for Dirichlet or flux cells
+        if (e->bc) e->mode = HEXSV_ENS_BATCHED;
     }
     // largest scenarios first: they bound the length of every launch
     std::vector<int32_t> order(n);
@@ -335,10 +341,12 @@ static hipError_t ens_launch(hexsv_ensemble *e, int mode, int v, int ksteps, hip
     hipError_t err = hipSuccess;
     for (int k = 0; k < ksteps && err == hipSuccess; ++k)
         err = e->prec == HEXSV_FP64
-                  ? launch_ens_step<double>(v, e->visc != 0, ens_base<double>(e), e->d_scen,
-                                            e->d_tile_scen, e->d_ctl, e->d_bpart, e->btotal, e->n, st)
-                  : launch_ens_step<float>(v, e->visc != 0, ens_base<float>(e), e->d_scen,
-                                           e->d_tile_scen, e->d_ctl, e->d_bpart, e->btotal, e->n, st);
+                  ? launch_ens_step<double>(v, e->visc != 0, e->bc != 0, ens_base<double>(e),
+                                            e->d_scen, e->d_tile_scen, e->d_ctl, e->d_bpart,
+                                            e->btotal, e->n, st)
+                  : launch_ens_step<float>(v, e->visc != 0, e->bc != 0, ens_base<float>(e),
+                                           e->d_scen, e->d_tile_scen, e->d_ctl, e->d_bpart,
+                                           e->btotal, e->n, st);
     return err;
 }
 
@@ -499,7 +507,8 @@ extern "C" int hexsv_ensemble_autotune(hexsv_ensemble *e, int32_t ksteps, const 
     for (int c = 0; c < nvar && he == hipSuccess; ++c) {
         const int mode = c < NUM_ENS_TILES ? HEXSV_ENS_PERSISTENT : HEXSV_ENS_BATCHED;
         const int v = c < NUM_ENS_TILES ? c : c - NUM_ENS_TILES;
-        if (e->visc && mode == HEXSV_ENS_PERSISTENT) continue;  // not built with viscosity
+        // the persistent kernel is built without viscosity and boundary cells
+        if ((e->visc || e->bc) && mode == HEXSV_ENS_PERSISTENT) continue;
         if (mode == HEXSV_ENS_PERSISTENT) ens_set_tile(e, v);
         else if (ens_set_btile(e, v) != HEXSV_OK) he = hipErrorUnknown;
         std::vector<Ctl> cc = c0;

@@ -137,8 +137,9 @@ __global__ __launch_bounds__(NT) void k_ensemble(KDom<T> base, const EnsScen *__
 // XCD-banded); each workgroup finds its scenario, reads that scenario's dt and
 // writes one partial record; k_ens_finalize (one workgroup per scenario) then
 // closes each scenario's step.  Kernel boundaries order the steps.
-// V: the augmented momentum flux with artificial viscosity (set_viscosity).
-template <typename T, int TQ, int TR, int NT, bool V>
+// V: the augmented momentum flux with artificial viscosity (set_viscosity);
+// BC: some scenario holds Dirichlet or given-flux cells.
+template <typename T, int TQ, int TR, int NT, bool V, bool BC>
 __global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__restrict__ scen,
                                                  const int32_t *__restrict__ tile_scen,
                                                  Ctl *__restrict__ ctl, Part *__restrict__ part,
@@ -156,36 +157,39 @@ __global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__
     const double r_next = rain_rate(scen[s].rn, st.t_next);
     __shared__ TileLDS<T, TQ, TR, V> L;
     Acc acc{0.0, 0.0, 0.0, 0.0};
-    tile_step<T, TQ, TR, NT, true, V>(L, d, g, kc, 0, tq, tr, st.dt, r_next, acc, &ctl[s].err,
-                                      &ctl[s].err_cell);
+    tile_step<T, TQ, TR, NT, true, V, BC>(L, d, g, kc, 0, tq, tr, st.dt, r_next, acc,
+                                          &ctl[s].err, &ctl[s].err_cell);
     const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
     if (threadIdx.x == 0) part[t] = p;
 }
 
 template <typename T, int TQ, int TR, int NT>
-static hipError_t launch_ens_step_v(bool visc, const KDom<T> &base, const EnsScen *scen,
-                                    const int32_t *tile_scen, Ctl *ctl, Part *part,
-                                    int ntiles_total, int nscen, hipStream_t stream) {
+static hipError_t launch_ens_step_v(bool visc, bool bc, const KDom<T> &base,
+                                    const EnsScen *scen, const int32_t *tile_scen, Ctl *ctl,
+                                    Part *part, int ntiles_total, int nscen, hipStream_t stream) {
     if (visc)
-        hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, true>), dim3(ntiles_total), dim3(NT), 0,
-                           stream, base, scen, tile_scen, ctl, part, ntiles_total);
+        hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, true, true>), dim3(ntiles_total), dim3(NT),
+                           0, stream, base, scen, tile_scen, ctl, part, ntiles_total);
+    else if (bc)
+        hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, false, true>), dim3(ntiles_total), dim3(NT),
+                           0, stream, base, scen, tile_scen, ctl, part, ntiles_total);
     else
-        hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, false>), dim3(ntiles_total), dim3(NT), 0,
-                           stream, base, scen, tile_scen, ctl, part, ntiles_total);
+        hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, false, false>), dim3(ntiles_total),
+                           dim3(NT), 0, stream, base, scen, tile_scen, ctl, part, ntiles_total);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_ens_finalize(scen, ctl, part, nscen, stream);
 }
 
 template <typename T>
-hipError_t launch_ens_step(int variant, bool visc, const KDom<T> &base, const EnsScen *scen,
-                           const int32_t *tile_scen, Ctl *ctl, Part *part, int ntiles_total,
-                           int nscen, hipStream_t stream) {
+hipError_t launch_ens_step(int variant, bool visc, bool bc, const KDom<T> &base,
+                           const EnsScen *scen, const int32_t *tile_scen, Ctl *ctl, Part *part,
+                           int ntiles_total, int nscen, hipStream_t stream) {
     switch (variant) {
 #define HEXSV_CASE(V)                                                                          \
     case V:                                                                                    \
         return launch_ens_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(                    \
-            visc, base, scen, tile_scen, ctl, part, ntiles_total, nscen, stream);
+            visc, bc, base, scen, tile_scen, ctl, part, ntiles_total, nscen, stream);
         HEXSV_TILE_SWITCH(HEXSV_CASE)
 #undef HEXSV_CASE
         default:
@@ -226,7 +230,7 @@ hipError_t launch_ensemble(int variant, const KDom<T> &base, const EnsScen *scen
     template hipError_t launch_ensemble<T>(int, const KDom<T> &, const EnsScen *, Ctl *,      \
                                            const int32_t *, int, uint32_t *, int, int,        \
                                            hipStream_t);                                      \
-    template hipError_t launch_ens_step<T>(int, bool, const KDom<T> &, const EnsScen *,       \
+    template hipError_t launch_ens_step<T>(int, bool, bool, const KDom<T> &, const EnsScen *, \
                                            const int32_t *, Ctl *, Part *, int, int,          \
                                            hipStream_t);
 

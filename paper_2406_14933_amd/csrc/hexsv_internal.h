@@ -31,9 +31,9 @@ struct EnsScen;
 // Batched-step mode of the ensemble: the tile kernel over the tiles of all
 // scenarios (one workgroup each) followed by the per-scenario finalize.
 template <typename T>
-hipError_t launch_ens_step(int variant, bool visc, const KDom<T> &base, const EnsScen *scen,
-                           const int32_t *tile_scen, Ctl *ctl, Part *part, int ntiles_total,
-                           int nscen, hipStream_t stream);
+hipError_t launch_ens_step(int variant, bool visc, bool bc, const KDom<T> &base,
+                           const EnsScen *scen, const int32_t *tile_scen, Ctl *ctl, Part *part,
+                           int ntiles_total, int nscen, hipStream_t stream);
 hipError_t launch_ens_finalize(const EnsScen *scen, Ctl *ctl, const Part *part, int nscen,
                                hipStream_t stream);
 // Reset the ensemble's scenario queue (a one-thread kernel, safe inside graphs).

@@ -157,7 +157,9 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
 // ----------------------------------------------------------------- stage
 
 // Write the LDS records; returns true if a staged raster cell is inactive.
-template <typename T, int TQ, int TR, int NT, bool V>
+// BC: the raster may hold Dirichlet or given-flux cells (theta < 0); an instance
+// without them keeps the plain records.
+template <typename T, int TQ, int TR, int NT, bool BC = false, bool V>
 __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ, TR, NT> &R,
                                   const KGrid &g, const KConst &kc, int tq, int tr) {
     using Regs = TileRegs<T, TQ, TR, NT>;
@@ -175,26 +177,28 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
         const int lr = cc / TQ, lq = cc - lr * TQ;
         const int s = (lr + 1) * W + (lq + 1);
         if (R.pos[k] != POS_OUTSIDE) {
-            T m = R.th[k] * R.h[k];
-            T w = G * (R.z[k] + R.h[k]);
-            if (R.th[k] < T(0)) {  // boundary cells: Dirichlet (-theta) or given flux (-2)
-                if (R.th[k] < T(-1.5)) {
-                    m = R.h[k];  // the discharge's depth
-                    w = R.z[k];  // the bed only: the edge adds the cell's own depth
-                } else {
-                    m = -R.th[k] * R.h[k];
-                }
+            const bool act = R.th[k] > T(0);
+            if constexpr (BC) {
+                // boundary cells: Dirichlet (-theta: |theta| h) or given flux (-2: the
+                // discharge's depth, and the bed only, as the edge adds the cell's depth)
+                const bool fl = R.th[k] < T(-1.5);
+                const T m = fl ? R.h[k] : __builtin_fabs(R.th[k]) * R.h[k];
+                const T w = fl ? R.z[k] : G * (R.z[k] + R.h[k]);
+                L.rec[s] = make_rec<T>(mscale * m, w, R.v1[k] * T(0.5), R.v2[k] * T(0.5));
+                if (need_codes)
+                    L.code[s] = act ? (uint8_t)CODE_INTERIOR
+                                    : (fl ? (uint8_t)CODE_FLUX
+                                          : R.th[k] < T(0) ? (uint8_t)CODE_DIRICHLET
+                                                           : (uint8_t)g.mask_bc);
+            } else {
+                const T m = R.th[k] * R.h[k];
+                L.rec[s] = make_rec<T>(mscale * m, G * (R.z[k] + R.h[k]), R.v1[k] * T(0.5),
+                                       R.v2[k] * T(0.5));
+                if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
             }
-            L.rec[s] = make_rec<T>(mscale * m, w, R.v1[k] * T(0.5), R.v2[k] * T(0.5));
             if constexpr (V)
                 L.c[s] = p_sqrt(R.v1[k] * R.v1[k] + R.v2[k] * R.v2[k]) + p_sqrt(G * R.h[k]);
-            const bool act = R.th[k] > T(0);
             bad |= !act;
-            if (need_codes)
-                L.code[s] = act ? (uint8_t)CODE_INTERIOR
-                                : (R.th[k] < T(-1.5) ? (uint8_t)CODE_FLUX
-                                   : R.th[k] < T(0) ? (uint8_t)CODE_DIRICHLET
-                                                    : (uint8_t)g.mask_bc);
         } else {
             int q = q0 + lq, r = r0 + lr;
             wrap_pos(g, q, r);
@@ -211,26 +215,26 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
         ring_slot<TQ, TR>(t, lq, lr);
         const int s = lr * W + lq;
         if (R.rpos[k] != POS_OUTSIDE) {
-            T m = R.rth[k] * R.rh[k];
-            T w = G * (R.rz[k] + R.rh[k]);
-            if (R.rth[k] < T(0)) {
-                if (R.rth[k] < T(-1.5)) {
-                    m = R.rh[k];
-                    w = R.rz[k];
-                } else {
-                    m = -R.rth[k] * R.rh[k];
-                }
+            const bool act = R.rth[k] > T(0);
+            if constexpr (BC) {
+                const bool fl = R.rth[k] < T(-1.5);
+                const T m = fl ? R.rh[k] : __builtin_fabs(R.rth[k]) * R.rh[k];
+                const T w = fl ? R.rz[k] : G * (R.rz[k] + R.rh[k]);
+                L.rec[s] = make_rec<T>(mscale * m, w, R.rv1[k] * T(0.5), R.rv2[k] * T(0.5));
+                if (need_codes)
+                    L.code[s] = act ? (uint8_t)CODE_INTERIOR
+                                    : (fl ? (uint8_t)CODE_FLUX
+                                          : R.rth[k] < T(0) ? (uint8_t)CODE_DIRICHLET
+                                                            : (uint8_t)g.mask_bc);
+            } else {
+                const T m = R.rth[k] * R.rh[k];
+                L.rec[s] = make_rec<T>(mscale * m, G * (R.rz[k] + R.rh[k]), R.rv1[k] * T(0.5),
+                                       R.rv2[k] * T(0.5));
+                if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
             }
-            L.rec[s] = make_rec<T>(mscale * m, w, R.rv1[k] * T(0.5), R.rv2[k] * T(0.5));
             if constexpr (V)
                 L.c[s] = p_sqrt(R.rv1[k] * R.rv1[k] + R.rv2[k] * R.rv2[k]) + p_sqrt(G * R.rh[k]);
-            const bool act = R.rth[k] > T(0);
             bad |= !act;
-            if (need_codes)
-                L.code[s] = act ? (uint8_t)CODE_INTERIOR
-                                : (R.rth[k] < T(-1.5) ? (uint8_t)CODE_FLUX
-                                   : R.rth[k] < T(0) ? (uint8_t)CODE_DIRICHLET
-                                                     : (uint8_t)g.mask_bc);
         } else {
             int q = q0 + lq - 1, r = r0 + lr - 1;
             wrap_pos(g, q, r);
@@ -244,7 +248,7 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
 
 // --------------------------------------------------------------- compute
 
-template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V>
+template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V, bool BC = false>
 __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ, TR, NT> &R,
                                     bool general, const KDom<T> &d, const KGrid &g,
                                     const KConst &kc, int par, int tq, int tr, double dt,
@@ -301,7 +305,8 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 cd = L.code[sn];
                 if (cd == CODE_WALL) continue;
             }
-            if (!GEN || cd != CODE_OUTFLOW) {  // a cell: interior or Dirichlet
+            // a cell: interior (or, BC, Dirichlet or flux)
+            if (!GEN || (BC ? cd != CODE_OUTFLOW : cd == CODE_INTERIOR)) {
                 const typename Rec<T>::type nb = L.rec[sn];
                 mj = nb.x;
                 wj = nb.y;
@@ -324,11 +329,11 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
             // interface velocity; an edge to a Dirichlet or flux cell carries the prescribed one
             T vb1 = vh1i + vh1j;
             T vb2 = vh2i + vh2j;
-            if (GEN && cd >= CODE_DIRICHLET) {
+            if (BC && GEN && cd >= CODE_DIRICHLET) {
                 vb1 = vh1j + vh1j;
                 vb2 = vh2j + vh2j;
             }
-            if (GEN && cd == CODE_FLUX) {
+            if (BC && GEN && cd == CODE_FLUX) {
                 // given mass flux: the discharge h_j v_j crosses the edge whatever the cell
                 // holds; the pressure term sees the cell's own depth over the neighbour's
                 // bed (wj holds that bed level)
@@ -370,7 +375,8 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 const T Q = dw * msel;
                 A1 -= Q * NXh[e];
                 if (e != 0 && e != 3) A2 -= Q * NYh[e];
-                if (GEN && cd != CODE_INTERIOR) Fout += F;  // outflow or Dirichlet edge
+                if (GEN && (BC ? cd != CODE_INTERIOR : cd == CODE_OUTFLOW))
+                    Fout += F;  // outflow or Dirichlet edge
             } else {
                 const T vn = vb1 * NX[e] + vb2 * NY[e];
                 const T mup = vn > T(0) ? mi : (vn < T(0) ? mj : T(0));
@@ -382,7 +388,8 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 const T P = half_l * (wj - wi) * mhat;
                 S1 -= P * NX[e];
                 S2 -= P * NY[e];
-                if (GEN && cd != CODE_INTERIOR) Fout += F;  // outflow or Dirichlet edge
+                if (GEN && (BC ? cd != CODE_INTERIOR : cd == CODE_OUTFLOW))
+                    Fout += F;  // outflow or Dirichlet edge
             }
             if constexpr (V) {
                 // artificial viscosity l c_ij mu_ij (v_j - v_i) of an interior edge (an
@@ -495,16 +502,16 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
 
 // All three phases for one tile (the caller separates consecutive tiles on
 // the same LDS with a barrier).
-template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V = false>
+template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V = false, bool BC = false>
 __device__ inline void tile_step(TileLDS<T, TQ, TR, V> &L, const KDom<T> &d, const KGrid &g,
                                  const KConst &kc, int par, int tq, int tr, double dt,
                                  double r_next, Acc &acc, int32_t *err_flag, int32_t *err_cell) {
     TileRegs<T, TQ, TR, NT> R;
     tile_load<T, TQ, TR, NT>(R, d, g, par, tq, tr);
-    const bool bad = tile_stage<T, TQ, TR, NT>(L, R, g, kc, tq, tr);
+    const bool bad = tile_stage<T, TQ, TR, NT, BC>(L, R, g, kc, tq, tr);
     const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
     const bool general = __syncthreads_or((!inner) || bad) != 0;
-    tile_compute<T, TQ, TR, NT, NT_STORE, V>(L, R, general, d, g, kc, par, tq, tr, dt, r_next,
+    tile_compute<T, TQ, TR, NT, NT_STORE, V, BC>(L, R, general, d, g, kc, par, tq, tr, dt, r_next,
                                              acc, err_flag, err_cell);
 }
 

@@ -81,12 +81,15 @@ def test_flume_ensemble_with_viscosity_matches_the_oracle(hx, precision):
         assert_books(got, ref, 1e-12 if precision == "fp64" else 1e-5)
 
 
-def test_viscosity_moves_a_persistent_ensemble_to_batched_steps(hx):
-    sc = _flume(visc=False)
+def test_viscosity_and_boundary_cells_move_an_ensemble_to_batched_steps(hx):
+    sc = synth.c1_planar(nq=40, nr=30, t_end=10.0)
     ens = hx.Ensemble.from_scenarios([sc, sc], "fp32", mode="persistent")
     assert ens.info()["mode"] == "persistent"
     ens.set_viscosity(True)
     assert ens.info()["mode"] == "batched"
+    fl = _flume(visc=False)
+    assert hx.Ensemble.from_scenarios([fl, fl], "fp32", mode="persistent").info()["mode"] == \
+        "batched"
     with pytest.raises(hx.HexsvError) as ei:
         hx._check(hx.lib().hexsv_ensemble_set_viscosity(ens._h, 2))
     assert ei.value.code == hx.EINVAL
