@@ -212,6 +212,19 @@ int hexsv_sim_set_viscosity(hexsv_sim *sim, int32_t on);
  * Takes effect from the next run.  EDOMAIN: tau < 0 or non-finite. */
 int hexsv_sim_set_linear_friction(hexsv_sim *sim, double tau);
 
+/* Infiltration in the mass source (the paper's future extension of the source
+ * term by an algebraic law, Sec. 4; the scalar equation for h^{n+1} of
+ * Appendix A): the source r(t) loses i(h) = f_inf h / (h + h_inf), taken at
+ * h^{n+1} (m/s; i rises from 0 on a dry cell to f_inf under deep water, half
+ * of it at depth h_inf).  The update theta x + dt i(x) = (theta h)^n + dt/sigma
+ * L + dt r is solved exactly for x = h^{n+1}: x = h_s - e with h_s the depth
+ * without infiltration and e the smaller root of a quadratic; the water that
+ * enters the soil is booked with the outflow.
+ * f_inf = 0 (the default) turns it off; the kernel used then is the plain one.
+ * Takes effect from the next run; surrogate windows refuse it.  EDOMAIN:
+ * f_inf < 0 or non-finite, or f_inf > 0 with h_inf <= 0. */
+int hexsv_sim_set_infiltration(hexsv_sim *sim, double f_inf, double h_inf);
+
 /* Initial state (the paper's "initial water layer", Sec. 3) at time t0:
  * h, v1, v2 per cell (device FP64 arrays of nq*nr).  Resets the books and
  * the step count, and computes the first CFL bound.  EDOMAIN: h < 0 or a

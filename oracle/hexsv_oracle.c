@@ -302,6 +302,24 @@ static void step_one(const int32_t *nbr, const uint8_t *code, double a,
         m1 = 0.0;
     }
     double h1 = m1 / th;
+    double infil = 0.0;
+    if (p->f_inf > 0.0 && m1 > 0.0) {
+        /* the mass source r - i(h^{n+1}) with i(h) = f h / (h + c) makes .05-1/.06-1 the
+         * scalar equation theta x + dt f x / (x + c) = m1 for x = h^{n+1}.  With
+         * x = hs - e (hs = m1 / theta, the depth without infiltration) the loss e is the
+         * smaller root of theta e^2 - P e + dt f hs = 0, P = theta (hs + c) + dt f, whose
+         * discriminant is (theta (hs + c) - dt f)^2 + 4 theta dt f c */
+        double c = p->h_inf, fd = dt * p->f_inf, hs = h1;
+        double P = th * (hs + c) + fd;
+        double Q = th * (hs + c) - fd;
+        double D = Q * Q + 4.0 * th * fd * c;
+        double e = (2.0 * fd * hs) / (P + sqrt(D));
+        double x = hs - e;
+        double mx = th * x;
+        infil = sigma * (m1 - mx); /* the water that went into the soil this step */
+        m1 = mx;
+        h1 = x;
+    }
     /* eq. fvm_2D_eq_frac.05-2: (theta h v)^*, with J^v = J + viscous sums when on */
     double g1, g2;
     if (p->visc) {
@@ -325,7 +343,7 @@ static void step_one(const int32_t *nbr, const uint8_t *code, double a,
     *v1n = mu * g1;
     *v2n = mu * g2;
     if (add) {
-        add[0] = dt * s[5];
+        add[0] = dt * s[5] + infil; /* water leaving the surface: open edges, soil */
         add[1] = clamp;
         add[2] = sigma * dt * r_next;
     }

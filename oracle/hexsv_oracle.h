@@ -81,6 +81,9 @@ typedef struct {
                       Appendix B), in 1/s; 0 for the paper's Darcy-Weisbach runs */
     int32_t visc;  /* 1: augmented momentum flux J^v with artificial viscosity
                       (eqs. eq_artif_visc, eq_visc1), for shocks */
+    double f_inf;  /* infiltration: the mass source loses i(h) = f_inf h / (h + h_inf)
+                      (m/s), taken at h^{n+1}; 0 disables (Sec. 4, future extensions) */
+    double h_inf;  /* depth at which i(h) reaches half of f_inf (m), > 0 when f_inf > 0 */
 } ref_params;
 
 typedef struct {

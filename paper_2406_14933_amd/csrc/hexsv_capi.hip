@@ -280,7 +280,9 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->kc.alpha_s = 0.0;
     s->kc.tau_lin = 0.0;
     s->kc.c_floor = 0.0;
-    s->kc.bc = grid->n_dirichlet > 0 ? 1 : 0;
+    s->kc.ext = grid->n_dirichlet > 0 ? 1 : 0;
+    s->kc.f_inf = 0.0;
+    s->kc.h_inf = 0.0;
     s->kc.visc = 0;
     s->kc.area_active = s->kc.sigma * (double)grid->n_active;
     s->rn.kind = 0;
@@ -405,6 +407,19 @@ extern "C" int hexsv_sim_set_linear_friction(hexsv_sim *s, double tau) {
     if (!(tau >= 0.0) || !isfinite(tau))
         return fail(HEXSV_EDOMAIN, "set_linear_friction: tau=%g must be finite and >= 0", tau);
     s->kc.tau_lin = tau;
+    drop_graph(s);
+    drop_win_graph(s);
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_set_infiltration(hexsv_sim *s, double f_inf, double h_inf) {
+    if (!s) return fail(HEXSV_EINVAL, "set_infiltration: null sim");
+    if (!(f_inf >= 0.0) || !isfinite(f_inf) || !isfinite(h_inf) || (f_inf > 0.0 && !(h_inf > 0.0)))
+        return fail(HEXSV_EDOMAIN, "set_infiltration: f_inf=%g must be >= 0 and h_inf=%g > 0", f_inf,
+                    h_inf);
+    s->kc.f_inf = f_inf;
+    s->kc.h_inf = f_inf > 0.0 ? h_inf : 0.0;
+    s->kc.ext = (s->grid->n_dirichlet > 0 || f_inf > 0.0) ? 1 : 0;
     drop_graph(s);
     drop_win_graph(s);
     return HEXSV_OK;
@@ -1018,6 +1033,8 @@ extern "C" int hexsv_sim_run_surrogate(hexsv_sim *s, hexsv_surrogate *sur, doubl
         return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for the viscous flux");
     if (s->grid->n_dirichlet)
         return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for Dirichlet cells");
+    if (s->kc.f_inf > 0.0)
+        return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for infiltration");
     int64_t a = 0, f = 0;
     const int rc =
         s->prec == HEXSV_FP64

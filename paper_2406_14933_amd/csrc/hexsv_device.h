@@ -105,8 +105,9 @@ struct KConst {
     double area_active;  // sigma * number of active cells
     double tau_lin;      // linear soil resistance -tau h v (Thacker test), 1/s; 0: off
     double c_floor;      // largest |v| + sqrt(g h) of the Dirichlet cells (fixed), 0 if none
+    double f_inf, h_inf; // infiltration i(h) = f_inf h / (h + h_inf) at h^{n+1}; f_inf 0: off
     int32_t visc;        // 1: augmented momentum flux with artificial viscosity
-    int32_t bc;          // 1: the raster holds Dirichlet or given-flux cells
+    int32_t ext;         // 1: Dirichlet or given-flux cells, or infiltration (extended instance)
 };
 
 template <typename T>

@@ -138,8 +138,8 @@ __global__ __launch_bounds__(NT) void k_ensemble(KDom<T> base, const EnsScen *__
 // writes one partial record; k_ens_finalize (one workgroup per scenario) then
 // closes each scenario's step.  Kernel boundaries order the steps.
 // V: the augmented momentum flux with artificial viscosity (set_viscosity);
-// BC: some scenario holds Dirichlet or given-flux cells.
-template <typename T, int TQ, int TR, int NT, bool V, bool BC>
+// EXT: the extended scheme (some scenario holds Dirichlet or given-flux cells).
+template <typename T, int TQ, int TR, int NT, bool V, bool EXT>
 __global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__restrict__ scen,
                                                  const int32_t *__restrict__ tile_scen,
                                                  Ctl *__restrict__ ctl, Part *__restrict__ part,
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__
     const double r_next = rain_rate(scen[s].rn, st.t_next);
     __shared__ TileLDS<T, TQ, TR, V> L;
     Acc acc{0.0, 0.0, 0.0, 0.0};
-    tile_step<T, TQ, TR, NT, true, V, BC>(L, d, g, kc, 0, tq, tr, st.dt, r_next, acc,
+    tile_step<T, TQ, TR, NT, true, V, EXT>(L, d, g, kc, 0, tq, tr, st.dt, r_next, acc,
                                           &ctl[s].err, &ctl[s].err_cell);
     const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
     if (threadIdx.x == 0) part[t] = p;

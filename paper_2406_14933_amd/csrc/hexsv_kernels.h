@@ -28,9 +28,9 @@ namespace hexsv {
 //
 // VISC: the momentum flux is the augmented J^v with artificial viscosity
 // (eqs. eq_artif_visc, eq_visc1), an instance of its own so that the plain
-// scheme pays nothing for it.  BC: the raster holds Dirichlet or given-flux
-// cells, likewise an instance of its own.
-template <typename T, int TQ, int TR, int NT, bool VISC, bool BC>
+// scheme pays nothing for it.  EXT: the extended scheme (Dirichlet or given-flux
+// cells, infiltration), likewise an instance of its own.
+template <typename T, int TQ, int TR, int NT, bool VISC, bool EXT>
 __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRain rn, Ctl *ctl,
                                              KClose cl, int ntq, int ntiles, int par_hint, int in,
                                              int set) {
@@ -51,11 +51,11 @@ __global__ __launch_bounds__(NT) void k_step(KDom<T> d, KGrid g, KConst kc, KRai
     const int rel = o.parity ^ par_hint;  // buffer parity relative to d
     if (rel) tile_load<T, TQ, TR, NT>(R, d, g, 1, tq, tr);
     const double r_next = rain_rate(rn, o.t_next);
-    const bool bad = tile_stage<T, TQ, TR, NT, BC>(L, R, g, kc, tq, tr);
+    const bool bad = tile_stage<T, TQ, TR, NT, EXT>(L, R, g, kc, tq, tr);
     const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
     const bool general = __syncthreads_or((!inner) || bad) != 0;
     Acc acc{0.0, 0.0, 0.0, 0.0};
-    tile_compute<T, TQ, TR, NT, true, VISC, BC>(L, R, general, d, g, kc, rel, tq, tr, o.dt, r_next,
+    tile_compute<T, TQ, TR, NT, true, VISC, EXT>(L, R, general, d, g, kc, rel, tq, tr, o.dt, r_next,
                                                 acc, &ctl->err, &ctl->err_cell);
     const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
     if (threadIdx.x == 0) {
@@ -78,11 +78,11 @@ static hipError_t launch_step_v(const KDom<T> &d, const KGrid &g, const KConst &
             dh.st[0][f] = d.st[1][f];
             dh.st[1][f] = d.st[0][f];
         }
-    // instances: plain, boundary cells, viscosity (which takes boundary cells as well)
+    // instances: plain, extended, viscosity (which takes the extended scheme as well)
     if (kc.visc)
         hipLaunchKernelGGL((k_step<T, TQ, TR, NT, true, true>), dim3(nwg), dim3(NT), 0, stream,
                            dh, g, kc, rn, ctl, cl, ntq, ntiles, par_hint & 1, in, set);
-    else if (kc.bc)
+    else if (kc.ext)
         hipLaunchKernelGGL((k_step<T, TQ, TR, NT, false, true>), dim3(nwg), dim3(NT), 0, stream,
                            dh, g, kc, rn, ctl, cl, ntq, ntiles, par_hint & 1, in, set);
     else

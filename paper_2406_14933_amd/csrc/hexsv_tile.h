@@ -157,9 +157,10 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
 // ----------------------------------------------------------------- stage
 
 // Write the LDS records; returns true if a staged raster cell is inactive.
-// BC: the raster may hold Dirichlet or given-flux cells (theta < 0); an instance
-// without them keeps the plain records.
-template <typename T, int TQ, int TR, int NT, bool BC = false, bool V>
+// EXT: the extended scheme: the raster may hold Dirichlet or given-flux cells
+// (theta < 0), and the mass source may lose infiltration; the plain instance keeps
+// the plain records and mass update.
+template <typename T, int TQ, int TR, int NT, bool EXT = false, bool V>
 __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ, TR, NT> &R,
                                   const KGrid &g, const KConst &kc, int tq, int tr) {
     using Regs = TileRegs<T, TQ, TR, NT>;
@@ -178,7 +179,7 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
         const int s = (lr + 1) * W + (lq + 1);
         if (R.pos[k] != POS_OUTSIDE) {
             const bool act = R.th[k] > T(0);
-            if constexpr (BC) {
+            if constexpr (EXT) {
                 // boundary cells: Dirichlet (-theta: |theta| h) or given flux (-2: the
                 // discharge's depth, and the bed only, as the edge adds the cell's depth)
                 const bool fl = R.th[k] < T(-1.5);
@@ -216,7 +217,7 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
         const int s = lr * W + lq;
         if (R.rpos[k] != POS_OUTSIDE) {
             const bool act = R.rth[k] > T(0);
-            if constexpr (BC) {
+            if constexpr (EXT) {
                 const bool fl = R.rth[k] < T(-1.5);
                 const T m = fl ? R.rh[k] : __builtin_fabs(R.rth[k]) * R.rh[k];
                 const T w = fl ? R.rz[k] : G * (R.rz[k] + R.rh[k]);
@@ -248,7 +249,7 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
 
 // --------------------------------------------------------------- compute
 
-template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V, bool BC = false>
+template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V, bool EXT = false>
 __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ, TR, NT> &R,
                                     bool general, const KDom<T> &d, const KGrid &g,
                                     const KConst &kc, int par, int tq, int tr, double dt,
@@ -305,8 +306,8 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 cd = L.code[sn];
                 if (cd == CODE_WALL) continue;
             }
-            // a cell: interior (or, BC, Dirichlet or flux)
-            if (!GEN || (BC ? cd != CODE_OUTFLOW : cd == CODE_INTERIOR)) {
+            // a cell: interior (or, EXT, a Dirichlet or flux cell)
+            if (!GEN || (EXT ? cd != CODE_OUTFLOW : cd == CODE_INTERIOR)) {
                 const typename Rec<T>::type nb = L.rec[sn];
                 mj = nb.x;
                 wj = nb.y;
@@ -329,11 +330,11 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
             // interface velocity; an edge to a Dirichlet or flux cell carries the prescribed one
             T vb1 = vh1i + vh1j;
             T vb2 = vh2i + vh2j;
-            if (BC && GEN && cd >= CODE_DIRICHLET) {
+            if (EXT && GEN && cd >= CODE_DIRICHLET) {
                 vb1 = vh1j + vh1j;
                 vb2 = vh2j + vh2j;
             }
-            if (BC && GEN && cd == CODE_FLUX) {
+            if (EXT && GEN && cd == CODE_FLUX) {
                 // given mass flux: the discharge h_j v_j crosses the edge whatever the cell
                 // holds; the pressure term sees the cell's own depth over the neighbour's
                 // bed (wj holds that bed level)
@@ -375,7 +376,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 const T Q = dw * msel;
                 A1 -= Q * NXh[e];
                 if (e != 0 && e != 3) A2 -= Q * NYh[e];
-                if (GEN && (BC ? cd != CODE_INTERIOR : cd == CODE_OUTFLOW))
+                if (GEN && (EXT ? cd != CODE_INTERIOR : cd == CODE_OUTFLOW))
                     Fout += F;  // outflow or Dirichlet edge
             } else {
                 const T vn = vb1 * NX[e] + vb2 * NY[e];
@@ -388,7 +389,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 const T P = half_l * (wj - wi) * mhat;
                 S1 -= P * NX[e];
                 S2 -= P * NY[e];
-                if (GEN && (BC ? cd != CODE_INTERIOR : cd == CODE_OUTFLOW))
+                if (GEN && (EXT ? cd != CODE_INTERIOR : cd == CODE_OUTFLOW))
                     Fout += F;  // outflow or Dirichlet edge
             }
             if constexpr (V) {
@@ -440,6 +441,25 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
             } else {
                 g1 = mi * v1i + dts * (A1 + S1);
                 g2 = mi * v2i + dts * (A2 + S2);
+            }
+        }
+        if constexpr (EXT) {
+            if (kc.f_inf > 0.0 && m1 > T(0)) {
+                // the mass source r - i(h^{n+1}) with i(h) = f h / (h + c) turns the mass
+                // update into theta x + dt f x / (x + c) = m1 for x = h^{n+1}.  With
+                // x = h1 - e (h1: the depth without infiltration, which FP32 keeps as an
+                // increment) the loss e is the smaller root of theta e^2 - P e + dt f h1,
+                // P = theta (h1 + c) + dt f; the soil's water is booked with the outflow
+                const T c = (T)kc.h_inf, fd = dtT * (T)kc.f_inf, hs = h1;
+                const T P = thi * (hs + c) + fd;
+                const T Q = thi * (hs + c) - fd;
+                const T Dq = Q * Q + T(4) * thi * fd * c;
+                const T e = p_div(T(2) * fd * hs, P + p_sqrt(Dq));
+                const T x = hs - e;
+                const T mx = thi * x;
+                acc.o += kc.sigma * (double)(m1 - mx);
+                m1 = mx;
+                h1 = x;
             }
         }
         const T K = R.ap[k] * h1 * (T(1) - thi) + thi * alpha_s;
@@ -502,16 +522,16 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
 
 // All three phases for one tile (the caller separates consecutive tiles on
 // the same LDS with a barrier).
-template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V = false, bool BC = false>
+template <typename T, int TQ, int TR, int NT, bool NT_STORE, bool V = false, bool EXT = false>
 __device__ inline void tile_step(TileLDS<T, TQ, TR, V> &L, const KDom<T> &d, const KGrid &g,
                                  const KConst &kc, int par, int tq, int tr, double dt,
                                  double r_next, Acc &acc, int32_t *err_flag, int32_t *err_cell) {
     TileRegs<T, TQ, TR, NT> R;
     tile_load<T, TQ, TR, NT>(R, d, g, par, tq, tr);
-    const bool bad = tile_stage<T, TQ, TR, NT, BC>(L, R, g, kc, tq, tr);
+    const bool bad = tile_stage<T, TQ, TR, NT, EXT>(L, R, g, kc, tq, tr);
     const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
     const bool general = __syncthreads_or((!inner) || bad) != 0;
-    tile_compute<T, TQ, TR, NT, NT_STORE, V, BC>(L, R, general, d, g, kc, par, tq, tr, dt, r_next,
+    tile_compute<T, TQ, TR, NT, NT_STORE, V, EXT>(L, R, general, d, g, kc, par, tq, tr, dt, r_next,
                                              acc, err_flag, err_cell);
 }
 

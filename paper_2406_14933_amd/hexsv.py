@@ -76,6 +76,7 @@ _SIGS = [
     ("hexsv_sim_set_rain", C.c_int, [_VP, C.POINTER(Rain)]),
     ("hexsv_sim_set_linear_friction", C.c_int, [_VP, C.c_double]),
     ("hexsv_sim_set_viscosity", C.c_int, [_VP, C.c_int32]),
+    ("hexsv_sim_set_infiltration", C.c_int, [_VP, C.c_double, C.c_double]),
     ("hexsv_sim_set_state", C.c_int, [_VP, C.c_double, _VP, _VP, _VP, _VP]),
     ("hexsv_sim_run", C.c_int, [_VP, C.c_double, C.c_int64, _VP]),
     ("hexsv_sim_get_state", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -254,6 +255,8 @@ class Sim:
             s.set_linear_friction(sc.tau_lin)
         if getattr(sc, "visc", False):
             s.set_viscosity(True)
+        if getattr(sc, "f_inf", 0.0):
+            s.set_infiltration(sc.f_inf, sc.h_inf)
         s.set_state(sc.h0, sc.v10, sc.v20, 0.0)
         return s
 
@@ -266,6 +269,10 @@ class Sim:
     def set_viscosity(self, on):
         """Momentum flux with artificial viscosity (for shocks); off by default."""
         _check(lib().hexsv_sim_set_viscosity(self._h, int(bool(on))))
+
+    def set_infiltration(self, f_inf, h_inf):
+        """Infiltration i(h) = f_inf h / (h + h_inf) (m/s) in the mass source; 0 turns it off."""
+        _check(lib().hexsv_sim_set_infiltration(self._h, float(f_inf), float(h_inf)))
 
     def set_linear_friction(self, tau):
         """Linear soil resistance -tau h v (1/s), the Thacker test's law; 0 turns it off."""

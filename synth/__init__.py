@@ -63,6 +63,8 @@ class Scenario:
     h_dry: float = 0.0
     tau_lin: float = 0.0  # linear soil resistance -tau*h*v (1/s); 0: the paper's Darcy-Weisbach law
     visc: bool = False    # augmented momentum flux with artificial viscosity (for shocks)
+    f_inf: float = 0.0    # infiltration i(h) = f_inf h / (h + h_inf), m/s; 0: none
+    h_inf: float = 0.0    # its half-rate depth, m
     meta: dict = field(default_factory=dict)
 
     def __post_init__(self):

@@ -9,7 +9,8 @@ def ref_grid(sc):
 
 
 def ref_params(sc):
-    return oracle.params(sc.g, sc.cfl, sc.dt_max, sc.h_dry, sc.alpha_s, sc.tau_lin, sc.visc)
+    return oracle.params(sc.g, sc.cfl, sc.dt_max, sc.h_dry, sc.alpha_s, sc.tau_lin, sc.visc,
+                         sc.f_inf, sc.h_inf)
 
 
 def ref_rain(sc):
