@@ -142,7 +142,9 @@ typedef struct {
     double initial;   /* sum sigma*theta*h at set_state */
     double stored;    /* sum sigma*theta*h now */
     double rain;      /* rain volume added */
-    double outflow;   /* volume that left through OUTFLOW edges */
+    double outflow;   /* volume that left the surface: through OUTFLOW edges, into
+                         the soil (infiltration), and through Dirichlet and flux
+                         edges, where inflow counts negative */
     double clamp;     /* volume added by clamping negative theta*h to zero */
     double residual;  /* |stored - (initial + rain - outflow + clamp)| /
                          (initial + rain + max(-outflow, 0)) */

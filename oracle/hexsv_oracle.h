@@ -96,9 +96,11 @@ typedef struct {
     double initial;  /* sum sigma*theta*h at the start */
     double stored;   /* sum sigma*theta*h now */
     double rain;     /* rain volume added */
-    double outflow;  /* volume that left through OUTFLOW edges */
+    double outflow;  /* volume that left the surface: OUTFLOW edges, the soil, and
+                        Dirichlet / flux edges (inflow counts negative) */
     double clamp;    /* volume added by clamping negative theta*h to 0 */
-    double residual; /* |stored - (initial + rain - outflow + clamp)| / (initial + rain) */
+    double residual; /* |stored - (initial + rain - outflow + clamp)| /
+                        (initial + rain + max(-outflow, 0)) */
     int64_t steps;
     double dt_min, dt_max_seen;
 } ref_books;
