@@ -131,3 +131,20 @@ def test_sensitivity_sweep_of_the_vegetated_flume(hx):
     print(f"[sensitivity] {len(envs) * 9} flumes x 300 s in one ensemble: {sec:.2f} s", flush=True)
     d_p = [r["delta_p"] for r in res[:3]]
     assert d_p[0] < d_p[1] < d_p[2]
+
+
+def test_autotune_keeps_a_viscous_flux_ensemble_batched(hx):
+    """The autotuner times batched variants only when the ensemble carries the viscous flux
+    or boundary cells (the persistent kernel is built for neither), and restores the state:
+    the tuned run still matches the oracle bit for bit."""
+    scs = [_flume(alpha_s=synth.ALPHA_S * k) for k in (0.9, 1.1)]
+    ens = hx.Ensemble.from_scenarios(scs, "fp64")
+    ens.autotune(ksteps=4)
+    assert ens.info()["mode"] == "batched"
+    ens.run(scs[0].t_end)
+    for s, sc in enumerate(scs):
+        ref = ref_run(sc, nthreads=8)
+        got = ens.state_numpy(s)
+        got["books"] = ens.books(s)
+        assert got["books"]["steps"] == ref["books"]["steps"]
+        assert_parity(got, ref, "fp64", f"flume-tuned-{s}")
