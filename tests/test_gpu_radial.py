@@ -92,3 +92,25 @@ def test_paths_without_dirichlet_support_refuse(hx):
     assert ei.value.code == hx.EUNSUPPORTED
     with pytest.raises(ValueError):
         hx.Grid(4, 4, 1.0, active=np.full(16, 4, np.uint8))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_radial_flows_in_one_ensemble(hx, precision):
+    """Crater and hillock (Dirichlet rings, viscous flux) as two scenarios of one batched
+    ensemble, each against its own oracle run."""
+    scs = []
+    for kind in ("crater", "hillock"):
+        sc = synth.radial(kind, a=1.5, t_end=4.0)
+        sc.visc = True
+        scs.append(sc)
+    ens = hx.Ensemble.from_scenarios(scs, precision)
+    assert ens.info()["mode"] == "batched"
+    ens.run(4.0)
+    for s, sc in enumerate(scs):
+        ref = ref_run(sc, nthreads=8)
+        got = ens.state_numpy(s)
+        got["books"] = ens.books(s)
+        if precision == "fp64":
+            assert got["books"]["steps"] == ref["books"]["steps"]
+        assert_parity(got, ref, precision, f"radial-ensemble-{s}")
+        assert_books(got, ref, 1e-12 if precision == "fp64" else 1e-5)
