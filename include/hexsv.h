@@ -390,7 +390,9 @@ int hexsv_surrogate_train_step(hexsv_surrogate *sur, int32_t batch, int32_t nq, 
  * one-sided with one), exact for a plane.  x is the change of one probe step
  * of the scheme (rain included; dt = min(dt_max, CFL bound of the state))
  * scaled by window/dt.  The state and books are not changed.  These are the
- * inputs run_surrogate feeds the network; training pairs use them too. */
+ * inputs run_surrogate feeds the network; training pairs use them too.
+ * EUNSUPPORTED: the sim has Dirichlet or flux cells, the viscous flux or
+ * infiltration (the probe step runs the plain scheme). */
 int hexsv_sim_surrogate_features(hexsv_sim *sim, hexsv_surrogate *sur, double window, int32_t k,
                                  float *d_features, hipStream_t stream);
 

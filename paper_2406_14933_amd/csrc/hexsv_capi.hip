@@ -867,6 +867,9 @@ extern "C" int hexsv_sim_surrogate_features(hexsv_sim *s, hexsv_surrogate *sur, 
     if (!s->state_set) return fail(HEXSV_ESTATE, "surrogate_features: call set_state first");
     if (s->grid->n_dirichlet)
         return fail(HEXSV_EUNSUPPORTED, "surrogate_features: windows are not built for Dirichlet cells");
+    if (s->kc.visc || s->kc.f_inf > 0.0)  // the window's probe step runs the plain scheme
+        return fail(HEXSV_EUNSUPPORTED,
+                    "surrogate_features: windows are not built for the viscous flux or infiltration");
     return s->prec == HEXSV_FP64 ? window_features<double>(s, sur, window, k, d_features, stream)
                                  : window_features<float>(s, sur, window, k, d_features, stream);
 }
@@ -1032,7 +1035,7 @@ extern "C" int hexsv_sim_run_surrogate(hexsv_sim *s, hexsv_surrogate *sur, doubl
     if (s->kc.visc)
         return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for the viscous flux");
     if (s->grid->n_dirichlet)
-        return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for Dirichlet cells");
+        return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for Dirichlet or flux cells");
     if (s->kc.f_inf > 0.0)
         return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for infiltration");
     int64_t a = 0, f = 0;

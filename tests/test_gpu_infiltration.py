@@ -68,6 +68,9 @@ def test_switch_edge_cases(hx):
     with pytest.raises(hx.HexsvError) as ei:
         sim.run_surrogate(hx.Surrogate(), sc.t_end + 10.0, 1.0, 4)
     assert ei.value.code == hx.EUNSUPPORTED
+    with pytest.raises(hx.HexsvError) as ei:
+        sim.surrogate_features(hx.Surrogate(), 1.0, 4)
+    assert ei.value.code == hx.EUNSUPPORTED
 
 
 def test_cost_on_the_catchment(hx):
