@@ -121,7 +121,14 @@ def test_geometry_closed_forms(golden):
         assert l == a
         assert phi == pytest.approx(SQ3 / 4.0 * a, rel=1e-15)
     g = golden("paper_grids.txt")
-    # a "radius" read as the edge length reproduces the paper's cell counts
+    # a "radius" read as the edge length reproduces the paper's printed cell count: 487123
+    # hexagons of edge 0.888231 m tile the 1000 m square of the Thacker test to 0.2 %
+    # (read as the inradius, the same square would hold 365 000 cells, 25 % fewer)
+    sigma, _, _ = oracle.geometry(g["thacker_radius"])
+    assert g["thacker_square"] ** 2 / sigma == pytest.approx(g["thacker_cells"], rel=2e-3)
+    sigma_in, _, _ = oracle.geometry(2.0 * g["thacker_radius"] / SQ3)
+    assert abs(g["thacker_square"] ** 2 / sigma_in / g["thacker_cells"] - 1.0) > 0.2
+    # and puts the derived 650 centres on a 1000 m row
     assert SQ3 * g["thacker_radius"] * g["thacker_row_cells"] == pytest.approx(
         g["thacker_row_length"], rel=1e-6)
     sigma, _, _ = oracle.geometry(g["radial_radius"])

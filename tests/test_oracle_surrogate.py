@@ -228,6 +228,24 @@ def test_apply_window_zero_change_keeps_the_state():
     np.testing.assert_array_equal(hn[:10], h[:10])
 
 
+def test_apply_window_worked_case(golden):
+    """One cell by hand: the new velocity is the predicted discharge over the predicted
+    mass theta h' (not over the start mass), and a depth driven below zero dries the cell."""
+    gv = golden("apply_window.txt")
+    one = lambda k: np.array([gv[k]])
+    out = np.array([[gv["out0"], gv["out1"], gv["out2"]]])
+    ext = (one("x_h"), one("x_q1"), one("x_q2"))
+    hn, v1n, v2n = so.apply_window(one("h"), one("v1"), one("v2"), one("theta"), out,
+                                   gv["dH"], gv["dQ"], ext)
+    assert hn[0] == pytest.approx(gv["h_new"], rel=1e-15)
+    assert v1n[0] == pytest.approx(gv["v1_new"], rel=1e-14)
+    assert v2n[0] == pytest.approx(gv["v2_new"], rel=1e-14)
+    out[0, 0] = gv["dry_out0"]
+    hn, v1n, v2n = so.apply_window(one("h"), one("v1"), one("v2"), one("theta"), out,
+                                   gv["dH"], gv["dQ"], ext)
+    assert hn[0] == 0.0 and v1n[0] == 0.0 and v2n[0] == 0.0
+
+
 def test_features_definition():
     G = oracle.grid(3, 1, 1.0)
     h = np.array([0.1, 0.0, 0.2])

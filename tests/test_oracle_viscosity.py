@@ -36,6 +36,24 @@ def _flat(nq=14, nr=12, seed=3, dry=False, uniform_v=False):
     return sc, G
 
 
+def test_viscous_sums_two_cell_worked_case(golden):
+    """eq_visc1 by value: c_ij is the larger wave speed and mu_ij the harmonic mean of
+    theta h (a minimum, a mean or another mean of either would miss these figures)."""
+    gv = golden("two_cell_viscosity.txt")
+    G = oracle.grid(2, 1, 1.0)
+    th = np.array([gv["theta_i"], gv["theta_j"]])
+    h = np.array([gv["h_i"], gv["h_j"]])
+    v1 = np.array([gv["v1_i"], gv["v1_j"]])
+    v2 = np.array([gv["v2_i"], gv["v2_j"]])
+    Vi = oracle.visc_sums(G, gv["g"], th, h, v1, v2, 0)
+    Vj = oracle.visc_sums(G, gv["g"], th, h, v1, v2, 1)
+    np.testing.assert_allclose(Vi, [gv["V1_i"], gv["V2_i"]], rtol=1e-14)
+    np.testing.assert_allclose(Vj, [gv["V1_j"], gv["V2_j"]], rtol=1e-14)
+    h_dry = np.array([gv["h_i"], 0.0])
+    Vd = oracle.visc_sums(G, gv["g"], th, h_dry, v1, v2, 0)
+    np.testing.assert_array_equal(Vd, [gv["dry_V1_i"], gv["dry_V2_i"]])
+
+
 def test_viscous_sums_vanish_for_a_uniform_velocity():
     sc, G = _flat(uniform_v=True)
     for i in range(G.n):
