@@ -347,7 +347,10 @@ int hexsv_ensemble_info(const hexsv_ensemble *ens, int32_t *workgroups, int32_t 
  * solver stays its fallback and judge).  Layers: hex_conv(11 -> C), ReLU,
  * (layers - 2) x [hex_conv(C -> C), ReLU], hex_conv(C -> 3), where
  * hex_conv(x)[i][o] = b[o] + sum_{t<7, c} W[o][c][t] x[nbr_t(i)][c], tap 0
- * the cell, tap 1+k its neighbour in direction k, zero outside the raster.
+ * the cell, tap 1+k its neighbour in direction k as the raster's neighbour
+ * table defines it (the INTERIOR edges of hexsv_grid_tables: periodic sides
+ * wrap; a tap t >= 1 is zero across a WALL or OUTFLOW side and, on a masked
+ * raster, unless both cells are in the domain).
  * Operands are bfloat16 with FP32 accumulation (MFMA); parameters are an FP32
  * master vector laid out per layer as W[o][c][t] then b[o].  Inputs are 11
  * FP32 features per cell (see hexsv_sim_surrogate_features), outputs 4 FP32 per cell (3 used), for a batch of
@@ -366,18 +369,27 @@ int hexsv_surrogate_get_params(const hexsv_surrogate *sur, float *d_params, int6
  * discharge, input slope (1 <= n <= 8; unset scales are 1). */
 int hexsv_surrogate_set_scales(hexsv_surrogate *sur, const float *scales, int32_t n);
 int hexsv_surrogate_get_scales(const hexsv_surrogate *sur, float *scales, int32_t n);
-/* Batched forward: d_features (batch*nq*nr x 11) -> d_out (batch*nq*nr x 4). */
-int hexsv_surrogate_forward(hexsv_surrogate *sur, int32_t batch, int32_t nq, int32_t nr,
-                            const float *d_features, float *d_out, hipStream_t stream);
-/* Mean L1 loss against d_target (batch*nq*nr x 3) and its parameter gradient
- * (d_grad nullable, num_params floats); synchronises `stream`. */
-int hexsv_surrogate_gradient(hexsv_surrogate *sur, int32_t batch, int32_t nq, int32_t nr,
-                             const float *d_features, const float *d_target, float *d_grad,
-                             double *loss, hipStream_t stream);
+/* Batched forward: d_features (batch*nq*nr x 11) -> d_out (batch*nq*nr x 4).
+ * grid (nullable): the raster whose neighbour rule the taps follow (its nq x nr
+ * must match; EUNSUPPORTED if it holds Dirichlet or flux cells); null means a
+ * walled nq x nr parallelogram with every cell in the domain.  Every cell gets
+ * an output, cells outside the domain included (their tap 0 reads their own
+ * input). */
+int hexsv_surrogate_forward(hexsv_surrogate *sur, const hexsv_grid *grid, int32_t batch,
+                            int32_t nq, int32_t nr, const float *d_features, float *d_out,
+                            hipStream_t stream);
+/* Mean L1 loss over every cell and the 3 outputs against d_target
+ * (batch*nq*nr x 3) and its parameter gradient (d_grad nullable, num_params
+ * floats); grid as for forward; synchronises `stream`. */
+int hexsv_surrogate_gradient(hexsv_surrogate *sur, const hexsv_grid *grid, int32_t batch,
+                             int32_t nq, int32_t nr, const float *d_features,
+                             const float *d_target, float *d_grad, double *loss,
+                             hipStream_t stream);
 /* gradient + one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at rate lr. */
-int hexsv_surrogate_train_step(hexsv_surrogate *sur, int32_t batch, int32_t nq, int32_t nr,
-                               const float *d_features, const float *d_target, float lr,
-                               double *loss, hipStream_t stream);
+int hexsv_surrogate_train_step(hexsv_surrogate *sur, const hexsv_grid *grid, int32_t batch,
+                               int32_t nq, int32_t nr, const float *d_features,
+                               const float *d_target, float lr, double *loss,
+                               hipStream_t stream);
 
 /* Network inputs of a window starting at the simulation's current state,
  * n x 11 FP32 into d_features (scales from set_scales):

@@ -898,7 +898,7 @@ static int window_body(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float
     HIP_TRY(launch_win_probe<T>(d, g, s->kc, s->rn, s->d_ctl, s->d_sw, scr, dt_max, st));
     HIP_TRY(launch_win_features<T>(d, g, l, s->d_ctl, s->d_sw, scr, s->d_slope, dt_max,
                                    feat_scale(sc), 1, x0, op0, st));
-    int rc = sur_forward_x0(sur, g.nq, g.nr, st, &s->d_sw->live);
+    int rc = sur_forward_x0(sur, s->grid, st, &s->d_sw->live);
     if (rc) return rc;
     HIP_TRY(launch_win_apply<T>(d, g, l, s->kc, s->d_ctl, s->d_sw, scr, dt_max, out,
                                 nn::OUT_STRIDE, sc[3], sc[4], 1e-6, part, st));

@@ -50,6 +50,8 @@ int tuned_tile(const char *kernel, int prec, int64_t cells, int fallback);
 // must be rebuilt).
 int sur_window_bind(hexsv_surrogate *s, int nq, int nr, void **x0, const float **out,
                     uint64_t *gen);
-// Network forward over the bound input into the bound output (stream-ordered);
-// the layers do nothing when *live (device, nullable) is 0.
-int sur_forward_x0(hexsv_surrogate *s, int nq, int nr, hipStream_t st, const int32_t *live);
+// Network forward over the bound input into the bound output (stream-ordered),
+// taps following the grid's neighbour rule (periodic sides, domain mask); the
+// layers do nothing when *live (device, nullable) is 0.
+int sur_forward_x0(hexsv_surrogate *s, const hexsv_grid *grid, hipStream_t st,
+                   const int32_t *live);

@@ -12,6 +12,18 @@ constexpr int OUT_STRIDE = 4;  // floats per cell of the network output (3 used)
 constexpr int FEATURES = 11;     // network input channels
 constexpr int FEATURES_PAD = 16; // stored input channels per cell (bf16, zero padded)
 
+// Which raster positions a tap may reach, as in the neighbour table of the
+// scheme: periodic sides wrap (perq: q, perr: r), positions outside the raster
+// are zero, and with an active mask (per raster cell, nonzero = in the domain;
+// nullable: every cell) a tap t >= 1 reads its neighbour only when both the cell
+// and the neighbour are in the domain (tap 0, the cell itself, is always read).
+// The rule is symmetric, so the transposed stencil of the data gradient uses it
+// unchanged.
+struct ConvMask {
+    const uint8_t *active;
+    int perq, perr;
+};
+
 // Workgroups (tiles of 64 x 4 cells) of one conv launch over a batch.
 int conv_tiles(int nq, int nr, int batch);
 
@@ -22,10 +34,11 @@ int conv_tiles(int nq, int nr, int batch);
 // live (nullable, device): the launch does nothing unless *live != 0.
 hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf16 *wm,
                        const float *bias, void *out, const __bf16 *mask, int nq, int nr,
-                       int batch, int cout_real, hipStream_t st, const int32_t *live = nullptr);
+                       int batch, int cout_real, const ConvMask &cm, hipStream_t st,
+                       const int32_t *live = nullptr);
 // Per-tile weight-gradient partials (7*coutp*cinp + coutp floats per tile).
 hipError_t launch_wgrad(int cinp, int coutp, const __bf16 *x, const __bf16 *dy, float *part,
-                        int nq, int nr, int batch, hipStream_t st);
+                        int nq, int nr, int batch, const ConvMask &cm, hipStream_t st);
 hipError_t launch_wgrad_reduce(const float *part, int ntiles, int cinp, int coutp, int cin,
                                int cout, float *grad, hipStream_t st);
 hipError_t launch_prepare_weights(const float *p, int cin, int cout, int cinp, int coutp,

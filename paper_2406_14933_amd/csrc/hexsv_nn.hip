@@ -4,8 +4,10 @@
 //
 // Hex convolution on an nq x nr raster (per sample of a batch):
 //   y[i][o] = b[o] + sum_{t<7, c} W[o][c][t] * x[nbr_t(i)][c]
-// tap 0 is the cell, tap 1+k its neighbour in direction k, zero outside the
-// raster.  Activations are channels-last bfloat16 (x[cell][c], C = 8 or 32).
+// tap 0 is the cell, tap 1+k its neighbour in direction k: the neighbour of
+// the scheme's tables (periodic sides wrap; zero outside the raster and, on a
+// masked raster, unless both cells are in the domain; see ConvMask).
+// Activations are channels-last bfloat16 (x[cell][c], C = 16 or 32).
 //
 // MFMA mapping (v_mfma_f32_16x16x32_bf16): the output block is 16 output
 // channels x 16 cells, A = weights (16 channels x 32 K), B = gathered
@@ -41,31 +43,41 @@ __device__ inline int tile_of(int tile, int ntq, int ntr, int &b, int &q0, int &
 }
 
 // Stage the (TQ+2) x (TR+2) halo of channels-last bf16 activations of one
-// sample into LDS as 16-byte chunks; positions outside the raster are zero.
-// All of a thread's loads are issued before any LDS store, so the staging
-// costs one memory latency rather than one per chunk.
+// sample into LDS as 16-byte chunks, with periodic wraps; positions outside the
+// raster are zero.  fl[slot] is 1 where the slot holds a cell of the domain
+// (written only on masked rasters, where the taps test it).  All of a thread's
+// loads are issued before any LDS store, so the staging costs one memory
+// latency rather than one per chunk.
 template <int C>
-__device__ inline void stage_act(uint4 *lds, const __bf16 *__restrict__ x, int nq, int nr,
-                                 int64_t sample_off, int q0, int r0) {
+__device__ inline void stage_act(uint4 *lds, uint8_t *fl, const __bf16 *__restrict__ x, int nq,
+                                 int nr, int64_t sample_off, int q0, int r0, const ConvMask &cm) {
     constexpr int CH = C / 8;  // 16-byte chunks per cell
     constexpr int ITERS = (NSLOT * CH + NT - 1) / NT;
     uint4 v[ITERS];
+    uint8_t a[ITERS];
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
         const int e = threadIdx.x + it * NT;
         const int s = e / CH, ch = e - s * CH;
         const int lr = s / SW, lq = s - lr * SW;
-        const int q = q0 + lq - 1, r = r0 + lr - 1;
+        int q = q0 + lq - 1, r = r0 + lr - 1;
+        if (cm.perq) q = q < 0 ? q + nq : (q >= nq ? q - nq : q);
+        if (cm.perr) r = r < 0 ? r + nr : (r >= nr ? r - nr : r);
         v[it] = make_uint4(0u, 0u, 0u, 0u);
+        a[it] = 0;
         if (e < NSLOT * CH && q >= 0 && q < nq && r >= 0 && r < nr) {
             const int64_t i = sample_off + (int64_t)r * nq + q;
             v[it] = reinterpret_cast<const uint4 *>(x + i * C)[ch];
+            if (cm.active && ch == 0) a[it] = cm.active[(int64_t)r * nq + q] != 0;
         }
     }
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
         const int e = threadIdx.x + it * NT;
-        if (e < NSLOT * CH) lds[e] = v[it];
+        if (e < NSLOT * CH) {
+            lds[e] = v[it];
+            if (cm.active && (e % CH) == 0) fl[e / CH] = a[it];
+        }
     }
 }
 
@@ -81,12 +93,13 @@ __global__ __launch_bounds__(NT) void k_hexconv(const __bf16 *__restrict__ x,
                                                 const float *__restrict__ bias, void *out,
                                                 const __bf16 *__restrict__ mask, int nq, int nr,
                                                 int ntiles_total, int cout_real,
-                                                const int32_t *live) {
+                                                const int32_t *live, ConvMask cm) {
     constexpr int CH = CIN / 8;
     constexpr int MB = COUT / 16;                 // output-channel blocks
     constexpr int TPK = 32 / CIN;                 // taps per K step of 32
     constexpr int KSTEPS = (7 + TPK - 1) / TPK;
     __shared__ uint4 lds[NSLOT * CH];
+    __shared__ uint8_t fl[NSLOT];
     const int ntq = (nq + TQ - 1) / TQ, ntr = (nr + TR - 1) / TR;
     // XCD-banded tile order: every layer gives a tile to the same XCD, so the
     // activations a layer writes are mostly read back from that XCD's L2
@@ -96,8 +109,9 @@ __global__ __launch_bounds__(NT) void k_hexconv(const __bf16 *__restrict__ x,
     int b, q0, r0;
     tile_of(tile, ntq, ntr, b, q0, r0);
     const int64_t soff = (int64_t)b * nq * nr;
-    stage_act<CIN>(lds, x, nq, nr, soff, q0, r0);
+    stage_act<CIN>(lds, fl, x, nq, nr, soff, q0, r0, cm);
     __syncthreads();
+    const bool masked = cm.active != nullptr;
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;  // wave w: tile row w
     const int g = lane >> 4, l16 = lane & 15;
@@ -127,7 +141,10 @@ __global__ __launch_bounds__(NT) void k_hexconv(const __bf16 *__restrict__ x,
             const int s = (w + 1) * SW + (lq + 1);   // its staged slot
             bf16x8 bv = bf16x8{};
             if (tap < 7) {
-                const uint4 raw = lds[(s + OFFS[tap]) * CH + c0 / 8];
+                uint4 raw = lds[(s + OFFS[tap]) * CH + c0 / 8];
+                // masked raster: a neighbour tap needs both cells in the domain
+                if (masked && tap > 0 && !(fl[s] & fl[s + OFFS[tap]]))
+                    raw = make_uint4(0u, 0u, 0u, 0u);
                 bv = *reinterpret_cast<const bf16x8 *>(&raw);
             }
 #pragma unroll
@@ -187,12 +204,13 @@ template <int CIN, int COUT>
 __global__ __launch_bounds__(NT) void k_hexconv_wgrad(const __bf16 *__restrict__ x,
                                                       const __bf16 *__restrict__ dy,
                                                       float *__restrict__ part, int nq, int nr,
-                                                      int ntiles_total) {
+                                                      int ntiles_total, ConvMask cm) {
     constexpr int CH = CIN / 8;
     constexpr int MB = COUT / 16;
     constexpr int NB = CIN == 32 ? 2 : 1;
     constexpr int PSZ = 7 * COUT * CIN + COUT;
     __shared__ uint4 lds[NSLOT * CH];
+    __shared__ uint8_t fl[NSLOT];
     __shared__ __bf16 sdy[TQ * TR * COUT];
     const int ntq = (nq + TQ - 1) / TQ, ntr = (nr + TR - 1) / TR;
     const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles_total, 0);
@@ -201,7 +219,8 @@ __global__ __launch_bounds__(NT) void k_hexconv_wgrad(const __bf16 *__restrict__
     int b, q0, r0;
     tile_of(tile, ntq, ntr, b, q0, r0);
     const int64_t soff = (int64_t)b * nq * nr;
-    stage_act<CIN>(lds, x, nq, nr, soff, q0, r0);
+    stage_act<CIN>(lds, fl, x, nq, nr, soff, q0, r0, cm);
+    const bool masked = cm.active != nullptr;
     // dy of the tile's cells (zero outside the raster), channels-last; loads first
     constexpr int DITERS = (TQ * TR * COUT / 8 + NT - 1) / NT;
     uint4 dv[DITERS];
@@ -254,8 +273,10 @@ __global__ __launch_bounds__(NT) void k_hexconv_wgrad(const __bf16 *__restrict__
                 const int ci = n * 16 + l16;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const int s = (lr + 1) * SW + (lq0 + j + 1) + OFFS[tap];
-                    const uint16_t u = ci < CIN ? sx16[s * CIN + ci] : (uint16_t)0;
+                    const int sc = (lr + 1) * SW + (lq0 + j + 1);
+                    const int s = sc + OFFS[tap];
+                    uint16_t u = ci < CIN ? sx16[s * CIN + ci] : (uint16_t)0;
+                    if (masked && tap > 0 && !(fl[sc] & fl[s])) u = 0;
                     bv[n][j] = __builtin_bit_cast(__bf16, u);
                 }
             }
@@ -408,12 +429,13 @@ int conv_tiles(int nq, int nr, int batch) {
 
 hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf16 *wm,
                        const float *bias, void *out, const __bf16 *mask, int nq, int nr,
-                       int batch, int cout_real, hipStream_t st, const int32_t *live) {
+                       int batch, int cout_real, const ConvMask &cm, hipStream_t st,
+                       const int32_t *live) {
     const int nt = conv_tiles(nq, nr, batch);
 #define HEXSV_CONV(CI, CO, E)                                                                   \
     if (cinp == CI && coutp == CO && epi == E) {                                                \
         hipLaunchKernelGGL((k_hexconv<CI, CO, E>), dim3(nt), dim3(NT), 0, st, x, wm, bias, out, \
-                           mask, nq, nr, nt, cout_real, live);                                  \
+                           mask, nq, nr, nt, cout_real, live, cm);                              \
         return hipGetLastError();                                                               \
     }
     HEXSV_CONV(16, 32, EPI_RELU)
@@ -426,12 +448,12 @@ hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf
 }
 
 hipError_t launch_wgrad(int cinp, int coutp, const __bf16 *x, const __bf16 *dy, float *part,
-                        int nq, int nr, int batch, hipStream_t st) {
+                        int nq, int nr, int batch, const ConvMask &cm, hipStream_t st) {
     const int nt = conv_tiles(nq, nr, batch);
 #define HEXSV_WG(CI, CO)                                                                       \
     if (cinp == CI && coutp == CO) {                                                           \
         hipLaunchKernelGGL((k_hexconv_wgrad<CI, CO>), dim3(nt), dim3(NT), 0, st, x, dy, part, nq, \
-                           nr, nt);                                                            \
+                           nr, nt, cm);                                                        \
         return hipGetLastError();                                                              \
     }
     HEXSV_WG(16, 32)

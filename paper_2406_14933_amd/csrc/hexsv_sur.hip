@@ -195,16 +195,30 @@ extern "C" int hexsv_surrogate_get_scales(const hexsv_surrogate *s, float *scale
     return HEXSV_OK;
 }
 
+// Tap rule of a raster: its periodic sides and its domain mask (no grid: a
+// walled nq x nr parallelogram with every cell in the domain).
+static int conv_mask(const hexsv_grid *g, int nq, int nr, nn::ConvMask *cm, const char *who) {
+    *cm = nn::ConvMask{nullptr, 0, 0};
+    if (!g) return HEXSV_OK;
+    if (g->kg.nq != nq || g->kg.nr != nr)
+        return fail(HEXSV_EINVAL, "%s: the raster is %d x %d, the grid %d x %d", who, nq, nr,
+                    g->kg.nq, g->kg.nr);
+    if (g->n_dirichlet)
+        return fail(HEXSV_EUNSUPPORTED, "%s: not built for Dirichlet or flux cells", who);
+    *cm = nn::ConvMask{g->d_active, g->kg.perq, g->kg.perr};
+    return HEXSV_OK;
+}
+
 // Forward over the packed features already in s->x0; output in s->out.
-static int forward_packed(hexsv_surrogate *s, int nq, int nr, int batch, hipStream_t st,
-                          const int32_t *live = nullptr) {
+static int forward_packed(hexsv_surrogate *s, int nq, int nr, int batch, const nn::ConvMask &cm,
+                          hipStream_t st, const int32_t *live = nullptr) {
     const __bf16 *x = s->x0;
     for (int l = 0; l < s->layers; ++l) {
         const SurLayer &y = s->L[l];
         const bool last = l == s->layers - 1;
         void *o = last ? (void *)s->out : (void *)s->act[l];
         HIP_TRY(nn::launch_conv(y.cinp, y.coutp, last ? nn::EPI_LIN : nn::EPI_RELU, x, y.wm, y.bias,
-                                o, nullptr, nq, nr, batch, y.cout, st, live));
+                                o, nullptr, nq, nr, batch, y.cout, cm, st, live));
         if (!last) x = s->act[l];
     }
     return HEXSV_OK;
@@ -217,14 +231,18 @@ static int check_shape(hexsv_surrogate *s, int batch, int nq, int nr, int64_t *c
     return ensure_ws(s, *cells, nn::conv_tiles(nq, nr, batch));
 }
 
-extern "C" int hexsv_surrogate_forward(hexsv_surrogate *s, int32_t batch, int32_t nq, int32_t nr,
-                                       const float *d_features, float *d_out, hipStream_t st) {
+extern "C" int hexsv_surrogate_forward(hexsv_surrogate *s, const hexsv_grid *grid, int32_t batch,
+                                       int32_t nq, int32_t nr, const float *d_features,
+                                       float *d_out, hipStream_t st) {
     if (!s || !d_features || !d_out) return fail(HEXSV_EINVAL, "surrogate_forward: null argument");
+    nn::ConvMask cm;
+    int rc = conv_mask(grid, nq, nr, &cm, "surrogate_forward");
+    if (rc) return rc;
     int64_t cells;
-    int rc = check_shape(s, batch, nq, nr, &cells);
+    rc = check_shape(s, batch, nq, nr, &cells);
     if (rc) return rc;
     HIP_TRY(nn::launch_pack_features(d_features, cells, s->x0, st));
-    rc = forward_packed(s, nq, nr, batch, st);
+    rc = forward_packed(s, nq, nr, batch, cm, st);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(d_out, s->out, sizeof(float) * nn::OUT_STRIDE * cells,
                            hipMemcpyDeviceToDevice, st));
@@ -244,18 +262,25 @@ int sur_window_bind(hexsv_surrogate *s, int nq, int nr, void **x0, const float *
     return HEXSV_OK;
 }
 
-int sur_forward_x0(hexsv_surrogate *s, int nq, int nr, hipStream_t st, const int32_t *live) {
-    return forward_packed(s, nq, nr, 1, st, live);
+int sur_forward_x0(hexsv_surrogate *s, const hexsv_grid *grid, hipStream_t st,
+                   const int32_t *live) {
+    nn::ConvMask cm;
+    int rc = conv_mask(grid, grid->kg.nq, grid->kg.nr, &cm, "run_surrogate");
+    if (rc) return rc;
+    return forward_packed(s, grid->kg.nq, grid->kg.nr, 1, cm, st, live);
 }
 
 // Forward + L1 loss + backward into s->d_g; loss in *loss (synchronises).
-static int gradient(hexsv_surrogate *s, int batch, int nq, int nr, const float *feat,
-                    const float *target, double *loss, hipStream_t st) {
+static int gradient(hexsv_surrogate *s, const hexsv_grid *grid, int batch, int nq, int nr,
+                    const float *feat, const float *target, double *loss, hipStream_t st) {
+    nn::ConvMask cm;
+    int rc = conv_mask(grid, nq, nr, &cm, "surrogate_gradient");
+    if (rc) return rc;
     int64_t cells;
-    int rc = check_shape(s, batch, nq, nr, &cells);
+    rc = check_shape(s, batch, nq, nr, &cells);
     if (rc) return rc;
     HIP_TRY(nn::launch_pack_features(feat, cells, s->x0, st));
-    rc = forward_packed(s, nq, nr, batch, st);
+    rc = forward_packed(s, nq, nr, batch, cm, st);
     if (rc) return rc;
     const double inv_count = 1.0 / (3.0 * (double)cells);
     HIP_TRY(nn::launch_l1_loss(s->out, target, cells, inv_count, s->dy_last, s->lpart, LOSS_PARTS, st));
@@ -265,13 +290,13 @@ static int gradient(hexsv_surrogate *s, int batch, int nq, int nr, const float *
     for (int l = s->layers - 1; l >= 0; --l) {
         const SurLayer &y = s->L[l];
         const __bf16 *xin = l == 0 ? s->x0 : s->act[l - 1];
-        HIP_TRY(nn::launch_wgrad(y.cinp, y.coutp, xin, dy, s->wpart, nq, nr, batch, st));
+        HIP_TRY(nn::launch_wgrad(y.cinp, y.coutp, xin, dy, s->wpart, nq, nr, batch, cm, st));
         HIP_TRY(nn::launch_wgrad_reduce(s->wpart, tiles, y.cinp, y.coutp, y.cin, y.cout, s->d_g + y.off, st));
         if (l > 0) {
             __bf16 *dx = buf[l & 1];
             // data gradient: input channels of the transposed stencil = coutp, output = cinp
             HIP_TRY(nn::launch_conv(y.coutp, y.cinp, nn::EPI_MASK, dy, y.wt, nullptr, dx, s->act[l - 1],
-                                    nq, nr, batch, y.cin, st));
+                                    nq, nr, batch, y.cin, cm, st));
             dy = dx;
         }
     }
@@ -283,22 +308,24 @@ static int gradient(hexsv_surrogate *s, int batch, int nq, int nr, const float *
     return HEXSV_OK;
 }
 
-extern "C" int hexsv_surrogate_gradient(hexsv_surrogate *s, int32_t batch, int32_t nq, int32_t nr,
-                                        const float *d_features, const float *d_target,
-                                        float *d_grad, double *loss, hipStream_t st) {
+extern "C" int hexsv_surrogate_gradient(hexsv_surrogate *s, const hexsv_grid *grid, int32_t batch,
+                                        int32_t nq, int32_t nr, const float *d_features,
+                                        const float *d_target, float *d_grad, double *loss,
+                                        hipStream_t st) {
     if (!s || !d_features || !d_target) return fail(HEXSV_EINVAL, "surrogate_gradient: null argument");
-    int rc = gradient(s, batch, nq, nr, d_features, d_target, loss, st);
+    int rc = gradient(s, grid, batch, nq, nr, d_features, d_target, loss, st);
     if (rc) return rc;
     if (d_grad)
         HIP_TRY(hipMemcpyAsync(d_grad, s->d_g, sizeof(float) * s->nparams, hipMemcpyDeviceToDevice, st));
     return HEXSV_OK;
 }
 
-extern "C" int hexsv_surrogate_train_step(hexsv_surrogate *s, int32_t batch, int32_t nq, int32_t nr,
+extern "C" int hexsv_surrogate_train_step(hexsv_surrogate *s, const hexsv_grid *grid,
+                                          int32_t batch, int32_t nq, int32_t nr,
                                           const float *d_features, const float *d_target, float lr,
                                           double *loss, hipStream_t st) {
     if (!s || !d_features || !d_target || !(lr > 0.f)) return fail(HEXSV_EINVAL, "surrogate_train_step: bad argument");
-    int rc = gradient(s, batch, nq, nr, d_features, d_target, loss, st);
+    int rc = gradient(s, grid, batch, nq, nr, d_features, d_target, loss, st);
     if (rc) return rc;
     s->adam_step += 1;
     HIP_TRY(nn::launch_adam(s->d_p, s->d_m, s->d_v, s->d_g, s->nparams, lr, s->adam_step, st));

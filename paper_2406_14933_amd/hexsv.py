@@ -111,10 +111,11 @@ _SIGS = [
     ("hexsv_surrogate_get_params", C.c_int, [_VP, _VP, C.c_int64, _VP]),
     ("hexsv_surrogate_set_scales", C.c_int, [_VP, C.POINTER(C.c_float), C.c_int32]),
     ("hexsv_surrogate_get_scales", C.c_int, [_VP, C.POINTER(C.c_float), C.c_int32]),
-    ("hexsv_surrogate_forward", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP, _VP]),
-    ("hexsv_surrogate_gradient", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP, _VP,
-                                           C.POINTER(C.c_double), _VP]),
-    ("hexsv_surrogate_train_step", C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
+    ("hexsv_surrogate_forward", C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
+                                          _VP]),
+    ("hexsv_surrogate_gradient", C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
+                                           _VP, C.POINTER(C.c_double), _VP]),
+    ("hexsv_surrogate_train_step", C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
                                              C.c_float, C.POINTER(C.c_double), _VP]),
     ("hexsv_sim_surrogate_features", C.c_int, [_VP, _VP, C.c_double, C.c_int32, _VP, _VP]),
     ("hexsv_sim_run_surrogate", C.c_int, [_VP, _VP, C.c_double, C.c_double, C.c_int32,
@@ -505,29 +506,33 @@ class Surrogate:
             raise ValueError("array does not hold whole samples")
         return n // (nq * nr)
 
-    def forward(self, features, nq, nr):
+    # grid (optional): the raster whose neighbour rule the taps follow (periodic sides, the
+    # domain mask); without it the raster is a walled nq x nr parallelogram
+    def forward(self, features, nq, nr, grid=None):
         f = _dev(features, dtype=torch.float32)
         batch = self._shape(f, nq, nr, self.FEATURES)
         out = torch.empty((batch * nq * nr, 4), dtype=torch.float32, device="cuda")
-        _check(lib().hexsv_surrogate_forward(self._h, batch, int(nq), int(nr), _ptr(f), _ptr(out),
-                                             _stream()))
+        _check(lib().hexsv_surrogate_forward(self._h, grid._h if grid else None, batch, int(nq),
+                                             int(nr), _ptr(f), _ptr(out), _stream()))
         return out
 
-    def gradient(self, features, target, nq, nr):
+    def gradient(self, features, target, nq, nr, grid=None):
         f = _dev(features, dtype=torch.float32)
         t = _dev(target, dtype=torch.float32)
         batch = self._shape(f, nq, nr, self.FEATURES)
         g = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
         loss = C.c_double()
-        _check(lib().hexsv_surrogate_gradient(self._h, batch, int(nq), int(nr), _ptr(f), _ptr(t),
-                                              _ptr(g), C.byref(loss), _stream()))
+        _check(lib().hexsv_surrogate_gradient(self._h, grid._h if grid else None, batch, int(nq),
+                                              int(nr), _ptr(f), _ptr(t), _ptr(g), C.byref(loss),
+                                              _stream()))
         return loss.value, g
 
-    def train_step(self, features, target, nq, nr, lr):
+    def train_step(self, features, target, nq, nr, lr, grid=None):
         batch = self._shape(features, nq, nr, self.FEATURES)
         loss = C.c_double()
-        _check(lib().hexsv_surrogate_train_step(self._h, batch, int(nq), int(nr), _ptr(features),
-                                                _ptr(target), float(lr), C.byref(loss), _stream()))
+        _check(lib().hexsv_surrogate_train_step(self._h, grid._h if grid else None, batch,
+                                                int(nq), int(nr), _ptr(features), _ptr(target),
+                                                float(lr), C.byref(loss), _stream()))
         return loss.value
 
     def __del__(self):

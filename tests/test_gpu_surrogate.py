@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+import synth
 from oracle import surrogate as so
 from tests.test_gpu_parity import hx  # noqa: F401  (fixture)
 
@@ -94,3 +95,96 @@ def test_training_reduces_loss(hx):
     losses = [sur.train_step(f, t, nq, nr, 3e-3) for _ in range(300)]
     print(f"[surrogate train] loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < 0.3 * losses[0]
+
+
+# Rasters whose neighbour rule is not the walled parallelogram's: a hexagonal domain cut by
+# the mask with an OUTFLOW rim (a cone's domain), a strip periodic in q with a ragged last
+# tile, and a raster periodic on both sides.  The oracle convolves through the tables of the
+# scheme (ref_tables), so these check that the kernels' taps follow the same rule: wrapped
+# across periodic seams, zero across the mask unless both cells are in the domain, and the
+# cell's own tap read even outside the domain.
+RASTERS = {
+    "cone-outflow-rim": dict(nq=73, nr=73, side=(synth.WALL,) * 4, mask_R=35,
+                             mask_bc=synth.OUTFLOW),
+    "strip-periodic-q": dict(nq=70, nr=9, side=(synth.OUTFLOW, synth.PERIODIC, synth.WALL,
+                                                 synth.PERIODIC)),
+    "torus": dict(nq=40, nr=12, side=(synth.PERIODIC,) * 4),
+}
+
+
+def raster(hx, kind):
+    d = RASTERS[kind]
+    nq, nr = d["nq"], d["nr"]
+    act = synth.hexagon_mask(nq, nr, d["mask_R"]) if "mask_R" in d else None
+    mbc = d.get("mask_bc", synth.WALL)
+    G = oracle.grid(nq, nr, 1.0, d["side"], (), act, mbc)
+    grid = hx.Grid(nq, nr, 1.0, d["side"], (), act, mbc)
+    return nq, nr, G, grid
+
+
+@pytest.mark.parametrize("kind", list(RASTERS))
+def test_forward_follows_the_raster_tables(hx, kind):
+    nq, nr, G, grid = raster(hx, kind)
+    batch, layers = 2, 4
+    rng = np.random.default_rng(21)
+    p = (so.init_params(21, layers, 32, out_scale=1.0)
+         + rng.normal(scale=0.02, size=so.num_params(layers, 32))).astype(np.float32)
+    # inputs everywhere, cells outside the domain included (their own tap reads them)
+    feats = rng.normal(size=(batch, nq * nr, so.FEATURES)).astype(np.float32)
+    sur = hx.Surrogate(layers, 32)
+    sur.set_params(p)
+    print(f"[surrogate fwd {kind} {nq}x{nr}]", flush=True)
+    out = sur.forward(feats.reshape(-1, so.FEATURES), nq, nr, grid=grid).cpu().numpy()
+    out = out.reshape(batch, nq * nr, 4)
+    plain = sur.forward(feats.reshape(-1, so.FEATURES), nq, nr).cpu().numpy()
+    plain = plain.reshape(batch, nq * nr, 4)
+    for b in range(batch):
+        ref, _, _ = so.forward(G, p, feats[b].astype(np.float64), layers, 32, bf16=True)
+        e = rel_l2(out[b, :, :3], ref)
+        # the walled-parallelogram rule differs from these tables
+        e_plain = rel_l2(plain[b, :, :3], ref)
+        print(f"  b{b}: rel L2 {e:.2e} (walled-parallelogram rule: {e_plain:.2e})")
+        assert e <= 1e-2
+        assert e_plain > 10 * e
+
+
+@pytest.mark.parametrize("kind", list(RASTERS))
+def test_gradient_follows_the_raster_tables(hx, kind):
+    nq, nr, G, grid = raster(hx, kind)
+    layers, batch = 4, 2
+    rng = np.random.default_rng(22)
+    p = (so.init_params(22, layers, 32, out_scale=1.0)
+         + rng.normal(scale=0.02, size=so.num_params(layers, 32))).astype(np.float32)
+    feats = rng.normal(size=(batch, nq * nr, so.FEATURES)).astype(np.float32)
+    tgt = rng.normal(size=(batch, nq * nr, 3)).astype(np.float32)
+    sur = hx.Surrogate(layers, 32)
+    sur.set_params(p)
+    print(f"[surrogate grad {kind} {nq}x{nr}]", flush=True)
+    loss, g = sur.gradient(feats.reshape(-1, so.FEATURES), tgt.reshape(-1, 3), nq, nr, grid=grid)
+    g = g.cpu().numpy()
+    rl, rg = so.loss_and_grad(G, p, [f.astype(np.float64) for f in feats],
+                              [t.astype(np.float64) for t in tgt], layers, 32, bf16=True)
+    assert loss == pytest.approx(rl, rel=2e-3)
+    k = 0
+    for li, (ci, co) in enumerate(so.layer_shapes(layers, 32)):
+        nw = co * ci * 7
+        ew = rel_l2(g[k:k + nw], rg[k:k + nw])
+        eb = rel_l2(g[k + nw:k + nw + co], rg[k + nw:k + nw + co])
+        print(f"  layer {li}: W rel L2 {ew:.2e}  b rel L2 {eb:.2e}")
+        assert ew <= 2e-2 and eb <= 2e-2
+        k += nw + co
+
+
+def test_conv_refuses_a_mismatched_or_dirichlet_grid(hx):
+    sur = hx.Surrogate(4, 32)
+    sur.set_params(so.init_params(1, 4, 32))
+    f = torch.zeros((20 * 12, so.FEATURES), dtype=torch.float32, device="cuda")
+    with pytest.raises(hx.HexsvError) as e:
+        sur.forward(f, 20, 12, grid=hx.Grid(12, 20, 1.0))
+    assert e.value.code == hx.EINVAL
+    act = np.ones(20 * 12, np.uint8)
+    act[:20] = 2  # a row of Dirichlet cells
+    with pytest.raises(hx.HexsvError) as e:
+        sur.forward(f, 20, 12, grid=hx.Grid(20, 12, 1.0, active=act))
+    assert e.value.code == hx.EUNSUPPORTED
+    torch.cuda.synchronize()
