@@ -37,7 +37,8 @@ def build(quiet: bool = True) -> str:
 class RefParams(C.Structure):
     _fields_ = [("g", C.c_double), ("cfl", C.c_double), ("dt_max", C.c_double),
                 ("h_dry", C.c_double), ("alpha_s", C.c_double), ("tau_lin", C.c_double),
-                ("visc", C.c_int32), ("f_inf", C.c_double), ("h_inf", C.c_double)]
+                ("visc", C.c_int32), ("f_inf", C.c_double), ("h_inf", C.c_double),
+                ("alpha_s_cell", C.c_void_p)]
 
 
 class RefRain(C.Structure):
@@ -188,7 +189,15 @@ def mu(alpha, beta, g1, g2):
 
 def params(g=9.81, cfl=0.5, dt_max=1.0, h_dry=0.0, alpha_s=0.0, tau_lin=0.0, visc=False,
            f_inf=0.0, h_inf=0.0):
-    return RefParams(g, cfl, dt_max, h_dry, alpha_s, tau_lin, int(bool(visc)), f_inf, h_inf)
+    """alpha_s: one Darcy-Weisbach coefficient, or an array of one per cell (eq_tsa_darcy)."""
+    field = None
+    if np.ndim(alpha_s) > 0:
+        field = np.ascontiguousarray(alpha_s, dtype=np.float64).reshape(-1)
+        alpha_s = 0.0
+    p = RefParams(g, cfl, dt_max, h_dry, float(alpha_s), tau_lin, int(bool(visc)), f_inf, h_inf,
+                  field.ctypes.data if field is not None else None)
+    p._alpha_s_field = field  # keeps the array alive while the parameters are used
+    return p
 
 
 def rain(kind=0, i_a=0.0, t_a=0.0, T_d=float("inf")):

@@ -332,7 +332,9 @@ static void step_one(const int32_t *nbr, const uint8_t *code, double a,
         g2 = mi * v2[i] + dts * (s[2] + s[4]);
     }
     /* eq. fvm_2D_eq_frac.06-2 solved by the miu-formula, with eq_K_h_theta */
-    double K = alpha_p[i] * h1 * (1.0 - th) + th * p->alpha_s;
+    /* eq_tsa_darcy: alpha_s of the soil under cell i (one value, or a field) */
+    double as = p->alpha_s_cell ? p->alpha_s_cell[i] : p->alpha_s;
+    double K = alpha_p[i] * h1 * (1.0 - th) + th * as;
     double beta = dt * K;
     /* the linear soil term theta*tau*h*v (Thacker test), implicit in v^{n+1}:
      * it adds dt*tau*theta*h^{n+1} = dt*tau*m^{n+1} to the coefficient of v */

@@ -84,6 +84,8 @@ typedef struct {
     double f_inf;  /* infiltration: the mass source loses i(h) = f_inf h / (h + h_inf)
                       (m/s), taken at h^{n+1}; 0 disables (Sec. 4, future extensions) */
     double h_inf;  /* depth at which i(h) reaches half of f_inf (m), > 0 when f_inf > 0 */
+    const double *alpha_s_cell; /* nullable: Darcy-Weisbach coefficient per cell (N values),
+                                   replacing alpha_s (eq_tsa_darcy with a soil that varies) */
 } ref_params;
 
 typedef struct {

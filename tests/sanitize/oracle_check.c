@@ -97,7 +97,13 @@ static void run_case(const Case *c) {
             else if (act[i] == 3) { th[i] = -1.0; h[i] = 0.04; v1[i] = 0.5; v2[i] = 0.0; }
         }
     }
-    ref_params p = {9.81, 0.5, 1.0, 0.0, 0.00709, 0.0, c->visc, c->f_inf, 0.005};
+    ref_params p = {9.81, 0.5, 1.0, 0.0, 0.00709, 0.0, c->visc, c->f_inf, 0.005, NULL};
+    double *soil = NULL;
+    if (strcmp(c->name, "walls") == 0) { /* a soil coefficient per cell */
+        soil = malloc(sizeof(double) * N);
+        for (int i = 0; i < N; ++i) soil[i] = urand(0.001, 0.02);
+        p.alpha_s_cell = soil;
+    }
     ref_rain rn = {1, 50.0 / 3.6e6, 100.0, 400.0};
     ref_books b;
     ref_books_init(N, 1.0, th, h, 0.0, &b);
@@ -146,6 +152,7 @@ static void run_case(const Case *c) {
         free(x); free(y); free(dy); free(dx);
     }
     free(nbr); free(code); free(act); free(z); free(th); free(ap); free(h); free(v1); free(v2);
+    free(soil);
 }
 
 int main(void) {

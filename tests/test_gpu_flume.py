@@ -29,7 +29,7 @@ def test_tables_with_flux_cells_bit_exact(hx):
     sc = _flume()
     nbr_ref, code_ref = oracle.tables(sc.nq, sc.nr, sc.side, sc.segs, sc.active, sc.mask_code)
     grid = hx.Grid.from_scenario(sc)
-    nbr, code = grid.tables()
+    nbr, code, _, _ = grid.tables()
     np.testing.assert_array_equal(nbr.cpu().numpy(), nbr_ref)
     np.testing.assert_array_equal(code.cpu().numpy(), code_ref)
     assert (code_ref == oracle.FLUX).sum() > 0

@@ -77,9 +77,35 @@ def test_tables_bit_exact(hx, gi):
     g = GRIDS[gi]
     nbr_ref, code_ref = oracle.tables(g["nq"], g["nr"], g["side"], g.get("segs", ()))
     grid = hx.Grid(g["nq"], g["nr"], 1.0, g["side"], g.get("segs", ()))
-    nbr, code = grid.tables()
+    nbr, code, _, _ = grid.tables()
     np.testing.assert_array_equal(nbr.cpu().numpy(), nbr_ref)
     np.testing.assert_array_equal(code.cpu().numpy(), code_ref)
+
+
+@pytest.mark.parametrize("gi", [0, 2, 3])
+def test_index_tables_and_host_tables(hx, gi):
+    """q[i], r[i] are the axial coordinates of i = r*nq + q, and every INTERIOR neighbour
+    of the table sits at (q + dq_k, r + dr_k) (wrapped on periodic sides); the host-array
+    call returns the device tables bit for bit."""
+    g = GRIDS[gi]
+    nq, nr = g["nq"], g["nr"]
+    grid = hx.Grid(nq, nr, 1.0, g["side"], g.get("segs", ()))
+    nbr, code, q, r = (t.cpu().numpy() for t in grid.tables())
+    i = np.arange(nq * nr)
+    np.testing.assert_array_equal(q, i % nq)
+    np.testing.assert_array_equal(r, i // nq)
+    np.testing.assert_array_equal(r * nq + q, i)
+    for k in range(6):
+        inter = code[:, k] == oracle.INTERIOR
+        qn = (q + oracle.DQ[k]) % nq
+        rn = (r + oracle.DR[k]) % nr
+        np.testing.assert_array_equal(nbr[inter, k], (rn * nq + qn)[inter])
+    h = grid.tables_host()
+    for a, b in zip(h, (nbr, code, q, r)):
+        np.testing.assert_array_equal(a, b)
+    nbr_ref, code_ref = oracle.tables(nq, nr, g["side"], g.get("segs", ()))
+    np.testing.assert_array_equal(h[0], nbr_ref)
+    np.testing.assert_array_equal(h[1], code_ref)
 
 
 @pytest.mark.parametrize("mask_bc", [synth.WALL, synth.OUTFLOW])
@@ -87,7 +113,7 @@ def test_tables_bit_exact_masked(hx, mask_bc):
     act = synth.hexagon_mask(31, 31, 12)
     nbr_ref, code_ref = oracle.tables(31, 31, (synth.WALL,) * 4, (), act, mask_bc)
     grid = hx.Grid(31, 31, 1.0, (synth.WALL,) * 4, (), act, mask_bc)
-    nbr, code = grid.tables()
+    nbr, code, _, _ = grid.tables()
     np.testing.assert_array_equal(nbr.cpu().numpy(), nbr_ref)
     np.testing.assert_array_equal(code.cpu().numpy(), code_ref)
     assert grid.active_cells == int(act.sum())

@@ -21,7 +21,7 @@ def test_tables_with_dirichlet_cells_bit_exact(hx, kind):
     sc = synth.radial(kind, a=2.0)
     nbr_ref, code_ref = oracle.tables(sc.nq, sc.nr, sc.side, sc.segs, sc.active, sc.mask_code)
     grid = hx.Grid.from_scenario(sc)
-    nbr, code = grid.tables()
+    nbr, code, _, _ = grid.tables()
     np.testing.assert_array_equal(nbr.cpu().numpy().reshape(-1), np.asarray(nbr_ref).reshape(-1))
     np.testing.assert_array_equal(code.cpu().numpy().reshape(-1), np.asarray(code_ref).reshape(-1))
     assert grid.active_cells == int((sc.active == 1).sum())

@@ -12,6 +12,7 @@ import pytest
 import oracle
 import synth
 from oracle import INTERIOR, OUTFLOW, PERIODIC, WALL
+from tests._util import ref_run
 
 SQ3 = math.sqrt(3.0)
 
@@ -438,3 +439,36 @@ def test_susita_mass_table_balances(golden):
     g = golden("paper_grids.txt")
     assert g["susita_rain"] - g["susita_out"] == g["susita_left"]
     assert g["susita_rain"] - g["susita_out_veg"] == g["susita_left_veg"]
+
+
+# ------------------------------------------------ soil coefficient per cell
+
+def _uniform_flow(alpha_s, nq=12, nr=10, dt=0.05):
+    N = nq * nr
+    P = oracle.PERIODIC
+    return synth.Scenario(name="soil", nq=nq, nr=nr, a=1.0, z=np.zeros(N), theta=np.ones(N),
+                          alpha_p=np.zeros(N), alpha_s=alpha_s, side=(P, P, P, P),
+                          h0=np.full(N, 0.5), v10=np.full(N, 0.3), v20=np.full(N, -0.2),
+                          dt_max=dt, t_end=dt)
+
+
+def test_soil_coefficient_per_cell():
+    """eq_tsa_darcy with alpha_s varying over the raster: a uniform flow on a flat periodic
+    raster has no edge sums, so one step is the friction solve of each cell alone,
+    v' = 2 gamma / (alpha + sqrt(alpha^2 + 4 beta |gamma|)) with gamma = theta h v,
+    alpha = theta h and beta = dt theta alpha_s of that cell (Appendix A, miu-formula)."""
+    rng = np.random.default_rng(31)
+    dt = 0.05
+    field = rng.uniform(0.001, 0.05, 120)
+    r = ref_run(_uniform_flow(field, dt=dt), max_steps=1)
+    assert r["books"]["steps"] == 1
+    m, g1, g2 = 0.5, 0.5 * 0.3, 0.5 * -0.2
+    G = math.hypot(g1, g2)
+    D = m + np.sqrt(m * m + 4.0 * dt * field * G)
+    np.testing.assert_allclose(r["v1"], 2.0 * g1 / D, rtol=1e-13)
+    np.testing.assert_allclose(r["v2"], 2.0 * g2 / D, rtol=1e-13)
+    # a field holding one value everywhere is the scalar coefficient, bit for bit
+    a = ref_run(_uniform_flow(np.full(120, 0.00709)), max_steps=3)
+    b = ref_run(_uniform_flow(0.00709), max_steps=3)
+    for k in ("h", "v1", "v2"):
+        np.testing.assert_array_equal(a[k], b[k])
