@@ -170,13 +170,24 @@ void hexsv_grid_destroy(hexsv_grid *grid);
 /* Number of cells nq*nr and of updated cells (active == 1). */
 int hexsv_grid_counts(const hexsv_grid *grid, int64_t *cells, int64_t *active);
 
-/* Neighbour and edge-code tables computed on the device (one thread per cell):
- * d_nbr[i*6+k] = index of the neighbour across edge k for INTERIOR, DIRICHLET
- * and FLUX edges, -1 otherwise; d_code[i*6+k] = edge code; cells outside the
- * domain (active == 0) get six WALL codes.
- * Caller-allocated device arrays of nq*nr*6 int32 and uint8. */
-int hexsv_grid_tables(const hexsv_grid *grid, int32_t *d_nbr, uint8_t *d_code,
-                      hipStream_t stream);
+/* Neighbour, edge-code and index tables of the raster (Sec. 2.2 (a): the cell
+ * decomposition and the neighbour set N(i) of each cell), computed on the device
+ * by one kernel (one thread per cell):
+ *   nbr[i*6+k]  index of the neighbour across edge k for INTERIOR (periodic
+ *               wraps included), DIRICHLET and FLUX edges, -1 otherwise;
+ *   code[i*6+k] edge code; cells outside the domain (active == 0) get six WALL;
+ *   q[i], r[i]  axial coordinates of cell i = r*nq + q.
+ * The step kernels do not read these tables (they derive neighbours and codes
+ * from (q, r) on the fly); they are for export and validation.
+ * hexsv_grid_tables_device writes caller-allocated device arrays (nq*nr*6 int32,
+ * nq*nr*6 uint8, nq*nr int32, nq*nr int32; each nullable), stream-ordered.
+ * hexsv_grid_tables writes caller-allocated host arrays of the same sizes (each
+ * nullable); it stages them in a temporary device buffer, runs the same kernel
+ * and synchronises the device.  ENOMEM / EHIP on allocation or copy failure. */
+int hexsv_grid_tables_device(const hexsv_grid *grid, int32_t *d_nbr, uint8_t *d_code,
+                             int32_t *d_q, int32_t *d_r, hipStream_t stream);
+int hexsv_grid_tables(const hexsv_grid *grid, int32_t *nbr, uint8_t *code, int32_t *q,
+                      int32_t *r);
 
 /* ------------------------------------------------------ single catchment */
 
@@ -187,12 +198,17 @@ int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *params, hexsv_s
 void hexsv_sim_destroy(hexsv_sim *sim);
 
 /* Static fields (Sec. 2.1 (a), (b), (f), (e)): terrain z, porosity theta and
- * plant coefficient alpha_p per cell (device FP64 arrays of nq*nr), uniform
- * soil coefficient alpha_s.  EDOMAIN (after a device check, synchronising
- * `stream`): theta not in (0,1] on an active cell, alpha_p < 0, non-finite z,
- * alpha_s < 0.  The message names the first offending cell. */
+ * plant coefficient alpha_p per cell (device FP64 arrays of nq*nr), and the
+ * Darcy-Weisbach soil coefficient of eq_tsa_darcy: per cell in d_alpha_s
+ * (device FP64, nq*nr; the step kernel then reads it as a seventh field, in the
+ * extended instance) or, when d_alpha_s is null, the one value alpha_s.
+ * EDOMAIN (after a device check, synchronising `stream`): theta not in (0,1] on
+ * an active cell, alpha_p < 0, non-finite z, alpha_s < 0 or non-finite (the
+ * scalar, or any active cell of the field).  The message names the first
+ * offending cell.  Surrogate windows refuse a simulation with a soil field. */
 int hexsv_sim_set_fields(hexsv_sim *sim, const double *d_z, const double *d_theta,
-                         const double *d_alpha_p, double alpha_s, hipStream_t stream);
+                         const double *d_alpha_p, const double *d_alpha_s, double alpha_s,
+                         hipStream_t stream);
 
 /* Rain forcing.  EDOMAIN: i_a < 0, kind 1 with t_a <= 0 or T_d <= t_a. */
 int hexsv_sim_set_rain(hexsv_sim *sim, const hexsv_rain *rain);
@@ -339,6 +355,23 @@ int hexsv_ensemble_autotune(hexsv_ensemble *ens, int32_t ksteps, const char *cac
                             int32_t *best_tile, double *best_ms, hipStream_t stream);
 int hexsv_ensemble_info(const hexsv_ensemble *ens, int32_t *workgroups, int32_t *tile,
                         int64_t *cells, int32_t *steps_per_launch, int32_t *mode);
+
+/* Standalone autotuner (no caller workload needed): builds the tuner's own
+ * workload of about cells_hint cells in `precision` (a planar 5 % slope under a
+ * flowing 5 cm sheet, every cell wet: the arithmetic of a wet catchment), times
+ * every tile variant as hexsv_sim_autotune (kernel HEXSV_TUNE_STEP: one square
+ * raster) or hexsv_ensemble_autotune (HEXSV_TUNE_ENSEMBLE: 8 equal square
+ * scenarios of cells_hint / 8 cells each, both modes) do, and records the
+ * fastest in the JSON cache at cache_path (keyed by architecture, kernel,
+ * precision and size bucket), where hexsv_sim_create / hexsv_ensemble_create
+ * find it through $HEXSV_TUNE_CACHE.  Everything it allocates is freed before it
+ * returns; synchronises `stream`.  best_tile / best_ms (nullable) receive the
+ * choice and its time per launch (or per ensemble step).
+ * EINVAL: no cache path, unknown kernel or precision, cells_hint outside
+ * [64, 2^30]. */
+enum { HEXSV_TUNE_STEP = 0, HEXSV_TUNE_ENSEMBLE = 1 };
+int hexsv_autotune(const char *cache_path, int32_t kernel, int32_t precision, int64_t cells_hint,
+                   int32_t *best_tile, double *best_ms, hipStream_t stream);
 
 /* ------------------------------------------------------ learned surrogate */
 

@@ -134,10 +134,36 @@ extern "C" int hexsv_grid_counts(const hexsv_grid *grid, int64_t *cells, int64_t
     return HEXSV_OK;
 }
 
-extern "C" int hexsv_grid_tables(const hexsv_grid *grid, int32_t *d_nbr, uint8_t *d_code,
-                                 hipStream_t stream) {
-    if (!grid || !d_nbr || !d_code) return fail(HEXSV_EINVAL, "grid_tables: null argument");
-    HIP_TRY(launch_tables(grid->kg, grid->d_active, d_nbr, d_code, stream));
+extern "C" int hexsv_grid_tables_device(const hexsv_grid *grid, int32_t *d_nbr, uint8_t *d_code,
+                                        int32_t *d_q, int32_t *d_r, hipStream_t stream) {
+    if (!grid) return fail(HEXSV_EINVAL, "grid_tables_device: null grid");
+    if (!d_nbr && !d_code && !d_q && !d_r) return HEXSV_OK;
+    HIP_TRY(launch_tables(grid->kg, grid->d_active, d_nbr, d_code, d_q, d_r, stream));
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_grid_tables(const hexsv_grid *grid, int32_t *nbr, uint8_t *code, int32_t *q,
+                                 int32_t *r) {
+    if (!grid) return fail(HEXSV_EINVAL, "grid_tables: null grid");
+    if (!nbr && !code && !q && !r) return HEXSV_OK;
+    const int64_t n = grid->n;
+    // device staging of the requested tables, computed by the same kernel
+    const size_t b_nbr = nbr ? sizeof(int32_t) * 6 * n : 0, b_code = code ? 6 * (size_t)n : 0;
+    const size_t b_q = q ? sizeof(int32_t) * n : 0, b_r = r ? sizeof(int32_t) * n : 0;
+    char *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, b_nbr + b_code + b_q + b_r);
+    if (e != hipSuccess) return fail(HEXSV_ENOMEM, "grid_tables: %s", hipGetErrorString(e));
+    int32_t *dn = nbr ? (int32_t *)buf : nullptr;
+    int32_t *dq = q ? (int32_t *)(buf + b_nbr) : nullptr;
+    int32_t *dr = r ? (int32_t *)(buf + b_nbr + b_q) : nullptr;
+    uint8_t *dc = code ? (uint8_t *)(buf + b_nbr + b_q + b_r) : nullptr;
+    e = launch_tables(grid->kg, grid->d_active, dn, dc, dq, dr, nullptr);
+    if (e == hipSuccess && nbr) e = hipMemcpy(nbr, dn, b_nbr, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && code) e = hipMemcpy(code, dc, b_code, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && q) e = hipMemcpy(q, dq, b_q, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && r) e = hipMemcpy(r, dr, b_r, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(HEXSV_EHIP, "grid_tables: %s", hipGetErrorString(e));
     return HEXSV_OK;
 }
 
@@ -157,6 +183,8 @@ struct hexsv_sim {
     int prec;
     size_t esz;
     void *buf;  // [h0 v10 v20 h1 v11 v21 z th ap], n elements each
+    void *d_as;     // soil coefficient per cell (n elements), allocated on first use
+    bool as_field;  // d_as holds the soil coefficient (else the scalar kc.alpha_s)
     KConst kc;
     KRain rn;
     Ctl *d_ctl;
@@ -209,6 +237,7 @@ static KDom<T> dom_of(const hexsv_sim *s) {
     d.z = b + 6 * n;
     d.th = b + 7 * n;
     d.ap = b + 8 * n;
+    d.as = s->as_field ? (const T *)s->d_as : nullptr;
     return d;
 }
 
@@ -316,6 +345,7 @@ extern "C" void hexsv_sim_destroy(hexsv_sim *s) {
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     if (s->buf) (void)hipFree(s->buf);
+    if (s->d_as) (void)hipFree(s->d_as);
     if (s->d_ctl) (void)hipFree(s->d_ctl);
     if (s->d_part) (void)hipFree(s->d_part);
     if (s->d_ring) (void)hipFree(s->d_ring);
@@ -361,9 +391,11 @@ static int run_check(hexsv_sim *s, hipStream_t stream, bool fields, const double
 }
 
 extern "C" int hexsv_sim_set_fields(hexsv_sim *s, const double *d_z, const double *d_theta,
-                                    const double *d_alpha_p, double alpha_s, hipStream_t stream) {
+                                    const double *d_alpha_p, const double *d_alpha_s,
+                                    double alpha_s, hipStream_t stream) {
     if (!s || !d_z || !d_theta || !d_alpha_p) return fail(HEXSV_EINVAL, "set_fields: null argument");
-    if (!(alpha_s >= 0.0) || !isfinite(alpha_s)) return fail(HEXSV_EDOMAIN, "set_fields: alpha_s must be >= 0");
+    if (!d_alpha_s && (!(alpha_s >= 0.0) || !isfinite(alpha_s)))
+        return fail(HEXSV_EDOMAIN, "set_fields: alpha_s must be >= 0");
     int32_t cnt, first, why;
     int rc = run_check(s, stream, true, d_z, d_theta, d_alpha_p, &cnt, &first, &why);
     if (rc) return rc;
@@ -372,8 +404,30 @@ extern "C" int hexsv_sim_set_fields(hexsv_sim *s, const double *d_z, const doubl
                     "set_fields: %d active cells invalid; first cell %d (%s%s%s)", cnt, first,
                     (why & 1) ? "theta not in (0,1] " : "", (why & 2) ? "alpha_p < 0 " : "",
                     (why & 4) ? "z not finite" : "");
+    if (d_alpha_s) {  // the same check with the soil field in the plant field's place
+        rc = run_check(s, stream, true, d_z, d_theta, d_alpha_s, &cnt, &first, &why);
+        if (rc) return rc;
+        if (cnt)
+            return fail(HEXSV_EDOMAIN, "set_fields: %d active cells invalid; first cell %d (%s)",
+                        cnt, first, (why & 2) ? "alpha_s < 0 or not finite" : "?");
+    }
     const int64_t n = s->grid->n;
     const uint8_t *act = s->grid->d_active;
+    if (d_alpha_s && !s->d_as) {
+        hipError_t e = hipMalloc(&s->d_as, s->esz * (size_t)n);
+        if (e != hipSuccess) {
+            s->d_as = nullptr;
+            return fail(HEXSV_ENOMEM, "set_fields: soil field: %s", hipGetErrorString(e));
+        }
+    }
+    if (d_alpha_s) {
+        if (s->prec == HEXSV_FP64)
+            HIP_TRY(launch_import<double>(d_alpha_s, (double *)s->d_as, act, 1, n, stream));
+        else
+            HIP_TRY(launch_import<float>(d_alpha_s, (float *)s->d_as, act, 1, n, stream));
+    }
+    s->as_field = d_alpha_s != nullptr;
+    s->kc.ext = (s->grid->n_dirichlet > 0 || s->kc.f_inf > 0.0 || s->as_field) ? 1 : 0;
     if (s->prec == HEXSV_FP64) {
         KDom<double> d = dom_of<double>(s);
         HIP_TRY(launch_import<double>(d_z, (double *)d.z, act, 0, n, stream));
@@ -419,7 +473,7 @@ extern "C" int hexsv_sim_set_infiltration(hexsv_sim *s, double f_inf, double h_i
                     h_inf);
     s->kc.f_inf = f_inf;
     s->kc.h_inf = f_inf > 0.0 ? h_inf : 0.0;
-    s->kc.ext = (s->grid->n_dirichlet > 0 || f_inf > 0.0) ? 1 : 0;
+    s->kc.ext = (s->grid->n_dirichlet > 0 || f_inf > 0.0 || s->as_field) ? 1 : 0;
     drop_graph(s);
     drop_win_graph(s);
     return HEXSV_OK;
@@ -604,12 +658,18 @@ static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, b
         // remain (the current dt bound, or the step limit): whole long graphs
         // while two or more of them remain, then the short graph as often as the
         // rest should need (a span of a few steps costs one host round trip).
+        // A step limit that leaves a whole number of long graphs before t_end (as a
+        // benchmark's step count does) is replayed as exactly those graphs.
         const double dt = c.tau < s->p.dt_max ? c.tau : s->p.dt_max;
         double need = dt > 0.0 ? (t_end - c.t) / dt + 1.0 : 1.0;
-        if ((double)(limit - c.steps) < need) need = (double)(limit - c.steps);
-        const bool use_short = shortg || need < 2.0 * s->gsteps;
+        const int64_t by_limit = limit - c.steps;
+        const bool exact = !shortg && (double)by_limit < need && by_limit % s->gsteps == 0;
+        if ((double)by_limit < need) need = (double)by_limit;
+        const bool use_short = !exact && (shortg || need < 2.0 * s->gsteps);
         int reps;
-        if (use_short)
+        if (exact)
+            reps = (int)(by_limit / s->gsteps < 64 ? by_limit / s->gsteps : 64);
+        else if (use_short)
             reps = need <= SHORT_STEPS ? 1 : (int)fmin(64.0, ceil(need / SHORT_STEPS));
         else
             reps = (int)fmin(64.0, floor(need / s->gsteps) - 1.0);
@@ -755,6 +815,100 @@ extern "C" int hexsv_sim_autotune(hexsv_sim *s, int32_t nlaunch, const char *cac
     return HEXSV_OK;
 }
 
+// ------------------------------------------------ autotuning without a caller's workload
+
+// The tuner's own workload on an nq x nr raster: a planar 5 % slope (downhill towards
+// r = 0, whose side drains), theta 0.8, the paper's plant coefficient, under a uniform
+// 5 cm sheet moving downslope at 0.2 m/s: every cell wet, the arithmetic of a flowing
+// catchment.  Device FP64 arrays in one allocation of 6 n values: z, theta, alpha_p,
+// h, v1, v2.
+static int tune_workload(int nq, int nr, double a, double **out) {
+    const int64_t n = (int64_t)nq * nr;
+    std::vector<double> host(6 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int r = (int)(i / nq);
+        host[i] = 0.05 * 1.5 * a * r;   // z over the row centres y = 1.5 a r
+        host[n + i] = 0.8;              // theta
+        host[2 * n + i] = 73.39;        // alpha_p
+        host[3 * n + i] = 0.05;         // h
+        host[4 * n + i] = 0.0;          // v1
+        host[5 * n + i] = -0.2;         // v2
+    }
+    double *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(double) * 6 * (size_t)n);
+    if (e != hipSuccess) return fail(HEXSV_ENOMEM, "autotune: %s", hipGetErrorString(e));
+    e = hipMemcpy(d, host.data(), sizeof(double) * 6 * (size_t)n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(HEXSV_EHIP, "autotune: %s", hipGetErrorString(e));
+    }
+    *out = d;
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_autotune(const char *cache_path, int32_t kernel, int32_t precision,
+                              int64_t cells_hint, int32_t *best_tile, double *best_ms,
+                              hipStream_t stream) {
+    if (!cache_path || !*cache_path) return fail(HEXSV_EINVAL, "autotune: no cache path");
+    if (kernel != HEXSV_TUNE_STEP && kernel != HEXSV_TUNE_ENSEMBLE)
+        return fail(HEXSV_EINVAL, "autotune: kernel %d is not HEXSV_TUNE_STEP or _ENSEMBLE", kernel);
+    if (precision != HEXSV_FP64 && precision != HEXSV_FP32)
+        return fail(HEXSV_EINVAL, "autotune: precision %d", precision);
+    if (cells_hint < 64 || cells_hint > ((int64_t)1 << 30))
+        return fail(HEXSV_EINVAL, "autotune: cells_hint %lld outside [64, 2^30]", (long long)cells_hint);
+    const int nscen = kernel == HEXSV_TUNE_STEP ? 1 : 8;
+    const int side = (int)ceil(sqrt((double)cells_hint / nscen));
+    const double a = 1.0;
+    hexsv_grid_desc gd;
+    memset(&gd, 0, sizeof gd);
+    gd.nq = side;
+    gd.nr = side;
+    gd.edge = a;
+    gd.side_bc[HEXSV_S] = HEXSV_OUTFLOW;
+    gd.side_bc[HEXSV_E] = gd.side_bc[HEXSV_N] = gd.side_bc[HEXSV_W] = HEXSV_WALL;
+    gd.mask_bc = HEXSV_WALL;
+    hexsv_grid *grid = nullptr;
+    int rc = hexsv_grid_create(&gd, &grid);
+    if (rc) return rc;
+    double *f = nullptr;
+    rc = tune_workload(side, side, a, &f);
+    if (rc) {
+        hexsv_grid_destroy(grid);
+        return rc;
+    }
+    const int64_t n = (int64_t)side * side;
+    hexsv_params p;
+    memset(&p, 0, sizeof p);
+    p.g = 9.81;
+    p.cfl = 0.5;
+    p.dt_max = 1.0;
+    p.precision = precision;
+    p.tile = -1;
+    if (kernel == HEXSV_TUNE_STEP) {
+        hexsv_sim *sim = nullptr;
+        rc = hexsv_sim_create(grid, &p, &sim);
+        if (!rc) rc = hexsv_sim_set_fields(sim, f, f + n, f + 2 * n, nullptr, 0.00709, stream);
+        if (!rc) rc = hexsv_sim_set_state(sim, 0.0, f + 3 * n, f + 4 * n, f + 5 * n, stream);
+        if (!rc) rc = hexsv_sim_autotune(sim, 30, cache_path, best_tile, best_ms, stream);
+        hexsv_sim_destroy(sim);
+    } else {
+        std::vector<const hexsv_grid *> grids(nscen, grid);
+        hexsv_ensemble *ens = nullptr;
+        p.ensemble_mode = HEXSV_ENS_AUTO;
+        rc = hexsv_ensemble_create(nscen, grids.data(), &p, &ens);
+        const hexsv_rain rain{0, 50.0 / 3.6e6, 0.0, INFINITY};
+        for (int sc = 0; sc < nscen && !rc; ++sc)
+            rc = hexsv_ensemble_set_scenario(ens, sc, f, f + n, f + 2 * n, 0.00709, &rain, 0.0,
+                                             f + 3 * n, f + 4 * n, f + 5 * n, stream);
+        if (!rc) rc = hexsv_ensemble_autotune(ens, 10, cache_path, best_tile, best_ms, stream);
+        hexsv_ensemble_destroy(ens);
+    }
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(f);
+    hexsv_grid_destroy(grid);
+    return rc;
+}
+
 extern "C" int hexsv_sim_get_books(hexsv_sim *s, hexsv_books *out, hipStream_t stream) {
     if (!s || !out) return fail(HEXSV_EINVAL, "get_books: null argument");
     if (!s->state_set) return fail(HEXSV_ESTATE, "get_books: no state set");
@@ -867,9 +1021,10 @@ extern "C" int hexsv_sim_surrogate_features(hexsv_sim *s, hexsv_surrogate *sur, 
     if (!s->state_set) return fail(HEXSV_ESTATE, "surrogate_features: call set_state first");
     if (s->grid->n_dirichlet)
         return fail(HEXSV_EUNSUPPORTED, "surrogate_features: windows are not built for Dirichlet cells");
-    if (s->kc.visc || s->kc.f_inf > 0.0)  // the window's probe step runs the plain scheme
+    if (s->kc.visc || s->kc.f_inf > 0.0 || s->as_field)  // the probe step runs the plain scheme
         return fail(HEXSV_EUNSUPPORTED,
-                    "surrogate_features: windows are not built for the viscous flux or infiltration");
+                    "surrogate_features: windows are not built for the viscous flux, infiltration "
+                    "or a soil field");
     return s->prec == HEXSV_FP64 ? window_features<double>(s, sur, window, k, d_features, stream)
                                  : window_features<float>(s, sur, window, k, d_features, stream);
 }
@@ -1036,8 +1191,9 @@ extern "C" int hexsv_sim_run_surrogate(hexsv_sim *s, hexsv_surrogate *sur, doubl
         return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for the viscous flux");
     if (s->grid->n_dirichlet)
         return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for Dirichlet or flux cells");
-    if (s->kc.f_inf > 0.0)
-        return fail(HEXSV_EUNSUPPORTED, "run_surrogate: windows are not built for infiltration");
+    if (s->kc.f_inf > 0.0 || s->as_field)
+        return fail(HEXSV_EUNSUPPORTED,
+                    "run_surrogate: windows are not built for infiltration or a soil field");
     int64_t a = 0, f = 0;
     const int rc =
         s->prec == HEXSV_FP64

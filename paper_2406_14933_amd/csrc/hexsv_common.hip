@@ -174,11 +174,15 @@ hipError_t launch_check_state(const double *h, const double *v1, const double *v
 
 // Neighbour / edge-code tables, one thread per cell, with the same target
 // rules the step kernel applies to its staged halo.
-__global__ void k_tables(KGrid g, const uint8_t *active, int32_t *nbr, uint8_t *code) {
+__global__ void k_tables(KGrid g, const uint8_t *active, int32_t *nbr, uint8_t *code,
+                         int32_t *qa, int32_t *ra) {
     const int64_t n = (int64_t)g.nq * g.nr;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(i / g.nq), q = (int)(i - (int64_t)r * g.nq);
+        if (qa) qa[i] = q;
+        if (ra) ra[i] = r;
+        if (!nbr && !code) continue;
         const bool act = active ? active[i] != 0 : true;
         for (int k = 0; k < 6; ++k) {
             int qn = q + dq_of(k), rn = r + dr_of(k);
@@ -197,8 +201,8 @@ __global__ void k_tables(KGrid g, const uint8_t *active, int32_t *nbr, uint8_t *
             } else {
                 cd = side_code(g, qn, rn);
             }
-            nbr[i * 6 + k] = j;
-            code[i * 6 + k] = (uint8_t)cd;
+            if (nbr) nbr[i * 6 + k] = j;
+            if (code) code[i * 6 + k] = (uint8_t)cd;
         }
     }
 }
@@ -305,9 +309,9 @@ hipError_t launch_queue_reset(uint32_t *queue, hipStream_t stream) {
 }
 
 hipError_t launch_tables(const KGrid &g, const uint8_t *active, int32_t *nbr, uint8_t *code,
-                         hipStream_t stream) {
+                         int32_t *q, int32_t *r, hipStream_t stream) {
     hipLaunchKernelGGL(k_tables, dim3(grid_blocks((int64_t)g.nq * g.nr)), dim3(256), 0, stream, g,
-                       active, nbr, code);
+                       active, nbr, code, q, r);
     return hipGetLastError();
 }
 

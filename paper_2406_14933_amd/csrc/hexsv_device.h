@@ -114,6 +114,8 @@ template <typename T>
 struct KDom {
     T *st[2][3];      // state buffers [parity][h, v1, v2]
     const T *z, *th, *ap;
+    const T *as = nullptr;  // soil coefficient per cell (eq_tsa_darcy), read by the
+                            // extended instance only; null: the scalar KConst::alpha_s
     __device__ __host__ T *buf(int p, int f) const { return st[p][f]; }
 };
 

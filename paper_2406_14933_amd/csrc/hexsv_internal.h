@@ -162,7 +162,8 @@ hipError_t launch_win_apply(const KDom<T> &d, const KGrid &g, double l, const KC
 template <typename T>
 hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,
                             hipStream_t stream);
+// Neighbour and edge-code tables and the axial index arrays (each output nullable).
 hipError_t launch_tables(const KGrid &g, const uint8_t *active, int32_t *nbr, uint8_t *code,
-                         hipStream_t stream);
+                         int32_t *q, int32_t *r, hipStream_t stream);
 
 }  // namespace hexsv

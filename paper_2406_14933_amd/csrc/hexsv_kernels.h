@@ -422,8 +422,10 @@ __global__ __launch_bounds__(256) void k_win_features(KDom<T> d, KGrid g, double
     double o = 0.0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         float f[FEATURES];
-        win_feature_vec<T>(h[i], v1[i], v2[i], d.z[i], d.th[i], scr[i], scr[n + i], scr[2 * n + i],
-                           slope[i], depth, xs, sc, f);
+        // the probe state's three fields, n apart: pointer offsets, as 2 n + i can pass 2^31
+        const T *s1 = scr + n, *s2 = scr + 2 * (size_t)n;
+        win_feature_vec<T>(h[i], v1[i], v2[i], d.z[i], d.th[i], scr[i], s1[i], s2[i], slope[i],
+                           depth, xs, sc, f);
         if constexpr (PACKED) {
             bf16x8 v[nn::FEATURES_PAD / 8];
 #pragma unroll
@@ -479,7 +481,7 @@ __global__ __launch_bounds__(256) void k_win_apply(KDom<T> d, KGrid g, double l,
     T *ho = par ? d.st[0][0] : d.st[1][0];
     T *v1o = par ? d.st[0][1] : d.st[1][1];
     T *v2o = par ? d.st[0][2] : d.st[1][2];
-    const T *hs = scr, *v1s = scr + n, *v2s = scr + 2 * n;
+    const T *hs = scr, *v1s = scr + n, *v2s = scr + 2 * (size_t)n;  // 2 n can pass 2^31
     const T G = (T)kc.g;
     double c = 0.0, s = 0.0, o = 0.0, bad = 0.0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {

@@ -462,7 +462,12 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 h1 = x;
             }
         }
-        const T K = R.ap[k] * h1 * (T(1) - thi) + thi * alpha_s;
+        const uint32_t i = (uint32_t)(r * g.nq + q);
+        T as_i = alpha_s;
+        if constexpr (EXT) {
+            if (d.as) as_i = ld(d.as, i);  // a soil coefficient per cell
+        }
+        const T K = R.ap[k] * h1 * (T(1) - thi) + thi * as_i;
         const T beta = dtT * K;
         const T Gm = p_sqrt(g1 * g1 + g2 * g2);
         T alpha = m1;
@@ -471,7 +476,6 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
         T mu = (D == T(0)) ? T(0) : p_div(T(2), D);
         if (h_dry > T(0) && h1 < h_dry) mu = T(0);
         const T v1n = mu * g1, v2n = mu * g2;
-        const uint32_t i = (uint32_t)(r * g.nq + q);
         put<T, NT_STORE>(at(hout, i), h1);
         put<T, NT_STORE>(at(v1out, i), v1n);
         put<T, NT_STORE>(at(v2out, i), v2n);

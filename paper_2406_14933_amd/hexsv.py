@@ -69,10 +69,11 @@ _SIGS = [
     ("hexsv_grid_create", C.c_int, [C.POINTER(GridDesc), C.POINTER(_VP)]),
     ("hexsv_grid_destroy", None, [_VP]),
     ("hexsv_grid_counts", C.c_int, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
-    ("hexsv_grid_tables", C.c_int, [_VP, _VP, _VP, _VP]),
+    ("hexsv_grid_tables_device", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    ("hexsv_grid_tables", C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     ("hexsv_sim_create", C.c_int, [_VP, C.POINTER(Params), C.POINTER(_VP)]),
     ("hexsv_sim_destroy", None, [_VP]),
-    ("hexsv_sim_set_fields", C.c_int, [_VP, _VP, _VP, _VP, C.c_double, _VP]),
+    ("hexsv_sim_set_fields", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_double, _VP]),
     ("hexsv_sim_set_rain", C.c_int, [_VP, C.POINTER(Rain)]),
     ("hexsv_sim_set_linear_friction", C.c_int, [_VP, C.c_double]),
     ("hexsv_sim_set_viscosity", C.c_int, [_VP, C.c_int32]),
@@ -122,6 +123,8 @@ _SIGS = [
                                           C.c_double, C.c_int32, C.POINTER(C.c_int64),
                                           C.POINTER(C.c_int64), _VP]),
     ("hexsv_sim_surrogate_stats", C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    ("hexsv_autotune", C.c_int, [C.c_char_p, C.c_int32, C.c_int32, C.c_int64,
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_double), _VP]),
     ("hexsv_tile_count", C.c_int, []),
     ("hexsv_tile_shape", C.c_int, [C.c_int32] + [C.POINTER(C.c_int32)] * 3),
 ]
@@ -172,6 +175,20 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+TUNE_STEP, TUNE_ENSEMBLE = 0, 1
+
+
+def autotune(cache_path, kernel="step", precision="fp32", cells_hint=1 << 20):
+    """Tune the step (or batched-ensemble) kernel on the library's own workload of about
+    cells_hint cells and record the choice in the JSON cache; returns (tile, ms)."""
+    k = {"step": TUNE_STEP, "ensemble": TUNE_ENSEMBLE}[kernel]
+    prec = {"fp64": FP64, "fp32": FP32}[precision]
+    best, ms = C.c_int32(), C.c_double()
+    _check(lib().hexsv_autotune(str(cache_path).encode(), k, prec, int(cells_hint),
+                                C.byref(best), C.byref(ms), _stream()))
+    return best.value, ms.value
+
+
 def tile_shapes():
     out = []
     for v in range(lib().hexsv_tile_count()):
@@ -219,11 +236,25 @@ class Grid:
         return cls(sc.nq, sc.nr, sc.a, sc.side, sc.segs, sc.active, sc.mask_code)
 
     def tables(self):
-        """(nbr int32 (N,6), code uint8 (N,6)) computed by the device table kernel."""
+        """Device tensors (nbr int32 (N,6), code uint8 (N,6), q int32 (N,), r int32 (N,))
+        computed by the table kernel on the current stream."""
         nbr = torch.empty((self.cells, 6), dtype=torch.int32, device="cuda")
         code = torch.empty((self.cells, 6), dtype=torch.uint8, device="cuda")
-        _check(lib().hexsv_grid_tables(self._h, _ptr(nbr), _ptr(code), _stream()))
-        return nbr, code
+        q = torch.empty(self.cells, dtype=torch.int32, device="cuda")
+        r = torch.empty(self.cells, dtype=torch.int32, device="cuda")
+        _check(lib().hexsv_grid_tables_device(self._h, _ptr(nbr), _ptr(code), _ptr(q), _ptr(r),
+                                              _stream()))
+        return nbr, code, q, r
+
+    def tables_host(self):
+        """The same tables as NumPy arrays, written by the library into host memory."""
+        nbr = np.empty((self.cells, 6), np.int32)
+        code = np.empty((self.cells, 6), np.uint8)
+        q = np.empty(self.cells, np.int32)
+        r = np.empty(self.cells, np.int32)
+        _check(lib().hexsv_grid_tables(self._h, *(C.c_void_p(a.ctypes.data)
+                                                  for a in (nbr, code, q, r))))
+        return nbr, code, q, r
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -262,10 +293,16 @@ class Sim:
         return s
 
     def set_fields(self, z, theta, alpha_p, alpha_s):
+        """alpha_s: one soil coefficient, or one per cell (an array of the raster's size)."""
         n = self.grid.cells
         z, th, ap = (_dev(x, n=n) for x in (z, theta, alpha_p))
-        _check(lib().hexsv_sim_set_fields(self._h, _ptr(z), _ptr(th), _ptr(ap), float(alpha_s),
-                                          _stream()))
+        field, scalar = None, 0.0
+        if np.ndim(alpha_s) > 0 or torch.is_tensor(alpha_s):
+            field = _dev(alpha_s, n=n)
+        else:
+            scalar = float(alpha_s)
+        _check(lib().hexsv_sim_set_fields(self._h, _ptr(z), _ptr(th), _ptr(ap), _ptr(field),
+                                          scalar, _stream()))
 
     def set_viscosity(self, on):
         """Momentum flux with artificial viscosity (for shocks); off by default."""

@@ -27,27 +27,6 @@ import torch
 from . import hexsv
 
 
-def rain_rate(kind, i_a, t_a, T_d, t):
-    """Rain rate (m/s) at time t: constant on [0, T_d] (kind 0) or the triangular hyetograph
-    rising to i_a at t_a and falling to 0 at T_d (kind 1; Appendix C)."""
-    if kind == 0:
-        return i_a if 0.0 <= t <= T_d else 0.0
-    if 0.0 <= t <= t_a:
-        return i_a * (t / t_a)
-    if t_a < t <= T_d:
-        return i_a * ((1.0 - t / T_d) / (1.0 - t_a / T_d))
-    return 0.0
-
-
-def window_rain_depth(kind, i_a, t_a, T_d, t0, window, k):
-    """Rain depth of a window of k equal sub-steps, each taking the rate at its end."""
-    dt = window / k
-    d = 0.0
-    for j in range(1, k + 1):
-        d += dt * rain_rate(kind, i_a, t_a, T_d, t0 + j * dt)
-    return d
-
-
 @dataclass
 class Scales:
     H: float   # input depth (m)
@@ -86,7 +65,6 @@ class _Raw:
     dh: torch.Tensor
     dq1: torch.Tensor
     dq2: torch.Tensor
-    depth: float
 
 
 def pilot_dt(scenario, t_end=None):
@@ -105,15 +83,14 @@ def _collect_raw(scenarios, times, window, k):
         ens.run([t] * n)
         s0 = [ens.state(s) for s in range(n)]
         ens.run([t + window] * n)
-        for s, sc in enumerate(scenarios):
+        for s in range(n):
             a, b = s0[s], ens.state(s)
             raw.append(_Raw(
                 s=s, t=t,
                 h0=a["h"].float(), q10=a["q1"].float(), q20=a["q2"].float(),
                 v10=a["v1"].float(), v20=a["v2"].float(),
                 dh=(b["h"] - a["h"]).float(), dq1=(b["q1"] - a["q1"]).float(),
-                dq2=(b["q2"] - a["q2"]).float(),
-                depth=window_rain_depth(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d, t, window, k)))
+                dq2=(b["q2"] - a["q2"]).float()))
     return raw
 
 

@@ -127,3 +127,28 @@ def test_sim_autotune_and_cache(hx, tmp_path, monkeypatch):
     sim2.run(10.0)
     sim2.run(sc.t_end)
     np.testing.assert_array_equal(sim2.state_numpy()["h"], sim.state_numpy()["h"])
+
+
+def test_standalone_autotune_writes_the_cache(hx, tmp_path, monkeypatch):
+    """hexsv_autotune tunes on the library's own workload and leaves a cache entry that a
+    simulation (or ensemble) of that size bucket then starts from."""
+    import json
+    cache = str(tmp_path / "tune.json")
+    print("[standalone autotune step fp32 2^16]", flush=True)
+    best, ms = hx.autotune(cache, "step", "fp32", 1 << 16)
+    assert 0 <= best < len(hx.tile_shapes()) and ms > 0
+    entry = json.load(open(cache))["gfx950/step/fp32/2^16"]
+    assert entry["tile"] == best and len(entry["all_us"]) == len(hx.tile_shapes())
+    monkeypatch.setenv("HEXSV_TUNE_CACHE", cache)
+    sc = synth.c1_planar(nq=256, nr=256, t_end=5.0)
+    sim = hx.Sim.from_scenario(sc, "fp32")
+    assert sim.info()["tile"] == best
+    sim.run(sc.t_end)
+    print("[standalone autotune ensemble fp32 8 x 64^2]", flush=True)
+    eb, ems = hx.autotune(cache, "ensemble", "fp32", 8 * 64 * 64)
+    assert ems > 0
+    keys = json.load(open(cache))
+    assert "gfx950/step/fp32/2^16" in keys and "gfx950/ensemble/fp32/2^15" in keys
+    with pytest.raises(hx.HexsvError):
+        hx.autotune(cache, "step", "fp32", 10)
+    torch.cuda.synchronize()
