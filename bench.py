@@ -2,12 +2,18 @@
 
 One benchmark "step" is one explicit time step of the whole scheme over the
 catchment: CFL bound, six-edge fluxes, mass update with rain and clamping,
-closed-form friction solve, FP64 books.  The default workload is the 1024 x 1024
-fractal catchment (edge 2 m, 100 mm/h rain) in FP32; the line also carries the
-same workload in FP64.  Inputs are synthetic (seeded) and already resident in
-HBM when the timed region starts.
+closed-form friction solve, FP64 books.  The headline workload is the
+4096 x 4096 fractal catchment (edge 2 m, 150 mm/h storm then recession) in
+FP32, whose 604 MB per step streams from HBM (the largest single-domain
+configuration); the line also carries the same catchment in FP64, the
+1024 x 1024 catchment (its 38 MB stay in the 256 MB Infinity Cache, so it is
+labelled cache-resident), the batched 256-scenario ensemble, the surrogate and
+the FP64 oracle on the host.  Inputs are synthetic (seeded) and already
+resident in HBM when the timed region starts.  The K timed steps are whole
+replays of captured graphs (graph length = the largest divisor of K up to 100),
+so the per-step figure does not depend on K.
 
-Prints ONE JSON line:  python bench.py [--steps K] [--warmup W] [--workload c2|c4]
+Prints ONE JSON line:  python bench.py [--steps K] [--warmup W] [--workload c4|c2]
 """
 from __future__ import annotations
 
@@ -16,6 +22,8 @@ import hashlib
 import json
 import math
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -71,13 +79,24 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_gpu(sc, wname, precision, steps, warmup, tile, spg):
-    """Time `steps` solver steps (graph replays) after `warmup`, then the step kernel alone."""
+def graph_length(steps):
+    """Largest divisor of the timed step count up to 100: the timed run is whole replays."""
+    return max(d for d in range(1, min(steps, 100) + 1) if steps % d == 0)
+
+
+def time_gpu(sc, wname, precision, steps, warmup, tile):
+    """Time `steps` solver steps (whole graph replays) after `warmup` steps.
+
+    The step kernel's duration is taken inside the graphs: hipEvents on the simulation's
+    stream around the timed replays, divided by the steps they took (each step is one
+    launch; the per-replay fold and the launch gaps are included, so this is an upper bound
+    on the kernel's own duration).  Back-to-back launches outside graphs are reported too."""
     import torch
     from paper_2406_14933_amd import hexsv
+    spg = graph_length(steps)
     sim = hexsv.Sim.from_scenario(sc, precision, tile=tile, steps_per_graph=spg)
     t_end = 1e30  # never reached: the step count bounds the run
-    sim.run(t_end, max_steps=warmup)
+    sim.run(t_end, max_steps=max(warmup, 1))
     torch.cuda.synchronize()
     sim.timing(True)
     b0 = sim.books()
@@ -89,30 +108,35 @@ def time_gpu(sc, wname, precision, steps, warmup, tile, spg):
     b1 = sim.books()
     sim.timing(False)
     assert b1["steps"] - b0["steps"] == steps, (b0["steps"], b1["steps"])
-    # the dominant kernel in isolation: back-to-back launches bracketed by hipEvents
-    kern_ms = sim.time_kernel(max(20, min(200, steps // 10)))
+    graph_us = 1e3 * tm["gpu_ms"] / max(tm["steps"], 1)
+    iso_us = 1e3 * sim.time_kernel(max(20, min(200, steps)))
     cells = sim.grid.active_cells
     bpc = BYTES_PER_CELL[precision]
-    achieved = bpc * cells / (kern_ms * 1e-3) / 1e9
+    achieved = bpc * cells / (graph_us * 1e-6) / 1e9
     return {
         "wall_s": wall,
         "value": cells * steps / wall,
         "ms_per_step": 1e3 * wall / steps,
-        "gpu_us_per_step": 1e3 * tm["gpu_ms"] / max(tm["steps"], 1),
-        "kernel_us": kern_ms * 1e3,
+        "graph_replays": tm["replays"],
+        "steps_per_graph": spg,
+        "kernel_us": graph_us,
+        "isolated_kernel_us": iso_us,
         "cells": cells,
         "info": sim.info(),
         "residual": b1["residual"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_of(wname, precision, sim.info()["tile"]), "kernel": "k_step",
-                     "kernel_us": kern_ms * 1e3, "bytes_per_cell": bpc,
+                     "traffic": traffic_of(wname, precision, sim.info()["tile"]),
+                     "kernel": "k_step", "kernel_us": graph_us,
+                     "kernel_us_source": "in-graph hipEvents per step",
+                     "isolated_kernel_us": iso_us, "bytes_per_cell": bpc,
                      "bytes_per_launch": bpc * cells},
     }
 
 
 def time_ensemble(precision, launches, ksteps, n_scen, tune):
-    """Batched ensemble of uneven catchments advanced by the persistent kernel."""
+    """Batched ensemble of uneven catchments: every scenario advances `launches * ksteps`
+    steps; the mode (persistent kernel or batched steps) and tile come from the autotuner."""
     import torch
 
     import synth
@@ -134,12 +158,14 @@ def time_ensemble(precision, launches, ksteps, n_scen, tune):
     info = ens.info()
     bpc = BYTES_PER_CELL[precision]
     achieved = bpc * tm["cell_updates"] / (tm["gpu_ms"] * 1e-3) / 1e9
+    kernel = "k_ensemble" if info["mode"] == "persistent" else "k_ens_step"
     return {"value": tm["cell_updates"] / wall, "cells": info["cells"], "scenarios": n_scen,
             "steps_per_scenario": launches * ksteps, "wall_s": wall,
             "gpu_value": tm["cell_updates"] / (tm["gpu_ms"] * 1e-3),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k_ensemble", "bytes_per_cell": bpc},
+                         "kernel": kernel, "kernel_us_source": "hipEvents around the step graphs",
+                         "bytes_per_cell": bpc},
             "info": info}
 
 
@@ -223,42 +249,80 @@ def window_cost(size=512, nwin=256, window=0.69, k=16):
             "plain_steps_per_window": steps / nwin}
 
 
-def cpu_baseline(sc, budget_s=12.0):
-    """The FP64 oracle as it stands, on the host cores, over a bounded number of steps."""
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_threads():
+    """Threads the host gives this process: OMP_NUM_THREADS when set (the GPU machine sets its
+    CPU share there), else the CPUs this process may run on."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return min(int(env), avail or int(env))
+    return avail or 1
+
+
+def cpu_baseline(sc, budget_s=12.0, budget_1_s=8.0):
+    """The FP64 oracle as it stands on the host: on every thread this process has and on one
+    thread, each over a bounded number of steps of the same workload from its dry start."""
     import numpy as np
 
     import oracle
     G = oracle.grid(sc.nq, sc.nr, sc.a, sc.side, sc.segs, sc.active, sc.mask_code)
     p = oracle.params(sc.g, sc.cfl, sc.dt_max, sc.h_dry, sc.alpha_s)
     r = oracle.rain(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d)
-    threads = min(os.cpu_count() or 1, 16)
-    # one probe step to size the sample
-    t0 = time.perf_counter()
-    h, v1, v2, b, _ = oracle.run(G, sc.z, sc.theta, sc.alpha_p, p, r, sc.h0, sc.v10, sc.v20,
-                                 1e30, max_steps=2, nthreads=threads)
-    per = (time.perf_counter() - t0) / 2
-    k = int(max(2, min(2000, budget_s / max(per, 1e-9))))
-    t0 = time.perf_counter()
-    oracle.run(G, sc.z, sc.theta, sc.alpha_p, p, r, h, v1, v2, 1e30, max_steps=k, books=b,
-               nthreads=threads)
-    dt = time.perf_counter() - t0
     cells = int(np.count_nonzero(G.active))
-    return {"value": cells * k / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{k} FP64 steps of the full {sc.nq}x{sc.nr} raster from the dry start, "
-                      f"{dt:.1f} s on {threads} OpenMP threads"}
+    out = {}
+    for label, threads, budget in (("all", host_threads(), budget_s), ("one", 1, budget_1_s)):
+        t0 = time.perf_counter()  # one probe step to size the sample
+        h, v1, v2, b, _ = oracle.run(G, sc.z, sc.theta, sc.alpha_p, p, r, sc.h0, sc.v10,
+                                     sc.v20, 1e30, max_steps=1, nthreads=threads)
+        per = time.perf_counter() - t0
+        k = int(max(2, min(2000, budget / max(per, 1e-9))))
+        t0 = time.perf_counter()
+        oracle.run(G, sc.z, sc.theta, sc.alpha_p, p, r, h, v1, v2, 1e30, max_steps=k, books=b,
+                   nthreads=threads)
+        dt = time.perf_counter() - t0
+        out[label] = {"value": cells * k / dt, "threads": threads, "steps": k, "seconds": dt}
+        print(f"[bench] cpu oracle, {threads} thread(s): {cells * k / dt:.3e} cell-updates/s",
+              file=sys.stderr, flush=True)
+    a = out["all"]
+    return {"value": a["value"], "unit": "cell-updates/s", "cores": a["threads"],
+            "kind": "oracle",
+            "sample": f"{a['steps']} FP64 steps of the full {sc.nq}x{sc.nr} raster after its "
+                      f"first step from the dry start, {a['seconds']:.1f} s on {a['threads']} "
+                      f"OpenMP threads; one thread: {out['one']['steps']} steps in "
+                      f"{out['one']['seconds']:.1f} s",
+            "single_thread_value": out["one"]["value"], "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count()}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="c4", choices=["c4", "c2", "c1"])
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--tile", type=int, default=-1)
-    ap.add_argument("--steps-per-graph", type=int, default=100)
-    ap.add_argument("--large-steps", type=int, default=400,
-                    help="steps of the 4096x4096 catchment timed beside the main workload (0: skip)")
+    ap.add_argument("--side-steps", type=int, default=400,
+                    help="steps of the 1024x1024 (cache-resident) side entry (0: skip)")
     ap.add_argument("--ensemble-launches", type=int, default=4,
                     help="timed launches of the 256-scenario batched ensemble (0: skip)")
     ap.add_argument("--ensemble-ksteps", type=int, default=25)
@@ -294,10 +358,10 @@ def main():
     sc, wname = workload(args.workload)
     print(f"[bench] workload {wname}: {sc.n} cells, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
-    main_run = time_gpu(sc, wname, args.precision, args.steps, args.warmup, args.tile,
-                        args.steps_per_graph)
-    print(f"[bench] {args.precision}: {main_run['value']:.3e} cell-updates/s, step kernel "
-          f"{main_run['kernel_us']:.1f} us", file=sys.stderr, flush=True)
+    main_run = time_gpu(sc, wname, args.precision, args.steps, args.warmup, args.tile)
+    print(f"[bench] {args.precision}: {main_run['value']:.3e} cell-updates/s, step "
+          f"{main_run['kernel_us']:.1f} us in graphs ({main_run['isolated_kernel_us']:.1f} us "
+          f"back to back)", file=sys.stderr, flush=True)
     line = {
         "metric": METRIC,
         "value": main_run["value"],
@@ -313,26 +377,32 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "cells": main_run["cells"], "edge_m": sc.a,
                    "precision": args.precision, "tile": main_run["info"],
-                   "steps_per_graph": args.steps_per_graph},
+                   "steps_per_graph": main_run["steps_per_graph"],
+                   "graph_replays": main_run["graph_replays"]},
         "roofline": main_run["roofline"],
-        "gpu_us_per_step": main_run["gpu_us_per_step"],
         "books_residual": main_run["residual"],
     }
     if not args.no_fp64 and args.precision == "fp32":
-        other = time_gpu(sc, wname, "fp64", args.steps, args.warmup, args.tile, args.steps_per_graph)
+        other = time_gpu(sc, wname, "fp64", args.steps, args.warmup, args.tile)
         print(f"[bench] fp64: {other['value']:.3e} cell-updates/s", file=sys.stderr, flush=True)
-        line["fp64"] = {"value": other["value"], "ms_per_step": other["ms_per_step"],
-                        "roofline": other["roofline"], "books_residual": other["residual"]}
-    if args.large_steps > 0 and args.workload != "c4":
-        big, bname = workload("c4")
-        print(f"[bench] large: {bname}", file=sys.stderr, flush=True)
-        lr = time_gpu(big, bname, args.precision, args.large_steps, 50, args.tile, args.steps_per_graph)
-        print(f"[bench] large {args.precision}: {lr['value']:.3e} cell-updates/s, step kernel "
-              f"{lr['kernel_us']:.1f} us", file=sys.stderr, flush=True)
-        line["large"] = {"workload": bname, "value": lr["value"], "steps": args.large_steps,
-                         "ms_per_step": lr["ms_per_step"], "roofline": lr["roofline"],
-                         "books_residual": lr["residual"]}
-        del big
+        line["fp64"] = {"workload": wname, "value": other["value"],
+                        "ms_per_step": other["ms_per_step"], "roofline": other["roofline"],
+                        "books_residual": other["residual"]}
+    if args.side_steps > 0 and args.workload != "c2":
+        del sc
+        side, sname = workload("c2")
+        print(f"[bench] side: {sname}", file=sys.stderr, flush=True)
+        entry = {"workload": sname, "cache_resident": True,
+                 "note": "37.7 MB (FP32) per step stay in the 256 MB Infinity Cache: the "
+                         "fraction of 8 TB/s is not an HBM figure"}
+        for prec in ("fp32", "fp64"):
+            sr = time_gpu(side, sname, prec, args.side_steps, 50, args.tile)
+            print(f"[bench] side {prec}: {sr['value']:.3e} cell-updates/s", file=sys.stderr,
+                  flush=True)
+            entry[prec] = {"value": sr["value"], "ms_per_step": sr["ms_per_step"],
+                           "steps": args.side_steps, "roofline": sr["roofline"]}
+        line["cache_resident"] = entry
+        sc = None
     if args.ensemble_launches > 0:
         print("[bench] batched ensemble", file=sys.stderr, flush=True)
         er = time_ensemble(args.precision, args.ensemble_launches, args.ensemble_ksteps,
@@ -351,6 +421,8 @@ def main():
               f"{sr['err_h_max']:.2e} (max over held-out)", file=sys.stderr, flush=True)
         line["surrogate"] = sr
     if not args.no_cpu:
+        if sc is None:
+            sc, _ = workload(args.workload)
         line["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(line), flush=True)
 

@@ -388,10 +388,14 @@ int hexsv_autotune(const char *cache_path, int32_t kernel, int32_t precision, in
  * master vector laid out per layer as W[o][c][t] then b[o].  Inputs are 11
  * FP32 features per cell (see hexsv_sim_surrogate_features), outputs 4 FP32 per cell (3 used), for a batch of
  * samples on one nq x nr raster (cell (b, r, q) at b*nq*nr + r*nq + q).
- * Only C = 32 is built (EUNSUPPORTED otherwise); 2 <= layers <= 16. */
-int hexsv_surrogate_create(int32_t layers, int32_t channels, hexsv_surrogate **out);
+ * Only C = 32 is built (EUNSUPPORTED otherwise); 2 <= layers <= 16; k >= 1 is
+ * the number of solver steps a window spans (the k of hexsv_sim_run_surrogate). */
+int hexsv_surrogate_create(int32_t layers, int32_t channels, int32_t k, hexsv_surrogate **out);
 void hexsv_surrogate_destroy(hexsv_surrogate *sur);
 int64_t hexsv_surrogate_num_params(const hexsv_surrogate *sur);
+/* k of create: the solver steps one window spans (EINVAL at create if k < 1).
+ * The window calls below take it when their own k is <= 0.  -1 for a null handle. */
+int32_t hexsv_surrogate_steps(const hexsv_surrogate *sur);
 /* Copy parameters in (device FP32, n == num_params; resets Adam) or out. */
 int hexsv_surrogate_set_params(hexsv_surrogate *sur, const float *d_params, int64_t n,
                                hipStream_t stream);
@@ -429,15 +433,15 @@ int hexsv_surrogate_train_step(hexsv_surrogate *sur, const hexsv_grid *grid, int
  *   h/H, theta h v1/Q, theta h v2/Q, z/Z, theta, rain_depth/H, (dz/dx)/S,
  *   (dz/dy)/S, x_h/dH, x_q1/dQ, x_q2/dQ,
  * all but theta zero on inactive cells.  rain_depth is the window's rain (k
- * equal sub-steps, each at the rate of its end).  The slope of a cell is the
+ * equal sub-steps, each at the rate of its end; k <= 0: the surrogate's k).  The slope of a cell is the
  * least-squares fit of the elevation differences along the three axes of its
  * hexagon (central differences of the two active neighbours on an axis,
  * one-sided with one), exact for a plane.  x is the change of one probe step
  * of the scheme (rain included; dt = min(dt_max, CFL bound of the state))
  * scaled by window/dt.  The state and books are not changed.  These are the
  * inputs run_surrogate feeds the network; training pairs use them too.
- * EUNSUPPORTED: the sim has Dirichlet or flux cells, the viscous flux or
- * infiltration (the probe step runs the plain scheme). */
+ * EUNSUPPORTED: the sim has Dirichlet or flux cells, the viscous flux,
+ * infiltration or a soil field (the probe step runs the plain scheme). */
 int hexsv_sim_surrogate_features(hexsv_sim *sim, hexsv_surrogate *sur, double window, int32_t k,
                                  float *d_features, hipStream_t stream);
 
@@ -459,9 +463,9 @@ int hexsv_sim_surrogate_features(hexsv_sim *sim, hexsv_surrogate *sur, double wi
  * the balance exactly (small residuals would otherwise add up over many
  * windows).  A refused window is discarded and the plain solver advances
  * that span (ENUMERIC if it stalls).  A last span shorter than `window` is
- * always solved.  Windows are chained several to a graph launch; the host
- * synchronises once per chain.  Counts of kept and solved windows are
- * returned.  The surrogate must not be used by another simulation while this
+ * always solved.  k <= 0 takes the surrogate's k.  Windows are chained
+ * several to a graph launch; the host synchronises once per chain.  Counts of
+ * kept and solved windows are returned.  The surrogate must not be used by another simulation while this
  * runs (its workspace is shared). */
 int hexsv_sim_run_surrogate(hexsv_sim *sim, hexsv_surrogate *sur, double t_end, double window,
                             int32_t k, double residual_tol, int32_t project, int64_t *n_accepted,

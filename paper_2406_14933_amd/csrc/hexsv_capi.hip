@@ -437,7 +437,7 @@ extern "C" int hexsv_sim_set_fields(hexsv_sim *s, const double *d_z, const doubl
         KDom<float> d = dom_of<float>(s);
         HIP_TRY(launch_import<float>(d_z, (float *)d.z, act, 0, n, stream));
         HIP_TRY(launch_import<float>(d_theta, (float *)d.th, act, 2, n, stream));
-        HIP_TRY(launch_import<float>(d_alpha_p, (float *)d.ap, act, 0, n, stream));
+        HIP_TRY(launch_import_kp<float>(d_alpha_p, d_theta, (float *)d.ap, n, stream));
     }
     s->kc.alpha_s = alpha_s;
     s->fields_set = true;
@@ -1016,6 +1016,7 @@ static int window_features(hexsv_sim *s, hexsv_surrogate *sur, double window, in
 
 extern "C" int hexsv_sim_surrogate_features(hexsv_sim *s, hexsv_surrogate *sur, double window,
                                             int32_t k, float *d_features, hipStream_t stream) {
+    if (sur && k <= 0) k = hexsv_surrogate_steps(sur);  // the surrogate's own window length
     if (!s || !sur || !d_features || !(window > 0.0) || !isfinite(window) || k < 1)
         return fail(HEXSV_EINVAL, "surrogate_features: bad argument");
     if (!s->state_set) return fail(HEXSV_ESTATE, "surrogate_features: call set_state first");
@@ -1184,6 +1185,7 @@ extern "C" int hexsv_sim_run_surrogate(hexsv_sim *s, hexsv_surrogate *sur, doubl
                                        double window, int32_t k, double residual_tol,
                                        int32_t project, int64_t *n_accepted, int64_t *n_fallback,
                                        hipStream_t st) {
+    if (sur && k <= 0) k = hexsv_surrogate_steps(sur);  // the surrogate's own window length
     if (!s || !sur || !(window > 0.0) || !isfinite(window) || k < 1 || !(residual_tol >= 0.0))
         return fail(HEXSV_EINVAL, "run_surrogate: bad argument");
     if (!s->state_set) return fail(HEXSV_ESTATE, "run_surrogate: call set_state first");

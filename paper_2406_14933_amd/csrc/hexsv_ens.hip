@@ -276,7 +276,10 @@ static int ens_import(hexsv_ensemble *e, int s, const double *z, const double *t
     const hexsv_grid *g = e->grids[s];
     HIP_TRY(launch_import<T>(z, (T *)d.z, g->d_active, 0, g->n, stream));
     HIP_TRY(launch_import<T>(th, (T *)d.th, g->d_active, 2, g->n, stream));
-    HIP_TRY(launch_import<T>(ap, (T *)d.ap, g->d_active, 0, g->n, stream));
+    if (sizeof(T) == 4)  // FP32: the plant field holds alpha_p (1 - theta)
+        HIP_TRY(launch_import_kp<T>(ap, th, (T *)d.ap, g->n, stream));
+    else
+        HIP_TRY(launch_import<T>(ap, (T *)d.ap, g->d_active, 0, g->n, stream));
     for (int p = 0; p < 2; ++p) {
         HIP_TRY(launch_import<T>(h, d.st[p][0], g->d_active, 1, g->n, stream));
         HIP_TRY(launch_import<T>(v1, d.st[p][1], g->d_active, 1, g->n, stream));

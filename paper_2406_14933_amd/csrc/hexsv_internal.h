@@ -84,6 +84,10 @@ hipError_t launch_prime(const KDom<T> &d, int64_t n, const KConst &kc, Ctl *ctl,
 template <typename T>
 hipError_t launch_import(const double *src, T *dst, const uint8_t *active, int zero_inactive,
                          int64_t n, hipStream_t stream);
+// alpha_p (1 - theta) of FP64 caller arrays -> the FP32 state's plant field.
+template <typename T>
+hipError_t launch_import_kp(const double *ap, const double *th, T *dst, int64_t n,
+                            hipStream_t stream);
 // internal state -> FP64 caller arrays (each output nullable).
 template <typename T>
 hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double *v1,

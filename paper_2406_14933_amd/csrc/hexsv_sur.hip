@@ -21,6 +21,7 @@ struct SurLayer {
 
 struct hexsv_surrogate {
     int layers, channels;
+    int k;  // solver steps a window spans (its rain sub-steps)
     int64_t nparams;
     float *d_p, *d_m, *d_v, *d_g;
     std::vector<SurLayer> L;
@@ -96,15 +97,18 @@ static int ensure_ws(hexsv_surrogate *s, int64_t cells, int tiles) {
     return HEXSV_OK;
 }
 
-extern "C" int hexsv_surrogate_create(int32_t layers, int32_t channels, hexsv_surrogate **out) {
+extern "C" int hexsv_surrogate_create(int32_t layers, int32_t channels, int32_t k,
+                                      hexsv_surrogate **out) {
     if (!out) return fail(HEXSV_EINVAL, "surrogate_create: null argument");
     *out = nullptr;
     if (channels != 32) return fail(HEXSV_EUNSUPPORTED, "surrogate_create: only 32 channels are built");
     if (layers < 2 || layers > 16) return fail(HEXSV_EINVAL, "surrogate_create: layers must be in [2, 16]");
+    if (k < 1) return fail(HEXSV_EINVAL, "surrogate_create: k must be >= 1");
     hexsv_surrogate *s = new (std::nothrow) hexsv_surrogate();
     if (!s) return fail(HEXSV_ENOMEM, "surrogate_create: out of host memory");
     s->layers = layers;
     s->channels = channels;
+    s->k = k;
     int64_t off = 0;
     for (int l = 0; l < layers; ++l) {
         SurLayer y{};
@@ -155,6 +159,7 @@ extern "C" void hexsv_surrogate_destroy(hexsv_surrogate *s) {
 }
 
 extern "C" int64_t hexsv_surrogate_num_params(const hexsv_surrogate *s) { return s ? s->nparams : -1; }
+extern "C" int32_t hexsv_surrogate_steps(const hexsv_surrogate *s) { return s ? s->k : -1; }
 
 static int prepare(hexsv_surrogate *s, hipStream_t st) {
     for (auto &y : s->L)

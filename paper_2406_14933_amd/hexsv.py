@@ -105,7 +105,8 @@ _SIGS = [
                                       C.POINTER(C.c_int32)]),
     ("hexsv_sim_autotune", C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), _VP]),
-    ("hexsv_surrogate_create", C.c_int, [C.c_int32, C.c_int32, C.POINTER(_VP)]),
+    ("hexsv_surrogate_create", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(_VP)]),
+    ("hexsv_surrogate_steps", C.c_int32, [_VP]),
     ("hexsv_surrogate_destroy", None, [_VP]),
     ("hexsv_surrogate_num_params", C.c_int64, [_VP]),
     ("hexsv_surrogate_set_params", C.c_int, [_VP, _VP, C.c_int64, _VP]),
@@ -507,11 +508,12 @@ class Ensemble:
 class Surrogate:
     """Hex-convolution residual network (BF16 MFMA kernels, FP32 master weights)."""
 
-    def __init__(self, layers=4, channels=32):
+    def __init__(self, layers=4, channels=32, k=16):
         h = C.c_void_p()
-        _check(lib().hexsv_surrogate_create(int(layers), int(channels), C.byref(h)))
+        _check(lib().hexsv_surrogate_create(int(layers), int(channels), int(k), C.byref(h)))
         self._h = h
         self.layers, self.channels = layers, channels
+        self.k = int(lib().hexsv_surrogate_steps(h))
         self.num_params = int(lib().hexsv_surrogate_num_params(h))
 
     def set_params(self, p):

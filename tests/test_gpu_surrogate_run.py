@@ -182,7 +182,22 @@ def test_surrogate_window_rejects_bad_arguments(hx):
     sc = wet_planar(nq=20, nr=12)
     sim = hx.Sim.from_scenario(sc, "fp32")
     sur, _ = make_surrogate(hx)
-    for window, k, tol in ((0.0, 16, 1e-3), (1.0, 0, 1e-3), (1.0, 16, -1.0)):
+    for window, k, tol in ((0.0, 16, 1e-3), (math.inf, 16, 1e-3), (1.0, 16, -1.0)):
         with pytest.raises(hx.HexsvError):
             sim.run_surrogate(sur, 10.0, window, k, tol)
+    with pytest.raises(hx.HexsvError):
+        hx.Surrogate(4, 32, k=0)
     torch.cuda.synchronize()
+
+
+def test_window_length_defaults_to_the_surrogates_k(hx):
+    """k <= 0 in the window calls takes the k the surrogate was created with."""
+    sc = wet_planar(nq=40, nr=24)
+    sur, _ = make_surrogate(hx)
+    assert sur.k == 16
+    out = []
+    for k in (16, 0):
+        sim = hx.Sim.from_scenario(sc, "fp64")
+        assert sim.run_surrogate(sur, 2 * WINDOW, WINDOW, k, math.inf, project=False) == (2, 0)
+        out.append(sim.state_numpy()["h"])
+    np.testing.assert_array_equal(out[0], out[1])
