@@ -84,8 +84,15 @@ def graph_length(steps):
     return max(d for d in range(1, min(steps, 100) + 1) if steps % d == 0)
 
 
-def time_gpu(sc, wname, precision, steps, warmup, tile):
+SPIN_UP_S = 300.0  # simulated time of the storm before the timed steps (setup, untimed)
+
+
+def time_gpu(sc, wname, precision, steps, warmup, tile, spin_up=SPIN_UP_S):
     """Time `steps` solver steps (whole graph replays) after `warmup` steps.
+
+    The timed state is the catchment `spin_up` seconds into its storm, which the setup
+    reaches with the solver itself: a wet, flowing catchment, as over most of the run (the
+    first steps from the dry start are unrepresentative: nearly every cell is dry).
 
     The step kernel's duration is taken inside the graphs: hipEvents on the simulation's
     stream around the timed replays, divided by the steps they took (each step is one
@@ -95,6 +102,7 @@ def time_gpu(sc, wname, precision, steps, warmup, tile):
     from paper_2406_14933_amd import hexsv
     spg = graph_length(steps)
     sim = hexsv.Sim.from_scenario(sc, precision, tile=tile, steps_per_graph=spg)
+    sim.run(min(spin_up, sc.t_end))
     t_end = 1e30  # never reached: the step count bounds the run
     sim.run(t_end, max_steps=max(warmup, 1))
     torch.cuda.synchronize()
@@ -169,9 +177,13 @@ def time_ensemble(precision, launches, ksteps, n_scen, tune):
             "info": info}
 
 
-def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=3e-5, seed=1, dt_scale=2.4):
-    """Train the window surrogate on solver trajectories (all on the GPU, the library's own
-    kernels) and time it against the plain FP32 solver on held-out scenarios to t_end."""
+def surrogate_block(n_train=16, n_test=100, size=512, k=16, tol=3e-5, seed=1, dt_scale=2.4):
+    """The window surrogate (512 x 512 scenarios of the ensemble distribution): trained on
+    FP32 solver trajectories with the library's own kernels, then evaluated on `n_test`
+    held-out seeds against the plain FP32 solver, seed by seed (the single-sample regime),
+    beside the same windows with a zero network (the probe step's extrapolation alone), and
+    the costs of the batched regime: the plain solver on all held-out seeds as one ensemble
+    and one network call over the whole batch."""
     import numpy as np
 
     import synth
@@ -184,7 +196,7 @@ def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=3e-5, seed=1, dt_s
     t0 = time.perf_counter()
     dt_fix = dt_scale * min(S.pilot_dt(sc) for sc in train_sc[:2])
     window = k * dt_fix
-    sur = hexsv.Surrogate(4, 32)
+    sur = hexsv.Surrogate(4, 32, k=k)
     rng = np.random.default_rng(seed)
     # He-normal start, last layer scaled down: the network starts near the probe extrapolation
     p = []
@@ -202,17 +214,82 @@ def surrogate_block(n_train=16, n_test=8, size=512, k=16, tol=3e-5, seed=1, dt_s
         data = S.merge(data, ro)
         S.train(sur, data, 3000, batch=4, lr=5e-4, lr_end=2e-5, seed=seed + 1 + rnd)
     train_s = time.perf_counter() - t0
+    print(f"[bench] surrogate: trained in {train_s:.0f} s; evaluating {n_test} held-out seeds",
+          file=sys.stderr, flush=True)
     ev = S.evaluate(sur, test_sc, window, k, tol, project=True)
-    plain_steps = sum(r["plain_steps"] for r in ev["rows"])
-    sur_steps = sum(r["surrogate_steps"] for r in ev["rows"])
-    return {"workload": f"surrogate-{n_test}-heldout-{size}x{size}-edge1m-to-{t_end:.0f}s",
-            "speedup": ev["speedup"], "err_h_max": ev["err_h_max"],
-            "err_h_mean": ev["err_h_mean"], "tol": tol, "accept_frac": ev["accept_frac"],
-            "solver_steps_avoided": 1.0 - sur_steps / max(plain_steps, 1),
-            "refused": {k: ev[k] for k in ("refused_residual", "refused_wave_speed",
-                                           "refused_nonfinite")},
-            "plain_s": ev["plain_s"], "surrogate_s": ev["surrogate_s"], "window_s": window,
-            "k": k, "train_pairs": data.pairs, "train_scenarios": n_train, "train_s": train_s}
+    zero = hexsv.Surrogate(4, 32, k=k)
+    zero.set_params(np.zeros(zero.num_params, np.float32))
+    zero.set_scales(scales.as_list())
+    ev0 = S.evaluate(zero, test_sc, window, k, tol, project=True)
+    print(f"[bench] surrogate: {ev['speedup']:.2f}x (zero network {ev0['speedup']:.2f}x)",
+          file=sys.stderr, flush=True)
+    batched = batched_regime(sur, test_sc, k, t_end)
+
+    def summary(e):
+        plain_steps = sum(r["plain_steps"] for r in e["rows"])
+        sur_steps = sum(r["surrogate_steps"] for r in e["rows"])
+        return {"speedup": e["speedup"], "err_h_max": e["err_h_max"],
+                "err_h_mean": e["err_h_mean"], "accept_frac": e["accept_frac"],
+                "solver_steps_avoided": 1.0 - sur_steps / max(plain_steps, 1),
+                "refused": {kk: e[kk] for kk in ("refused_residual", "refused_wave_speed",
+                                                 "refused_nonfinite")},
+                "plain_s": e["plain_s"], "surrogate_s": e["surrogate_s"]}
+
+    out = {"workload": f"surrogate-{n_test}-heldout-{size}x{size}-edge1m-to-{t_end:.0f}s",
+           "regime": "single-sample: each held-out seed alone, solver and surrogate timed "
+                     "seed by seed", **summary(ev), "tol": tol, "window_s": window, "k": k,
+           "zero_network": summary(ev0), "batched": batched,
+           "train_pairs": data.pairs, "train_scenarios": n_train, "train_s": train_s}
+    return out
+
+
+def batched_regime(sur, scs, k, t_end):
+    """What the held-out batch costs as one batch: the plain FP32 solver on every seed as one
+    batched ensemble to t_end, and one network call over the whole batch (random inputs; the
+    cost does not depend on them).  A window spans k solver steps and needs at least the
+    network call and a probe step, so 16 steps of the batch over (call + 1 step) bounds the
+    speed-up a surrogate of this network could reach on the batch even if it kept every
+    window."""
+    import numpy as np
+    import torch
+
+    from paper_2406_14933_amd import hexsv
+    n = len(scs)
+    nq, nr = scs[0].nq, scs[0].nr
+    ens = hexsv.Ensemble.from_scenarios(scs, "fp32", mode="batched")
+    ens.autotune(ksteps=3)
+    torch.cuda.synchronize()
+    ens.timing(True)
+    t0 = time.perf_counter()
+    ens.run([t_end] * n)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = ens.timing()
+    steps = [ens.books(s)["steps"] for s in range(n)]
+    cells = ens.info()["cells"]
+    del ens
+    step_ms = wall * 1e3 / max(steps)  # one launch advances every live scenario
+    f = torch.randn((n * nq * nr, hexsv.Surrogate.FEATURES), dtype=torch.float32, device="cuda")
+    sur.forward(f, nq, nr)  # sizes the workspace
+    torch.cuda.synchronize()
+    calls = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        sur.forward(f, nq, nr)
+        torch.cuda.synchronize()
+        calls.append(time.perf_counter() - t1)
+    call_ms = 1e3 * min(calls)
+    del f
+    torch.cuda.empty_cache()
+    # FLOPs the MFMA units execute per cell (channels padded to 16 and 32): 4 layers
+    flop = 2 * 7 * (16 * 32 + 32 * 32 + 32 * 32 + 32 * 16) * n * nq * nr
+    return {"scenarios": n, "cells": cells, "plain_s": wall,
+            "plain_cell_updates_per_s": tm["cell_updates"] / wall,
+            "plain_step_ms": step_ms, "steps_max": max(steps),
+            "network_call_ms": call_ms, "network_tflops": flop / (call_ms * 1e-3) / 1e12,
+            "network_mfma_frac": flop / (call_ms * 1e-3) / 2.5e15,
+            "window_vs_steps": f"{k} solver steps of the batch = {k * step_ms:.2f} ms",
+            "speedup_bound": k * step_ms / (call_ms + step_ms)}
 
 
 def window_cost(size=512, nwin=256, window=0.69, k=16):
@@ -247,6 +324,32 @@ def window_cost(size=512, nwin=256, window=0.69, k=16):
     return {"workload": f"still-water-{size}x{size}", "windows": acc,
             "window_us": 1e6 * tw / nwin, "plain_step_us": 1e6 * tp / steps,
             "plain_steps_per_window": steps / nwin}
+
+
+def network_cost(batch=16, size=512, calls=5):
+    """Device cost of one surrogate network call over a batch of 512 x 512 samples (random
+    inputs and parameters: the cost does not depend on them), for the MFMA profile."""
+    import numpy as np
+    import torch
+
+    from paper_2406_14933_amd import hexsv
+    sur = hexsv.Surrogate(4, 32)
+    rng = np.random.default_rng(3)
+    sur.set_params(rng.normal(scale=0.05, size=sur.num_params).astype(np.float32))
+    f = torch.randn((batch * size * size, hexsv.Surrogate.FEATURES), dtype=torch.float32,
+                    device="cuda")
+    sur.forward(f, size, size)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(calls):
+        t0 = time.perf_counter()
+        sur.forward(f, size, size)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0))
+    flop = 2 * 7 * (16 * 32 + 32 * 32 + 32 * 32 + 32 * 16) * batch * size * size
+    return {"workload": f"network-{batch}x{size}x{size}", "call_ms": min(ms),
+            "tflops": flop / (min(ms) * 1e-3) / 1e12, "mfma_frac": flop / (min(ms) * 1e-3) / 2.5e15,
+            "flop_per_call": flop}
 
 
 def cpu_model():
@@ -330,11 +433,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="skip training and timing the window surrogate")
+    ap.add_argument("--surrogate-seeds", type=int, default=100,
+                    help="held-out 512x512 seeds of the surrogate evaluation")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--window-cost", action="store_true",
                     help="only time surrogate windows against plain steps on still water")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for counter calibration)")
+    ap.add_argument("--network-cost", action="store_true",
+                    help="only time the surrogate network over a batch of 16 512x512 samples")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -346,6 +453,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     if args.window_cost:
         print(json.dumps(window_cost()))
+        return
+    if args.network_cost:
+        print(json.dumps(network_cost()))
         return
     if args.copy_calibration:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -376,7 +486,8 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": wname, "cells": main_run["cells"], "edge_m": sc.a,
-                   "precision": args.precision, "tile": main_run["info"],
+                   "precision": args.precision, "timed_from_s": SPIN_UP_S,
+                   "tile": main_run["info"],
                    "steps_per_graph": main_run["steps_per_graph"],
                    "graph_replays": main_run["graph_replays"]},
         "roofline": main_run["roofline"],
@@ -415,10 +526,11 @@ def main():
                            "roofline": er["roofline"], "config": er["info"]}
     if args.surrogate:
         print("[bench] surrogate: training on solver trajectories", file=sys.stderr, flush=True)
-        sr = surrogate_block()
+        sr = surrogate_block(n_test=args.surrogate_seeds)
         sr["window_cost"] = window_cost()
         print(f"[bench] surrogate: speed-up {sr['speedup']:.2f}x at rel L1 error "
-              f"{sr['err_h_max']:.2e} (max over held-out)", file=sys.stderr, flush=True)
+              f"{sr['err_h_max']:.2e} (max over held-out); batched bound "
+              f"{sr['batched']['speedup_bound']:.2f}x", file=sys.stderr, flush=True)
         line["surrogate"] = sr
     if not args.no_cpu:
         if sc is None:

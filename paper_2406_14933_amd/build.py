@@ -28,12 +28,12 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
 # (source, extra flags)
 UNITS = [
     ("hexsv_f64.hip", ["-ffp-contract=off"]),
-    ("hexsv_f32.hip", ["-ffp-contract=fast"]),
+    ("hexsv_f32.hip", ["-ffp-contract=fast-honor-pragmas"]),
     ("hexsv_common.hip", ["-ffp-contract=off"]),
     ("hexsv_capi.hip", ["-ffp-contract=off"]),
     ("hexsv_ens.hip", ["-ffp-contract=off"]),
     ("hexsv_tune.cpp", ["-x", "hip"]),
-    ("hexsv_nn.hip", ["-ffp-contract=fast"]),
+    ("hexsv_nn.hip", ["-ffp-contract=fast-honor-pragmas"]),
     ("hexsv_sur.hip", ["-ffp-contract=off"]),
 ]
 

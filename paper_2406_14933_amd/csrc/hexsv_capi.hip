@@ -437,7 +437,7 @@ extern "C" int hexsv_sim_set_fields(hexsv_sim *s, const double *d_z, const doubl
         KDom<float> d = dom_of<float>(s);
         HIP_TRY(launch_import<float>(d_z, (float *)d.z, act, 0, n, stream));
         HIP_TRY(launch_import<float>(d_theta, (float *)d.th, act, 2, n, stream));
-        HIP_TRY(launch_import_kp<float>(d_alpha_p, d_theta, (float *)d.ap, n, stream));
+        HIP_TRY(launch_import<float>(d_alpha_p, (float *)d.ap, act, 0, n, stream));
     }
     s->kc.alpha_s = alpha_s;
     s->fields_set = true;

@@ -129,6 +129,12 @@ template <typename T>
 __device__ inline T ld(const T *p, uint32_t i) {
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + i * (uint32_t)sizeof(T));
 }
+// The same with the nontemporal (streaming) hint, for data read once per step.
+template <typename T>
+__device__ inline T ld_stream(const T *p, uint32_t i) {
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + i * (uint32_t)sizeof(T)));
+}
 template <typename T>
 __device__ inline T *at(T *p, uint32_t i) {
     return reinterpret_cast<T *>(reinterpret_cast<char *>(p) + i * (uint32_t)sizeof(T));
@@ -169,6 +175,9 @@ __device__ inline int side_code(const KGrid &g, int q, int r) {
 }
 
 __device__ inline double rain_rate(const KRain &rn, double t) {
+    // FP64 time and books: rounded as written in every translation unit, whatever its
+    // contraction setting, so all kernels that close steps agree bit for bit
+#pragma clang fp contract(off)
     if (rn.kind == 0) return (t >= 0.0 && t <= rn.T_d) ? rn.i_a : 0.0;
     double gamma = rn.t_a / rn.T_d;
     if (t >= 0.0 && t <= rn.t_a) return rn.i_a * (t / rn.t_a);
@@ -183,6 +192,9 @@ struct StepTime {
     bool live;
 };
 __device__ inline StepTime step_time(const Ctl *ctl) {
+    // FP64 time and books: rounded as written in every translation unit, whatever its
+    // contraction setting, so all kernels that close steps agree bit for bit
+#pragma clang fp contract(off)
     StepTime s;
     double t = ctl->t, t_end = ctl->t_end;
     double dt = ctl->dt_max;
@@ -282,6 +294,9 @@ struct OpenStep {
 // into (read whether or not a step is pending, so the loads start at once).
 __device__ inline OpenStep open_step(const Ctl *ctl, int in, const unsigned long long *prev_set,
                                      const KConst &kc) {
+    // FP64 time and books: rounded as written in every translation unit, whatever its
+    // contraction setting, so all kernels that close steps agree bit for bit
+#pragma clang fp contract(off)
     const double prev_max = acc_max(prev_set);
     const Ctl *c = ctl + in;
     const int err = ctl[0].err;
@@ -318,6 +333,9 @@ __device__ inline OpenStep open_step(const Ctl *ctl, int in, const unsigned long
 // and the launch's own step pending.  err and err_cell are left alone.
 __device__ inline void write_slot(Ctl *out, const Ctl *in, const OpenStep o, const KConst &kc,
                                   const KRain &rn, bool pending) {
+    // FP64 time and books: rounded as written in every translation unit, whatever its
+    // contraction setting, so all kernels that close steps agree bit for bit
+#pragma clang fp contract(off)
     double rain = in->rain, dmin = in->dt_min, dmax = in->dt_max_seen, lc = in->last_cmax;
     if (o.closed) {
         const double pdt = in->p_dt;
@@ -352,6 +370,9 @@ __device__ inline void write_slot(Ctl *out, const Ctl *in, const OpenStep o, con
 
 __device__ inline void close_step(Ctl *ctl, const Part &p, const StepTime &st, const KConst &kc,
                                   double r_next) {
+    // FP64 time and books: rounded as written in every translation unit, whatever its
+    // contraction setting, so all kernels that close steps agree bit for bit
+#pragma clang fp contract(off)
     ctl->stored = p.stored;
     ctl->outflow += p.outflow;
     ctl->clamp += p.clamp;

@@ -24,7 +24,7 @@ struct hexsv_ensemble {
     int visc;                   // 1: artificial viscosity (batched mode only)
     int bc;                     // 1: a scenario holds Dirichlet or flux cells (batched mode only)
     int btile, btotal;          // batched mode: tile variant and total tiles
-    int32_t *d_tile_scen;       // batched mode: scenario of every global tile
+    EnsTile *d_tiles;           // batched mode: descriptor of every global tile
     Part *d_bpart;              // batched mode: one record per global tile
     double dt_max;
     std::vector<const hexsv_grid *> grids;
@@ -41,8 +41,8 @@ struct hexsv_ensemble {
     uint32_t *d_queue;
     std::vector<char> ready;
     hipStream_t cap;
-    hipGraph_t graph;
-    hipGraphExec_t gexec;
+    hipGraph_t graph[2];        // ksteps launches, live scenarios starting at parity 0 / 1
+    hipGraphExec_t gexec[2];
     bool timing;
     hipEvent_t ev0, ev1;
     double timed_ms;
@@ -74,10 +74,12 @@ static KDom<T> ens_dom(const hexsv_ensemble *e, int s) {
 }
 
 static void ens_drop_graph(hexsv_ensemble *e) {
-    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
-    if (e->graph) (void)hipGraphDestroy(e->graph);
-    e->gexec = nullptr;
-    e->graph = nullptr;
+    for (int p = 0; p < 2; ++p) {
+        if (e->gexec[p]) (void)hipGraphExecDestroy(e->gexec[p]);
+        if (e->graph[p]) (void)hipGraphDestroy(e->graph[p]);
+        e->gexec[p] = nullptr;
+        e->graph[p] = nullptr;
+    }
 }
 
 static void ens_set_tile(hexsv_ensemble *e, int v) {
@@ -96,7 +98,7 @@ static void ens_set_tile(hexsv_ensemble *e, int v) {
 static int ens_set_btile(hexsv_ensemble *e, int v) {
     e->btile = v;
     int base = 0;
-    std::vector<int32_t> map;
+    std::vector<EnsTile> map;
     for (int s = 0; s < e->n; ++s) {
         EnsScen &sc = e->scen[s];
         int ntq, nt;
@@ -105,12 +107,22 @@ static int ens_set_btile(hexsv_ensemble *e, int v) {
         sc.bntiles = nt;
         sc.bbase = base;
         base += nt;
-        map.insert(map.end(), (size_t)nt, s);
+        for (int lt = 0; lt < nt; ++lt) {
+            EnsTile tl;
+            tl.off = sc.off;
+            tl.nq = sc.g.nq;
+            tl.nr = sc.g.nr;
+            tl.tr = lt / ntq;
+            tl.tq = lt - tl.tr * ntq;
+            tl.s = s;
+            tl.wrap = (sc.g.perq ? 1 : 0) | (sc.g.perr ? 2 : 0);
+            map.push_back(tl);
+        }
     }
     e->btotal = base;
     ens_drop_graph(e);
-    if (e->d_tile_scen) HIP_TRY(hipMemcpy(e->d_tile_scen, map.data(), sizeof(int32_t) * map.size(),
-                                          hipMemcpyHostToDevice));
+    if (e->d_tiles) HIP_TRY(hipMemcpy(e->d_tiles, map.data(), sizeof(EnsTile) * map.size(),
+                                      hipMemcpyHostToDevice));
     return HEXSV_OK;
 }
 
@@ -127,7 +139,7 @@ extern "C" void hexsv_ensemble_destroy(hexsv_ensemble *e) {
     if (e->d_chk) (void)hipFree(e->d_chk);
     if (e->d_order) (void)hipFree(e->d_order);
     if (e->d_queue) (void)hipFree(e->d_queue);
-    if (e->d_tile_scen) (void)hipFree(e->d_tile_scen);
+    if (e->d_tiles) (void)hipFree(e->d_tiles);
     if (e->d_bpart) (void)hipFree(e->d_bpart);
     if (e->h_ctl) (void)hipHostFree(e->h_ctl);
     if (e->h_chk) (void)hipHostFree(e->h_chk);
@@ -233,7 +245,7 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         maxtiles = std::max(maxtiles, tot);
     }
     if (err == hipSuccess) err = hipMalloc(&e->d_bpart, sizeof(Part) * (size_t)maxtiles);
-    if (err == hipSuccess) err = hipMalloc(&e->d_tile_scen, sizeof(int32_t) * (size_t)maxtiles);
+    if (err == hipSuccess) err = hipMalloc(&e->d_tiles, sizeof(EnsTile) * (size_t)maxtiles);
     if (err == hipSuccess) err = hipHostMalloc(&e->h_ctl, sizeof(Ctl) * n, hipHostMallocDefault);
     if (err == hipSuccess) err = hipHostMalloc(&e->h_chk, 8 * sizeof(int32_t), hipHostMallocDefault);
     if (err == hipSuccess) err = hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking);
@@ -276,10 +288,7 @@ static int ens_import(hexsv_ensemble *e, int s, const double *z, const double *t
     const hexsv_grid *g = e->grids[s];
     HIP_TRY(launch_import<T>(z, (T *)d.z, g->d_active, 0, g->n, stream));
     HIP_TRY(launch_import<T>(th, (T *)d.th, g->d_active, 2, g->n, stream));
-    if (sizeof(T) == 4)  // FP32: the plant field holds alpha_p (1 - theta)
-        HIP_TRY(launch_import_kp<T>(ap, th, (T *)d.ap, g->n, stream));
-    else
-        HIP_TRY(launch_import<T>(ap, (T *)d.ap, g->d_active, 0, g->n, stream));
+    HIP_TRY(launch_import<T>(ap, (T *)d.ap, g->d_active, 0, g->n, stream));
     for (int p = 0; p < 2; ++p) {
         HIP_TRY(launch_import<T>(h, d.st[p][0], g->d_active, 1, g->n, stream));
         HIP_TRY(launch_import<T>(v1, d.st[p][1], g->d_active, 1, g->n, stream));
@@ -333,8 +342,10 @@ extern "C" int hexsv_ensemble_set_scenario(hexsv_ensemble *e, int32_t s, const d
     return HEXSV_OK;
 }
 
-// One persistent launch of ksteps steps, or ksteps batched steps.
-static hipError_t ens_launch(hexsv_ensemble *e, int mode, int v, int ksteps, hipStream_t st) {
+// One persistent launch of ksteps steps, or ksteps batched steps whose live
+// scenarios start from buffer parity p0 (launch k reads parity (p0 + k) & 1).
+static hipError_t ens_launch(hexsv_ensemble *e, int mode, int v, int ksteps, int p0,
+                             hipStream_t st) {
     if (mode == HEXSV_ENS_PERSISTENT)
         return e->prec == HEXSV_FP64
                    ? launch_ensemble<double>(v, ens_base<double>(e), e->d_scen, e->d_ctl, e->d_order,
@@ -345,30 +356,44 @@ static hipError_t ens_launch(hexsv_ensemble *e, int mode, int v, int ksteps, hip
     for (int k = 0; k < ksteps && err == hipSuccess; ++k)
         err = e->prec == HEXSV_FP64
                   ? launch_ens_step<double>(v, e->visc != 0, e->bc != 0, ens_base<double>(e),
-                                            e->d_scen, e->d_tile_scen, e->d_ctl, e->d_bpart,
-                                            e->btotal, e->n, st)
+                                            e->d_scen, e->d_tiles, e->d_ctl, e->d_bpart,
+                                            e->btotal, e->n, (p0 + k) & 1, st)
                   : launch_ens_step<float>(v, e->visc != 0, e->bc != 0, ens_base<float>(e),
-                                           e->d_scen, e->d_tile_scen, e->d_ctl, e->d_bpart,
-                                           e->btotal, e->n, st);
+                                           e->d_scen, e->d_tiles, e->d_ctl, e->d_bpart,
+                                           e->btotal, e->n, (p0 + k) & 1, st);
     return err;
 }
 
 static int ens_capture(hexsv_ensemble *e) {
     ens_drop_graph(e);
-    HIP_TRY(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t err = ens_launch(e, e->mode, e->mode == HEXSV_ENS_PERSISTENT ? e->tile : e->btile,
-                                e->ksteps, e->cap);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(e->cap, &g);
-    if (err != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(HEXSV_EHIP, "ensemble graph capture failed: %s",
-                    hipGetErrorString(err != hipSuccess ? err : e2));
+    for (int p0 = 0; p0 < 2; ++p0) {
+        HIP_TRY(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
+        hipError_t err = ens_launch(e, e->mode,
+                                    e->mode == HEXSV_ENS_PERSISTENT ? e->tile : e->btile,
+                                    e->ksteps, p0, e->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(e->cap, &g);
+        if (err != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(HEXSV_EHIP, "ensemble graph capture failed: %s",
+                        hipGetErrorString(err != hipSuccess ? err : e2));
+        }
+        e->graph[p0] = g;
+        HIP_TRY(hipGraphInstantiate(&e->gexec[p0], g, nullptr, nullptr, 0));
     }
-    e->graph = g;
-    HIP_TRY(hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0));
     return HEXSV_OK;
 }
+
+// Buffer parity of most live scenarios of n control blocks (the batched
+// launches' load hint).
+static int live_parity(const Ctl *c, int n) {
+    int count[2] = {0, 0};
+    for (int s = 0; s < n; ++s)
+        if (!(c[s].err || c[s].t >= c[s].t_end || c[s].steps >= c[s].step_limit))
+            count[c[s].parity & 1] += 1;
+    return count[1] > count[0] ? 1 : 0;
+}
+static int ens_live_parity(const hexsv_ensemble *e) { return live_parity(e->h_ctl, e->n); }
 
 static bool ens_done(const Ctl &c) { return c.err || c.t >= c.t_end || c.steps >= c.step_limit; }
 
@@ -389,13 +414,13 @@ extern "C" int hexsv_ensemble_run(hexsv_ensemble *e, const double *t_end, int64_
         steps0[s] = c.steps;
     }
     HIP_TRY(hipMemcpyAsync(e->d_ctl, e->h_ctl, sizeof(Ctl) * e->n, hipMemcpyHostToDevice, stream));
-    if (!e->gexec) {
+    if (!e->gexec[0]) {
         int rc = ens_capture(e);
         if (rc) return rc;
     }
     for (;;) {
         if (e->timing) HIP_TRY(hipEventRecord(e->ev0, stream));
-        HIP_TRY(hipGraphLaunch(e->gexec, stream));
+        HIP_TRY(hipGraphLaunch(e->gexec[ens_live_parity(e)], stream));
         if (e->timing) HIP_TRY(hipEventRecord(e->ev1, stream));
         HIP_TRY(hipMemcpyAsync(e->h_ctl, e->d_ctl, sizeof(Ctl) * e->n, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -522,7 +547,8 @@ extern "C" int hexsv_ensemble_autotune(hexsv_ensemble *e, int32_t ksteps, const 
         if (he == hipSuccess) he = hipMemcpyAsync(e->d_scen, e->scen.data(), sizeof(EnsScen) * e->n, hipMemcpyHostToDevice, stream);
         if (he == hipSuccess) he = hipMemcpyAsync(e->d_ctl, cc.data(), sizeof(Ctl) * e->n, hipMemcpyHostToDevice, stream);
         if (he == hipSuccess) he = hipEventRecord(a, stream);
-        if (he == hipSuccess) he = ens_launch(e, mode, v, ksteps, stream);
+        if (he == hipSuccess)
+            he = ens_launch(e, mode, v, ksteps, live_parity(cc.data(), e->n), stream);
         if (he == hipSuccess) he = hipEventRecord(b, stream);
         if (he == hipSuccess) he = hipEventSynchronize(b);
         float ms = 0.f;

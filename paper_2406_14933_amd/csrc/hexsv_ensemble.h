@@ -32,6 +32,18 @@ struct EnsScen {
     int32_t bntq, bntiles, bbase;  // batched-step mode tiling and first global tile
 };
 
+// One tile of the batched-step mode: everything its loads need (where the
+// scenario's cells start, its raster size and periodic sides, the tile's
+// position), so that a workgroup issues its tile loads before it reads the
+// scenario's control block and constants.
+struct alignas(16) EnsTile {
+    int64_t off;
+    int32_t nq, nr;
+    int32_t tq, tr;
+    int32_t s;
+    int32_t wrap;  // bit 0: periodic in q, bit 1: periodic in r
+};
+
 // The domain of the scenario at `off`, with its buffers ordered so that
 // parity 0 is the current state (a run-time parity index into a local copy of
 // the struct would place it in scratch memory).
@@ -134,48 +146,66 @@ __global__ __launch_bounds__(NT) void k_ensemble(KDom<T> base, const EnsScen *__
 
 // Batched-step mode: one launch advances every live scenario by one step.
 // The tiles of all scenarios form one index space (one workgroup per tile,
-// XCD-banded); each workgroup finds its scenario, reads that scenario's dt and
-// writes one partial record; k_ens_finalize (one workgroup per scenario) then
-// closes each scenario's step.  Kernel boundaries order the steps.
+// XCD-banded).  A workgroup reads its tile descriptor and issues the tile's
+// loads from the buffers of the parity the launcher expects (par_hint: live
+// scenarios step together, so their parities agree), then reads the
+// scenario's control block; a scenario of the other parity reloads (a cost,
+// never a wrong result).  It writes one partial record; k_ens_finalize (one
+// workgroup per scenario) then closes each scenario's step.  Kernel
+// boundaries order the steps.
 // V: the augmented momentum flux with artificial viscosity (set_viscosity);
 // EXT: the extended scheme (some scenario holds Dirichlet or given-flux cells).
 template <typename T, int TQ, int TR, int NT, bool V, bool EXT>
 __global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__restrict__ scen,
-                                                 const int32_t *__restrict__ tile_scen,
+                                                 const EnsTile *__restrict__ tiles,
                                                  Ctl *__restrict__ ctl, Part *__restrict__ part,
-                                                 int ntiles_total) {
+                                                 int ntiles_total, int par_hint) {
     const int t = xcd_tile(blockIdx.x, gridDim.x, ntiles_total, 0);
     if (t < 0) return;
-    const int s = tile_scen[t];
+    const EnsTile tl = tiles[t];
+    // what tile_load reads of the raster: its size and periodic sides
+    KGrid gl;
+    gl.nq = tl.nq;
+    gl.nr = tl.nr;
+    gl.perq = tl.wrap & 1;
+    gl.perr = (tl.wrap >> 1) & 1;
+    TileRegs<T, TQ, TR, NT> R;
+    tile_load<T, TQ, TR, NT>(R, dom_at(base, tl.off, par_hint), gl, 0, tl.tq, tl.tr);
+    const int s = tl.s;
     const StepTime st = step_time(&ctl[s]);
     if (!st.live) return;
+    const int par = ctl[s].parity;
+    const KDom<T> d = dom_at(base, tl.off, par);
+    if (par != par_hint) tile_load<T, TQ, TR, NT>(R, d, gl, 0, tl.tq, tl.tr);
     const KGrid &g = scen[s].g;  // by reference (see k_ensemble)
     const KConst &kc = scen[s].kc;
-    const int lt = t - scen[s].bbase, ntq = scen[s].bntq;
-    const int tr = lt / ntq, tq = lt - tr * ntq;
-    const KDom<T> d = dom_at(base, scen[s].off, ctl[s].parity);
     const double r_next = rain_rate(scen[s].rn, st.t_next);
     __shared__ TileLDS<T, TQ, TR, V> L;
+    const bool bad = tile_stage<T, TQ, TR, NT, EXT>(L, R, g, kc, tl.tq, tl.tr);
+    const bool inner = tile_inner(g, tl.tq * TQ, tl.tr * TR, TQ, TR);
+    const bool general = __syncthreads_or((!inner) || bad) != 0;
     Acc acc{0.0, 0.0, 0.0, 0.0};
-    tile_step<T, TQ, TR, NT, true, V, EXT>(L, d, g, kc, 0, tq, tr, st.dt, r_next, acc,
-                                          &ctl[s].err, &ctl[s].err_cell);
+    tile_compute<T, TQ, TR, NT, true, V, EXT>(L, R, general, d, g, kc, 0, tl.tq, tl.tr, st.dt,
+                                             r_next, acc, &ctl[s].err, &ctl[s].err_cell);
     const Part p = block_reduce<NT>(acc.c, acc.s, acc.o, acc.cl);
     if (threadIdx.x == 0) part[t] = p;
 }
 
 template <typename T, int TQ, int TR, int NT>
 static hipError_t launch_ens_step_v(bool visc, bool bc, const KDom<T> &base,
-                                    const EnsScen *scen, const int32_t *tile_scen, Ctl *ctl,
-                                    Part *part, int ntiles_total, int nscen, hipStream_t stream) {
+                                    const EnsScen *scen, const EnsTile *tiles, Ctl *ctl,
+                                    Part *part, int ntiles_total, int nscen, int par_hint,
+                                    hipStream_t stream) {
     if (visc)
         hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, true, true>), dim3(ntiles_total), dim3(NT),
-                           0, stream, base, scen, tile_scen, ctl, part, ntiles_total);
+                           0, stream, base, scen, tiles, ctl, part, ntiles_total, par_hint);
     else if (bc)
         hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, false, true>), dim3(ntiles_total), dim3(NT),
-                           0, stream, base, scen, tile_scen, ctl, part, ntiles_total);
+                           0, stream, base, scen, tiles, ctl, part, ntiles_total, par_hint);
     else
         hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, false, false>), dim3(ntiles_total),
-                           dim3(NT), 0, stream, base, scen, tile_scen, ctl, part, ntiles_total);
+                           dim3(NT), 0, stream, base, scen, tiles, ctl, part, ntiles_total,
+                           par_hint);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_ens_finalize(scen, ctl, part, nscen, stream);
@@ -183,13 +213,13 @@ static hipError_t launch_ens_step_v(bool visc, bool bc, const KDom<T> &base,
 
 template <typename T>
 hipError_t launch_ens_step(int variant, bool visc, bool bc, const KDom<T> &base,
-                           const EnsScen *scen, const int32_t *tile_scen, Ctl *ctl, Part *part,
-                           int ntiles_total, int nscen, hipStream_t stream) {
+                           const EnsScen *scen, const EnsTile *tiles, Ctl *ctl, Part *part,
+                           int ntiles_total, int nscen, int par_hint, hipStream_t stream) {
     switch (variant) {
 #define HEXSV_CASE(V)                                                                          \
     case V:                                                                                    \
         return launch_ens_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(                    \
-            visc, bc, base, scen, tile_scen, ctl, part, ntiles_total, nscen, stream);
+            visc, bc, base, scen, tiles, ctl, part, ntiles_total, nscen, par_hint, stream);
         HEXSV_TILE_SWITCH(HEXSV_CASE)
 #undef HEXSV_CASE
         default:
@@ -231,7 +261,7 @@ hipError_t launch_ensemble(int variant, const KDom<T> &base, const EnsScen *scen
                                            const int32_t *, int, uint32_t *, int, int,        \
                                            hipStream_t);                                      \
     template hipError_t launch_ens_step<T>(int, bool, bool, const KDom<T> &, const EnsScen *, \
-                                           const int32_t *, Ctl *, Part *, int, int,          \
+                                           const EnsTile *, Ctl *, Part *, int, int, int,     \
                                            hipStream_t);
 
 }  // namespace hexsv

@@ -28,12 +28,14 @@ constexpr TileShape ENS_TILES[] = {{64, 16, 1024}, {64, 32, 1024}, {128, 16, 102
 constexpr int NUM_ENS_TILES = sizeof(ENS_TILES) / sizeof(ENS_TILES[0]);
 
 struct EnsScen;
+struct EnsTile;
 // Batched-step mode of the ensemble: the tile kernel over the tiles of all
 // scenarios (one workgroup each) followed by the per-scenario finalize.
+// par_hint: the buffer parity the live scenarios are expected to read.
 template <typename T>
 hipError_t launch_ens_step(int variant, bool visc, bool bc, const KDom<T> &base,
-                           const EnsScen *scen, const int32_t *tile_scen, Ctl *ctl, Part *part,
-                           int ntiles_total, int nscen, hipStream_t stream);
+                           const EnsScen *scen, const EnsTile *tiles, Ctl *ctl, Part *part,
+                           int ntiles_total, int nscen, int par_hint, hipStream_t stream);
 hipError_t launch_ens_finalize(const EnsScen *scen, Ctl *ctl, const Part *part, int nscen,
                                hipStream_t stream);
 // Reset the ensemble's scenario queue (a one-thread kernel, safe inside graphs).
@@ -84,10 +86,6 @@ hipError_t launch_prime(const KDom<T> &d, int64_t n, const KConst &kc, Ctl *ctl,
 template <typename T>
 hipError_t launch_import(const double *src, T *dst, const uint8_t *active, int zero_inactive,
                          int64_t n, hipStream_t stream);
-// alpha_p (1 - theta) of FP64 caller arrays -> the FP32 state's plant field.
-template <typename T>
-hipError_t launch_import_kp(const double *ap, const double *th, T *dst, int64_t n,
-                            hipStream_t stream);
 // internal state -> FP64 caller arrays (each output nullable).
 template <typename T>
 hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double *v1,

@@ -169,24 +169,6 @@ hipError_t launch_import(const double *src, T *dst, const uint8_t *active, int z
     return hipGetLastError();
 }
 
-// The FP32 state's plant field: alpha_p (1 - theta), the static factor of the plant
-// term alpha_p h (1 - theta) of eq_K_h_theta, formed in FP64 and rounded once.
-template <typename T>
-__global__ void k_import_kp(const double *ap, const double *th, T *dst, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = (T)(ap[i] * (1.0 - th[i]));
-}
-
-template <typename T>
-hipError_t launch_import_kp(const double *ap, const double *th, T *dst, int64_t n,
-                            hipStream_t stream) {
-    const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-    hipLaunchKernelGGL((k_import_kp<T>), dim3(nb > 0 ? nb : 1), dim3(256), 0, stream, ap, th,
-                       dst, n);
-    return hipGetLastError();
-}
-
 template <typename T>
 __global__ void k_export(KDom<T> d, int par, int64_t n, double *h, double *v1, double *v2,
                          double *q1, double *q2) {
@@ -589,8 +571,6 @@ hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const S
                                             const SurWin *, hipStream_t);                     \
     template hipError_t launch_import<T>(const double *, T *, const uint8_t *, int, int64_t,  \
                                          hipStream_t);                                        \
-    template hipError_t launch_import_kp<T>(const double *, const double *, T *, int64_t,     \
-                                            hipStream_t);                                     \
     template hipError_t launch_export<T>(const KDom<T> &, int, int64_t, double *, double *,   \
                                          double *, double *, double *, hipStream_t);
 

@@ -43,16 +43,12 @@ struct Rec<double> {
 // V: the step adds the artificial viscosity of the augmented momentum flux
 // (eqs. eq_artif_visc, eq_visc1), which needs c = |v| + sqrt(g h) of every
 // staged position as well.
-// pn (FP32 plain scheme only): the staged half-velocity projected on the normals of
-// directions 1 and 2, {vh . n_1, vh . n_2}, so that the normal velocity of eq.
-// fvm_2D_eq.04 across an edge is one add of the two cells' projections.
 template <typename T, int TQ, int TR, bool V = false>
 struct TileLDS {
     static constexpr int W = TQ + 2, H = TR + 2, NS = W * H;
     typename Rec<T>::type rec[NS];
     uint8_t code[NS];
     T c[V ? NS : 1];
-    float2 pn[(sizeof(T) == 4 && !V) ? NS : 1];
 };
 
 // Map ring index t (0 <= t < 2*(TQ+2) + 2*TR) to a halo slot (lq, lr) in
@@ -92,14 +88,6 @@ __device__ inline typename Rec<T>::type make_rec(T m_or_M, T w, T vh1, T vh2) {
     return r;
 }
 
-// {vh . n_1, vh . n_2} of a staged half-velocity (FP32 plain scheme), n_1 = (1/2, s),
-// n_2 = (-1/2, s), s = sqrt(3)/2: the staged values both cells of an edge read.
-template <typename T>
-__device__ inline float2 proj(T vh1, T vh2) {
-    const float t = (float)vh2 * 0.86602540378443864676f;
-    return make_float2(t + 0.5f * (float)vh1, t - 0.5f * (float)vh1);
-}
-
 template <typename T, bool NT_STORE>
 __device__ inline void put(T *p, T v) {
     if constexpr (NT_STORE) __builtin_nontemporal_store(v, p);
@@ -137,12 +125,14 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
         R.pos[k] = pos;
         if (pos != POS_OUTSIDE) {
             const uint32_t i = (uint32_t)(r * g.nq + q);
-            R.h[k] = ld(hin, i);
+            // the state is read once per step (streaming loads); the static fields use the
+            // ordinary cache policy
+            R.h[k] = ld_stream(hin, i);
             R.th[k] = ld(d.th, i);
             R.ap[k] = ld(d.ap, i);
             R.z[k] = ld(d.z, i);
-            R.v1[k] = ld(v1in, i);
-            R.v2[k] = ld(v2in, i);
+            R.v1[k] = ld_stream(v1in, i);
+            R.v2[k] = ld_stream(v2in, i);
         }
     }
 #pragma unroll
@@ -178,7 +168,6 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
     using Regs = TileRegs<T, TQ, TR, NT>;
     constexpr int W = TQ + 2;
     constexpr bool F32 = sizeof(T) == 4;
-    constexpr bool FAST32 = F32 && !V && !EXT;
     const int q0 = tq * TQ, r0 = tr * TR;
     const bool inner = tile_inner(g, q0, r0, TQ, TR);
     const bool need_codes = !inner || g.has_mask;
@@ -206,9 +195,8 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
                                                            : (uint8_t)g.mask_bc);
             } else {
                 const T m = R.th[k] * R.h[k];
-                const T vh1 = R.v1[k] * T(0.5), vh2 = R.v2[k] * T(0.5);
-                L.rec[s] = make_rec<T>(mscale * m, G * (R.z[k] + R.h[k]), vh1, vh2);
-                if constexpr (FAST32) L.pn[s] = proj(vh1, vh2);
+                L.rec[s] = make_rec<T>(mscale * m, G * (R.z[k] + R.h[k]), R.v1[k] * T(0.5),
+                                       R.v2[k] * T(0.5));
                 if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
             }
             if constexpr (V)
@@ -219,7 +207,6 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
             wrap_pos(g, q, r);
             L.rec[s] = make_rec<T>(T(0), T(0), T(0), T(0));
             if constexpr (V) L.c[s] = T(0);
-            if constexpr (FAST32) L.pn[s] = make_float2(0.f, 0.f);
             L.code[s] = (uint8_t)side_code(g, q, r);
         }
     }
@@ -244,9 +231,8 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
                                                             : (uint8_t)g.mask_bc);
             } else {
                 const T m = R.rth[k] * R.rh[k];
-                const T vh1 = R.rv1[k] * T(0.5), vh2 = R.rv2[k] * T(0.5);
-                L.rec[s] = make_rec<T>(mscale * m, G * (R.rz[k] + R.rh[k]), vh1, vh2);
-                if constexpr (FAST32) L.pn[s] = proj(vh1, vh2);
+                L.rec[s] = make_rec<T>(mscale * m, G * (R.rz[k] + R.rh[k]), R.rv1[k] * T(0.5),
+                                       R.rv2[k] * T(0.5));
                 if (need_codes) L.code[s] = act ? (uint8_t)CODE_INTERIOR : (uint8_t)g.mask_bc;
             }
             if constexpr (V)
@@ -257,7 +243,6 @@ __device__ inline bool tile_stage(TileLDS<T, TQ, TR, V> &L, const TileRegs<T, TQ
             wrap_pos(g, q, r);
             L.rec[s] = make_rec<T>(T(0), T(0), T(0), T(0));
             if constexpr (V) L.c[s] = T(0);
-            if constexpr (FAST32) L.pn[s] = make_float2(0.f, 0.f);
             L.code[s] = (uint8_t)side_code(g, q, r);
         }
     }
@@ -275,10 +260,6 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
     using Regs = TileRegs<T, TQ, TR, NT>;
     constexpr int W = TQ + 2;
     constexpr bool F32 = sizeof(T) == 4;
-    // FP32 plain scheme: the flux's momentum term F v_(ij) is split as F v_i + F v_j, and
-    // sum_e F_e v_i = -L v_i is added once per cell, so an edge needs only the neighbour's
-    // half-velocity; its normal velocity is the sum of the two staged projections
-    constexpr bool FAST32 = F32 && !V && !EXT;
     const int q0 = tq * TQ, r0 = tr * TR;
     T *__restrict__ hout = d.buf(par ^ 1, 0);
     T *__restrict__ v1out = d.buf(par ^ 1, 1);
@@ -296,7 +277,6 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
     const bool lin = kc.tau_lin != 0.0;
     const T ftau = T(1) + dtT * (T)kc.tau_lin;
     const T h_dry = (T)kc.h_dry;
-    const T fdt4 = (T)(4.0 * dt);
     const T S3H = (T)0.86602540378443864676;
     const T NX[6] = {T(1), T(0.5), T(-0.5), T(-1), T(-0.5), T(0.5)};
     const T NY[6] = {T(0), S3H, S3H, T(0), -S3H, -S3H};
@@ -312,21 +292,17 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
         const int lr = cc / TQ, lq = cc - lr * TQ;
         const int s = (lr + 1) * W + (lq + 1);
         const int q = q0 + lq, r = r0 + lr;
-        const T hi = R.h[k], thi = R.th[k];
+        const T hi = R.h[k], thi = R.th[k], zi = R.z[k];
         const T mi = thi * hi;
-        // the cell's own staged record: the same values its neighbours read (terrain and
-        // half-velocities need no registers through the staging)
-        const typename Rec<T>::type own = L.rec[s];
-        const T Mi = own.x, wi = own.y, vh1i = own.z, vh2i = own.w;
+        const T wi = G * (zi + hi);
+        const T vh1i = R.v1[k] * T(0.5), vh2i = R.v2[k] * T(0.5);
+        const T Mi = mscale * mi;
         T Ls = T(0), A1 = T(0), A2 = T(0), S1 = T(0), S2 = T(0), Fout = T(0);
         T V1 = T(0), V2 = T(0);  // viscous part of J^v (V only)
-        float2 pi = make_float2(0.f, 0.f);  // FAST32: the cell's own staged projections
-        if constexpr (FAST32) pi = L.pn[s];
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
             const int sn = s + OFF[e];
             T mj, wj, vh1j, vh2j;
-            T pj = T(0);  // FAST32: the neighbour's projection on axis e mod 3
             int cd = CODE_INTERIOR;
             if constexpr (GEN) {
                 cd = L.code[sn];
@@ -339,14 +315,9 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 wj = nb.y;
                 vh1j = nb.z;
                 vh2j = nb.w;
-                if constexpr (FAST32) {
-                    if (e % 3 == 1) pj = L.pn[sn].x;
-                    else if (e % 3 == 2) pj = L.pn[sn].y;
-                }
             } else {
                 // free outflow ghost: the cell's h, v, theta; terrain extrapolated linearly
                 // through the opposite neighbour (read from memory: rim cells only)
-                const T zi = d.z[(int64_t)r * g.nq + q];
                 T zg = zi;
                 if (L.code[s - OFF[e]] == CODE_INTERIOR) {
                     int qo = q - dq_of(e), ro = r - dr_of(e);
@@ -357,23 +328,6 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 wj = G * (zg + hi);
                 vh1j = vh1i;
                 vh2j = vh2i;
-                if constexpr (FAST32) pj = e % 3 == 1 ? pi.x : pi.y;
-            }
-            if constexpr (FAST32) {
-                const T un = e % 3 == 0 ? vh1i + vh1j : (e % 3 == 1 ? pi.x : pi.y) + pj;
-                const T vn = e < 3 ? un : -un;
-                const T dw = wj - wi;
-                const T key = (vn != T(0)) ? vn : -dw;  // w_i > w_j decides at vn = 0
-                const T msel = key > T(0) ? Mi : mj;   // (mj holds l*theta_j*h_j)
-                const T F = msel * vn;
-                Ls -= F;
-                A1 -= F * vh1j;
-                A2 -= F * vh2j;
-                const T Q = dw * msel;
-                A1 -= Q * NXh[e];
-                if (e != 0 && e != 3) A2 -= Q * NYh[e];
-                if (GEN && cd == CODE_OUTFLOW) Fout += F;
-                continue;
             }
             // interface velocity; an edge to a Dirichlet or flux cell carries the prescribed one
             T vb1 = vh1i + vh1j;
@@ -455,10 +409,6 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 }
             }
         }
-        if constexpr (FAST32) {  // the own half-velocity's share of every edge's F v_(ij)
-            A1 += vh1i * Ls;
-            A2 += vh2i * Ls;
-        }
         const T v1i = R.v1[k], v2i = R.v2[k];
         T m1, h1, g1, g2;
         if constexpr (F32) {
@@ -519,19 +469,12 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
         if constexpr (EXT) {
             if (d.as) as_i = ld(d.as, i);  // a soil coefficient per cell
         }
-        // eq_K_h_theta: FP32 stores the plant term's static factor alpha_p (1 - theta) (formed
-        // in FP64 at import), FP64 alpha_p itself, evaluated in the oracle's order
-        const T K = F32 ? R.ap[k] * h1 + thi * as_i : R.ap[k] * h1 * (T(1) - thi) + thi * as_i;
+        const T K = R.ap[k] * h1 * (T(1) - thi) + thi * as_i;
+        const T beta = dtT * K;
         const T Gm = p_sqrt(g1 * g1 + g2 * g2);
         T alpha = m1;
         if (lin) alpha = m1 * ftau;
-        T D;
-        if constexpr (F32) {
-            D = alpha + p_sqrt(alpha * alpha + fdt4 * K * Gm);  // fdt4 = 4 dt
-        } else {
-            const T beta = dtT * K;
-            D = alpha + p_sqrt(alpha * alpha + T(4) * beta * Gm);
-        }
+        const T D = alpha + p_sqrt(alpha * alpha + T(4) * beta * Gm);
         T mu = (D == T(0)) ? T(0) : p_div(T(2), D);
         if (h_dry > T(0) && h1 < h_dry) mu = T(0);
         const T v1n = mu * g1, v2n = mu * g2;

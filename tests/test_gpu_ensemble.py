@@ -152,3 +152,54 @@ def test_standalone_autotune_writes_the_cache(hx, tmp_path, monkeypatch):
     with pytest.raises(hx.HexsvError):
         hx.autotune(cache, "step", "fp32", 10)
     torch.cuda.synchronize()
+
+
+def test_full_ensemble_one_step_sampled(hx):
+    """The whole 256-scenario ensemble (128^2 .. 512^2, about 29.9 M cells) in the batched
+    FP32 mode the benchmark times: after 40 steps, each scenario's next step matches the
+    oracle's step of the same state on sampled cells (its four sides and random interior
+    cells), and its time step is the oracle's from that state."""
+    import oracle
+    from tests._util import ref_grid, ref_params, ref_rain
+    from tests.test_gpu_parity import assert_parity
+    scs = synth.c3_ensemble(n_scen=256)
+    ens = hx.Ensemble.from_scenarios(scs, "fp32", mode="batched", steps_per_launch=20)
+    print(f"[full ensemble] {ens.info()['cells']} cells", flush=True)
+    ens.run([sc.t_end for sc in scs], max_steps=40)
+    s0 = [ens.state_numpy(s) for s in range(len(scs))]
+    b0 = [ens.books(s) for s in range(len(scs))]
+    ens.run([sc.t_end for sc in scs], max_steps=1)
+    rng = np.random.Generator(np.random.PCG64(17))
+    worst = {"h": 0.0, "q": 0.0, "dt": 0.0}
+    for s, sc in enumerate(scs):
+        st1, b1 = ens.state_numpy(s), ens.books(s)
+        G = ref_grid(sc)
+        st0 = s0[s]
+        th0 = np.where(G.active, sc.theta, 0.0)
+        cmax = oracle.cmax(G, sc.g, th0, st0["h"], st0["v1"], st0["v2"])
+        dt_ref = oracle.dt(sc.a, ref_params(sc), cmax, b0[s]["t"], sc.t_end)
+        dt = b1["t"] - b0[s]["t"]
+        worst["dt"] = max(worst["dt"], abs(dt / dt_ref - 1.0))
+        assert dt == pytest.approx(dt_ref, rel=1e-6), (s, dt, dt_ref)
+        n, nq = sc.n, sc.nq
+        cells = np.unique(np.concatenate([
+            rng.integers(0, n, 300), np.arange(0, nq), np.arange(n - nq, n),
+            np.arange(0, n, nq), np.arange(nq - 1, n, nq)]).astype(np.int32))
+        hn, v1n, v2n, _ = oracle.step_cells(G, sc.z, sc.theta, sc.alpha_p, ref_params(sc),
+                                            ref_rain(sc), dt, b1["t"], st0["h"], st0["v1"],
+                                            st0["v2"], cells)
+        th = sc.theta[cells]
+        ref = {"h": hn, "v1": v1n, "v2": v2n, "q1": th * hn * v1n, "q2": th * hn * v2n}
+        got = {k: st1[k][cells] for k in ("h", "v1", "v2")}
+        got["q1"] = th * got["h"] * got["v1"]
+        got["q2"] = th * got["h"] * got["v2"]
+        e = assert_parity(got, ref, "fp32", f"ens{s}") if s % 64 == 0 else None
+        if e is None:
+            from tests._util import rel_l1
+            e = {"h": rel_l1(got["h"], ref["h"]),
+                 "q": max(rel_l1(got["q1"], ref["q1"]), rel_l1(got["q2"], ref["q2"]))}
+            assert e["h"] <= 1e-4 and e["q"] <= 1e-3, (s, e)
+        worst["h"] = max(worst["h"], e["h"])
+        worst["q"] = max(worst["q"], e["q"])
+    print(f"[full ensemble] worst over 256 scenarios: h {worst['h']:.2e} q {worst['q']:.2e} "
+          f"dt {worst['dt']:.2e}", flush=True)

@@ -337,6 +337,17 @@ def test_full_size_one_step_sampled(hx, precision, which):
     sim.run(sc.t_end, max_steps=1)
     s1 = sim.state_numpy()
     b1 = sim.books()
+    G = ref_grid(sc)
+    # the step the oracle takes from the same state (eqs. fvm_2D_eq_frac.12-13)
+    th0 = np.where(G.active, sc.theta, 0.0)
+    cmax = oracle.cmax(G, sc.g, th0, s0["h"], s0["v1"], s0["v2"])
+    dt_ref = oracle.dt(sc.a, ref_params(sc), cmax, b0["t"], sc.t_end)
+    t_ref = sc.t_end if dt_ref == sc.t_end - b0["t"] else b0["t"] + dt_ref
+    print(f"[{which}-sampled {precision}] dt GPU {b1['t'] - b0['t']:.17g} oracle {dt_ref:.17g}")
+    if precision == "fp64":
+        assert b1["t"] == t_ref  # c_max, tau and dt bit for bit
+    else:  # c_max from the FP32 state
+        assert b1["t"] - b0["t"] == pytest.approx(dt_ref, rel=1e-6)
     dt = b1["t"] - b0["t"]
     assert dt > 0
     rng = np.random.Generator(np.random.PCG64(11))
@@ -349,7 +360,6 @@ def test_full_size_one_step_sampled(hx, precision, which):
         np.nonzero(s0["h"] > np.quantile(s0["h"], 0.999))[0][:2000],  # deepest cells
     ]).astype(np.int32)
     cells = np.unique(cells)
-    G = ref_grid(sc)
     hn, v1n, v2n, _ = oracle.step_cells(G, sc.z, sc.theta, sc.alpha_p, ref_params(sc),
                                         ref_rain(sc), dt, b1["t"], s0["h"], s0["v1"], s0["v2"],
                                         cells)

@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import synth
-from tests._util import ref_params, ref_run
+from tests._util import ref_grid, ref_params, ref_run, rel_l1
 
 P = oracle.PERIODIC
 
@@ -125,3 +125,103 @@ def test_riemann_supercritical_inflow_is_kept_only_with_the_viscous_flux():
     # without it the scheme rings upstream of the jump
     r0 = ref_run(synth.Scenario(**{**sc.__dict__, "visc": False}), nthreads=8)
     assert max(_left_state(r0, sc, x)) > 0.05
+
+
+# ------------------------------------------------------------ the sheared layer
+
+def _shear(t_end=30.0):
+    """A sheared layer over a rough vegetated bed (plant drag, random z and theta), periodic,
+    with the viscous flux: the flow decays towards rest over 30 s."""
+    nq, nr = 40, 34
+    n = nq * nr
+    r = np.repeat(np.arange(nr), nq)
+    rng = np.random.default_rng(11)
+    return synth.Scenario(name="shear", nq=nq, nr=nr, a=1.0, z=rng.uniform(0, 0.05, n),
+                          theta=rng.uniform(0.6, 1.0, n), alpha_p=np.full(n, synth.ALPHA_P),
+                          side=(P, P, P, P), h0=rng.uniform(0.05, 0.4, n),
+                          v10=np.where(r < nr // 2, 0.5, -0.5), v20=rng.normal(0, 0.1, n),
+                          t_end=t_end, visc=True)
+
+
+_NX = [1.0, 0.5, -0.5, -1.0, -0.5, 0.5]
+_S3H = 0.86602540378443864676
+_NY = [0.0, _S3H, _S3H, 0.0, -_S3H, -_S3H]
+
+
+def _steps(sc, on_step=None):
+    """The oracle's trajectory step by step; on_step(k, t, h, v1, v2) sees each start state
+    and may return a velocity increment (cell, component, value) applied before the step."""
+    G = ref_grid(sc)
+    p, r = ref_params(sc), oracle.rain(sc.rain_kind, sc.i_a, sc.t_a, sc.T_d)
+    h, v1, v2 = sc.h0.copy(), sc.v10.copy(), sc.v20.copy()
+    b = oracle.books_init(G, sc.theta, h)
+    k = 0
+    while b.t < sc.t_end:
+        if on_step is not None:
+            kick = on_step(k, b.t, h, v1, v2)
+            if kick is not None:
+                cell, comp, dv = kick
+                (v1 if comp == 0 else v2)[cell] += dv
+        h, v1, v2, b, _ = oracle.run(G, sc.z, sc.theta, sc.alpha_p, p, r, h, v1, v2, sc.t_end,
+                                     max_steps=1, books=b, nthreads=1)
+        k += 1
+    th = sc.theta
+    return {"h": h, "v1": v1, "v2": v2, "q1": th * h * v1, "q2": th * h * v2}
+
+
+def shear_branch_events(sc):
+    """Steps at which an interior edge's normal velocity v_n (eq. fvm_2D_eq.04) is nonzero but
+    below FP32 resolution, |v_n| < 2^-23 max(|v_i|, |v_j|): there the upwind choice of the
+    interface mass (eqs. fvm_2D_eq.05-.06) is decided by less than one FP32 rounding of the
+    velocities.  Returns [(step, t, cell, edge, v_n)], each edge once."""
+    G = ref_grid(sc)
+    ev = []
+
+    def scan(k, t, h, v1, v2):
+        sp = np.hypot(v1, v2)
+        for e in range(3):  # each edge once: directions 0..2 of every cell
+            j = G.nbr[:, e]
+            vn = (v1 + v1[j]) * 0.5 * _NX[e] + (v2 + v2[j]) * 0.5 * _NY[e]
+            small = (vn != 0.0) & (np.abs(vn) < 2.0 ** -23 * np.maximum(sp, sp[j]))
+            for i in np.nonzero(small)[0]:
+                ev.append((k, t, int(i), e, float(vn[i])))
+
+    _steps(sc, scan)
+    return ev
+
+
+def branch_flipped_run(sc, event):
+    """The oracle's trajectory with the one edge of `event` taking the other upwind branch: a
+    velocity increment of three times |v_n| at its step (well inside FP32 rounding of the
+    velocities) reverses the sign of v_n and changes nothing else of note."""
+    k0, _, i, e, vn = event
+    comp = 1 if _NY[e] != 0.0 else 0
+    n_c = _NY[e] if comp else _NX[e]
+    dv = -3.0 * vn / (0.5 * n_c)  # v_n + 0.5 n_c dv = -2 v_n
+
+    def kick(k, t, h, v1, v2):
+        return (i, comp, dv) if k == k0 else None
+
+    return _steps(sc, kick)
+
+
+def test_shear_layer_has_one_upwind_decision_below_fp32_resolution():
+    """On the decaying sheared layer the scheme's upwind choice of the interface mass (eqs.
+    fvm_2D_eq.05-.06) is discontinuous in v_n at 0.  Over 30 s exactly one edge meets a v_n
+    below FP32 resolution (-9.65e-10 m/s at t = 15.75 s, 8e-8 of the flow speed there), and
+    taking the other branch there, by a velocity change of 6.7e-9 m/s, moves q at 30 s by
+    1e-2 relative L1 in FP64: the gap an FP32 state (rounded at 6e-8) cannot avoid.  The same
+    change that keeps the branch moves it by less than 1e-8."""
+    sc = _shear()
+    ev = shear_branch_events(sc)
+    assert len(ev) == 1, ev
+    k, t, i, e, vn = ev[0]
+    assert 15.5 < t < 16.0 and abs(vn) < 1e-9
+    base = _steps(sc)
+    flip = branch_flipped_run(sc, ev[0])
+    dq = max(rel_l1(flip["q1"], base["q1"]), rel_l1(flip["q2"], base["q2"]))
+    assert dq > 3e-3, dq
+    # the same increment with the opposite sign keeps the branch (v_n becomes 4 v_n)
+    keep = branch_flipped_run(sc, (k, t, i, e, -vn))
+    dq_keep = max(rel_l1(keep["q1"], base["q1"]), rel_l1(keep["q2"], base["q2"]))
+    assert dq_keep < 1e-8, dq_keep
