@@ -193,6 +193,9 @@ def surrogate_block(n_train=16, n_test=100, size=512, k=16, tol=3e-5, seed=1, dt
     train_sc = [synth.ensemble_member(s, size=size, config=5, t_end=t_end) for s in range(n_train)]
     test_sc = [synth.ensemble_member(1000 + s, size=size, config=5, t_end=t_end)
                for s in range(n_test)]
+    def log(m):
+        print(f"[bench] surrogate: {m}", file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
     dt_fix = dt_scale * min(S.pilot_dt(sc) for sc in train_sc[:2])
     window = k * dt_fix
@@ -206,21 +209,23 @@ def surrogate_block(n_train=16, n_test=100, size=512, k=16, tol=3e-5, seed=1, dt
         p.append(np.zeros(co))
     sur.set_params(np.concatenate(p).astype(np.float32))
     times = list(np.linspace(window, t_end - 2 * window, 32))
+    log(f"collecting windows from {n_train} training runs")
     data, scales = S.collect(train_sc, times, window, k, sur)
-    S.train(sur, data, 3000, batch=4, lr=1e-3, lr_end=5e-5, seed=seed)
+    S.train(sur, data, 3000, batch=4, lr=1e-3, lr_end=5e-5, seed=seed, log=log)
     for rnd in range(2):  # pairs from the network's own runs, then more training
+        log(f"rollout pairs, round {rnd}")
         ro = S.rollout_pairs(sur, train_sc, list(np.linspace(2 * window, t_end - 2 * window, 16)),
                              window, k, scales, tol=tol)
         data = S.merge(data, ro)
-        S.train(sur, data, 3000, batch=4, lr=5e-4, lr_end=2e-5, seed=seed + 1 + rnd)
+        S.train(sur, data, 3000, batch=4, lr=5e-4, lr_end=2e-5, seed=seed + 1 + rnd, log=log)
     train_s = time.perf_counter() - t0
     print(f"[bench] surrogate: trained in {train_s:.0f} s; evaluating {n_test} held-out seeds",
           file=sys.stderr, flush=True)
-    ev = S.evaluate(sur, test_sc, window, k, tol, project=True)
+    ev = S.evaluate(sur, test_sc, window, k, tol, project=True, log=log)
     zero = hexsv.Surrogate(4, 32, k=k)
     zero.set_params(np.zeros(zero.num_params, np.float32))
     zero.set_scales(scales.as_list())
-    ev0 = S.evaluate(zero, test_sc, window, k, tol, project=True)
+    ev0 = S.evaluate(zero, test_sc, window, k, tol, project=True, log=log)
     print(f"[bench] surrogate: {ev['speedup']:.2f}x (zero network {ev0['speedup']:.2f}x)",
           file=sys.stderr, flush=True)
     batched = batched_regime(sur, test_sc, k, t_end)

@@ -204,13 +204,15 @@ def _timed(fn):
     return out, time.perf_counter() - t0
 
 
-def evaluate(sur, scenarios, window, k, tol=1e-3, t_end=None, project=True):
+def evaluate(sur, scenarios, window, k, tol=1e-3, t_end=None, project=True, log=None):
     """Plain FP32 solver against the surrogate run, scenario by scenario, to t_end.
 
     Returns per-scenario rows (relative L1 error of h at t_end, kept and solved windows,
     wall times) and the totals."""
     rows = []
-    for sc in scenarios:
+    for n, sc in enumerate(scenarios):
+        if log and n % 10 == 0:
+            log(f"evaluate scenario {n} of {len(scenarios)}")
         te = sc.t_end if t_end is None else t_end
         plain = hexsv.Sim.from_scenario(sc, "fp32")
         _, tp = _timed(lambda: plain.run(te))
