@@ -415,6 +415,21 @@ int hexsv_surrogate_get_scales(const hexsv_surrogate *sur, float *scales, int32_
 int hexsv_surrogate_forward(hexsv_surrogate *sur, const hexsv_grid *grid, int32_t batch,
                             int32_t nq, int32_t nr, const float *d_features, float *d_out,
                             hipStream_t stream);
+/* hexsv_surrogate_forward for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and result (outputs 0..2 of each cell; the fourth float of d_out is
+ * not written), with the packed input and the hidden activations in a static
+ * device workspace of 40 MiB that every GPU the library runs on holds until the
+ * process ends, instead of the surrogate's own workspace.  It calls no
+ * hipMalloc, hipFree or allocating library routine.  The caller passes inputs
+ * and outputs as for hexsv_surrogate_forward.  Every call on one GPU shares
+ * that GPU's workspace: calls that overlap on one GPU (other streams or host
+ * threads) race; calls on one stream are ordered.  EINVAL: batch*nq*nr above
+ * 262144 cells (one 512 x 512 sample), or the arguments hexsv_surrogate_forward
+ * refuses.  EHIP: the workspace's device address could not be looked up. */
+int hexsv_surrogate_forward_noalloc(hexsv_surrogate *sur, const hexsv_grid *grid, int32_t batch,
+                                    int32_t nq, int32_t nr, const float *d_features,
+                                    float *d_out, hipStream_t stream);
 /* Mean L1 loss over every cell and the 3 outputs against d_target
  * (batch*nq*nr x 3) and its parameter gradient (d_grad nullable, num_params
  * floats); grid as for forward; synchronises `stream`. */

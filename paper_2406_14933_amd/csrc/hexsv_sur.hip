@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -335,4 +336,79 @@ extern "C" int hexsv_surrogate_train_step(hexsv_surrogate *s, const hexsv_grid *
     s->adam_step += 1;
     HIP_TRY(nn::launch_adam(s->d_p, s->d_m, s->d_v, s->d_g, s->nparams, lr, s->adam_step, st));
     return prepare(s, st);
+}
+
+// ---- forward without allocation
+//
+// For callers that cannot allocate (graph capture, serving loops): the packed
+// input and two ping-pong hidden-activation buffers live in one static device
+// array, `scratch`, held by every GPU the library runs on until the process
+// ends.  Host code reaches it only through the address hipGetSymbolAddress
+// returns on each device (the array's name is a host-side stand-in).
+constexpr int64_t NOALLOC_MAX_CELLS = (int64_t)1 << 18;  // a 512 x 512 sample
+constexpr int64_t NOALLOC_CH = 32;                        // hidden channels built
+constexpr size_t NOALLOC_X0 = sizeof(__bf16) * nn::FEATURES_PAD * NOALLOC_MAX_CELLS;
+constexpr size_t NOALLOC_ACT = sizeof(__bf16) * NOALLOC_CH * NOALLOC_MAX_CELLS;
+constexpr size_t NOALLOC_BYTES = NOALLOC_X0 + 2 * NOALLOC_ACT;  // 40 MiB
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+static const int NOALLOC_MAX_DEVICES = 64;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up once per device).
+static int scratch_of_device(unsigned char **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(HEXSV_EUNSUPPORTED, "surrogate_forward_noalloc: device %d", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HEXSV_EHIP, "surrogate_forward_noalloc: hipGetSymbolAddress: %s",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (unsigned char *)g_scratch_ptr[dev];
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_surrogate_forward_noalloc(hexsv_surrogate *s, const hexsv_grid *grid,
+                                               int32_t batch, int32_t nq, int32_t nr,
+                                               const float *d_features, float *d_out,
+                                               hipStream_t st) {
+    if (!s || !d_features || !d_out)
+        return fail(HEXSV_EINVAL, "surrogate_forward_noalloc: null argument");
+    if (batch < 1 || nq < 1 || nr < 1)
+        return fail(HEXSV_EINVAL, "surrogate_forward_noalloc: bad batch or raster size");
+    if (!s->weights_ready) return fail(HEXSV_ESTATE, "surrogate_forward_noalloc: set the parameters first");
+    const int64_t cells = (int64_t)batch * nq * nr;
+    if (cells > NOALLOC_MAX_CELLS)
+        return fail(HEXSV_EINVAL,
+                    "surrogate_forward_noalloc: %lld cells exceed the %lld of its static workspace "
+                    "(use hexsv_surrogate_forward)", (long long)cells, (long long)NOALLOC_MAX_CELLS);
+    if (s->channels != NOALLOC_CH)
+        return fail(HEXSV_EUNSUPPORTED, "surrogate_forward_noalloc: %d channels", s->channels);
+    nn::ConvMask cm;
+    int rc = conv_mask(grid, nq, nr, &cm, "surrogate_forward_noalloc");
+    if (rc) return rc;
+    unsigned char *ws = nullptr;
+    rc = scratch_of_device(&ws);
+    if (rc) return rc;
+    __bf16 *x0 = (__bf16 *)ws;
+    __bf16 *act[2] = {(__bf16 *)(ws + NOALLOC_X0), (__bf16 *)(ws + NOALLOC_X0 + NOALLOC_ACT)};
+    // every buffer is written in full before it is read: nothing needs clearing
+    HIP_TRY(nn::launch_pack_features(d_features, cells, x0, st));
+    const __bf16 *x = x0;
+    for (int l = 0; l < s->layers; ++l) {
+        const SurLayer &y = s->L[l];
+        const bool last = l == s->layers - 1;
+        void *o = last ? (void *)d_out : (void *)act[l & 1];
+        HIP_TRY(nn::launch_conv(y.cinp, y.coutp, last ? nn::EPI_LIN : nn::EPI_RELU, x, y.wm, y.bias,
+                                o, nullptr, nq, nr, batch, y.cout, cm, st));
+        if (!last) x = act[l & 1];
+    }
+    return HEXSV_OK;
 }

@@ -115,6 +115,8 @@ _SIGS = [
     ("hexsv_surrogate_get_scales", C.c_int, [_VP, C.POINTER(C.c_float), C.c_int32]),
     ("hexsv_surrogate_forward", C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
                                           _VP]),
+    ("hexsv_surrogate_forward_noalloc", C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_int32,
+                                                  _VP, _VP, _VP]),
     ("hexsv_surrogate_gradient", C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
                                            _VP, C.POINTER(C.c_double), _VP]),
     ("hexsv_surrogate_train_step", C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
@@ -553,6 +555,21 @@ class Surrogate:
         out = torch.empty((batch * nq * nr, 4), dtype=torch.float32, device="cuda")
         _check(lib().hexsv_surrogate_forward(self._h, grid._h if grid else None, batch, int(nq),
                                              int(nr), _ptr(f), _ptr(out), _stream()))
+        return out
+
+    def forward_noalloc(self, features, nq, nr, out, grid=None):
+        """forward into the caller's `out` ((cells, 4) FP32 on the device; columns 0..2
+        written) with the library's static workspace: no allocation inside the call."""
+        for name, t in (("features", features), ("out", out)):
+            if not (torch.is_tensor(t) and t.is_cuda and t.dtype == torch.float32
+                    and t.is_contiguous()):
+                raise ValueError(f"{name}: a contiguous FP32 device tensor (no copy is made)")
+        batch = self._shape(features, nq, nr, self.FEATURES)
+        if out.numel() != 4 * batch * nq * nr:
+            raise ValueError("out: 4 floats per cell")
+        _check(lib().hexsv_surrogate_forward_noalloc(self._h, grid._h if grid else None, batch,
+                                                     int(nq), int(nr), _ptr(features), _ptr(out),
+                                                     _stream()))
         return out
 
     def gradient(self, features, target, nq, nr, grid=None):
