@@ -64,6 +64,7 @@ extern "C" int hexsv_grid_create(const hexsv_grid_desc *desc, hexsv_grid **out) 
     memset(&kg, 0, sizeof kg);
     kg.nq = desc->nq;
     kg.nr = desc->nr;
+    kg.pitch = desc->nq;
     kg.perq = perq;
     kg.perr = perr;
     for (int s = 0; s < 4; ++s) kg.side[s] = desc->side_bc[s];

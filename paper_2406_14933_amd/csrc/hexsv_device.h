@@ -36,6 +36,7 @@ constexpr int MAX_SEG = 8;
 // Raster description as the kernels see it (passed by value).
 struct KGrid {
     int32_t nq, nr;
+    int32_t pitch;  // row stride of the cell arrays (nq, or more for aligned rows)
     int32_t perq, perr;
     int32_t side[4];
     int32_t nseg;

@@ -31,7 +31,8 @@ struct hexsv_ensemble {
     std::vector<EnsScen> scen;  // host copy
     std::vector<int64_t> active;
     int64_t total;
-    void *buf;                  // [h0 v10 v20 h1 v11 v21 z th ap], total elements each
+    void *buf;                  // [h0 v10 v20 h1 v11 v21 z th ap], total elements each;
+                                // scenario s at scen[s].off, rows scen[s].g.pitch apart
     EnsScen *d_scen;
     Ctl *d_ctl;
     Ctl *h_ctl;                 // pinned mirror, n entries
@@ -48,6 +49,11 @@ struct hexsv_ensemble {
     double timed_ms;
     int64_t timed_updates, timed_launches;
 };
+
+// Row stride of a scenario's arrays: nq rounded up to 16 cells, so that every row
+// starts on a 64-byte boundary (128 in FP64) and a row's stores cover whole cache
+// lines instead of sharing a line with the next row.  The padding cells stay zero.
+static int ens_pitch(int nq) { return (nq + 15) / 16 * 16; }
 
 template <typename T>
 static KDom<T> ens_base(const hexsv_ensemble *e) {
@@ -112,6 +118,7 @@ static int ens_set_btile(hexsv_ensemble *e, int v) {
             tl.off = sc.off;
             tl.nq = sc.g.nq;
             tl.nr = sc.g.nr;
+            tl.pitch = sc.g.pitch;
             tl.tr = lt / ntq;
             tl.tq = lt - tl.tr * ntq;
             tl.s = s;
@@ -159,7 +166,8 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         return fail(HEXSV_EINVAL, "ensemble_create: mode %d unknown", p.ensemble_mode);
     for (int s = 0; s < n; ++s) {
         if (!grids[s]) return fail(HEXSV_EINVAL, "ensemble_create: grid %d is null", s);
-        if ((uint64_t)grids[s]->n * (p.precision == HEXSV_FP64 ? 8u : 4u) >= (1ull << 32))
+        if ((uint64_t)grids[s]->kg.nr * ens_pitch(grids[s]->kg.nq) *
+                (p.precision == HEXSV_FP64 ? 8u : 4u) >= (1ull << 32))
             return fail(HEXSV_EUNSUPPORTED, "ensemble_create: scenario %d exceeds 4 GiB per field", s);
     }
     hexsv_ensemble *e = new (std::nothrow) hexsv_ensemble();
@@ -184,6 +192,7 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         memset(&sc, 0, sizeof sc);
         sc.off = off;
         sc.g = grids[s]->kg;
+        sc.g.pitch = ens_pitch(sc.g.nq);
         const double a = grids[s]->edge;
         sc.kc.g = p.g;
         sc.kc.a = a;
@@ -193,8 +202,8 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
         sc.rn.kind = 0;
         sc.rn.T_d = INFINITY;
         e->active[s] = grids[s]->n_active;
-        off += grids[s]->n;
-        off = (off + 63) / 64 * 64;  // keep every scenario 256-byte aligned
+        off += (int64_t)sc.g.nr * sc.g.pitch;
+        off = (off + 63) / 64 * 64;  // keep every scenario 64 cells aligned
     }
     e->total = off;
     // mode and tile: explicit, else from the tuning cache (encoded as
@@ -286,15 +295,18 @@ static int ens_import(hexsv_ensemble *e, int s, const double *z, const double *t
                       const double *h, const double *v1, const double *v2, hipStream_t stream) {
     const KDom<T> d = ens_dom<T>(e, s);
     const hexsv_grid *g = e->grids[s];
-    HIP_TRY(launch_import<T>(z, (T *)d.z, g->d_active, 0, g->n, stream));
-    HIP_TRY(launch_import<T>(th, (T *)d.th, g->d_active, 2, g->n, stream));
-    HIP_TRY(launch_import<T>(ap, (T *)d.ap, g->d_active, 0, g->n, stream));
+    // rows land at the scenario's pitch; the padding cells stay zero (theta 0: outside)
+    const int nq = g->kg.nq, pitch = e->scen[s].g.pitch;
+    HIP_TRY(launch_import<T>(z, (T *)d.z, g->d_active, 0, g->n, stream, nq, pitch));
+    HIP_TRY(launch_import<T>(th, (T *)d.th, g->d_active, 2, g->n, stream, nq, pitch));
+    HIP_TRY(launch_import<T>(ap, (T *)d.ap, g->d_active, 0, g->n, stream, nq, pitch));
     for (int p = 0; p < 2; ++p) {
-        HIP_TRY(launch_import<T>(h, d.st[p][0], g->d_active, 1, g->n, stream));
-        HIP_TRY(launch_import<T>(v1, d.st[p][1], g->d_active, 1, g->n, stream));
-        HIP_TRY(launch_import<T>(v2, d.st[p][2], g->d_active, 1, g->n, stream));
+        HIP_TRY(launch_import<T>(h, d.st[p][0], g->d_active, 1, g->n, stream, nq, pitch));
+        HIP_TRY(launch_import<T>(v1, d.st[p][1], g->d_active, 1, g->n, stream, nq, pitch));
+        HIP_TRY(launch_import<T>(v2, d.st[p][2], g->d_active, 1, g->n, stream, nq, pitch));
     }
-    HIP_TRY(launch_prime<T>(d, g->n, e->scen[s].kc, e->d_ctl + s, e->d_part, PRIME_BLOCKS, 1, stream));
+    HIP_TRY(launch_prime<T>(d, (int64_t)g->kg.nr * pitch, e->scen[s].kc, e->d_ctl + s, e->d_part,
+                            PRIME_BLOCKS, 1, stream));
     return HEXSV_OK;
 }
 
@@ -454,10 +466,13 @@ extern "C" int hexsv_ensemble_get_state(const hexsv_ensemble *ec, int32_t s, dou
     HIP_TRY(hipStreamSynchronize(stream));
     const int par = e->h_ctl[s].parity;
     const int64_t n = e->grids[s]->n;
+    const int nq = e->grids[s]->kg.nq, pitch = e->scen[s].g.pitch;
     if (e->prec == HEXSV_FP64)
-        HIP_TRY(launch_export<double>(ens_dom<double>(e, s), par, n, d_h, d_v1, d_v2, d_q1, d_q2, stream));
+        HIP_TRY(launch_export<double>(ens_dom<double>(e, s), par, n, d_h, d_v1, d_v2, d_q1, d_q2, stream,
+                                      nq, pitch));
     else
-        HIP_TRY(launch_export<float>(ens_dom<float>(e, s), par, n, d_h, d_v1, d_v2, d_q1, d_q2, stream));
+        HIP_TRY(launch_export<float>(ens_dom<float>(e, s), par, n, d_h, d_v1, d_v2, d_q1, d_q2, stream,
+                                     nq, pitch));
     return HEXSV_OK;
 }
 

@@ -38,7 +38,7 @@ struct EnsScen {
 // scenario's control block and constants.
 struct alignas(16) EnsTile {
     int64_t off;
-    int32_t nq, nr;
+    int32_t nq, nr, pitch;
     int32_t tq, tr;
     int32_t s;
     int32_t wrap;  // bit 0: periodic in q, bit 1: periodic in r
@@ -167,6 +167,7 @@ __global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__
     KGrid gl;
     gl.nq = tl.nq;
     gl.nr = tl.nr;
+    gl.pitch = tl.pitch;
     gl.perq = tl.wrap & 1;
     gl.perr = (tl.wrap >> 1) & 1;
     TileRegs<T, TQ, TR, NT> R;

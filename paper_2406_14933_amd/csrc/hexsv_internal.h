@@ -83,13 +83,15 @@ hipError_t launch_prime(const KDom<T> &d, int64_t n, const KConst &kc, Ctl *ctl,
                         int nblocks, int reset_books, hipStream_t stream);
 
 // FP64 caller arrays -> internal precision (theta forced to 0 outside the mask).
+// nq, pitch: the internal rows are `pitch` cells apart (0: the caller's layout).
 template <typename T>
 hipError_t launch_import(const double *src, T *dst, const uint8_t *active, int zero_inactive,
-                         int64_t n, hipStream_t stream);
-// internal state -> FP64 caller arrays (each output nullable).
+                         int64_t n, hipStream_t stream, int64_t nq = 0, int64_t pitch = 0);
+// internal state -> FP64 caller arrays (each output nullable); nq, pitch as above.
 template <typename T>
 hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double *v1,
-                         double *v2, double *q1, double *q2, hipStream_t stream);
+                         double *v2, double *q1, double *q2, hipStream_t stream,
+                         int64_t nq = 0, int64_t pitch = 0);
 
 // Validation of caller inputs: counts offending active cells and records the
 // lowest offending index in chk[0] (count) / chk[1] (index) / chk[2] (reason).

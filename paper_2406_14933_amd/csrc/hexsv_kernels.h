@@ -144,41 +144,49 @@ hipError_t launch_prime(const KDom<T> &d, int64_t n, const KConst &kc, Ctl *ctl,
     return launch_prime_finalize(ctl, part, nblocks, kc, reset_books, stream);
 }
 
+// Cell i of a row-major raster of nq columns sits at element (i / nq) pitch + i % nq
+// of an array whose rows are `pitch` apart (pitch == nq: the same index).
+__device__ inline int64_t pitched(int64_t i, int64_t nq, int64_t pitch) {
+    return pitch == nq ? i : (i / nq) * pitch + (i % nq);
+}
+
 // zero_inactive: 0 copies, 1 writes zero outside the domain, 2 also negates the
 // value on Dirichlet cells and writes -2 on flux cells (theta: the step kernel tells
 // such cells by theta < 0 and theta < -1.5).
 template <typename T>
 __global__ void k_import(const double *src, T *dst, const uint8_t *active, int zero_inactive,
-                         int64_t n) {
+                         int64_t n, int64_t nq, int64_t pitch) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint8_t a = active ? active[i] : (uint8_t)1;
         T v = (zero_inactive && a == 0) ? T(0) : (T)src[i];
         if (zero_inactive == 2 && a == 2) v = -v;
         if (zero_inactive == 2 && a == 3) v = T(-2);
-        dst[i] = v;
+        dst[pitched(i, nq, pitch)] = v;
     }
 }
 
 template <typename T>
 hipError_t launch_import(const double *src, T *dst, const uint8_t *active, int zero_inactive,
-                         int64_t n, hipStream_t stream) {
+                         int64_t n, hipStream_t stream, int64_t nq, int64_t pitch) {
     const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (nq <= 0 || pitch < nq) nq = pitch = 1;
     hipLaunchKernelGGL((k_import<T>), dim3(nb > 0 ? nb : 1), dim3(256), 0, stream, src, dst,
-                       active, zero_inactive, n);
+                       active, zero_inactive, n, nq, pitch);
     return hipGetLastError();
 }
 
 template <typename T>
 __global__ void k_export(KDom<T> d, int par, int64_t n, double *h, double *v1, double *v2,
-                         double *q1, double *q2) {
+                         double *q1, double *q2, int64_t nq, int64_t pitch) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double hh = (double)d.buf(par, 0)[i];
-        const double a = (double)d.buf(par, 1)[i];
-        const double b = (double)d.buf(par, 2)[i];
+        const int64_t j = pitched(i, nq, pitch);
+        const double hh = (double)d.buf(par, 0)[j];
+        const double a = (double)d.buf(par, 1)[j];
+        const double b = (double)d.buf(par, 2)[j];
         // Dirichlet cells hold -theta; flux cells hold -2 and carry the discharge h v
-        const double ts = (double)d.th[i];
+        const double ts = (double)d.th[j];
         const double th = ts < -1.5 ? 1.0 : __builtin_fabs(ts);
         if (h) h[i] = hh;
         if (v1) v1[i] = a;
@@ -190,10 +198,12 @@ __global__ void k_export(KDom<T> d, int par, int64_t n, double *h, double *v1, d
 
 template <typename T>
 hipError_t launch_export(const KDom<T> &d, int par, int64_t n, double *h, double *v1,
-                         double *v2, double *q1, double *q2, hipStream_t stream) {
+                         double *v2, double *q1, double *q2, hipStream_t stream, int64_t nq,
+                         int64_t pitch) {
     const int nb = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (nq <= 0 || pitch < nq) nq = pitch = 1;
     hipLaunchKernelGGL((k_export<T>), dim3(nb > 0 ? nb : 1), dim3(256), 0, stream, d, par, n,
-                       h, v1, v2, q1, q2);
+                       h, v1, v2, q1, q2, nq, pitch);
     return hipGetLastError();
 }
 
@@ -570,8 +580,9 @@ hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const S
     template hipError_t launch_win_scale<T>(const KDom<T> &, int64_t, const Ctl *,            \
                                             const SurWin *, hipStream_t);                     \
     template hipError_t launch_import<T>(const double *, T *, const uint8_t *, int, int64_t,  \
-                                         hipStream_t);                                        \
+                                         hipStream_t, int64_t, int64_t);                      \
     template hipError_t launch_export<T>(const KDom<T> &, int, int64_t, double *, double *,   \
-                                         double *, double *, double *, hipStream_t);
+                                         double *, double *, double *, hipStream_t, int64_t,  \
+                                         int64_t);
 
 }  // namespace hexsv

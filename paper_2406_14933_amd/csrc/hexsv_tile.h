@@ -124,7 +124,7 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
             pos = wrap_pos(g, q, r) ? POS_NEIGHBOUR : POS_OUTSIDE;
         R.pos[k] = pos;
         if (pos != POS_OUTSIDE) {
-            const uint32_t i = (uint32_t)(r * g.nq + q);
+            const uint32_t i = (uint32_t)(r * g.pitch + q);
             // the state is read once per step (streaming loads); the static fields use the
             // ordinary cache policy
             R.h[k] = ld_stream(hin, i);
@@ -145,7 +145,7 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
             int q = q0 + lq - 1, r = r0 + lr - 1;
             if (inner || wrap_pos(g, q, r)) {
                 R.rpos[k] = POS_NEIGHBOUR;
-                const uint32_t i = (uint32_t)(r * g.nq + q);
+                const uint32_t i = (uint32_t)(r * g.pitch + q);
                 R.rh[k] = ld(hin, i);
                 R.rth[k] = ld(d.th, i);
                 R.rz[k] = ld(d.z, i);
@@ -322,7 +322,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 if (L.code[s - OFF[e]] == CODE_INTERIOR) {
                     int qo = q - dq_of(e), ro = r - dr_of(e);
                     wrap_pos(g, qo, ro);
-                    zg = T(2) * zi - d.z[(int64_t)ro * g.nq + qo];
+                    zg = T(2) * zi - d.z[(int64_t)ro * g.pitch + qo];
                 }
                 mj = Mi;
                 wj = G * (zg + hi);
@@ -464,7 +464,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 h1 = x;
             }
         }
-        const uint32_t i = (uint32_t)(r * g.nq + q);
+        const uint32_t i = (uint32_t)(r * g.pitch + q);
         T as_i = alpha_s;
         if constexpr (EXT) {
             if (d.as) as_i = ld(d.as, i);  // a soil coefficient per cell
@@ -519,7 +519,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 if (R.pos[k] != POS_OWN) continue;
                 const int cc = threadIdx.x + k * NT;
                 const int lr = cc / TQ, lq = cc - lr * TQ;
-                const uint32_t i = (uint32_t)((r0 + lr) * g.nq + q0 + lq);
+                const uint32_t i = (uint32_t)((r0 + lr) * g.pitch + q0 + lq);
                 if (!__builtin_isfinite(ld(hout, i)) || !__builtin_isfinite(ld(v1out, i)) ||
                     !__builtin_isfinite(ld(v2out, i))) {
                     if (atomicOr(err_flag, 1) == 0) *err_cell = (int32_t)i;
