@@ -292,11 +292,23 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
         const int lr = cc / TQ, lq = cc - lr * TQ;
         const int s = (lr + 1) * W + (lq + 1);
         const int q = q0 + lq, r = r0 + lr;
-        const T hi = R.h[k], thi = R.th[k], zi = R.z[k];
+        const T hi = R.h[k], thi = R.th[k];
         const T mi = thi * hi;
-        const T wi = G * (zi + hi);
-        const T vh1i = R.v1[k] * T(0.5), vh2i = R.v2[k] * T(0.5);
-        const T Mi = mscale * mi;
+        // FP32 takes the cell's own staged record (the values the neighbours see), so that
+        // bed and velocity registers are free after staging; FP64 keeps them
+        T wi, vh1i, vh2i, Mi;
+        if constexpr (F32) {
+            const typename Rec<T>::type me = L.rec[s];
+            Mi = me.x;
+            wi = me.y;
+            vh1i = me.z;
+            vh2i = me.w;
+        } else {
+            wi = G * (R.z[k] + hi);
+            vh1i = R.v1[k] * T(0.5);
+            vh2i = R.v2[k] * T(0.5);
+            Mi = mscale * mi;
+        }
         T Ls = T(0), A1 = T(0), A2 = T(0), S1 = T(0), S2 = T(0), Fout = T(0);
         T V1 = T(0), V2 = T(0);  // viscous part of J^v (V only)
 #pragma unroll
@@ -318,14 +330,15 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
             } else {
                 // free outflow ghost: the cell's h, v, theta; terrain extrapolated linearly
                 // through the opposite neighbour (read from memory: rim cells only)
-                T zg = zi;
+                wj = wi;
                 if (L.code[s - OFF[e]] == CODE_INTERIOR) {
                     int qo = q - dq_of(e), ro = r - dr_of(e);
                     wrap_pos(g, qo, ro);
-                    zg = T(2) * zi - d.z[(int64_t)ro * g.pitch + qo];
+                    const T zi = ld(d.z, (uint32_t)(r * g.pitch + q));
+                    const T zg = T(2) * zi - d.z[(int64_t)ro * g.pitch + qo];
+                    wj = G * (zg + hi);
                 }
                 mj = Mi;
-                wj = G * (zg + hi);
                 vh1j = vh1i;
                 vh2j = vh2i;
             }
@@ -409,7 +422,7 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
                 }
             }
         }
-        const T v1i = R.v1[k], v2i = R.v2[k];
+        const T v1i = F32 ? vh1i + vh1i : R.v1[k], v2i = F32 ? vh2i + vh2i : R.v2[k];
         T m1, h1, g1, g2;
         if constexpr (F32) {
             const T dm = dts * Ls + dtT * rT;
