@@ -39,15 +39,21 @@ BYTES_PER_CELL = {"fp32": 9 * 4, "fp64": 9 * 8}
 # Measured HBM bytes of one step-kernel launch: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB
 # per dispatch, in runs of their own) scaled by what the same counters read for a plain 1 GiB
 # device copy (x2.000 and x1.000); the summaries with their commands are
-# profiles/k_step_catchment-{4096x4096,1024x1024}_fp32.md (at 1024 x 1024 the working set sits
-# in the Infinity Cache, whose hits these counters include).  A figure holds only for the
-# kernel source it was taken on (digest below); otherwise the line reports null.
+# profiles/k_step_catchment-4096x4096_fp32.md and profiles/k_ens_step_ensemble-256-catchments.md.
+# A figure holds only for the kernel source it was taken on (digest below); otherwise the line
+# reports null.
 TRAFFIC = {
-    ("catchment-4096x4096-edge2m-storm150mmh", "fp32", 2): {
-        "bytes": 607022052, "digest": "2747f7c54e97d04c"},
-    ("catchment-1024x1024-edge2m-rain100mmh", "fp32", 2): {
-        "bytes": 38561426, "digest": "2747f7c54e97d04c"},
+    ("catchment-4096x4096-edge2m-storm150mmh", "fp32", 4): {
+        "bytes": 654465120, "digest": "9e1757e4b51ca5bc"},
 }
+# the batched ensemble's k_ens_step (64 x 16 tiles) per launch over all 256 scenarios
+ENS_TRAFFIC = {("fp32", 2): {"bytes": 1220714464, "digest": "3416da37e77f4e42"}}
+
+
+# Surrogate network FLOPs per cell (7 taps, 4 layers): what the MFMA units execute (11 input
+# features padded to 16 channels, 3 outputs to 16) and the algorithmic count (11 and 3).
+NET_FLOP_EXECUTED = 2 * 7 * (16 * 32 + 32 * 32 + 32 * 32 + 32 * 16)
+NET_FLOP_ALGORITHMIC = 2 * 7 * (11 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
 
 
 def step_kernel_digest():
@@ -66,6 +72,21 @@ def step_kernel_digest():
 def traffic_of(wname, precision, tile):
     t = TRAFFIC.get((wname, precision, tile))
     return t["bytes"] if t and t["digest"] == step_kernel_digest() else None
+
+
+def ens_kernel_digest():
+    """Digest of the batched ensemble step kernel's source (with the tile phases)."""
+    d = os.path.join(ROOT, "paper_2406_14933_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("hexsv_device.h", "hexsv_tile.h", "hexsv_ensemble.h"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def ens_traffic_of(precision, tile):
+    t = ENS_TRAFFIC.get((precision, tile))
+    return t["bytes"] if t and t["digest"] == ens_kernel_digest() else None
 
 
 def workload(name):
@@ -171,9 +192,12 @@ def time_ensemble(precision, launches, ksteps, n_scen, tune):
             "steps_per_scenario": launches * ksteps, "wall_s": wall,
             "gpu_value": tm["cell_updates"] / (tm["gpu_ms"] * 1e-3),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": kernel, "kernel_us_source": "hipEvents around the step graphs",
-                         "bytes_per_cell": bpc},
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": (ens_traffic_of(precision, info["tile"])
+                                     if info["mode"] == "batched" else None),
+                         "kernel": kernel, "kernel_us_source": "hipEvents around the step graphs "
+                                                               "(k_ens_step and k_ens_finalize)",
+                         "bytes_per_cell": bpc, "bytes_per_launch": bpc * info["cells"]},
             "info": info}
 
 
@@ -286,8 +310,7 @@ def batched_regime(sur, scs, k, t_end):
     call_ms = 1e3 * min(calls)
     del f
     torch.cuda.empty_cache()
-    # FLOPs the MFMA units execute per cell (channels padded to 16 and 32): 4 layers
-    flop = 2 * 7 * (16 * 32 + 32 * 32 + 32 * 32 + 32 * 16) * n * nq * nr
+    flop = NET_FLOP_EXECUTED * n * nq * nr
     return {"scenarios": n, "cells": cells, "plain_s": wall,
             "plain_cell_updates_per_s": tm["cell_updates"] / wall,
             "plain_step_ms": step_ms, "steps_max": max(steps),
@@ -351,10 +374,11 @@ def network_cost(batch=16, size=512, calls=5):
         sur.forward(f, size, size)
         torch.cuda.synchronize()
         ms.append(1e3 * (time.perf_counter() - t0))
-    flop = 2 * 7 * (16 * 32 + 32 * 32 + 32 * 32 + 32 * 16) * batch * size * size
+    cells = batch * size * size
+    flop = NET_FLOP_EXECUTED * cells
     return {"workload": f"network-{batch}x{size}x{size}", "call_ms": min(ms),
             "tflops": flop / (min(ms) * 1e-3) / 1e12, "mfma_frac": flop / (min(ms) * 1e-3) / 2.5e15,
-            "flop_per_call": flop}
+            "flop_per_call": flop, "algorithmic_flop_per_call": NET_FLOP_ALGORITHMIC * cells}
 
 
 def cpu_model():
