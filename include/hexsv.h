@@ -396,6 +396,13 @@ int64_t hexsv_surrogate_num_params(const hexsv_surrogate *sur);
 /* k of create: the solver steps one window spans (EINVAL at create if k < 1).
  * The window calls below take it when their own k is <= 0.  -1 for a null handle. */
 int32_t hexsv_surrogate_steps(const hexsv_surrogate *sur);
+/* Forward of the 4-layer, 32-channel network as one fused kernel (on = 1:
+ * activations stay on chip, 16 x 16 output cells per workgroup with a 4-cell
+ * halo, 1.46x the MFMA work for the recomputed halo) or one launch per layer
+ * (on = 0, the default, which measures faster on 512 x 512 rasters).  Both give
+ * the same outputs bit for bit; other depths always run per layer.  EINVAL:
+ * null handle or on not 0/1. */
+int hexsv_surrogate_set_fused(hexsv_surrogate *sur, int32_t on);
 /* Copy parameters in (device FP32, n == num_params; resets Adam) or out. */
 int hexsv_surrogate_set_params(hexsv_surrogate *sur, const float *d_params, int64_t n,
                                hipStream_t stream);

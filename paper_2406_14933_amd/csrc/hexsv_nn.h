@@ -36,6 +36,18 @@ hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf
                        const float *bias, void *out, const __bf16 *mask, int nq, int nr,
                        int batch, int cout_real, const ConvMask &cm, hipStream_t st,
                        const int32_t *live = nullptr);
+// The 4-layer network with 32 hidden channels in one launch (k_hexnet4): weights
+// and biases of each layer as for launch_conv (layer 0: 16 -> 32, layers 1-2:
+// 32 -> 32, layer 3: 32 -> 16 with cout_real outputs written, FP32, OUT_STRIDE
+// per cell); the output equals the layer-by-layer launch_conv chain bit for bit.
+struct Net4 {
+    const __bf16 *wm[4];
+    const float *bias[4];
+};
+int net4_tiles(int nq, int nr, int batch);
+hipError_t launch_net4(const __bf16 *x, const Net4 &nw, float *out, int nq, int nr, int batch,
+                       int cout_real, const ConvMask &cm, hipStream_t st,
+                       const int32_t *live = nullptr);
 // Per-tile weight-gradient partials (7*coutp*cinp + coutp floats per tile).
 hipError_t launch_wgrad(int cinp, int coutp, const __bf16 *x, const __bf16 *dy, float *part,
                         int nq, int nr, int batch, const ConvMask &cm, hipStream_t st);

@@ -195,6 +195,192 @@ __global__ __launch_bounds__(NT) void k_hexconv(const __bf16 *__restrict__ x,
     }
 }
 
+// ------------------------------------------------------- fused 4-layer forward
+//
+// The whole 4-layer network (16 -> 32 -> 32 -> 32 -> 16 channels) for a 16 x 16
+// tile of output cells in one workgroup.  The packed input features of the tile
+// and a 4-cell margin (24 x 24 positions) are staged once; layer l is evaluated on
+// the tile grown by 3 - l cells on each side and its activations stay in LDS for
+// layer l + 1, so hidden activations never leave the CU.  Each layer's arithmetic
+// is that of k_hexconv (the same MFMA, the same K order, bias and ReLU, the same
+// bf16 rounding of hidden activations), so the output equals the layer-by-layer
+// chain's bit for bit.  fl[p] is 1 where staged position p holds a cell of the
+// domain (wrapped through periodic sides); a tap t >= 1 reads its neighbour only
+// when the centre and the neighbour both are, which also zeroes every position
+// outside the raster, as the chain's zero staging does.
+namespace f4 {
+constexpr int OT = 16;        // output tile edge
+constexpr int WI = OT + 8;    // staged input frame edge (margin 4)
+constexpr int NG = 4;         // 16-cell column groups per wave pass
+}
+
+// One layer over a WO x WO frame.  taps_all: every staged position of the tile is
+// a domain cell (an interior tile of an unmasked raster), so no tap is cut.
+// SSTR: 16-byte chunks between consecutive source cells; DSTR: bf16 values
+// between consecutive destination cells (hidden activations are padded from 64
+// to 80 bytes per cell, so that the 16 cells of an MFMA column fall on distinct
+// LDS banks when gathered and when written).
+template <int CIN, int COUT, int EPI, int WO, int SSTR, int DSTR>
+__device__ inline void net_layer(const uint4 *src, uint4 *dst, const uint8_t *fl,
+                                 const __bf16 *__restrict__ wm, const float *__restrict__ bias,
+                                 float *__restrict__ out, int nq, int nr, int64_t soff, int q0,
+                                 int r0, int cout_real, bool taps_all) {
+    using namespace f4;
+    constexpr int CH = CIN / 8;            // 16-byte chunks per source cell
+    constexpr int MB = COUT / 16;
+    constexpr int TPK = 32 / CIN;
+    constexpr int KSTEPS = (7 + TPK - 1) / TPK;
+    constexpr int WS = WO + 2;             // source frame edge
+    constexpr int OI = (WI - WO) / 2;      // this frame's origin in the staged frame
+    constexpr int NCELL = WO * WO;
+    constexpr int NGRP = (NCELL + 15) / 16;
+    constexpr int NCHUNK = (NGRP + NG - 1) / NG;
+    constexpr int OFF_S[7] = {0, 1, WS, WS - 1, -1, -WS, -WS + 1};
+    constexpr int OFF_I[7] = {0, 1, WI, WI - 1, -1, -WI, -WI + 1};
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, l16 = lane & 15;
+    // this lane's weight fragments for every K step, loaded once per layer
+    bf16x8 av[KSTEPS][MB];
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        const int tap = ks * TPK + g / CH;
+        const int c0 = (g % CH) * 8;
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+            av[ks][m] = tap < 7 ? *reinterpret_cast<const bf16x8 *>(
+                                      wm + ((int64_t)(tap * COUT + m * 16 + l16)) * CIN + c0)
+                                : bf16x8{};
+    }
+    for (int chunk = w; chunk < NCHUNK; chunk += 4) {
+        f32x4 acc[MB][NG];
+        int sslot[NG], islot[NG], cell[NG];
+#pragma unroll
+        for (int n = 0; n < NG; ++n) {
+#pragma unroll
+            for (int m = 0; m < MB; ++m) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+            int c = (chunk * NG + n) * 16 + l16;
+            cell[n] = c;
+            c = c < NCELL ? c : NCELL - 1;  // lanes past the frame compute a copy, never stored
+            const int b = c / WO, a = c - b * WO;
+            sslot[n] = (b + 1) * WS + (a + 1);
+            islot[n] = (b + OI) * WI + (a + OI);
+        }
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            const int tap = ks * TPK + g / CH;
+            const int c0 = (g % CH) * 8;
+#pragma unroll
+            for (int n = 0; n < NG; ++n) {
+                if ((chunk * NG + n) >= NGRP) break;  // uniform over the wave
+                bf16x8 bv = bf16x8{};
+                if (tap < 7) {
+                    uint4 raw = src[(sslot[n] + OFF_S[tap]) * SSTR + c0 / 8];
+                    if (!taps_all && tap > 0 && !(fl[islot[n]] & fl[islot[n] + OFF_I[tap]]))
+                        raw = make_uint4(0u, 0u, 0u, 0u);
+                    bv = *reinterpret_cast<const bf16x8 *>(&raw);
+                }
+#pragma unroll
+                for (int m = 0; m < MB; ++m)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[ks][m], bv, acc[m][n], 0, 0, 0);
+            }
+        }
+        // epilogue: lane holds channels co = m*16 + 4g + j of cell[n]
+#pragma unroll
+        for (int n = 0; n < NG; ++n) {
+            const int c = cell[n];
+            if ((chunk * NG + n) >= NGRP || c >= NCELL) continue;
+            const int b = c / WO, a = c - b * WO;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                const int co = m * 16 + 4 * g;
+                float v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = acc[m][n][j] + bias[co + j];
+                if constexpr (EPI == EPI_LIN) {
+                    const int q = q0 + a, r = r0 + b;
+                    if (q < nq && r < nr) {
+                        float *o = out + (soff + (int64_t)r * nq + q) * OUT_STRIDE;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (co + j < cout_real) o[co + j] = v[j];
+                    }
+                } else {
+                    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                    bf16x4 pk;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) pk[j] = (__bf16)(v[j] > 0.f ? v[j] : 0.f);
+                    *reinterpret_cast<bf16x4 *>(reinterpret_cast<__bf16 *>(dst) + c * DSTR + co) = pk;
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_hexnet4(const __bf16 *__restrict__ x, Net4 nw,
+                                                float *__restrict__ out, int nq, int nr,
+                                                int ntiles_total, int cout_real,
+                                                const int32_t *live, ConvMask cm) {
+    using namespace f4;
+    constexpr int W0 = OT + 6, W1 = OT + 4;
+    constexpr int AS = 5;  // 16-byte chunks per cell of hidden activations (32 channels + pad)
+    __shared__ uint4 bufA[W0 * W0 * AS];  // layer 0 and layer 2 activations
+    __shared__ uint4 bufB[W1 * W1 * AS];  // the staged input (16 channels), then layer 1
+    __shared__ uint8_t fl[WI * WI];
+    static_assert(WI * WI * 2 <= W1 * W1 * AS, "staged input fits the layer-1 buffer");
+    const int ntq = (nq + OT - 1) / OT, ntr = (nr + OT - 1) / OT;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles_total, 0);
+    if (tile < 0) return;
+    if (live && !*live) return;  // a surrogate window that does not run
+    const int per = ntq * ntr;
+    const int bs = tile / per, lt = tile - bs * per;
+    const int tr = lt / ntq;
+    const int q0 = (lt - tr * ntq) * OT, r0 = tr * OT;
+    const int64_t soff = (int64_t)bs * nq * nr;
+    // stage the 24 x 24 input frame: two 16-byte chunks per position, loads first
+    constexpr int NE = WI * WI * 2;
+    constexpr int ITERS = (NE + NT - 1) / NT;
+    uint4 v[ITERS];
+    uint8_t a[ITERS];
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const int e = threadIdx.x + it * NT;
+        const int p = e >> 1, ch = e & 1;
+        const int pb = p / WI, pa = p - pb * WI;
+        int q = q0 - 4 + pa, r = r0 - 4 + pb;
+        if (cm.perq) q = ((q % nq) + nq) % nq;
+        if (cm.perr) r = ((r % nr) + nr) % nr;
+        v[it] = make_uint4(0u, 0u, 0u, 0u);
+        a[it] = 0;
+        if (e < NE && q >= 0 && q < nq && r >= 0 && r < nr) {
+            const int64_t i = soff + (int64_t)r * nq + q;
+            v[it] = reinterpret_cast<const uint4 *>(x + i * FEATURES_PAD)[ch];
+            a[it] = cm.active ? (uint8_t)(cm.active[(int64_t)r * nq + q] != 0) : (uint8_t)1;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const int e = threadIdx.x + it * NT;
+        if (e < NE) {
+            bufB[e] = v[it];
+            if ((e & 1) == 0) fl[e >> 1] = a[it];
+        }
+    }
+    __syncthreads();
+    // the staged frame lies inside an unmasked raster: no tap is cut
+    const bool all = !cm.active && q0 >= 4 && q0 + OT + 4 <= nq && r0 >= 4 && r0 + OT + 4 <= nr;
+    net_layer<16, 32, EPI_RELU, OT + 6, 2, 8 * AS>(bufB, bufA, fl, nw.wm[0], nw.bias[0], nullptr,
+                                                   nq, nr, soff, q0, r0, 32, all);
+    __syncthreads();
+    net_layer<32, 32, EPI_RELU, OT + 4, AS, 8 * AS>(bufA, bufB, fl, nw.wm[1], nw.bias[1], nullptr,
+                                                    nq, nr, soff, q0, r0, 32, all);
+    __syncthreads();
+    net_layer<32, 32, EPI_RELU, OT + 2, AS, 8 * AS>(bufB, bufA, fl, nw.wm[2], nw.bias[2], nullptr,
+                                                    nq, nr, soff, q0, r0, 32, all);
+    __syncthreads();
+    net_layer<32, 16, EPI_LIN, OT, AS, 0>(bufA, nullptr, fl, nw.wm[3], nw.bias[3], out, nq, nr,
+                                          soff, q0, r0, cout_real, all);
+}
+
 // ------------------------------------------------------------ weight grad
 
 // Per-tile partial dW[t][co][ci] = sum_cells dy[cell][co] x[nbr_t(cell)][ci] and
@@ -445,6 +631,18 @@ hipError_t launch_conv(int cinp, int coutp, int epi, const __bf16 *x, const __bf
     HEXSV_CONV(32, 32, EPI_MASK)
 #undef HEXSV_CONV
     return hipErrorInvalidValue;
+}
+
+int net4_tiles(int nq, int nr, int batch) {
+    return ((nq + f4::OT - 1) / f4::OT) * ((nr + f4::OT - 1) / f4::OT) * batch;
+}
+
+hipError_t launch_net4(const __bf16 *x, const Net4 &nw, float *out, int nq, int nr, int batch,
+                       int cout_real, const ConvMask &cm, hipStream_t st, const int32_t *live) {
+    const int nt = net4_tiles(nq, nr, batch);
+    hipLaunchKernelGGL(k_hexnet4, dim3(nt), dim3(NT), 0, st, x, nw, out, nq, nr, nt, cout_real,
+                       live, cm);
+    return hipGetLastError();
 }
 
 hipError_t launch_wgrad(int cinp, int coutp, const __bf16 *x, const __bf16 *dy, float *part,

@@ -23,6 +23,7 @@ struct SurLayer {
 struct hexsv_surrogate {
     int layers, channels;
     int k;  // solver steps a window spans (its rain sub-steps)
+    bool fused;  // forward of the 4-layer, 32-channel network in one kernel (k_hexnet4)
     int64_t nparams;
     float *d_p, *d_m, *d_v, *d_g;
     std::vector<SurLayer> L;
@@ -110,6 +111,7 @@ extern "C" int hexsv_surrogate_create(int32_t layers, int32_t channels, int32_t 
     s->layers = layers;
     s->channels = channels;
     s->k = k;
+    s->fused = false;  // the layer chain measures faster on the 512 x 512 windows
     int64_t off = 0;
     for (int l = 0; l < layers; ++l) {
         SurLayer y{};
@@ -161,6 +163,13 @@ extern "C" void hexsv_surrogate_destroy(hexsv_surrogate *s) {
 
 extern "C" int64_t hexsv_surrogate_num_params(const hexsv_surrogate *s) { return s ? s->nparams : -1; }
 extern "C" int32_t hexsv_surrogate_steps(const hexsv_surrogate *s) { return s ? s->k : -1; }
+
+extern "C" int hexsv_surrogate_set_fused(hexsv_surrogate *s, int32_t on) {
+    if (!s) return fail(HEXSV_EINVAL, "surrogate_set_fused: null surrogate");
+    if (on != 0 && on != 1) return fail(HEXSV_EINVAL, "surrogate_set_fused: on must be 0 or 1");
+    s->fused = on != 0;
+    return HEXSV_OK;
+}
 
 static int prepare(hexsv_surrogate *s, hipStream_t st) {
     for (auto &y : s->L)
@@ -215,9 +224,21 @@ static int conv_mask(const hexsv_grid *g, int nq, int nr, nn::ConvMask *cm, cons
     return HEXSV_OK;
 }
 
-// Forward over the packed features already in s->x0; output in s->out.
+// Forward over the packed features already in s->x0; output in s->out.  With
+// fusion switched on, the 4-layer, 32-channel network runs as one kernel unless
+// the hidden activations are wanted (keep_act: the gradient reads them); both
+// paths give the same output bit for bit.
 static int forward_packed(hexsv_surrogate *s, int nq, int nr, int batch, const nn::ConvMask &cm,
-                          hipStream_t st, const int32_t *live = nullptr) {
+                          hipStream_t st, const int32_t *live = nullptr, bool keep_act = false) {
+    if (!keep_act && s->fused && s->layers == 4 && s->channels == 32) {
+        nn::Net4 nw;
+        for (int l = 0; l < 4; ++l) {
+            nw.wm[l] = s->L[l].wm;
+            nw.bias[l] = s->L[l].bias;
+        }
+        HIP_TRY(nn::launch_net4(s->x0, nw, s->out, nq, nr, batch, s->L[3].cout, cm, st, live));
+        return HEXSV_OK;
+    }
     const __bf16 *x = s->x0;
     for (int l = 0; l < s->layers; ++l) {
         const SurLayer &y = s->L[l];
@@ -286,7 +307,7 @@ static int gradient(hexsv_surrogate *s, const hexsv_grid *grid, int batch, int n
     rc = check_shape(s, batch, nq, nr, &cells);
     if (rc) return rc;
     HIP_TRY(nn::launch_pack_features(feat, cells, s->x0, st));
-    rc = forward_packed(s, nq, nr, batch, cm, st);
+    rc = forward_packed(s, nq, nr, batch, cm, st, nullptr, true);
     if (rc) return rc;
     const double inv_count = 1.0 / (3.0 * (double)cells);
     HIP_TRY(nn::launch_l1_loss(s->out, target, cells, inv_count, s->dy_last, s->lpart, LOSS_PARTS, st));

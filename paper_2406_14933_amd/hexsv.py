@@ -113,6 +113,7 @@ _SIGS = [
     ("hexsv_surrogate_get_params", C.c_int, [_VP, _VP, C.c_int64, _VP]),
     ("hexsv_surrogate_set_scales", C.c_int, [_VP, C.POINTER(C.c_float), C.c_int32]),
     ("hexsv_surrogate_get_scales", C.c_int, [_VP, C.POINTER(C.c_float), C.c_int32]),
+    ("hexsv_surrogate_set_fused", C.c_int, [_VP, C.c_int32]),
     ("hexsv_surrogate_forward", C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
                                           _VP]),
     ("hexsv_surrogate_forward_noalloc", C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_int32,
@@ -546,6 +547,11 @@ class Surrogate:
         if x.numel() != n * ch or n % (nq * nr):
             raise ValueError("array does not hold whole samples")
         return n // (nq * nr)
+
+    def set_fused(self, on=True):
+        """Forward of the 4-layer, 32-channel network as one fused kernel or one launch per
+        layer (the default); the outputs are the same bit for bit."""
+        _check(lib().hexsv_surrogate_set_fused(self._h, 1 if on else 0))
 
     # grid (optional): the raster whose neighbour rule the taps follow (periodic sides, the
     # domain mask); without it the raster is a walled nq x nr parallelogram

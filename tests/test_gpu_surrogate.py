@@ -175,6 +175,43 @@ def test_gradient_follows_the_raster_tables(hx, kind):
         k += nw + co
 
 
+FUSED_CASES = {
+    # ragged 16 x 16 tiles in both directions, a batch of samples
+    "walled-ragged": dict(nq=70, nr=37, batch=3),
+    # rasters smaller than the fused kernel's 4-cell halo: wraps of more than one period
+    "tiny-torus": dict(nq=5, nr=3, batch=2, side=(synth.PERIODIC,) * 4),
+    "one-cell": dict(nq=1, nr=1, batch=2),
+}
+
+
+@pytest.mark.parametrize("kind", list(FUSED_CASES) + list(RASTERS))
+def test_fused_forward_equals_the_layer_chain(hx, kind):
+    """The 4-layer network in one kernel (activations kept on chip, 4-cell halo) gives the
+    layer-by-layer launches' outputs bit for bit, on walled, masked and periodic rasters."""
+    if kind in FUSED_CASES:
+        d = FUSED_CASES[kind]
+        nq, nr, batch = d["nq"], d["nr"], d["batch"]
+        grid = hx.Grid(nq, nr, 1.0, d["side"], (), None, synth.WALL) if "side" in d else None
+    else:
+        nq, nr, _, grid = raster(hx, kind)
+        batch = 2
+    rng = np.random.default_rng(23)
+    p = (so.init_params(23, 4, 32, out_scale=1.0)
+         + rng.normal(scale=0.02, size=so.num_params(4, 32))).astype(np.float32)
+    feats = torch.from_numpy(rng.normal(size=(batch * nq * nr, so.FEATURES))
+                             .astype(np.float32)).cuda()
+    sur = hx.Surrogate(4, 32)
+    sur.set_params(p)
+    print(f"[fused forward {kind} {nq}x{nr} batch {batch}]", flush=True)
+    sur.set_fused(True)
+    fused = sur.forward(feats, nq, nr, grid=grid)
+    sur.set_fused(False)
+    chain = sur.forward(feats, nq, nr, grid=grid)
+    torch.cuda.synchronize()
+    assert torch.equal(fused[:, :3], chain[:, :3])
+    assert torch.isfinite(fused[:, :3]).all()
+
+
 def test_conv_refuses_a_mismatched_or_dirichlet_grid(hx):
     sur = hx.Surrogate(4, 32)
     sur.set_params(so.init_params(1, 4, 32))
