@@ -354,14 +354,16 @@ def window_cost(size=512, nwin=256, window=0.69, k=16):
             "plain_steps_per_window": steps / nwin}
 
 
-def network_cost(batch=16, size=512, calls=5):
+def network_cost(batch=16, size=512, calls=5, fused=False):
     """Device cost of one surrogate network call over a batch of 512 x 512 samples (random
-    inputs and parameters: the cost does not depend on them), for the MFMA profile."""
+    inputs and parameters: the cost does not depend on them), for the MFMA profile; fused:
+    the one-kernel forward instead of the layer chain."""
     import numpy as np
     import torch
 
     from paper_2406_14933_amd import hexsv
     sur = hexsv.Surrogate(4, 32)
+    sur.set_fused(fused)
     rng = np.random.default_rng(3)
     sur.set_params(rng.normal(scale=0.05, size=sur.num_params).astype(np.float32))
     f = torch.randn((batch * size * size, hexsv.Surrogate.FEATURES), dtype=torch.float32,
@@ -376,7 +378,7 @@ def network_cost(batch=16, size=512, calls=5):
         ms.append(1e3 * (time.perf_counter() - t0))
     cells = batch * size * size
     flop = NET_FLOP_EXECUTED * cells
-    return {"workload": f"network-{batch}x{size}x{size}", "call_ms": min(ms),
+    return {"workload": f"network-{batch}x{size}x{size}", "fused": fused, "call_ms": min(ms),
             "tflops": flop / (min(ms) * 1e-3) / 1e12, "mfma_frac": flop / (min(ms) * 1e-3) / 2.5e15,
             "flop_per_call": flop, "algorithmic_flop_per_call": NET_FLOP_ALGORITHMIC * cells}
 
@@ -471,6 +473,8 @@ def main():
                     help="only run a plain 1 GiB device copy (for counter calibration)")
     ap.add_argument("--network-cost", action="store_true",
                     help="only time the surrogate network over a batch of 16 512x512 samples")
+    ap.add_argument("--network-fused", action="store_true",
+                    help="with --network-cost: the one-kernel forward (k_hexnet4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -484,7 +488,7 @@ def main():
         print(json.dumps(window_cost()))
         return
     if args.network_cost:
-        print(json.dumps(network_cost()))
+        print(json.dumps(network_cost(fused=args.network_fused)))
         return
     if args.copy_calibration:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
