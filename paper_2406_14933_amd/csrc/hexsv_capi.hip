@@ -963,7 +963,9 @@ static int window_buffers(hexsv_sim *s) {
     if (!s->d_sw) {
         HIP_TRY(hipMalloc(&s->d_sw, sizeof(SurWin)));
         HIP_TRY(hipHostMalloc(&s->h_sw, sizeof(SurWin), hipHostMallocDefault));
-        HIP_TRY(hipMalloc(&s->d_op, sizeof(Part) * 2 * WIN_PARTS));
+        // the predicted state's WIN_PARTS records, then one per probe tile
+        HIP_TRY(hipMalloc(&s->d_op, sizeof(Part) * (WIN_PARTS + (size_t)win_probe_tiles(
+                                                                   s->grid->kg.nq, s->grid->kg.nr))));
         HIP_TRY(hipMalloc(&s->d_scr, s->esz * 3 * (size_t)s->grid->n));
         HIP_TRY(hipMalloc(&s->d_slope, sizeof(float2) * (size_t)s->grid->n));
     }
@@ -1009,10 +1011,8 @@ static int window_features(hexsv_sim *s, hexsv_surrogate *sur, double window, in
     const KDom<T> d = dom_of<T>(s);
     HIP_TRY(launch_win_reset(s->d_sw, st));
     HIP_TRY(launch_win_probe<T>(d, s->grid->kg, s->kc, s->rn, s->d_ctl, s->d_sw, (T *)s->d_scr,
-                                s->p.dt_max, st));
-    HIP_TRY(launch_win_features<T>(d, s->grid->kg, s->grid->edge, s->d_ctl, s->d_sw,
-                                   (const T *)s->d_scr, s->d_slope, s->p.dt_max, feat_scale(sc), 0,
-                                   d_features, s->d_op, st));
+                                s->p.dt_max, s->d_slope, feat_scale(sc), 2, d_features,
+                                s->d_op + WIN_PARTS, st));
     return HEXSV_OK;
 }
 
@@ -1040,9 +1040,9 @@ static const int WIN_CHAINS[4] = {2, 4, 8, 16};
 // Most plain steps one refused window may take before the run reports a stall.
 static const int64_t FALLBACK_STEP_LIMIT = 1 << 20;
 
-// One window: probe step (which starts the window), features (with the start
-// state's outflow rate), network, predicted state (with its sums and outflow
-// rate), gate, and the optional projection.
+// One window: probe step (which starts the window and forms the network's
+// features with the start state's outflow rate), network, predicted state (with
+// its sums and outflow rate), gate, and the optional projection.
 template <typename T>
 static int window_body(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float *out,
                        const float *sc, hipStream_t st) {
@@ -1052,15 +1052,15 @@ static int window_body(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float
     const int64_t n = s->grid->n;
     T *scr = (T *)s->d_scr;
     const double dt_max = s->p.dt_max;
-    Part *op0 = s->d_op, *part = s->d_op + WIN_PARTS;
-    HIP_TRY(launch_win_probe<T>(d, g, s->kc, s->rn, s->d_ctl, s->d_sw, scr, dt_max, st));
-    HIP_TRY(launch_win_features<T>(d, g, l, s->d_ctl, s->d_sw, scr, s->d_slope, dt_max,
-                                   feat_scale(sc), 1, x0, op0, st));
+    Part *part = s->d_op, *op0 = s->d_op + WIN_PARTS;
+    const int n_op0 = win_probe_tiles(g.nq, g.nr);
+    HIP_TRY(launch_win_probe<T>(d, g, s->kc, s->rn, s->d_ctl, s->d_sw, scr, dt_max, s->d_slope,
+                                feat_scale(sc), 1, x0, op0, st));
     int rc = sur_forward_x0(sur, s->grid, st, &s->d_sw->live);
     if (rc) return rc;
     HIP_TRY(launch_win_apply<T>(d, g, l, s->kc, s->d_ctl, s->d_sw, scr, dt_max, out,
                                 nn::OUT_STRIDE, sc[3], sc[4], 1e-6, part, st));
-    HIP_TRY(launch_win_gate(s->d_ctl, s->d_sw, part, op0, s->kc, st));
+    HIP_TRY(launch_win_gate(s->d_ctl, s->d_sw, part, op0, n_op0, s->kc, st));
     HIP_TRY(launch_win_scale<T>(d, n, s->d_ctl, s->d_sw, st));
     return HEXSV_OK;
 }

@@ -142,24 +142,35 @@ struct FeatScale {
 };
 
 hipError_t launch_win_reset(SurWin *sw, hipStream_t stream);
-hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, const Part *op0,
+// Gate of a window: part holds WIN_PARTS records of the predicted state, op0 the
+// probe's n_op0 records of the start state's outflow rate.
+hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, const Part *op0, int n_op0,
                            const KConst &kc, hipStream_t stream);
 // Window kernels on the current state (buffer ctl->parity), each a no-op unless sw->live
 // (which the probe, the first of them, decides).
-// scr holds 3 x cells values of T (the probe step's h, v1, v2).
+// scr holds 3 x cells values of T (the probe step's h, v1, v2).  The probe also
+// writes the network's features of the current state into fout (feat 1: packed
+// bf16; 2: FP32; 0: none) and one record per probe tile of the current state's
+// outflow rate into op0[].stored (win_probe_tiles of them).
 template <typename T>
 hipError_t launch_win_probe(const KDom<T> &d, const KGrid &g, const KConst &kc, const KRain &rn,
-                            const Ctl *ctl, SurWin *sw, T *scr, double dt_max, hipStream_t stream);
+                            const Ctl *ctl, SurWin *sw, T *scr, double dt_max,
+                            const float2 *slope, FeatScale fs, int feat, void *fout, Part *op0,
+                            hipStream_t stream);
+// Tile of a window's probe launch: 64 x 4 cells, one per thread, so that the
+// features the probe writes are spread over four times the workgroups of the
+// step's default tile (a 512 x 512 raster: 1024).
+constexpr int PROBE_TILE = 0;
+// Workgroups (tiles) of a window's probe launch on an nq x nr raster.
+inline int win_probe_tiles(int nq, int nr) {
+    int ntq, ntiles;
+    tile_grid(PROBE_TILE, nq, nr, &ntq, &ntiles);
+    return ntiles;
+}
 // Terrain slope of every cell (float2), static for a simulation.
 template <typename T>
 hipError_t launch_win_slope(const KDom<T> &d, const KGrid &g, double a, float2 *slope,
                             hipStream_t stream);
-// Features of the current state (packed bf16 network input, or FP32) and the
-// outflow rate of the current state (WIN_PARTS partials in op0[].stored).
-template <typename T>
-hipError_t launch_win_features(const KDom<T> &d, const KGrid &g, double l, const Ctl *ctl,
-                               const SurWin *sw, const T *scr, const float2 *slope, double dt_max,
-                               FeatScale sc, int packed, void *out, Part *op0, hipStream_t stream);
 // Predicted state into the other buffer, with its reductions (WIN_PARTS partials
 // {c_max, stored, outflow rate, non-finite count}).
 template <typename T>

@@ -272,69 +272,6 @@ __device__ inline double win_probe_dt(const Ctl *ctl, double dt_max) {
     return tau < dt_max ? tau : dt_max;
 }
 
-// Probe step of a window: one explicit step of the scheme (rain included)
-// from the current state into the scratch buffers, with the control block
-// untouched.  Its change, scaled to the window, is the extrapolation the
-// network corrects.
-//
-// The probe also starts the window: every workgroup decides (identically)
-// whether it runs -- the chain is alive and the span fits before t_stop -- and
-// workgroup 0 records that and the window's rain depth (k equal sub-steps,
-// each at the rate of its end: the solver's right-endpoint rule), rain volume,
-// start time, stored volume and c_max for the kernels that follow.
-template <typename T, int TQ, int TR, int NT>
-__global__ __launch_bounds__(NT) void k_win_probe(KDom<T> d, KGrid g, KConst kc, KRain rn,
-                                                  const Ctl *ctl, SurWin *sw, T *scr, int ntq,
-                                                  int ntiles, double dt_max) {
-    const double t0 = ctl->t;
-    const bool live = sw->alive && !ctl->err && t0 + sw->window <= sw->t_stop;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sw->scale_live = 0;
-        sw->live = live ? 1 : 0;
-        if (live) {
-            const double dts = sw->window / sw->k;
-            double depth = 0.0;
-            for (int j = 1; j <= sw->k; ++j) depth += dts * rain_rate(rn, t0 + j * dts);
-            sw->depth = depth;
-            sw->R = kc.area_active * depth;
-            sw->t0 = t0;
-            sw->S0 = ctl->stored;
-            if (!(sw->c0 >= 0.0)) sw->c0 = ctl->last_cmax;
-        }
-    }
-    if (!live) return;
-    const int tile = blockIdx.x;
-    if (tile >= ntiles) return;
-    const int par = ctl->parity;
-    const int64_t n = (int64_t)g.nq * g.nr;
-    KDom<T> e;
-    for (int f = 0; f < 3; ++f) {
-        e.st[0][f] = par ? d.st[1][f] : d.st[0][f];
-        e.st[1][f] = scr + f * n;
-    }
-    e.z = d.z;
-    e.th = d.th;
-    e.ap = d.ap;
-    const double dt = win_probe_dt(ctl, dt_max);
-    const double r_next = rain_rate(rn, ctl->t + dt);
-    __shared__ TileLDS<T, TQ, TR> L;
-    Acc acc{0.0, 0.0, 0.0, 0.0};
-    const int tr = tile / ntq, tq = tile - tr * ntq;
-    tile_step<T, TQ, TR, NT, false>(L, e, g, kc, 0, tq, tr, dt, r_next, acc, &sw->perr,
-                                    &sw->perr_cell);
-}
-
-template <typename T>
-hipError_t launch_win_probe(const KDom<T> &d, const KGrid &g, const KConst &kc, const KRain &rn,
-                            const Ctl *ctl, SurWin *sw, T *scr, double dt_max, hipStream_t stream) {
-    constexpr TileShape S = TILES[DEFAULT_TILE];
-    int ntq, ntiles;
-    tile_grid(DEFAULT_TILE, g.nq, g.nr, &ntq, &ntiles);
-    hipLaunchKernelGGL((k_win_probe<T, S.tq, S.tr, S.nt>), dim3(ntiles), dim3(S.nt), 0, stream, d, g,
-                       kc, rn, ctl, sw, scr, ntq, ntiles, dt_max);
-    return hipGetLastError();
-}
-
 // Terrain slope of every cell (static: computed once per run of windows).
 template <typename T>
 __global__ __launch_bounds__(256) void k_win_slope(KDom<T> d, KGrid g, double a,
@@ -409,62 +346,121 @@ __device__ inline void win_feature_vec(T h, T v1, T v2, T z, T th, T hs, T v1s, 
     f[10] = (float)(xs * (double)(th * hs * v2s - q2)) / sc.dQ;
 }
 
-// Features of the current state (PACKED: bf16, FEATURES_PAD channels per cell,
-// the network's input buffer; otherwise FP32, FEATURES channels per cell),
-// and the outflow rate of the current state: one partial per workgroup in
-// op0[b].stored (WIN_PARTS workgroups).
-template <typename T, bool PACKED>
-__global__ __launch_bounds__(256) void k_win_features(KDom<T> d, KGrid g, double l,
-                                                      const Ctl *ctl, const SurWin *sw,
-                                                      const T *scr, const float2 *slope,
-                                                      double dt_max, FeatScale sc, void *out,
-                                                      Part *op0) {
-    if (!sw->live) return;
-    const int par = ctl->parity;
-    const double depth = sw->depth;
-    const double xs = sw->window / win_probe_dt(ctl, dt_max);
-    // 32-bit cell indices: creation limits a field to 4 GiB
-    const int n = g.nq * g.nr;
-    const T *h = par ? d.st[1][0] : d.st[0][0];
-    const T *v1 = par ? d.st[1][1] : d.st[0][1];
-    const T *v2 = par ? d.st[1][2] : d.st[0][2];
-    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-    double o = 0.0;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        float f[FEATURES];
-        // the probe state's three fields, n apart: pointer offsets, as 2 n + i can pass 2^31
-        const T *s1 = scr + n, *s2 = scr + 2 * (size_t)n;
-        win_feature_vec<T>(h[i], v1[i], v2[i], d.z[i], d.th[i], scr[i], s1[i], s2[i], slope[i],
-                           depth, xs, sc, f);
-        if constexpr (PACKED) {
-            bf16x8 v[nn::FEATURES_PAD / 8];
-#pragma unroll
-            for (int c = 0; c < nn::FEATURES_PAD; ++c)
-                v[c / 8][c % 8] = c < FEATURES ? (__bf16)f[c] : (__bf16)0.f;
-#pragma unroll
-            for (int u = 0; u < nn::FEATURES_PAD / 8; ++u)
-                reinterpret_cast<bf16x8 *>((__bf16 *)out + (size_t)i * nn::FEATURES_PAD)[u] = v[u];
-        } else {
-#pragma unroll
-            for (int c = 0; c < FEATURES; ++c) ((float *)out)[(size_t)i * FEATURES + c] = f[c];
+// Probe step of a window, with the network's features: one explicit step of the
+// scheme (rain included) from the current state into the scratch buffers, with
+// the control block untouched; its change, scaled to the window, is the
+// extrapolation the network corrects.  In the same launch every cell's features
+// are formed from the start state (still in the tile's registers) and the probe
+// state (the values this thread just stored) and written as the network's input
+// (FEAT 1: bf16, FEATURES_PAD channels per cell; FEAT 2: FP32, FEATURES
+// channels), and each workgroup sums the start state's outflow rate over its
+// cells into op0[tile].stored.
+//
+// The probe also starts the window: every workgroup decides (identically)
+// whether it runs -- the chain is alive and the span fits before t_stop -- and
+// workgroup 0 records that and the window's rain depth (k equal sub-steps,
+// each at the rate of its end: the solver's right-endpoint rule), rain volume,
+// start time, stored volume and c_max for the kernels that follow.
+template <typename T, int TQ, int TR, int NT, int FEAT>
+__global__ __launch_bounds__(NT) void k_win_probe(KDom<T> d, KGrid g, KConst kc, KRain rn,
+                                                  const Ctl *ctl, SurWin *sw, T *scr, int ntq,
+                                                  int ntiles, double dt_max,
+                                                  const float2 *__restrict__ slope, FeatScale fs,
+                                                  void *fout, Part *op0) {
+    const double t0 = ctl->t;
+    const bool live = sw->alive && !ctl->err && t0 + sw->window <= sw->t_stop;
+    // the window's rain depth over k equal sub-steps (every workgroup forms the same sum)
+    const double dts = sw->window / sw->k;
+    double depth = 0.0;
+    for (int j = 1; j <= sw->k; ++j) depth += dts * rain_rate(rn, t0 + j * dts);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sw->scale_live = 0;
+        sw->live = live ? 1 : 0;
+        if (live) {
+            sw->depth = depth;
+            sw->R = kc.area_active * depth;
+            sw->t0 = t0;
+            sw->S0 = ctl->stored;
+            if (!(sw->c0 >= 0.0)) sw->c0 = ctl->last_cmax;
         }
-        const int r = i / g.nq, q = i - r * g.nq;
-        if (may_outflow(g, q, r)) o += cell_outflow<T>(g, l, h, v1, v2, d.th, q, r, i);
     }
-    const Part p = block_reduce<256>(0.0, o, 0.0, 0.0);
-    if (threadIdx.x == 0) op0[blockIdx.x] = p;
+    if (!live) return;
+    const int tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const int par = ctl->parity;
+    const int64_t n = (int64_t)g.nq * g.nr;
+    KDom<T> e;
+    for (int f = 0; f < 3; ++f) {
+        e.st[0][f] = par ? d.st[1][f] : d.st[0][f];
+        e.st[1][f] = scr + f * n;
+    }
+    e.z = d.z;
+    e.th = d.th;
+    e.ap = d.ap;
+    const double dt = win_probe_dt(ctl, dt_max);
+    const double r_next = rain_rate(rn, ctl->t + dt);
+    __shared__ TileLDS<T, TQ, TR> L;
+    Acc acc{0.0, 0.0, 0.0, 0.0};
+    const int tr = tile / ntq, tq = tile - tr * ntq;
+    TileRegs<T, TQ, TR, NT> R;
+    tile_load<T, TQ, TR, NT>(R, e, g, 0, tq, tr);
+    const bool bad = tile_stage<T, TQ, TR, NT>(L, R, g, kc, tq, tr);
+    const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
+    const bool general = __syncthreads_or((!inner) || bad) != 0;
+    tile_compute<T, TQ, TR, NT, false, false>(L, R, general, e, g, kc, 0, tq, tr, dt, r_next, acc,
+                                              &sw->perr, &sw->perr_cell);
+    if constexpr (FEAT != 0) {
+        using Regs = TileRegs<T, TQ, TR, NT>;
+        typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+        const double xs = sw->window / dt;
+        const T *h0 = e.st[0][0], *v10 = e.st[0][1], *v20 = e.st[0][2];
+        double o = 0.0;
+#pragma unroll
+        for (int k = 0; k < Regs::CPT; ++k) {
+            if (R.pos[k] != POS_OWN) continue;
+            const int cc = threadIdx.x + k * NT;
+            const int lr = cc / TQ, lq = cc - lr * TQ;
+            const int q = tq * TQ + lq, r = tr * TR + lr;
+            const uint32_t i = (uint32_t)(r * g.pitch + q);
+            // the probe state of this cell: this thread's own stores above (unwritten, and
+            // unused, on cells outside the domain)
+            float f[FEATURES];
+            win_feature_vec<T>(R.h[k], R.v1[k], R.v2[k], R.z[k], R.th[k], e.st[1][0][i],
+                               e.st[1][1][i], e.st[1][2][i], slope[i], depth, xs, fs, f);
+            if constexpr (FEAT == 1) {
+                bf16x8 v[nn::FEATURES_PAD / 8];
+#pragma unroll
+                for (int c = 0; c < nn::FEATURES_PAD; ++c)
+                    v[c / 8][c % 8] = c < FEATURES ? (__bf16)f[c] : (__bf16)0.f;
+#pragma unroll
+                for (int u = 0; u < nn::FEATURES_PAD / 8; ++u)
+                    reinterpret_cast<bf16x8 *>((__bf16 *)fout + (size_t)i * nn::FEATURES_PAD)[u] = v[u];
+            } else {
+#pragma unroll
+                for (int c = 0; c < FEATURES; ++c) ((float *)fout)[(size_t)i * FEATURES + c] = f[c];
+            }
+            if (may_outflow(g, q, r)) o += cell_outflow<T>(g, kc.a, h0, v10, v20, d.th, q, r, i);
+        }
+        const Part p = block_reduce<NT>(0.0, o, 0.0, 0.0);
+        if (threadIdx.x == 0) op0[tile] = p;
+    }
 }
 
 template <typename T>
-hipError_t launch_win_features(const KDom<T> &d, const KGrid &g, double l, const Ctl *ctl,
-                               const SurWin *sw, const T *scr, const float2 *slope, double dt_max,
-                               FeatScale sc, int packed, void *out, Part *op0, hipStream_t stream) {
-    if (packed)
-        hipLaunchKernelGGL((k_win_features<T, true>), dim3(WIN_PARTS), dim3(256), 0, stream, d, g, l,
-                           ctl, sw, scr, slope, dt_max, sc, out, op0);
-    else
-        hipLaunchKernelGGL((k_win_features<T, false>), dim3(WIN_PARTS), dim3(256), 0, stream, d, g, l,
-                           ctl, sw, scr, slope, dt_max, sc, out, op0);
+hipError_t launch_win_probe(const KDom<T> &d, const KGrid &g, const KConst &kc, const KRain &rn,
+                            const Ctl *ctl, SurWin *sw, T *scr, double dt_max,
+                            const float2 *slope, FeatScale fs, int feat, void *fout, Part *op0,
+                            hipStream_t stream) {
+    constexpr TileShape S = TILES[PROBE_TILE];
+    int ntq, ntiles;
+    tile_grid(PROBE_TILE, g.nq, g.nr, &ntq, &ntiles);
+#define HEXSV_PROBE(F)                                                                          \
+    hipLaunchKernelGGL((k_win_probe<T, S.tq, S.tr, S.nt, F>), dim3(ntiles), dim3(S.nt), 0, stream, \
+                       d, g, kc, rn, ctl, sw, scr, ntq, ntiles, dt_max, slope, fs, fout, op0)
+    if (feat == 1) HEXSV_PROBE(1);
+    else if (feat == 2) HEXSV_PROBE(2);
+    else HEXSV_PROBE(0);
+#undef HEXSV_PROBE
     return hipGetLastError();
 }
 
@@ -566,13 +562,10 @@ hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const S
                                         int, int, hipStream_t);                               \
     template hipError_t launch_win_probe<T>(const KDom<T> &, const KGrid &, const KConst &,   \
                                             const KRain &, const Ctl *, SurWin *, T *, double, \
+                                            const float2 *, FeatScale, int, void *, Part *,   \
                                             hipStream_t);                                     \
     template hipError_t launch_win_slope<T>(const KDom<T> &, const KGrid &, double, float2 *, \
                                             hipStream_t);                                     \
-    template hipError_t launch_win_features<T>(const KDom<T> &, const KGrid &, double,        \
-                                               const Ctl *, const SurWin *, const T *,        \
-                                               const float2 *, double, FeatScale, int, void *, \
-                                               Part *, hipStream_t);                          \
     template hipError_t launch_win_apply<T>(const KDom<T> &, const KGrid &, double,           \
                                             const KConst &, const Ctl *, const SurWin *,      \
                                             const T *, double, const float *, int, float,     \
