@@ -958,13 +958,19 @@ extern "C" int hexsv_sim_set_books(hexsv_sim *s, const hexsv_books *b, hipStream
 
 // ------------------------------------------------------------ surrogate
 
+// Records of a window's predicted state: one per workgroup of the apply kernel
+// (WIN_PARTS) or per conv tile of the last-layer kernel, whichever runs.
+static int win_part_count(const hexsv_sim *s) {
+    return std::max(WIN_PARTS, nn::conv_tiles(s->grid->kg.nq, s->grid->kg.nr, 1));
+}
+
 // Scratch of the windows (probe state) and their control record.
 static int window_buffers(hexsv_sim *s) {
     if (!s->d_sw) {
         HIP_TRY(hipMalloc(&s->d_sw, sizeof(SurWin)));
         HIP_TRY(hipHostMalloc(&s->h_sw, sizeof(SurWin), hipHostMallocDefault));
-        // the predicted state's WIN_PARTS records, then one per probe tile
-        HIP_TRY(hipMalloc(&s->d_op, sizeof(Part) * (WIN_PARTS + (size_t)win_probe_tiles(
+        // the predicted state's records, then one per probe tile
+        HIP_TRY(hipMalloc(&s->d_op, sizeof(Part) * ((size_t)win_part_count(s) + win_probe_tiles(
                                                                    s->grid->kg.nq, s->grid->kg.nr))));
         HIP_TRY(hipMalloc(&s->d_scr, s->esz * 3 * (size_t)s->grid->n));
         HIP_TRY(hipMalloc(&s->d_slope, sizeof(float2) * (size_t)s->grid->n));
@@ -1012,7 +1018,7 @@ static int window_features(hexsv_sim *s, hexsv_surrogate *sur, double window, in
     HIP_TRY(launch_win_reset(s->d_sw, st));
     HIP_TRY(launch_win_probe<T>(d, s->grid->kg, s->kc, s->rn, s->d_ctl, s->d_sw, (T *)s->d_scr,
                                 s->p.dt_max, s->d_slope, feat_scale(sc), 2, d_features,
-                                s->d_op + WIN_PARTS, st));
+                                s->d_op + win_part_count(s), st));
     return HEXSV_OK;
 }
 
@@ -1052,15 +1058,28 @@ static int window_body(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float
     const int64_t n = s->grid->n;
     T *scr = (T *)s->d_scr;
     const double dt_max = s->p.dt_max;
-    Part *part = s->d_op, *op0 = s->d_op + WIN_PARTS;
+    Part *part = s->d_op, *op0 = s->d_op + win_part_count(s);
     const int n_op0 = win_probe_tiles(g.nq, g.nr);
     HIP_TRY(launch_win_probe<T>(d, g, s->kc, s->rn, s->d_ctl, s->d_sw, scr, dt_max, s->d_slope,
                                 feat_scale(sc), 1, x0, op0, st));
-    int rc = sur_forward_x0(sur, s->grid, st, &s->d_sw->live);
-    if (rc) return rc;
-    HIP_TRY(launch_win_apply<T>(d, g, l, s->kc, s->d_ctl, s->d_sw, scr, dt_max, out,
-                                nn::OUT_STRIDE, sc[3], sc[4], 1e-6, part, st));
-    HIP_TRY(launch_win_gate(s->d_ctl, s->d_sw, part, op0, n_op0, s->kc, st));
+    // the hidden layers, then the last layer with the predicted state as its epilogue;
+    // a fused forward runs whole and the predicted state follows from its output
+    SurLast last;
+    int rc = sur_forward_hidden(sur, s->grid, st, &s->d_sw->live, &last);
+    int n_part = WIN_PARTS;
+    if (rc == HEXSV_OK) {
+        HIP_TRY(launch_win_last<T>(last.x, last.wm, last.bias, last.cm, d, g, l, s->kc, s->d_ctl,
+                                   s->d_sw, scr, dt_max, sc[3], sc[4], 1e-6, part, st));
+        n_part = nn::conv_tiles(g.nq, g.nr, 1);
+    } else if (rc == HEXSV_EUNSUPPORTED) {
+        rc = sur_forward_x0(sur, s->grid, st, &s->d_sw->live);
+        if (rc) return rc;
+        HIP_TRY(launch_win_apply<T>(d, g, l, s->kc, s->d_ctl, s->d_sw, scr, dt_max, out,
+                                    nn::OUT_STRIDE, sc[3], sc[4], 1e-6, part, st));
+    } else {
+        return rc;
+    }
+    HIP_TRY(launch_win_gate(s->d_ctl, s->d_sw, part, n_part, op0, n_op0, s->kc, st));
     HIP_TRY(launch_win_scale<T>(d, n, s->d_ctl, s->d_sw, st));
     return HEXSV_OK;
 }

@@ -253,9 +253,10 @@ hipError_t launch_win_reset(SurWin *sw, hipStream_t stream) {
 // windows.  A window is also refused if its fastest wave speed more than
 // doubles.  Refused: the chain stops and the state at t0 is untouched.
 __global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const Part *part,
-                                                   const Part *op0, int n_op0, KConst kc) {
+                                                   int n_part, const Part *op0, int n_op0,
+                                                   KConst kc) {
     if (!sw->live) return;
-    const Part p = reduce_parts<1024>(part, WIN_PARTS);
+    const Part p = reduce_parts<1024>(part, n_part);
     const Part o0 = reduce_parts<1024>(op0, n_op0);
     if (threadIdx.x != 0) return;
     const double Ow = 0.5 * (o0.stored + p.outflow) * sw->window;
@@ -293,9 +294,10 @@ __global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const P
     sw->live = 0;
 }
 
-hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, const Part *op0, int n_op0,
-                           const KConst &kc, hipStream_t stream) {
-    hipLaunchKernelGGL(k_win_gate, dim3(1), dim3(1024), 0, stream, ctl, sw, part, op0, n_op0, kc);
+hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, int n_part, const Part *op0,
+                           int n_op0, const KConst &kc, hipStream_t stream) {
+    hipLaunchKernelGGL(k_win_gate, dim3(1), dim3(1024), 0, stream, ctl, sw, part, n_part, op0,
+                       n_op0, kc);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 
 #include "hexsv.h"
 #include "hexsv_device.h"
+#include "hexsv_nn.h"
 
 // Record a thread-local message (read by hexsv_last_error) and return code.
 int hexsv_fail(int code, const char *fmt, ...);
@@ -55,3 +56,15 @@ int sur_window_bind(hexsv_surrogate *s, int nq, int nr, void **x0, const float *
 // layers do nothing when *live (device, nullable) is 0.
 int sur_forward_x0(hexsv_surrogate *s, const hexsv_grid *grid, hipStream_t st,
                    const int32_t *live);
+// The layers before the last one, as sur_forward_x0 runs them; *last receives
+// the last layer's input (32 channels per cell), forward weights and bias, for a
+// kernel that applies the last layer itself.  EUNSUPPORTED when the forward runs
+// fused (hexsv_surrogate_set_fused): the caller then uses sur_forward_x0.
+struct SurLast {
+    const __bf16 *x;
+    const __bf16 *wm;
+    const float *bias;
+    hexsv::nn::ConvMask cm;
+};
+int sur_forward_hidden(hexsv_surrogate *s, const hexsv_grid *grid, hipStream_t st,
+                       const int32_t *live, SurLast *last);

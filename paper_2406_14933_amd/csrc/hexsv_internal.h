@@ -142,10 +142,10 @@ struct FeatScale {
 };
 
 hipError_t launch_win_reset(SurWin *sw, hipStream_t stream);
-// Gate of a window: part holds WIN_PARTS records of the predicted state, op0 the
+// Gate of a window: part holds n_part records of the predicted state, op0 the
 // probe's n_op0 records of the start state's outflow rate.
-hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, const Part *op0, int n_op0,
-                           const KConst &kc, hipStream_t stream);
+hipError_t launch_win_gate(Ctl *ctl, SurWin *sw, const Part *part, int n_part, const Part *op0,
+                           int n_op0, const KConst &kc, hipStream_t stream);
 // Window kernels on the current state (buffer ctl->parity), each a no-op unless sw->live
 // (which the probe, the first of them, decides).
 // scr holds 3 x cells values of T (the probe step's h, v1, v2).  The probe also
@@ -178,6 +178,15 @@ hipError_t launch_win_apply(const KDom<T> &d, const KGrid &g, double l, const KC
                             const Ctl *ctl, const SurWin *sw, const T *scr, double dt_max,
                             const float *out, int out_stride, float dH, float dQ, double m_min,
                             Part *part, hipStream_t stream);
+// The network's last layer (input x: 32 channels per cell, weights wm, bias) with
+// the predicted state as its epilogue, as launch_win_apply computes it from the
+// stored network output; one record per conv tile (nn::conv_tiles of them) in part.
+template <typename T>
+hipError_t launch_win_last(const __bf16 *x, const __bf16 *wm, const float *bias,
+                           const nn::ConvMask &cm, const KDom<T> &d, const KGrid &g, double l,
+                           const KConst &kc, const Ctl *ctl, const SurWin *sw, const T *scr,
+                           double dt_max, float dH, float dQ, double m_min, Part *part,
+                           hipStream_t stream);
 // Rescaling of an accepted state onto the water balance (no-op unless sw->scale_live).
 template <typename T>
 hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,

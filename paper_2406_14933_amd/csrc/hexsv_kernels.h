@@ -4,6 +4,7 @@
 
 #include <math.h>
 
+#include "hexsv_conv.h"
 #include "hexsv_internal.h"
 #include "hexsv_tile.h"
 
@@ -534,6 +535,110 @@ hipError_t launch_win_apply(const KDom<T> &d, const KGrid &g, double l, const KC
     return hipGetLastError();
 }
 
+// The network's last layer (32 -> 3 channels) with the window's predicted state
+// as its epilogue: the tile's MFMA accumulators plus bias are the network's
+// outputs (the values k_hexconv would store), and the lanes holding channels
+// 0..2 of a cell apply k_win_apply's arithmetic to them directly.  One record
+// per tile of the predicted state's {c_max, stored, outflow rate, non-finite
+// count} in part[tile].
+template <typename T>
+__global__ __launch_bounds__(nn::NT) void k_win_last(const __bf16 *__restrict__ x,
+                                                     const __bf16 *__restrict__ wm,
+                                                     const float *__restrict__ bias,
+                                                     nn::ConvMask cm, KDom<T> d, KGrid g,
+                                                     double l, KConst kc, const Ctl *ctl,
+                                                     const SurWin *sw, const T *scr,
+                                                     double dt_max, float dH, float dQ,
+                                                     double m_min, Part *part, int ntiles) {
+    using namespace nn;
+    __shared__ uint4 lds[NSLOT * 4];
+    __shared__ uint8_t fl[NSLOT];
+    if (!sw->live) return;
+    const int nq = g.nq, nr = g.nr;
+    const int ntq = (nq + TQ - 1) / TQ, ntr = (nr + TR - 1) / TR;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles, 0);
+    if (tile < 0) return;
+    int b, q0, r0;
+    tile_of(tile, ntq, ntr, b, q0, r0);
+    stage_act<32>(lds, fl, x, nq, nr, 0, q0, r0, cm);
+    __syncthreads();
+    f32x4 acc[1][4];
+    conv_acc<32, 16>(lds, fl, cm.active != nullptr, wm, acc);
+    // the network's outputs of the tile's cells, through LDS to one cell per thread
+    static_assert(TQ * TR == NT, "one cell of the tile per thread");
+    __shared__ float net[TQ * TR][3];
+    {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        if ((lane >> 4) == 0) {  // lanes holding output channels 0..3
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const int c = w * TQ + nb * 16 + (lane & 15);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) net[c][j] = acc[0][nb][j] + bias[j];
+            }
+        }
+    }
+    __syncthreads();
+    const int par = ctl->parity;
+    const int n = nq * nr;  // 32-bit cell indices: creation limits a field to 4 GiB
+    const double xs = sw->window / win_probe_dt(ctl, dt_max);
+    const T *h = par ? d.st[1][0] : d.st[0][0];
+    const T *v1 = par ? d.st[1][1] : d.st[0][1];
+    const T *v2 = par ? d.st[1][2] : d.st[0][2];
+    T *ho = par ? d.st[0][0] : d.st[1][0];
+    T *v1o = par ? d.st[0][1] : d.st[1][1];
+    T *v2o = par ? d.st[0][2] : d.st[1][2];
+    const T *hs = scr, *v1s = scr + n, *v2s = scr + 2 * (size_t)n;  // 2 n can pass 2^31
+    const T G = (T)kc.g;
+    double c = 0.0, s = 0.0, o = 0.0, bad = 0.0;
+    const int lr = threadIdx.x / TQ, lq = threadIdx.x - lr * TQ;
+    const int q = q0 + lq, r = r0 + lr;
+    if (q < nq && r < nr) {
+        const int i = r * g.pitch + q;
+        const T th = d.th[i];
+        if (!(th > T(0))) {
+            ho[i] = h[i];
+            v1o[i] = v1[i];
+            v2o[i] = v2[i];
+        } else {
+            const T q1 = th * h[i] * v1[i], q2 = th * h[i] * v2[i];
+            const double xh = xs * (double)(hs[i] - h[i]);
+            const double xq1 = xs * (double)(th * hs[i] * v1s[i] - q1);
+            const double xq2 = xs * (double)(th * hs[i] * v2s[i] - q2);
+            double hn = (double)h[i] + xh + (double)dH * (double)net[threadIdx.x][0];
+            hn = hn > 0.0 ? hn : 0.0;
+            const double p1 = (double)q1 + xq1 + (double)dQ * (double)net[threadIdx.x][1];
+            const double p2 = (double)q2 + xq2 + (double)dQ * (double)net[threadIdx.x][2];
+            const double mn = (double)th * hn;
+            const T hT = (T)hn;
+            const T a1 = mn > m_min ? (T)(p1 / mn) : T(0);
+            const T a2 = mn > m_min ? (T)(p2 / mn) : T(0);
+            ho[i] = hT;
+            v1o[i] = a1;
+            v2o[i] = a2;
+            const double cc = (double)(p_sqrt(a1 * a1 + a2 * a2) + p_sqrt(G * hT));
+            if (__builtin_isfinite(cc)) c = cc > c ? cc : c;
+            else bad += 1.0;  // the gate refuses such a window
+            s += kc.sigma * ((double)th * (double)hT);
+            if (may_outflow(g, q, r)) o += cell_outflow<T>(g, l, ho, v1o, v2o, d.th, q, r, i);
+        }
+    }
+    const Part p = block_reduce<NT>(c, s, o, bad);
+    if (threadIdx.x == 0) part[tile] = p;
+}
+
+template <typename T>
+hipError_t launch_win_last(const __bf16 *x, const __bf16 *wm, const float *bias,
+                           const nn::ConvMask &cm, const KDom<T> &d, const KGrid &g, double l,
+                           const KConst &kc, const Ctl *ctl, const SurWin *sw, const T *scr,
+                           double dt_max, float dH, float dQ, double m_min, Part *part,
+                           hipStream_t stream) {
+    const int nt = nn::conv_tiles(g.nq, g.nr, 1);
+    hipLaunchKernelGGL((k_win_last<T>), dim3(nt), dim3(nn::NT), 0, stream, x, wm, bias, cm, d, g,
+                       l, kc, ctl, sw, scr, dt_max, dH, dQ, m_min, part, nt);
+    return hipGetLastError();
+}
+
 // h *= scale on the state an accepted window produced (its velocities kept).
 template <typename T>
 __global__ __launch_bounds__(256) void k_win_scale(KDom<T> d, int64_t n, const Ctl *ctl,
@@ -570,6 +675,11 @@ hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const S
                                             const KConst &, const Ctl *, const SurWin *,      \
                                             const T *, double, const float *, int, float,     \
                                             float, double, Part *, hipStream_t);              \
+    template hipError_t launch_win_last<T>(const __bf16 *, const __bf16 *, const float *,    \
+                                           const nn::ConvMask &, const KDom<T> &, const KGrid &, \
+                                           double, const KConst &, const Ctl *, const SurWin *, \
+                                           const T *, double, float, float, double, Part *,   \
+                                           hipStream_t);                                      \
     template hipError_t launch_win_scale<T>(const KDom<T> &, int64_t, const Ctl *,            \
                                             const SurWin *, hipStream_t);                     \
     template hipError_t launch_import<T>(const double *, T *, const uint8_t *, int, int64_t,  \

@@ -297,6 +297,25 @@ int sur_forward_x0(hexsv_surrogate *s, const hexsv_grid *grid, hipStream_t st,
     return forward_packed(s, grid->kg.nq, grid->kg.nr, 1, cm, st, live);
 }
 
+int sur_forward_hidden(hexsv_surrogate *s, const hexsv_grid *grid, hipStream_t st,
+                       const int32_t *live, SurLast *last) {
+    if (s->fused || s->channels != 32) return HEXSV_EUNSUPPORTED;
+    nn::ConvMask cm;
+    int rc = conv_mask(grid, grid->kg.nq, grid->kg.nr, &cm, "run_surrogate");
+    if (rc) return rc;
+    const int nq = grid->kg.nq, nr = grid->kg.nr;
+    const __bf16 *x = s->x0;
+    for (int l = 0; l + 1 < s->layers; ++l) {
+        const SurLayer &y = s->L[l];
+        HIP_TRY(nn::launch_conv(y.cinp, y.coutp, nn::EPI_RELU, x, y.wm, y.bias, s->act[l],
+                                nullptr, nq, nr, 1, y.cout, cm, st, live));
+        x = s->act[l];
+    }
+    const SurLayer &y = s->L[s->layers - 1];
+    *last = SurLast{x, y.wm, y.bias, cm};
+    return HEXSV_OK;
+}
+
 // Forward + L1 loss + backward into s->d_g; loss in *loss (synchronises).
 static int gradient(hexsv_surrogate *s, const hexsv_grid *grid, int batch, int nq, int nr,
                     const float *feat, const float *target, double *loss, hipStream_t st) {
