@@ -399,6 +399,43 @@ def test_kinematic_wave_on_planar_slope():
     assert max(ok) < 0.05, max(ok)
 
 
+def _sheet_on_plane(slope, h0=0.1, v_down=0.5, nq=7, nr=12, sides=(OUTFLOW, PERIODIC,
+                                                                      OUTFLOW, PERIODIC)):
+    """A uniform sheet flowing down a plane z = slope * y, periodic across the slope."""
+    n = nq * nr
+    _, y = synth.centres(nq, nr, 1.0)
+    return synth.Scenario(name="sheet", nq=nq, nr=nr, a=1.0, z=slope * y,
+                          theta=np.full(n, 0.8), alpha_p=np.full(n, synth.ALPHA_P), side=sides,
+                          h0=np.full(n, h0), v10=np.zeros(n), v20=np.full(n, -v_down),
+                          t_end=1e9)
+
+
+def test_outflow_ghost_continues_the_plane():
+    """The free-outflow ghost (the cell's own h, v and theta; the bed extrapolated linearly
+    through the opposite neighbour) continues a uniform sheet on a plane: one step from
+    such a sheet changes every cell alike, the rim rows (two OUTFLOW edges each, the
+    downstream rim losing water through them and the upstream rim gaining it) exactly as
+    the interior.  A flat ghost bed, a reflecting ghost or a dropped edge would each set
+    the rim rows apart."""
+    sc = _sheet_on_plane(0.02)
+    G, p, r = _setup(sc)
+    h, v1, v2, b, _ = oracle.run(G, sc.z, sc.theta, sc.alpha_p, p, r, sc.h0, sc.v10, sc.v20,
+                                 sc.t_end, max_steps=1)
+    assert b.steps == 1
+    for f, ref in ((h, sc.h0[0]), (v1, 0.0), (v2, v2.mean())):
+        assert np.abs(f - f.mean()).max() <= 1e-13 * max(abs(ref), 1e-3), np.abs(f - f.mean()).max()
+    # the step did something: friction against gravity, and the sheet's own outflow and
+    # inflow balance (the depth is unchanged)
+    assert abs(v2.mean() + 0.5) > 1e-6
+    np.testing.assert_allclose(h, sc.h0, rtol=1e-14)
+    # against a check that is not vacuous: with WALL sides instead, the rim rows differ
+    walled = _sheet_on_plane(0.02, sides=(WALL, PERIODIC, WALL, PERIODIC))
+    Gw, pw, rw = _setup(walled)
+    hw, _, v2w, _, _ = oracle.run(Gw, walled.z, walled.theta, walled.alpha_p, pw, rw, walled.h0,
+                                  walled.v10, walled.v20, walled.t_end, max_steps=1)
+    assert np.abs(hw - hw.mean()).max() > 1e-6
+
+
 # ------------------------------------------------------------- P12 rain
 
 def test_triangular_hyetograph(golden):
