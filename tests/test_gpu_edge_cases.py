@@ -60,3 +60,23 @@ def test_fields_beyond_the_32_bit_offsets_are_refused(hx):
     with pytest.raises(hx.HexsvError) as ei:
         hx.Sim(grid, "fp32")
     assert ei.value.code == hx.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sheet_on_a_plane_with_outflow_rims(hx, precision):
+    """The uniform sheet of the outflow-ghost pin (OUTFLOW rims up- and downstream, periodic
+    across the slope) on a raster of ragged 64 x 16 tiles: FP64 bit for bit the oracle's
+    over 30 steps, and after one step every cell alike, rims included."""
+    from tests.test_oracle_pins import _sheet_on_plane
+    sc = _sheet_on_plane(0.02, nq=70, nr=45)
+    ref = ref_run(sc, max_steps=30)
+    got = gpu_run(hx, sc, precision, max_steps=30)
+    assert got["books"]["steps"] == 30
+    if precision == "fp64":
+        for k in ("h", "v1", "v2"):
+            np.testing.assert_array_equal(got[k], ref[k])
+    assert_parity(got, ref, precision, "sheet")
+    one = gpu_run(hx, sc, precision, max_steps=1)
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    for k in ("h", "v2"):
+        assert np.abs(one[k] - one[k].mean()).max() <= tol * np.abs(one[k]).max(), k
