@@ -252,14 +252,68 @@ hipError_t launch_win_reset(SurWin *sw, hipStream_t stream) {
 // exactly, which keeps the accepted residuals from adding up over many
 // windows.  A window is also refused if its fastest wave speed more than
 // doubles.  Refused: the chain stops and the state at t0 is untouched.
+// The predicted state's records and the start state's outflow records reduced in
+// one pass (their loads in flight together), each in reduce_parts' order.
+__device__ inline void reduce_window_parts(const Part *part, int n_part, const Part *op0,
+                                           int n_op0, Part &p, double &o0) {
+    constexpr int NT = 1024;
+    double c = 0.0, s = 0.0, o = 0.0, cl = 0.0, s0 = 0.0;
+    const int n = n_part > n_op0 ? n_part : n_op0;
+    for (int base = 0; base < n; base += NT * 4) {
+        Part a[4];
+        double b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * NT + threadIdx.x;
+            a[u] = i < n_part ? part[i] : Part{0.0, 0.0, 0.0, 0.0};
+            b[u] = i < n_op0 ? op0[i].stored : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c = a[u].cmax > c ? a[u].cmax : c;
+            s += a[u].stored;
+            o += a[u].outflow;
+            cl += a[u].clamp;
+            s0 += b[u];
+        }
+    }
+    __shared__ double red[5][NT / 64];
+    c = wave_max(c);
+    s = wave_sum(s);
+    o = wave_sum(o);
+    cl = wave_sum(cl);
+    s0 = wave_sum(s0);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = c;
+        red[1][w] = s;
+        red[2][w] = o;
+        red[3][w] = cl;
+        red[4][w] = s0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        p = Part{red[0][0], red[1][0], red[2][0], red[3][0]};
+        o0 = red[4][0];
+        for (int i = 1; i < NT / 64; ++i) {
+            p.cmax = red[0][i] > p.cmax ? red[0][i] : p.cmax;
+            p.stored += red[1][i];
+            p.outflow += red[2][i];
+            p.clamp += red[3][i];
+            o0 += red[4][i];
+        }
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const Part *part,
                                                    int n_part, const Part *op0, int n_op0,
                                                    KConst kc) {
     if (!sw->live) return;
-    const Part p = reduce_parts<1024>(part, n_part);
-    const Part o0 = reduce_parts<1024>(op0, n_op0);
+    Part p{0.0, 0.0, 0.0, 0.0};
+    double o0_stored = 0.0;
+    reduce_window_parts(part, n_part, op0, n_op0, p, o0_stored);
     if (threadIdx.x != 0) return;
-    const double Ow = 0.5 * (o0.stored + p.outflow) * sw->window;
+    const double Ow = 0.5 * (o0_stored + p.outflow) * sw->window;
     double ref = sw->S0 + sw->R;
     if (ref < 1e-300) ref = 1e-300;
     const double rho = fabs(p.stored - sw->S0 - (sw->R - Ow)) / ref;
