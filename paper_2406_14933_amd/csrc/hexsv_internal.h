@@ -47,11 +47,14 @@ hipError_t launch_ensemble(int variant, const KDom<T> &base, const EnsScen *scen
                            const int32_t *order, int nscen, uint32_t *queue, int ksteps, int nwg,
                            hipStream_t stream);
 constexpr int DEFAULT_TILE = 2;
-// Step tile of a single domain when the tuning cache has no entry: 128 x 8 cells
-// (256 threads) for rasters at least 2048 cells wide, whose long row segments it
-// streams fastest, else 64 x 16.
+// Step tile of a single domain when the tuning cache has no entry: in FP32, 128 x 8
+// cells (256 threads) for rasters at least 2048 cells wide, whose long row
+// segments it streams fastest; else 64 x 16 (FP64 measures 64 x 16 fastest at
+// every width).
 constexpr int WIDE_TILE = 4;
-inline int default_step_tile(int nq) { return nq >= 2048 ? WIDE_TILE : DEFAULT_TILE; }
+inline int default_step_tile(int nq, bool fp32) {
+    return fp32 && nq >= 2048 ? WIDE_TILE : DEFAULT_TILE;
+}
 
 // Number of tiles covering an nq x nr raster with variant v.
 inline void tile_grid(int v, int nq, int nr, int *ntq, int *ntiles) {

@@ -294,21 +294,11 @@ __device__ inline void tile_compute(const TileLDS<T, TQ, TR, V> &L, const TileRe
         const int q = q0 + lq, r = r0 + lr;
         const T hi = R.h[k], thi = R.th[k];
         const T mi = thi * hi;
-        // FP32 takes the cell's own staged record (the values the neighbours see), so that
-        // bed and velocity registers are free after staging; FP64 keeps them
-        T wi, vh1i, vh2i, Mi;
-        if constexpr (F32) {
-            const typename Rec<T>::type me = L.rec[s];
-            Mi = me.x;
-            wi = me.y;
-            vh1i = me.z;
-            vh2i = me.w;
-        } else {
-            wi = G * (R.z[k] + hi);
-            vh1i = R.v1[k] * T(0.5);
-            vh2i = R.v2[k] * T(0.5);
-            Mi = mscale * mi;
-        }
+        // the cell's own staged record (the values its neighbours see, formed by the same
+        // operations), so that the bed register is free after staging; FP32 also takes
+        // its velocity as twice the staged half, FP64 keeps the loaded one
+        const typename Rec<T>::type me = L.rec[s];
+        const T Mi = me.x, wi = me.y, vh1i = me.z, vh2i = me.w;
         T Ls = T(0), A1 = T(0), A2 = T(0), S1 = T(0), S2 = T(0), Fout = T(0);
         T V1 = T(0), V2 = T(0);  // viscous part of J^v (V only)
 #pragma unroll
