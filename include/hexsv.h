@@ -433,7 +433,8 @@ int hexsv_surrogate_forward(hexsv_surrogate *sur, const hexsv_grid *grid, int32_
  * that GPU's workspace: calls that overlap on one GPU (other streams or host
  * threads) race; calls on one stream are ordered.  EINVAL: batch*nq*nr above
  * 262144 cells (one 512 x 512 sample), or the arguments hexsv_surrogate_forward
- * refuses.  EHIP: the workspace's device address could not be looked up. */
+ * refuses.  EUNSUPPORTED: a device index above 63.  EHIP: the workspace's device
+ * address could not be looked up. */
 int hexsv_surrogate_forward_noalloc(hexsv_surrogate *sur, const hexsv_grid *grid, int32_t batch,
                                     int32_t nq, int32_t nr, const float *d_features,
                                     float *d_out, hipStream_t stream);
