@@ -1056,7 +1056,6 @@ static int window_body(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float
     const KDom<T> d = dom_of<T>(s);
     const KGrid &g = s->grid->kg;
     const double l = s->grid->edge;
-    const int64_t n = s->grid->n;
     T *scr = (T *)s->d_scr;
     const double dt_max = s->p.dt_max;
     Part *part = s->d_op, *op0 = s->d_op + win_part_count(s);
@@ -1081,7 +1080,6 @@ static int window_body(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float
         return rc;
     }
     HIP_TRY(launch_win_gate(s->d_ctl, s->d_sw, part, n_part, op0, n_op0, s->kc, st));
-    HIP_TRY(launch_win_scale<T>(d, n, s->d_ctl, s->d_sw, st));
     return HEXSV_OK;
 }
 
@@ -1093,6 +1091,8 @@ static int window_chain(hexsv_sim *s, hexsv_surrogate *sur, int nwin, void *x0, 
         int rc = window_body<T>(s, sur, x0, out, sc, st);
         if (rc) return rc;
     }
+    // the projection of the chain's last accepted window (the windows read it scaled)
+    HIP_TRY(launch_win_scale<T>(dom_of<T>(s), s->grid->n, s->d_ctl, s->d_sw, st));
     return HEXSV_OK;
 }
 

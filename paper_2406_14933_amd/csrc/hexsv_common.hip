@@ -326,6 +326,9 @@ __global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const P
     if (ok) {
         const double target = sw->S0 + sw->R - Ow;
         double stored = p.stored;
+        // the new state waits for its projection factor (applied by the next window's
+        // loads and once after the chain); the start state's factor is spent
+        sw->scale_live = 0;
         if (sw->project && p.stored > 0.0 && target > 0.0) {
             sw->scale = target / p.stored;
             sw->scale_live = 1;

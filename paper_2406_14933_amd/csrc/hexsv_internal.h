@@ -125,7 +125,9 @@ struct alignas(64) SurWin {
     int32_t rejected;               // a window of this chain was refused
     int32_t accepted;               // windows accepted in this chain
     int32_t project;                // 1: rescale an accepted state onto the balance
-    int32_t scale_live;             // the accepted state waits for its rescaling
+    int32_t scale_live;             // the current state waits for its rescaling by `scale`:
+                                    // the windows of a chain read it scaled, and one
+                                    // k_win_scale after the chain stores it
     int32_t perr, perr_cell;        // non-finite value met by a probe step
     double scale;                   // factor of that rescaling
     double c0;                      // reference c_max: of the last state the solver made
@@ -190,7 +192,8 @@ hipError_t launch_win_last(const __bf16 *x, const __bf16 *wm, const float *bias,
                            const KConst &kc, const Ctl *ctl, const SurWin *sw, const T *scr,
                            double dt_max, float dH, float dQ, double m_min, Part *part,
                            hipStream_t stream);
-// Rescaling of an accepted state onto the water balance (no-op unless sw->scale_live).
+// Rescaling of the current state onto the water balance (no-op unless sw->scale_live),
+// once after a chain of windows; the next chain's reset clears the flag.
 template <typename T>
 hipError_t launch_win_scale(const KDom<T> &d, int64_t n, const Ctl *ctl, const SurWin *sw,
                             hipStream_t stream);

@@ -298,9 +298,11 @@ hipError_t launch_win_slope(const KDom<T> &d, const KGrid &g, double a, float2 *
 // Volume flux (m^3/s) out of cell (q, r) through its OUTFLOW edges: the ghost
 // carries the cell's own h, v and theta, so each such edge passes
 // l * theta h * (v . n_k) whatever its sign.
+// hscale: a factor the stored depths still wait for (1: none).
 template <typename T>
 __device__ inline double cell_outflow(const KGrid &g, double l, const T *h, const T *v1,
-                                      const T *v2, const T *th, int q, int r, int64_t i) {
+                                      const T *v2, const T *th, int q, int r, int64_t i,
+                                      T hscale = T(1)) {
     const double S3 = 0.86602540378443864676;
     const double NX[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
     const double NY[6] = {0.0, S3, S3, 0.0, -S3, -S3};
@@ -312,7 +314,7 @@ __device__ inline double cell_outflow(const KGrid &g, double l, const T *h, cons
         if (wrap_pos(g, qn, rn)) cd = th[(int64_t)rn * g.nq + qn] > T(0) ? CODE_INTERIOR : g.mask_bc;
         else cd = side_code(g, qn, rn);
         if (cd != CODE_OUTFLOW) continue;
-        const double m = (double)th[i] * (double)h[i];
+        const double m = (double)th[i] * (double)(hscale == T(1) ? h[i] : h[i] * hscale);
         acc += l * m * ((double)v1[i] * NX[k] + (double)v2[i] * NY[k]);
     }
     return acc;
@@ -375,7 +377,6 @@ __global__ __launch_bounds__(NT) void k_win_probe(KDom<T> d, KGrid g, KConst kc,
     double depth = 0.0;
     for (int j = 1; j <= sw->k; ++j) depth += dts * rain_rate(rn, t0 + j * dts);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sw->scale_live = 0;
         sw->live = live ? 1 : 0;
         if (live) {
             sw->depth = depth;
@@ -405,6 +406,17 @@ __global__ __launch_bounds__(NT) void k_win_probe(KDom<T> d, KGrid g, KConst kc,
     const int tr = tile / ntq, tq = tile - tr * ntq;
     TileRegs<T, TQ, TR, NT> R;
     tile_load<T, TQ, TR, NT>(R, e, g, 0, tq, tr);
+    // the depths of an accepted, projected window wait for their rescaling until the
+    // chain ends: read them scaled (the product the rescaling stores)
+    const bool sc_live = sw->scale_live != 0;
+    const T hf = (T)sw->scale;
+    if (sc_live) {
+        using Regs = TileRegs<T, TQ, TR, NT>;
+#pragma unroll
+        for (int k = 0; k < Regs::CPT; ++k) R.h[k] = R.h[k] * hf;
+#pragma unroll
+        for (int k = 0; k < Regs::RPT; ++k) R.rh[k] = R.rh[k] * hf;
+    }
     const bool bad = tile_stage<T, TQ, TR, NT>(L, R, g, kc, tq, tr);
     const bool inner = tile_inner(g, tq * TQ, tr * TR, TQ, TR);
     const bool general = __syncthreads_or((!inner) || bad) != 0;
@@ -440,7 +452,8 @@ __global__ __launch_bounds__(NT) void k_win_probe(KDom<T> d, KGrid g, KConst kc,
 #pragma unroll
                 for (int c = 0; c < FEATURES; ++c) ((float *)fout)[(size_t)i * FEATURES + c] = f[c];
             }
-            if (may_outflow(g, q, r)) o += cell_outflow<T>(g, kc.a, h0, v10, v20, d.th, q, r, i);
+            if (may_outflow(g, q, r))
+                o += cell_outflow<T>(g, kc.a, h0, v10, v20, d.th, q, r, i, sc_live ? hf : T(1));
         }
         const Part p = block_reduce<NT>(0.0, o, 0.0, 0.0);
         if (threadIdx.x == 0) op0[tile] = p;
@@ -490,20 +503,23 @@ __global__ __launch_bounds__(256) void k_win_apply(KDom<T> d, KGrid g, double l,
     T *v2o = par ? d.st[0][2] : d.st[1][2];
     const T *hs = scr, *v1s = scr + n, *v2s = scr + 2 * (size_t)n;  // 2 n can pass 2^31
     const T G = (T)kc.g;
+    const bool sc_live = sw->scale_live != 0;  // the start state's depths await a factor
+    const T hf = (T)sw->scale;
     double c = 0.0, s = 0.0, o = 0.0, bad = 0.0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const T th = d.th[i];
+        const T hi = sc_live ? h[i] * hf : h[i];
         if (!(th > T(0))) {
-            ho[i] = h[i];
+            ho[i] = hi;
             v1o[i] = v1[i];
             v2o[i] = v2[i];
             continue;
         }
-        const T q1 = th * h[i] * v1[i], q2 = th * h[i] * v2[i];
-        const double xh = xs * (double)(hs[i] - h[i]);
+        const T q1 = th * hi * v1[i], q2 = th * hi * v2[i];
+        const double xh = xs * (double)(hs[i] - hi);
         const double xq1 = xs * (double)(th * hs[i] * v1s[i] - q1);
         const double xq2 = xs * (double)(th * hs[i] * v2s[i] - q2);
-        double hn = (double)h[i] + xh + (double)dH * (double)out[(size_t)i * os + 0];
+        double hn = (double)hi + xh + (double)dH * (double)out[(size_t)i * os + 0];
         hn = hn > 0.0 ? hn : 0.0;
         const double p1 = (double)q1 + xq1 + (double)dQ * (double)out[(size_t)i * os + 1];
         const double p2 = (double)q2 + xq2 + (double)dQ * (double)out[(size_t)i * os + 2];
@@ -590,22 +606,25 @@ __global__ __launch_bounds__(nn::NT) void k_win_last(const __bf16 *__restrict__ 
     T *v2o = par ? d.st[0][2] : d.st[1][2];
     const T *hs = scr, *v1s = scr + n, *v2s = scr + 2 * (size_t)n;  // 2 n can pass 2^31
     const T G = (T)kc.g;
+    const bool sc_live = sw->scale_live != 0;  // the start state's depths await a factor
+    const T hf = (T)sw->scale;
     double c = 0.0, s = 0.0, o = 0.0, bad = 0.0;
     const int lr = threadIdx.x / TQ, lq = threadIdx.x - lr * TQ;
     const int q = q0 + lq, r = r0 + lr;
     if (q < nq && r < nr) {
         const int i = r * g.pitch + q;
         const T th = d.th[i];
+        const T hi = sc_live ? h[i] * hf : h[i];
         if (!(th > T(0))) {
-            ho[i] = h[i];
+            ho[i] = hi;
             v1o[i] = v1[i];
             v2o[i] = v2[i];
         } else {
-            const T q1 = th * h[i] * v1[i], q2 = th * h[i] * v2[i];
-            const double xh = xs * (double)(hs[i] - h[i]);
+            const T q1 = th * hi * v1[i], q2 = th * hi * v2[i];
+            const double xh = xs * (double)(hs[i] - hi);
             const double xq1 = xs * (double)(th * hs[i] * v1s[i] - q1);
             const double xq2 = xs * (double)(th * hs[i] * v2s[i] - q2);
-            double hn = (double)h[i] + xh + (double)dH * (double)net[threadIdx.x][0];
+            double hn = (double)hi + xh + (double)dH * (double)net[threadIdx.x][0];
             hn = hn > 0.0 ? hn : 0.0;
             const double p1 = (double)q1 + xq1 + (double)dQ * (double)net[threadIdx.x][1];
             const double p2 = (double)q2 + xq2 + (double)dQ * (double)net[threadIdx.x][2];
