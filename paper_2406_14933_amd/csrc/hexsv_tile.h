@@ -114,6 +114,11 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
     const T *__restrict__ v1in = d.buf(par, 1);
     const T *__restrict__ v2in = d.buf(par, 2);
     const bool inner = tile_inner(g, q0, r0, TQ, TR);
+    // The state is read once per step.  Tiles 128 cells wide read their own cells with
+    // streaming loads, which leave the L2 to the halo reads of neighbouring tiles; on
+    // narrower tiles a larger share of each row is a neighbour's halo, and the ordinary
+    // policy keeps those lines for it.
+    constexpr bool STREAM = TQ >= 128;
 #pragma unroll
     for (int k = 0; k < Regs::CPT; ++k) {
         const int cc = threadIdx.x + k * NT;
@@ -125,14 +130,13 @@ __device__ inline void tile_load(TileRegs<T, TQ, TR, NT> &R, const KDom<T> &d, c
         R.pos[k] = pos;
         if (pos != POS_OUTSIDE) {
             const uint32_t i = (uint32_t)(r * g.pitch + q);
-            // the state is read once per step (streaming loads); the static fields use the
-            // ordinary cache policy
-            R.h[k] = ld_stream(hin, i);
+            // the static fields always use the ordinary cache policy
+            R.h[k] = STREAM ? ld_stream(hin, i) : ld(hin, i);
             R.th[k] = ld(d.th, i);
             R.ap[k] = ld(d.ap, i);
             R.z[k] = ld(d.z, i);
-            R.v1[k] = ld_stream(v1in, i);
-            R.v2[k] = ld_stream(v2in, i);
+            R.v1[k] = STREAM ? ld_stream(v1in, i) : ld(v1in, i);
+            R.v2[k] = STREAM ? ld_stream(v2in, i) : ld(v2in, i);
         }
     }
 #pragma unroll
