@@ -485,14 +485,25 @@ int hexsv_sim_surrogate_features(hexsv_sim *sim, hexsv_surrogate *sur, double wi
  * depths are then scaled by (S + R - O) / S' so that the kept state closes
  * the balance exactly (small residuals would otherwise add up over many
  * windows).  A refused window is discarded and the plain solver advances
- * that span (ENUMERIC if it stalls).  A last span shorter than `window` is
+ * that span (ENUMERIC if it stalls); after n >= 2 refusals in a row it also
+ * advances the next min(2^(n-1), 8) whole spans before a window is tried
+ * again, each span to its own end (hexsv_sim_set_surrogate_backoff).  A last span shorter than `window` is
  * always solved.  k <= 0 takes the surrogate's k.  Windows are chained
- * several to a graph launch; the host synchronises once per chain.  Counts of
- * kept and solved windows are returned.  The surrogate must not be used by another simulation while this
- * runs (its workspace is shared). */
+ * several to a graph launch (after a refusal the next chain is as long as the
+ * run of kept windows before it plus one; a chain kept whole is followed by
+ * one at least twice as long); the host synchronises once per chain.  Counts
+ * of kept windows and of spans the solver advanced are returned.  The
+ * surrogate must not be used by another simulation while this runs (its
+ * workspace is shared). */
 int hexsv_sim_run_surrogate(hexsv_sim *sim, hexsv_surrogate *sur, double t_end, double window,
                             int32_t k, double residual_tol, int32_t project, int64_t *n_accepted,
                             int64_t *n_fallback, hipStream_t stream);
+
+/* The back-off of hexsv_sim_run_surrogate: after n >= 2 refusals in a row the
+ * solver also advances min(2^(n-1), max_spans) whole spans before the next
+ * window (default 8; 0 turns the back-off off, so that every whole span is
+ * tried).  EINVAL: null sim or max_spans < 0. */
+int hexsv_sim_set_surrogate_backoff(hexsv_sim *sim, int32_t max_spans);
 
 /* Window counts of every run_surrogate call on this simulation so far:
  * counts[0] kept, counts[1] refused for the water-balance residual, counts[2]

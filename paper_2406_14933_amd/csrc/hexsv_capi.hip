@@ -174,6 +174,11 @@ extern "C" int hexsv_grid_tables(const hexsv_grid *grid, int32_t *nbr, uint8_t *
 // fallback of a refused surrogate window): the long graph would replay its
 // whole length of no-op steps past the span's end.
 static const int SHORT_STEPS = 8;
+// Surrogate runs: after n >= 2 windows refused in a row the plain solver also
+// advances the next min(2^(n-1), w_backoff) spans before windows are tried
+// again, so phases in which the network fails (a wetting front) cost solver
+// steps only; w_backoff starts at this value (hexsv_sim_set_surrogate_backoff).
+static const int WIN_BACKOFF_MAX = 8;
 // Most closed steps whose books wait in the step ring before a fold.
 static const int RING_MAX = 128;
 static const size_t ACC_BYTES = sizeof(unsigned long long) * ACC_SETS * ACC_SET_WORDS;
@@ -215,12 +220,13 @@ struct hexsv_sim {
     void *d_scr;  // probe state: 3 x cells of the state's precision
     float2 *d_slope;  // terrain slope per cell (static; rebuilt after set_fields)
     bool slope_ok;
-    hipGraph_t wgraph[4];     // chains of WIN_CHAINS[j] windows
-    hipGraphExec_t wexec[4];
+    hipGraph_t wgraph[6];     // chains of WIN_CHAINS[j] windows
+    hipGraphExec_t wexec[6];
     const hexsv_surrogate *w_sur;
     uint64_t w_gen;
     float w_scales[8];
     int64_t w_stats[4];  // windows kept; refused for the residual, the wave speed, non-finite
+    int32_t w_backoff;   // most spans solved after a run of refusals (0: none)
     // optional device timing of graph replays (hipEvents on the run stream)
     bool timing;
     hipEvent_t ev0, ev1;
@@ -257,7 +263,7 @@ static void drop_graph(hexsv_sim *s) {
 }
 
 static void drop_win_graph(hexsv_sim *s) {
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 6; ++j) {
         if (s->wexec[j]) (void)hipGraphExecDestroy(s->wexec[j]);
         if (s->wgraph[j]) (void)hipGraphDestroy(s->wgraph[j]);
         s->wexec[j] = nullptr;
@@ -302,6 +308,7 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
                                        default_step_tile(grid->kg.nq, p.precision == HEXSV_FP32));
     tile_grid(s->tile, grid->kg.nq, grid->kg.nr, &s->ntq, &s->ntiles);
     s->gsteps = p.steps_per_graph > 0 ? p.steps_per_graph : 100;
+    s->w_backoff = WIN_BACKOFF_MAX;
     s->ring_len = s->gsteps < RING_MAX ? s->gsteps : RING_MAX;
     if (s->ring_len < SHORT_STEPS) s->ring_len = SHORT_STEPS;
     const double a = grid->edge;
@@ -1043,7 +1050,23 @@ extern "C" int hexsv_sim_surrogate_features(hexsv_sim *s, hexsv_surrogate *sur, 
 // its chain, whose kernels then return at once).  The chain length adapts: it
 // shrinks after a chain with a refusal (fewer dead windows launched) and grows
 // after a chain without one (fewer host round trips).
-static const int WIN_CHAINS[4] = {2, 4, 8, 16};
+// Chain lengths with a captured graph.  After a refusal the next chain is as long
+// as the run of kept windows before it plus one (refusals tend to recur at that
+// period, so the chain ends where the next refusal is expected, and a run of
+// refusals tries one window at a time); a chain kept whole is followed by one at
+// least twice as long.
+constexpr int N_CHAINS = 6;
+static const int WIN_CHAINS[N_CHAINS] = {1, 2, 3, 4, 8, 16};
+static int chain_at_most(int n) {  // the longest captured chain of at most n windows
+    int j = 0;
+    while (j + 1 < N_CHAINS && WIN_CHAINS[j + 1] <= n) ++j;
+    return j;
+}
+static int chain_at_least(int n) {  // the shortest captured chain of at least n windows
+    int j = 0;
+    while (j + 1 < N_CHAINS && WIN_CHAINS[j] < n) ++j;
+    return j;
+}
 // Most plain steps one refused window may take before the run reports a stall.
 static const int64_t FALLBACK_STEP_LIMIT = 1 << 20;
 
@@ -1100,7 +1123,7 @@ template <typename T>
 static int capture_windows(hexsv_sim *s, hexsv_surrogate *sur, void *x0, const float *out,
                            const float *sc, uint64_t gen) {
     drop_win_graph(s);
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < N_CHAINS; ++j) {
         HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
         int rc = window_chain<T>(s, sur, WIN_CHAINS[j], x0, out, sc, s->cap);
         hipGraph_t g = nullptr;
@@ -1136,7 +1159,7 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
     if (rc) return rc;
     // the scales are kernel arguments of the graph: rebuild when they change
     static_assert(sizeof(sc) == 8 * sizeof(float), "scales");
-    bool same = s->wexec[3] && s->w_sur == sur && s->w_gen == gen;
+    bool same = s->wexec[N_CHAINS - 1] && s->w_sur == sur && s->w_gen == gen;
     for (int j = 0; j < 8 && same; ++j) same = s->w_scales[j] == sc[j];
     if (!same) {
         rc = capture_windows<T>(s, sur, x0, out, sc, gen);
@@ -1149,7 +1172,9 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
     Ctl &c = *s->h_ctl;
     HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    int level = 3;  // index into WIN_CHAINS
+    int level = chain_at_most(2);  // index into WIN_CHAINS
+    int streak = 0;                // windows refused since the last kept one
+    int run = 0;                   // windows kept since the last refusal
     for (;;) {  // c is current here
         if (c.err) return fail(HEXSV_ENUMERIC, "run_surrogate: non-finite value at cell %d", c.err_cell);
         const double t0 = c.t;
@@ -1176,24 +1201,40 @@ static int surrogate_windows(hexsv_sim *s, hexsv_surrogate *sur, double t_end, d
         *n_acc += w.accepted;
         s->w_stats[0] += w.accepted;
         if (w.rejected) s->w_stats[w.why == 1 ? 1 : (w.why == 2 ? 2 : 3)] += 1;
+        if (w.accepted) streak = 0;
+        run += (int)w.accepted;
         if (w.rejected) {  // the refused window's span, by the plain solver from its start
-            if (level > 0) --level;
+            level = chain_at_most(run + 1);
+            run = 0;
             if (c.err) continue;
-            const double target = c.t + window;
-            rc = sim_run(s, target, FALLBACK_STEP_LIMIT, true, true, st);
-            if (rc) return rc;
-            if (!(c.t >= target))
-                return fail(HEXSV_ENUMERIC, "run_surrogate: the solver stalled at t=%g before %g",
-                            c.t, target);
-            *n_fb += 1;
+            ++streak;
+            // the refused span, then the back-off spans; each span ends where a window would
+            int spans = 1;
+            if (streak >= 2) spans += std::min(1 << std::min(streak - 1, 30), s->w_backoff);
+            for (int j = 0; j < spans; ++j) {
+                const double target = c.t + window;
+                if (j > 0 && (c.err || target > t_end)) break;
+                rc = sim_run(s, target, FALLBACK_STEP_LIMIT, true, true, st);
+                if (rc) return rc;
+                if (!(c.t >= target))
+                    return fail(HEXSV_ENUMERIC,
+                                "run_surrogate: the solver stalled at t=%g before %g", c.t, target);
+                *n_fb += 1;
+            }
             // the solver's state is the new reference wave speed of the windows that follow
             static const double fresh = -1.0;
             HIP_TRY(hipMemcpyAsync((char *)s->d_sw + offsetof(SurWin, c0), &fresh, sizeof fresh,
                                    hipMemcpyHostToDevice, st));
-        } else if (level < 3) {
-            ++level;
+        } else {
+            level = chain_at_least(2 * left);
         }
     }
+    return HEXSV_OK;
+}
+
+extern "C" int hexsv_sim_set_surrogate_backoff(hexsv_sim *s, int32_t max_spans) {
+    if (!s || max_spans < 0) return fail(HEXSV_EINVAL, "set_surrogate_backoff: bad argument");
+    s->w_backoff = max_spans;
     return HEXSV_OK;
 }
 

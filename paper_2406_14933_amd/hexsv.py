@@ -127,6 +127,7 @@ _SIGS = [
                                           C.c_double, C.c_int32, C.POINTER(C.c_int64),
                                           C.POINTER(C.c_int64), _VP]),
     ("hexsv_sim_surrogate_stats", C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    ("hexsv_sim_set_surrogate_backoff", C.c_int, [_VP, C.c_int32]),
     ("hexsv_autotune", C.c_int, [C.c_char_p, C.c_int32, C.c_int32, C.c_int64,
                                  C.POINTER(C.c_int32), C.POINTER(C.c_double), _VP]),
     ("hexsv_tile_count", C.c_int, []),
@@ -384,6 +385,10 @@ class Sim:
                                              float(residual_tol), int(bool(project)), C.byref(a),
                                              C.byref(f), _stream()))
         return a.value, f.value
+
+    def set_surrogate_backoff(self, max_spans):
+        """Most spans the solver advances after a run of refused windows (0: none)."""
+        _check(lib().hexsv_sim_set_surrogate_backoff(self._h, int(max_spans)))
 
     def surrogate_stats(self):
         """Windows of all run_surrogate calls: kept and refused (by reason)."""

@@ -147,7 +147,9 @@ def rollout_pairs(sur, scenarios, times, window, k, scales, tol=1e-5):
     """Pairs whose start states come from surrogate runs of the scenarios, i.e. the states the
     network meets once it drives a simulation, with the plain solver's change over the
     window from each such state as the target (the same correction form as ``collect``).
-    Training on them as well keeps a run from drifting away from the data it was fitted on."""
+    Training on them as well keeps a run from drifting away from the data it was fitted on.
+    The runs try a window on every span (no back-off after refusals), so that they sample
+    the states the network drives a run into wherever it is used."""
     nq, nr = scenarios[0].nq, scenarios[0].nr
     F = hexsv.Surrogate.FEATURES
     n = len(scenarios) * len(times)
@@ -156,6 +158,7 @@ def rollout_pairs(sur, scenarios, times, window, k, scales, tol=1e-5):
     p = 0
     for sc in scenarios:
         run = hexsv.Sim.from_scenario(sc, "fp32")
+        run.set_surrogate_backoff(0)
         probe = hexsv.Sim.from_scenario(sc, "fp32")
         th = torch.as_tensor(np.asarray(sc.theta, np.float64), device="cuda")
         for t in times:

@@ -153,16 +153,23 @@ def test_projection_closes_the_balance(hx, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_zero_tolerance_falls_back_to_the_solver(hx, prec):
+@pytest.mark.parametrize("backoff", [None, 0])
+def test_zero_tolerance_falls_back_to_the_solver(hx, prec, backoff):
     sc = wet_planar(nq=66, nr=33, seed=12)
     t_end = 5 * WINDOW + 0.7
     sim = hx.Sim.from_scenario(sc, prec)
+    if backoff is not None:
+        sim.set_surrogate_backoff(backoff)
     sur, _ = make_surrogate(hx, seed=5)
-    print(f"[surrogate fallback {prec}]", flush=True)
+    print(f"[surrogate fallback {prec} backoff {backoff}]", flush=True)
     acc, fb = sim.run_surrogate(sur, t_end, WINDOW, K, residual_tol=0.0)
     assert (acc, fb) == (0, 6)
-    st = sim.surrogate_stats()  # 5 whole windows refused on their residual, then a short span
-    assert st == {"kept": 0, "refused_residual": 5, "refused_wave_speed": 0,
+    # by default windows are tried on spans 1, 2 and 5 and refused on their residual: after
+    # the second refusal in a row the solver also advances spans 3 and 4 (back-off); without
+    # the back-off a window is tried on every whole span.  Then the short last span.
+    st = sim.surrogate_stats()
+    refused = 3 if backoff is None else 5
+    assert st == {"kept": 0, "refused_residual": refused, "refused_wave_speed": 0,
                   "refused_nonfinite": 0}, st
     ref = hx.Sim.from_scenario(sc, prec)
     t = 0.0
@@ -185,6 +192,8 @@ def test_surrogate_window_rejects_bad_arguments(hx):
     for window, k, tol in ((0.0, 16, 1e-3), (math.inf, 16, 1e-3), (1.0, 16, -1.0)):
         with pytest.raises(hx.HexsvError):
             sim.run_surrogate(sur, 10.0, window, k, tol)
+    with pytest.raises(hx.HexsvError):
+        sim.set_surrogate_backoff(-1)
     with pytest.raises(hx.HexsvError):
         hx.Surrogate(4, 32, k=0)
     torch.cuda.synchronize()
