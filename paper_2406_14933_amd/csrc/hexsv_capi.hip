@@ -174,6 +174,11 @@ extern "C" int hexsv_grid_tables(const hexsv_grid *grid, int32_t *nbr, uint8_t *
 // fallback of a refused surrogate window): the long graph would replay its
 // whole length of no-op steps past the span's end.
 static const int SHORT_STEPS = 8;
+// Short graphs of 1, 2, 4, 8 and 16 steps (each ends with its fold) for spans of
+// a few steps; a span is replayed as the set of them that costs least (see
+// short_plan).
+constexpr int N_SHORT = 5;
+static const int SHORT_LEN[N_SHORT] = {1, 2, 4, 8, 16};
 // Surrogate runs: after n >= 2 windows refused in a row the plain solver also
 // advances the next min(2^(n-1), w_backoff) spans before windows are tried
 // again, so phases in which the network fails (a wetting front) cost solver
@@ -210,8 +215,8 @@ struct hexsv_sim {
     hipStream_t cap;
     hipGraph_t graph[2];    // gsteps steps, starting from buffer parity 0 / 1
     hipGraphExec_t gexec[2];
-    hipGraph_t sgraph[2];   // short graphs (SHORT_STEPS steps) for spans of a few steps
-    hipGraphExec_t sexec[2];
+    hipGraph_t sgraph[N_SHORT][2];  // short graphs (SHORT_LEN[j] steps), per start parity
+    hipGraphExec_t sexec[N_SHORT][2];
     bool graph_ok, fields_set, state_set;
     // surrogate windows: control record (device + pinned mirror), outflow
     // partials of both ends, and a graph of WIN_CHAIN chained windows
@@ -252,12 +257,14 @@ static void drop_graph(hexsv_sim *s) {
     for (int p = 0; p < 2; ++p) {
         if (s->gexec[p]) (void)hipGraphExecDestroy(s->gexec[p]);
         if (s->graph[p]) (void)hipGraphDestroy(s->graph[p]);
-        if (s->sexec[p]) (void)hipGraphExecDestroy(s->sexec[p]);
-        if (s->sgraph[p]) (void)hipGraphDestroy(s->sgraph[p]);
+        for (int j = 0; j < N_SHORT; ++j) {
+            if (s->sexec[j][p]) (void)hipGraphExecDestroy(s->sexec[j][p]);
+            if (s->sgraph[j][p]) (void)hipGraphDestroy(s->sgraph[j][p]);
+            s->sexec[j][p] = nullptr;
+            s->sgraph[j][p] = nullptr;
+        }
         s->gexec[p] = nullptr;
         s->graph[p] = nullptr;
-        s->sexec[p] = nullptr;
-        s->sgraph[p] = nullptr;
     }
     s->graph_ok = false;
 }
@@ -625,11 +632,42 @@ static int capture(hexsv_sim *s) {
     for (int p = 0; p < 2; ++p) {
         int rc = capture_steps(s, s->gsteps, p, &s->graph[p], &s->gexec[p]);
         if (rc) return rc;
-        rc = capture_steps(s, SHORT_STEPS, p, &s->sgraph[p], &s->sexec[p]);
+        for (int j = 0; j < N_SHORT && !rc; ++j)
+            rc = capture_steps(s, SHORT_LEN[j], p, &s->sgraph[j][p], &s->sexec[j][p]);
         if (rc) return rc;
     }
     s->graph_ok = true;
     return HEXSV_OK;
+}
+
+// Short graphs (indices into SHORT_LEN, longest first) that replay at least n
+// steps at the least cost: 16-step graphs while 16 or more steps remain, then the
+// cheapest set for the rest, a graph's fold counting as two steps that find the
+// run over (each such step still issues its loads).  Returns the count (<= cap).
+static int short_plan(int n, int *plan, int cap) {
+    int m = 0;
+    while (n >= SHORT_LEN[N_SHORT - 1] && m < cap) {
+        plan[m++] = N_SHORT - 1;
+        n -= SHORT_LEN[N_SHORT - 1];
+    }
+    if (n <= 0) return m;
+    int best = 0, best_cost = 1 << 30;
+    for (int set = 1; set < (1 << N_SHORT); ++set) {
+        int sum = 0, cnt = 0;
+        for (int j = 0; j < N_SHORT; ++j)
+            if (set >> j & 1) {
+                sum += SHORT_LEN[j];
+                ++cnt;
+            }
+        const int cost = 2 * cnt + (sum - n);
+        if (sum >= n && cost < best_cost) {
+            best_cost = cost;
+            best = set;
+        }
+    }
+    for (int j = N_SHORT - 1; j >= 0; --j)
+        if ((best >> j & 1) && m < cap) plan[m++] = j;
+    return m;
 }
 
 static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, bool ctl_fresh,
@@ -666,8 +704,8 @@ static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, b
         // A launch past the end of the run still issues its tile loads before it
         // finds out, so each batch of replays is sized from the steps expected to
         // remain (the current dt bound, or the step limit): whole long graphs
-        // while two or more of them remain, then the short graph as often as the
-        // rest should need (a span of a few steps costs one host round trip).
+        // while two or more of them remain, then short graphs for the rest (a
+        // span of a few steps costs one host round trip).
         // A step limit that leaves a whole number of long graphs before t_end (as a
         // benchmark's step count does) is replayed as exactly those graphs.
         const double dt = c.tau < s->p.dt_max ? c.tau : s->p.dt_max;
@@ -677,19 +715,29 @@ static int sim_run(hexsv_sim *s, double t_end, int64_t max_steps, bool shortg, b
         if ((double)by_limit < need) need = (double)by_limit;
         const bool use_short = !exact && (shortg || need < 2.0 * s->gsteps);
         int reps;
-        if (exact)
+        int plan[48];  // short graphs of this batch
+        if (exact) {
             reps = (int)(by_limit / s->gsteps < 64 ? by_limit / s->gsteps : 64);
-        else if (use_short)
-            reps = need <= SHORT_STEPS ? 1 : (int)fmin(64.0, ceil(need / SHORT_STEPS));
-        else
+        } else if (use_short) {
+            const double n = ceil(fmin(need, 512.0));
+            reps = short_plan(n < 1.0 ? 1 : (int)n, plan, 48);
+        } else {
             reps = (int)fmin(64.0, floor(need / s->gsteps) - 1.0);
-        const int per = use_short ? SHORT_STEPS : s->gsteps;
+        }
         if (s->timing) HIP_TRY(hipEventRecord(s->ev0, stream));
-        // replays after the first start from a parity the host no longer knows: for
-        // a live step the graph's hint is still right whenever its step count is even
+        // replays after the first start from a parity the host no longer knows: for a
+        // live step the graph's hint is right while the steps before it were live (the
+        // short graphs go longest first, so the odd ones come last)
+        int64_t launched = 0;
         for (int k = 0; k < reps; ++k) {
-            const int p = (int)((c.parity + (int64_t)k * per) & 1);
-            HIP_TRY(hipGraphLaunch(use_short ? s->sexec[p] : s->gexec[p], stream));
+            const int p = (int)((c.parity + launched) & 1);
+            if (use_short) {
+                HIP_TRY(hipGraphLaunch(s->sexec[plan[k]][p], stream));
+                launched += SHORT_LEN[plan[k]];
+            } else {
+                HIP_TRY(hipGraphLaunch(s->gexec[p], stream));
+                launched += s->gsteps;
+            }
         }
         if (s->timing) HIP_TRY(hipEventRecord(s->ev1, stream));
         HIP_TRY(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
