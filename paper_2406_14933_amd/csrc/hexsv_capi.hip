@@ -312,7 +312,8 @@ extern "C" int hexsv_sim_create(const hexsv_grid *grid, const hexsv_params *para
     s->esz = p.precision == HEXSV_FP64 ? sizeof(double) : sizeof(float);
     s->tile = p.tile >= 0 ? p.tile
                           : tuned_tile("step", p.precision, grid->n,
-                                       default_step_tile(grid->kg.nq, p.precision == HEXSV_FP32));
+                                       default_step_tile(grid->kg.nq, grid->kg.nr,
+                                                         p.precision == HEXSV_FP32));
     tile_grid(s->tile, grid->kg.nq, grid->kg.nr, &s->ntq, &s->ntiles);
     s->gsteps = p.steps_per_graph > 0 ? p.steps_per_graph : 100;
     s->w_backoff = WIN_BACKOFF_MAX;

@@ -49,11 +49,19 @@ hipError_t launch_ensemble(int variant, const KDom<T> &base, const EnsScen *scen
 constexpr int DEFAULT_TILE = 2;
 // Step tile of a single domain when the tuning cache has no entry: in FP32, 128 x 8
 // cells (256 threads) for rasters at least 2048 cells wide, whose long row
-// segments it streams fastest; else 64 x 16 (FP64 measures 64 x 16 fastest at
-// every width).
+// segments it streams fastest; else the tallest of 64 x 16, 64 x 8 and 64 x 4
+// (variants 2, 1, 0) that still makes 512 workgroups, two per CU (on smaller
+// rasters a step is bound by latency, which more workgroups in flight hide),
+// and 64 x 4 below that.
 constexpr int WIDE_TILE = 4;
-inline int default_step_tile(int nq, bool fp32) {
-    return fp32 && nq >= 2048 ? WIDE_TILE : DEFAULT_TILE;
+inline int default_step_tile(int nq, int nr, bool fp32) {
+    if (fp32 && nq >= 2048) return WIDE_TILE;
+    for (int v = DEFAULT_TILE; v > 0; --v) {
+        const int64_t n = (int64_t)((nq + TILES[v].tq - 1) / TILES[v].tq) *
+                          ((nr + TILES[v].tr - 1) / TILES[v].tr);
+        if (n >= 512) return v;
+    }
+    return 0;
 }
 
 // Number of tiles covering an nq x nr raster with variant v.

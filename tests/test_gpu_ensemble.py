@@ -37,7 +37,7 @@ def test_ensemble_fp64_matches_oracle_and_single(hx, mode, tile):
         assert got["books"]["t"] == sc.t_end
         assert got["books"]["steps"] == ref["books"]["steps"], s
         assert_parity(got, ref, "fp64", f"ens{s}")
-        single = hx.Sim.from_scenario(sc, "fp64")
+        single = hx.Sim.from_scenario(sc, "fp64", tile=2)
         single.run(sc.t_end)
         st = single.state_numpy()
         # the same per-cell arithmetic and the same time steps: bit-identical states
