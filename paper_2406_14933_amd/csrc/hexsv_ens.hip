@@ -26,6 +26,8 @@ struct hexsv_ensemble {
     int btile, btotal;          // batched mode: tile variant and total tiles
     EnsTile *d_tiles;           // batched mode: descriptor of every global tile
     Part *d_bpart;              // batched mode: one record per global tile
+    uint8_t *d_tpar;            // batched mode: parity offset of every global tile
+    std::vector<uint8_t> h_tpar;  // what d_tpar holds (empty: not set)
     double dt_max;
     std::vector<const hexsv_grid *> grids;
     std::vector<EnsScen> scen;  // host copy
@@ -127,6 +129,7 @@ static int ens_set_btile(hexsv_ensemble *e, int v) {
         }
     }
     e->btotal = base;
+    e->h_tpar.clear();
     ens_drop_graph(e);
     if (e->d_tiles) HIP_TRY(hipMemcpy(e->d_tiles, map.data(), sizeof(EnsTile) * map.size(),
                                       hipMemcpyHostToDevice));
@@ -148,6 +151,7 @@ extern "C" void hexsv_ensemble_destroy(hexsv_ensemble *e) {
     if (e->d_queue) (void)hipFree(e->d_queue);
     if (e->d_tiles) (void)hipFree(e->d_tiles);
     if (e->d_bpart) (void)hipFree(e->d_bpart);
+    if (e->d_tpar) (void)hipFree(e->d_tpar);
     if (e->h_ctl) (void)hipHostFree(e->h_ctl);
     if (e->h_chk) (void)hipHostFree(e->h_chk);
     delete e;
@@ -255,6 +259,7 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
     }
     if (err == hipSuccess) err = hipMalloc(&e->d_bpart, sizeof(Part) * (size_t)maxtiles);
     if (err == hipSuccess) err = hipMalloc(&e->d_tiles, sizeof(EnsTile) * (size_t)maxtiles);
+    if (err == hipSuccess) err = hipMalloc(&e->d_tpar, (size_t)maxtiles);
     if (err == hipSuccess) err = hipHostMalloc(&e->h_ctl, sizeof(Ctl) * n, hipHostMallocDefault);
     if (err == hipSuccess) err = hipHostMalloc(&e->h_chk, 8 * sizeof(int32_t), hipHostMallocDefault);
     if (err == hipSuccess) err = hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking);
@@ -368,11 +373,11 @@ static hipError_t ens_launch(hexsv_ensemble *e, int mode, int v, int ksteps, int
     for (int k = 0; k < ksteps && err == hipSuccess; ++k)
         err = e->prec == HEXSV_FP64
                   ? launch_ens_step<double>(v, e->visc != 0, e->bc != 0, ens_base<double>(e),
-                                            e->d_scen, e->d_tiles, e->d_ctl, e->d_bpart,
-                                            e->btotal, e->n, (p0 + k) & 1, st)
+                                            e->d_scen, e->d_tiles, e->d_tpar, e->d_ctl,
+                                            e->d_bpart, e->btotal, e->n, (p0 + k) & 1, st)
                   : launch_ens_step<float>(v, e->visc != 0, e->bc != 0, ens_base<float>(e),
-                                           e->d_scen, e->d_tiles, e->d_ctl, e->d_bpart,
-                                           e->btotal, e->n, (p0 + k) & 1, st);
+                                           e->d_scen, e->d_tiles, e->d_tpar, e->d_ctl,
+                                           e->d_bpart, e->btotal, e->n, (p0 + k) & 1, st);
     return err;
 }
 
@@ -396,16 +401,24 @@ static int ens_capture(hexsv_ensemble *e) {
     return HEXSV_OK;
 }
 
-// Buffer parity of most live scenarios of n control blocks (the batched
-// launches' load hint).
-static int live_parity(const Ctl *c, int n) {
-    int count[2] = {0, 0};
-    for (int s = 0; s < n; ++s)
-        if (!(c[s].err || c[s].t >= c[s].t_end || c[s].steps >= c[s].step_limit))
-            count[c[s].parity & 1] += 1;
-    return count[1] > count[0] ? 1 : 0;
+// The batched launches' load hints: every tile of scenario s gets the offset
+// c[s].parity, so that launch k after this call hints parity k & 1 to all tiles
+// and every scenario that is live then reads the buffers of its own parity
+// (scenarios stopped at different step counts by runs to their own t_end keep
+// their relative parities while they step together).  Uploads only a change.
+static hipError_t ens_set_parities(hexsv_ensemble *e, const Ctl *c, hipStream_t st) {
+    std::vector<uint8_t> tp((size_t)e->btotal);
+    for (int s = 0; s < e->n; ++s)
+        std::fill(tp.begin() + e->scen[s].bbase, tp.begin() + e->scen[s].bbase + e->scen[s].bntiles,
+                  (uint8_t)(c[s].parity & 1));
+    if (tp == e->h_tpar) return hipSuccess;
+    // ordered before the launches that read it: the stream's pending work first, then a
+    // copy that has finished when it returns
+    hipError_t err = hipStreamSynchronize(st);
+    if (err == hipSuccess) err = hipMemcpy(e->d_tpar, tp.data(), tp.size(), hipMemcpyHostToDevice);
+    if (err == hipSuccess) e->h_tpar.swap(tp);
+    return err;
 }
-static int ens_live_parity(const hexsv_ensemble *e) { return live_parity(e->h_ctl, e->n); }
 
 static bool ens_done(const Ctl &c) { return c.err || c.t >= c.t_end || c.steps >= c.step_limit; }
 
@@ -430,9 +443,12 @@ extern "C" int hexsv_ensemble_run(hexsv_ensemble *e, const double *t_end, int64_
         int rc = ens_capture(e);
         if (rc) return rc;
     }
+    if (e->mode == HEXSV_ENS_BATCHED) HIP_TRY(ens_set_parities(e, e->h_ctl, stream));
+    int64_t launched = 0;  // batched launches since the parities were set
     for (;;) {
         if (e->timing) HIP_TRY(hipEventRecord(e->ev0, stream));
-        HIP_TRY(hipGraphLaunch(e->gexec[ens_live_parity(e)], stream));
+        HIP_TRY(hipGraphLaunch(e->gexec[launched & 1], stream));
+        launched += e->ksteps;
         if (e->timing) HIP_TRY(hipEventRecord(e->ev1, stream));
         HIP_TRY(hipMemcpyAsync(e->h_ctl, e->d_ctl, sizeof(Ctl) * e->n, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -561,9 +577,9 @@ extern "C" int hexsv_ensemble_autotune(hexsv_ensemble *e, int32_t ksteps, const 
         }
         if (he == hipSuccess) he = hipMemcpyAsync(e->d_scen, e->scen.data(), sizeof(EnsScen) * e->n, hipMemcpyHostToDevice, stream);
         if (he == hipSuccess) he = hipMemcpyAsync(e->d_ctl, cc.data(), sizeof(Ctl) * e->n, hipMemcpyHostToDevice, stream);
+        if (he == hipSuccess && mode == HEXSV_ENS_BATCHED) he = ens_set_parities(e, cc.data(), stream);
         if (he == hipSuccess) he = hipEventRecord(a, stream);
-        if (he == hipSuccess)
-            he = ens_launch(e, mode, v, ksteps, live_parity(cc.data(), e->n), stream);
+        if (he == hipSuccess) he = ens_launch(e, mode, v, ksteps, 0, stream);
         if (he == hipSuccess) he = hipEventRecord(b, stream);
         if (he == hipSuccess) he = hipEventSynchronize(b);
         float ms = 0.f;

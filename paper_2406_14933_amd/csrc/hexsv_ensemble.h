@@ -147,10 +147,11 @@ __global__ __launch_bounds__(NT) void k_ensemble(KDom<T> base, const EnsScen *__
 // Batched-step mode: one launch advances every live scenario by one step.
 // The tiles of all scenarios form one index space (one workgroup per tile,
 // XCD-banded).  A workgroup reads its tile descriptor and issues the tile's
-// loads from the buffers of the parity the launcher expects (par_hint: live
-// scenarios step together, so their parities agree), then reads the
-// scenario's control block; a scenario of the other parity reloads (a cost,
-// never a wrong result).  It writes one partial record; k_ens_finalize (one
+// loads from the buffers of the parity the launcher expects, par_hint XOR the
+// tile's offset tpar[t] (live scenarios step together, so each keeps its
+// parity relative to the others; the offsets record it for scenarios that
+// stopped at different step counts), then reads the scenario's control block;
+// a scenario of the other parity reloads (a cost, never a wrong result).  It writes one partial record; k_ens_finalize (one
 // workgroup per scenario) then closes each scenario's step.  Kernel
 // boundaries order the steps.
 // V: the augmented momentum flux with artificial viscosity (set_viscosity);
@@ -158,11 +159,13 @@ __global__ __launch_bounds__(NT) void k_ensemble(KDom<T> base, const EnsScen *__
 template <typename T, int TQ, int TR, int NT, bool V, bool EXT>
 __global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__restrict__ scen,
                                                  const EnsTile *__restrict__ tiles,
+                                                 const uint8_t *__restrict__ tpar,
                                                  Ctl *__restrict__ ctl, Part *__restrict__ part,
                                                  int ntiles_total, int par_hint) {
     const int t = xcd_tile(blockIdx.x, gridDim.x, ntiles_total, 0);
     if (t < 0) return;
     const EnsTile tl = tiles[t];
+    const int hint = par_hint ^ (int)tpar[t];
     // what tile_load reads of the raster: its size and periodic sides
     KGrid gl;
     gl.nq = tl.nq;
@@ -171,13 +174,13 @@ __global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__
     gl.perq = tl.wrap & 1;
     gl.perr = (tl.wrap >> 1) & 1;
     TileRegs<T, TQ, TR, NT> R;
-    tile_load<T, TQ, TR, NT>(R, dom_at(base, tl.off, par_hint), gl, 0, tl.tq, tl.tr);
+    tile_load<T, TQ, TR, NT>(R, dom_at(base, tl.off, hint), gl, 0, tl.tq, tl.tr);
     const int s = tl.s;
     const StepTime st = step_time(&ctl[s]);
     if (!st.live) return;
     const int par = ctl[s].parity;
     const KDom<T> d = dom_at(base, tl.off, par);
-    if (par != par_hint) tile_load<T, TQ, TR, NT>(R, d, gl, 0, tl.tq, tl.tr);
+    if (par != hint) tile_load<T, TQ, TR, NT>(R, d, gl, 0, tl.tq, tl.tr);
     const KGrid &g = scen[s].g;  // by reference (see k_ensemble)
     const KConst &kc = scen[s].kc;
     const double r_next = rain_rate(scen[s].rn, st.t_next);
@@ -194,18 +197,18 @@ __global__ __launch_bounds__(NT) void k_ens_step(KDom<T> base, const EnsScen *__
 
 template <typename T, int TQ, int TR, int NT>
 static hipError_t launch_ens_step_v(bool visc, bool bc, const KDom<T> &base,
-                                    const EnsScen *scen, const EnsTile *tiles, Ctl *ctl,
-                                    Part *part, int ntiles_total, int nscen, int par_hint,
-                                    hipStream_t stream) {
+                                    const EnsScen *scen, const EnsTile *tiles,
+                                    const uint8_t *tpar, Ctl *ctl, Part *part, int ntiles_total,
+                                    int nscen, int par_hint, hipStream_t stream) {
     if (visc)
         hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, true, true>), dim3(ntiles_total), dim3(NT),
-                           0, stream, base, scen, tiles, ctl, part, ntiles_total, par_hint);
+                           0, stream, base, scen, tiles, tpar, ctl, part, ntiles_total, par_hint);
     else if (bc)
         hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, false, true>), dim3(ntiles_total), dim3(NT),
-                           0, stream, base, scen, tiles, ctl, part, ntiles_total, par_hint);
+                           0, stream, base, scen, tiles, tpar, ctl, part, ntiles_total, par_hint);
     else
         hipLaunchKernelGGL((k_ens_step<T, TQ, TR, NT, false, false>), dim3(ntiles_total),
-                           dim3(NT), 0, stream, base, scen, tiles, ctl, part, ntiles_total,
+                           dim3(NT), 0, stream, base, scen, tiles, tpar, ctl, part, ntiles_total,
                            par_hint);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -214,13 +217,14 @@ static hipError_t launch_ens_step_v(bool visc, bool bc, const KDom<T> &base,
 
 template <typename T>
 hipError_t launch_ens_step(int variant, bool visc, bool bc, const KDom<T> &base,
-                           const EnsScen *scen, const EnsTile *tiles, Ctl *ctl, Part *part,
-                           int ntiles_total, int nscen, int par_hint, hipStream_t stream) {
+                           const EnsScen *scen, const EnsTile *tiles, const uint8_t *tpar,
+                           Ctl *ctl, Part *part, int ntiles_total, int nscen, int par_hint,
+                           hipStream_t stream) {
     switch (variant) {
 #define HEXSV_CASE(V)                                                                          \
     case V:                                                                                    \
         return launch_ens_step_v<T, TILES[V].tq, TILES[V].tr, TILES[V].nt>(                    \
-            visc, bc, base, scen, tiles, ctl, part, ntiles_total, nscen, par_hint, stream);
+            visc, bc, base, scen, tiles, tpar, ctl, part, ntiles_total, nscen, par_hint, stream);
         HEXSV_TILE_SWITCH(HEXSV_CASE)
 #undef HEXSV_CASE
         default:
@@ -262,7 +266,7 @@ hipError_t launch_ensemble(int variant, const KDom<T> &base, const EnsScen *scen
                                            const int32_t *, int, uint32_t *, int, int,        \
                                            hipStream_t);                                      \
     template hipError_t launch_ens_step<T>(int, bool, bool, const KDom<T> &, const EnsScen *, \
-                                           const EnsTile *, Ctl *, Part *, int, int, int,     \
-                                           hipStream_t);
+                                           const EnsTile *, const uint8_t *, Ctl *, Part *,   \
+                                           int, int, int, hipStream_t);
 
 }  // namespace hexsv

@@ -31,11 +31,13 @@ struct EnsScen;
 struct EnsTile;
 // Batched-step mode of the ensemble: the tile kernel over the tiles of all
 // scenarios (one workgroup each) followed by the per-scenario finalize.
-// par_hint: the buffer parity the live scenarios are expected to read.
+// Tile t loads the buffers of parity par_hint ^ tpar[t] first (tpar: the
+// scenarios' parities relative to the launch hint).
 template <typename T>
 hipError_t launch_ens_step(int variant, bool visc, bool bc, const KDom<T> &base,
-                           const EnsScen *scen, const EnsTile *tiles, Ctl *ctl, Part *part,
-                           int ntiles_total, int nscen, int par_hint, hipStream_t stream);
+                           const EnsScen *scen, const EnsTile *tiles, const uint8_t *tpar,
+                           Ctl *ctl, Part *part, int ntiles_total, int nscen, int par_hint,
+                           hipStream_t stream);
 hipError_t launch_ens_finalize(const EnsScen *scen, Ctl *ctl, const Part *part, int nscen,
                                hipStream_t stream);
 // Reset the ensemble's scenario queue (a one-thread kernel, safe inside graphs).

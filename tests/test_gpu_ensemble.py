@@ -80,6 +80,29 @@ def test_ensemble_step_limit_and_resume(hx, mode):
         assert_parity(got, ref, "fp64", f"resume{s}")
 
 
+@pytest.mark.parametrize("tile", [2, 0])
+def test_ensemble_resumes_from_mixed_parities(hx, tile):
+    """Runs to each scenario's own stop leave the scenarios at different step counts, so
+    their buffer parities differ when the next run starts (the batched launches' per-tile
+    load hints carry them); every scenario still ends bit-identical to a single-catchment
+    run with the same stops."""
+    scs = mixed_scenarios()
+    stops = [0.37 * sc.t_end + 3.1 * s for s, sc in enumerate(scs)]
+    ens = hx.Ensemble.from_scenarios(scs, "fp64", steps_per_launch=7, tile=tile, mode="batched")
+    ens.run(stops)
+    parities = {ens.books(s)["steps"] % 2 for s in range(len(scs))}
+    assert parities == {0, 1}, parities
+    ens.run([sc.t_end for sc in scs])
+    for s, sc in enumerate(scs):
+        single = hx.Sim.from_scenario(sc, "fp64", tile=tile)
+        single.run(stops[s])
+        single.run(sc.t_end)
+        got, st = ens.state_numpy(s), single.state_numpy()
+        assert ens.books(s)["steps"] == single.books()["steps"], s
+        for k in ("h", "v1", "v2"):
+            np.testing.assert_array_equal(got[k], st[k])
+
+
 def test_ensemble_timing_counts_cell_updates(hx):
     scs = mixed_scenarios()[:4]
     ens = hx.Ensemble.from_scenarios(scs, "fp32")
