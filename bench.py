@@ -39,12 +39,15 @@ BYTES_PER_CELL = {"fp32": 9 * 4, "fp64": 9 * 8}
 # Measured HBM bytes of one step-kernel launch: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB
 # per dispatch, in runs of their own) scaled by what the same counters read for a plain 1 GiB
 # device copy (x2.000 and x1.000); the summaries with their commands are
-# profiles/k_step_catchment-4096x4096_fp32.md and profiles/k_ens_step_ensemble-256-catchments.md.
+# profiles/k_step_catchment-4096x4096_fp32.md, profiles/k_step_catchment-4096x4096_fp64.md and
+# profiles/k_ens_step_ensemble-256-catchments.md.
 # A figure holds only for the kernel source it was taken on (digest below); otherwise the line
 # reports null.
 TRAFFIC = {
     ("catchment-4096x4096-edge2m-storm150mmh", "fp32", 4): {
         "bytes": 654594432, "digest": "46b96e45981a54c7"},
+    ("catchment-4096x4096-edge2m-storm150mmh", "fp64", 2): {
+        "bytes": 1245442368, "digest": "46b96e45981a54c7"},
 }
 # the batched ensemble's k_ens_step (64 x 16 tiles) per launch over all 256 scenarios, 300 s
 # into the storms (the timed launches)
