@@ -260,6 +260,7 @@ extern "C" int hexsv_ensemble_create(int32_t n, const hexsv_grid *const *grids,
     if (err == hipSuccess) err = hipMalloc(&e->d_bpart, sizeof(Part) * (size_t)maxtiles);
     if (err == hipSuccess) err = hipMalloc(&e->d_tiles, sizeof(EnsTile) * (size_t)maxtiles);
     if (err == hipSuccess) err = hipMalloc(&e->d_tpar, (size_t)maxtiles);
+    if (err == hipSuccess) err = hipMemset(e->d_tpar, 0, (size_t)maxtiles);
     if (err == hipSuccess) err = hipHostMalloc(&e->h_ctl, sizeof(Ctl) * n, hipHostMallocDefault);
     if (err == hipSuccess) err = hipHostMalloc(&e->h_chk, 8 * sizeof(int32_t), hipHostMallocDefault);
     if (err == hipSuccess) err = hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking);
