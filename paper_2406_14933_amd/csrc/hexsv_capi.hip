@@ -1096,14 +1096,13 @@ extern "C" int hexsv_sim_surrogate_features(hexsv_sim *s, hexsv_surrogate *sur, 
 }
 
 // Windows chained in one graph launch (a refused window stops the rest of
-// its chain, whose kernels then return at once).  The chain length adapts: it
-// shrinks after a chain with a refusal (fewer dead windows launched) and grows
-// after a chain without one (fewer host round trips).
-// Chain lengths with a captured graph.  After a refusal the next chain is as long
-// as the run of kept windows before it plus one (refusals tend to recur at that
-// period, so the chain ends where the next refusal is expected, and a run of
-// refusals tries one window at a time); a chain kept whole is followed by one at
-// least twice as long.
+// its chain, whose kernels then return at once: dead windows, each still a few
+// launches).  Graphs are captured for the chain lengths below.  After a refusal
+// the next chain is as long as the run of kept windows before it plus one
+// (refusals tend to recur at that period, so the chain ends where the next
+// refusal is expected, and a run of refusals tries one window at a time); a
+// chain kept whole is followed by one at least twice as long (fewer host round
+// trips).
 constexpr int N_CHAINS = 6;
 static const int WIN_CHAINS[N_CHAINS] = {1, 2, 3, 4, 8, 16};
 static int chain_at_most(int n) {  // the longest captured chain of at most n windows
