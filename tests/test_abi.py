@@ -59,3 +59,4 @@ def test_host_only_calls_without_gpu():
     d.mask_bc = hexsv.WALL
     d.nseg = 9
     assert L.hexsv_grid_create(ctypes.byref(d), ctypes.byref(h)) == hexsv.EINVAL
+    assert L.hexsv_sim_set_surrogate_backoff(None, 4) == hexsv.EINVAL
