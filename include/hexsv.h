@@ -377,7 +377,7 @@ int hexsv_autotune(const char *cache_path, int32_t kernel, int32_t precision, in
 
 /* A hex-convolution residual network that predicts the change of the state
  * over a window of k solver steps (not part of the paper's method; the
- * solver stays its fallback and judge).  Layers: hex_conv(11 -> C), ReLU,
+ * solver stays its fallback and the reference for its error).  Layers: hex_conv(11 -> C), ReLU,
  * (layers - 2) x [hex_conv(C -> C), ReLU], hex_conv(C -> 3), where
  * hex_conv(x)[i][o] = b[o] + sum_{t<7, c} W[o][c][t] x[nbr_t(i)][c], tap 0
  * the cell, tap 1+k its neighbour in direction k as the raster's neighbour

@@ -3,7 +3,7 @@
 The network is trained on the GPU by the library's own BF16 MFMA forward/backward kernels on
 FP32 solver trajectories of the ensemble distribution (planar slopes, vegetation patches,
 constant or triangular rain), then drives held-out scenarios with the water-balance gate.
-Judged by the plain FP32 solver: the depth at t_end must stay within 1 % relative L1 while a
+Measured against the plain FP32 solver: the depth at t_end must stay within 1 % relative L1 while a
 substantial share of the solver's steps is replaced by network windows; the untrained
 network (the probe extrapolation alone) is run the same way for comparison.
 """
