@@ -2,8 +2,9 @@
 
 The surrogate is not part of the paper's method: it is a small residual
 network that maps the solver state at time t to the state change after k
-explicit steps, used with the paper's solver as fallback and as the reference for its error.  This
-module defines its arithmetic plainly so the GPU kernels can be checked:
+explicit steps, used with the paper's solver as fallback and as the reference
+for its error.  This module defines its arithmetic plainly so the GPU kernels
+can be checked:
 
   features  x0 (N x 11): h/H, q1/Q, q2/Q, z/Z, theta, (rain depth of the window)/H,
                          the terrain slope (dz/dx, dz/dy)/S, and the change of one probe step
