@@ -611,7 +611,7 @@ static int capture_steps(hexsv_sim *s, int nsteps, int par0, hipGraph_t *graph,
     for (int k = 0; k < nsteps && e == hipSuccess; ++k, ++j) {
         e = step_launch(s, cl, (par0 + k) & 1, j & 1, j % ACC_SETS, s->cap);
         if (e == hipSuccess && (j + 1 == s->ring_len || k + 1 == nsteps)) {
-            e = launch_fold(s->d_ctl, cl, s->ntiles, s->kc, s->rn, (j + 1) & 1, j % ACC_SETS,
+            e = launch_fold(s->d_ctl, cl, s->ntiles, s->kc, s->rn, (j + 1) & 1, j % ACC_SETS, j + 1,
                             s->cap);
             j = -1;
         }

@@ -73,9 +73,9 @@ __global__ __launch_bounds__(64) void k_fold_close(Ctl *ctl, KClose cl, KConst k
 }
 
 hipError_t launch_fold(Ctl *ctl, const KClose &cl, int ntiles, const KConst &kc, const KRain &rn,
-                       int in, int set, hipStream_t stream) {
-    hipLaunchKernelGGL(k_fold_slots, dim3(cl.ring_len), dim3(1024), 0, stream, ctl, cl, ntiles,
-                       in);
+                       int in, int set, int launches, hipStream_t stream) {
+    const int slots = launches < 1 ? 1 : (launches < cl.ring_len ? launches : cl.ring_len);
+    hipLaunchKernelGGL(k_fold_slots, dim3(slots), dim3(1024), 0, stream, ctl, cl, ntiles, in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fold_close, dim3(1), dim3(64), 0, stream, ctl, cl, kc, rn, in, set);
@@ -309,36 +309,53 @@ __global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const P
                                                    int n_part, const Part *op0, int n_op0,
                                                    KConst kc) {
     if (!sw->live) return;
+    // the window's record and the books it updates, loaded while the partial sums
+    // are reduced (nothing else writes them during this launch)
+    double window = 0.0, S0 = 0.0, R = 0.0, c0 = 0.0, tol = 0.0, t0 = 0.0, rain = 0.0,
+           outflow = 0.0;
+    int project = 0, parity = 0;
+    if (threadIdx.x == 0) {
+        window = sw->window;
+        S0 = sw->S0;
+        R = sw->R;
+        c0 = sw->c0;
+        tol = sw->tol;
+        t0 = sw->t0;
+        project = sw->project;
+        rain = ctl->rain;
+        outflow = ctl->outflow;
+        parity = ctl->parity;
+    }
     Part p{0.0, 0.0, 0.0, 0.0};
     double o0_stored = 0.0;
     reduce_window_parts(part, n_part, op0, n_op0, p, o0_stored);
     if (threadIdx.x != 0) return;
-    const double Ow = 0.5 * (o0_stored + p.outflow) * sw->window;
-    double ref = sw->S0 + sw->R;
+    const double Ow = 0.5 * (o0_stored + p.outflow) * window;
+    double ref = S0 + R;
     if (ref < 1e-300) ref = 1e-300;
-    const double rho = fabs(p.stored - sw->S0 - (sw->R - Ow)) / ref;
+    const double rho = fabs(p.stored - S0 - (R - Ow)) / ref;
     sw->rho = rho;
     // also refused: a prediction whose fastest wave more than doubles within the
     // window (it would shrink the solver's next steps for no physical reason)
     // (an infinite tolerance keeps every finite window)
-    const bool calm = !(sw->c0 > 0.0) || p.cmax <= 2.0 * sw->c0 || isinf(sw->tol);
-    const bool ok = p.clamp == 0.0 && isfinite(p.stored) && isfinite(Ow) && rho <= sw->tol && calm;
+    const bool calm = !(c0 > 0.0) || p.cmax <= 2.0 * c0 || isinf(tol);
+    const bool ok = p.clamp == 0.0 && isfinite(p.stored) && isfinite(Ow) && rho <= tol && calm;
     if (ok) {
-        const double target = sw->S0 + sw->R - Ow;
+        const double target = S0 + R - Ow;
         double stored = p.stored;
         // the new state waits for its projection factor (applied by the next window's
         // loads and once after the chain); the start state's factor is spent
         sw->scale_live = 0;
-        if (sw->project && p.stored > 0.0 && target > 0.0) {
+        if (project && p.stored > 0.0 && target > 0.0) {
             sw->scale = target / p.stored;
             sw->scale_live = 1;
             stored = target;
         }
-        ctl->t = sw->t0 + sw->window;
-        ctl->parity ^= 1;
+        ctl->t = t0 + window;
+        ctl->parity = parity ^ 1;
         ctl->stored = stored;
-        ctl->rain += sw->R;
-        ctl->outflow += Ow;
+        ctl->rain = rain + R;
+        ctl->outflow = outflow + Ow;
         ctl->last_cmax = p.cmax;
         ctl->tau = p.cmax > 0.0 ? kc.cfl_phi / p.cmax : INFINITY;
         sw->accepted += 1;
@@ -346,7 +363,7 @@ __global__ __launch_bounds__(1024) void k_win_gate(Ctl *ctl, SurWin *sw, const P
         sw->alive = 0;
         sw->rejected = 1;
         const bool finite = p.clamp == 0.0 && isfinite(p.stored) && isfinite(Ow);
-        sw->why = !finite ? 4 : (rho > sw->tol ? 1 : 2);
+        sw->why = !finite ? 4 : (rho > tol ? 1 : 2);
     }
     sw->live = 0;
 }

@@ -84,12 +84,14 @@ hipError_t launch_step(int variant, const KDom<T> &d, const KGrid &g, const KCon
                        const KRain &rn, Ctl *ctl, const KClose &cl, int ntq, int ntiles, int nwg,
                        int par_hint, int in, int set, hipStream_t stream);
 
-// After a run of step launches whose last one read slot `in` with
-// accumulator set `set`: close its pending step, add the books of every
-// closed step in the ring to ctl[0] in step order, empty the ring and clear
-// the accumulators (one workgroup per ring slot, then one wave).
+// After a run of `launches` step launches since the previous fold, the last of
+// which read slot `in` with accumulator set `set`: close its pending step, add
+// the books of every closed step in the ring to ctl[0] in step order, empty the
+// ring and clear the accumulators (one workgroup per ring slot the run can have
+// filled, at most `launches`: the first launch after a fold has nothing to close,
+// then one wave).
 hipError_t launch_fold(Ctl *ctl, const KClose &cl, int ntiles, const KConst &kc, const KRain &rn,
-                       int in, int set, hipStream_t stream);
+                       int in, int set, int launches, hipStream_t stream);
 // Close a priming pass over nparts partial records: tau (and, with
 // reset_books, the initial books) of the current state.
 hipError_t launch_prime_finalize(Ctl *ctl, const Part *part, int nparts, const KConst &kc,
